@@ -1,0 +1,185 @@
+"""Benchmark of the dynamic-circuit state-vector path on one MI355X.
+
+A step is one qsv_run_shots call that runs every shot of the workload through
+the whole hot path (state init, fused gate passes, mid-circuit measurement,
+feed-forward, final measure-all). Default workload: 28 qubits, complex128,
+40 U3 + CX brickwork layers, a 4-qubit mid-circuit measurement, a multi-bit
+predicate block, an if/else on one bit and a final measure-all; 16 shots per
+step (4 GiB of state per shot, all resident in HBM).
+
+Prints one JSON line. `value` is shots/s over the timed steps. `roofline`
+describes the dominant kernel (the tile pass), timed with HIP events inside
+the library during the timed steps. `cpu_baseline` times the CPU oracle on a
+bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c2|c1|c3]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 128 FP64 flops/clock (64 FMA lanes) x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import workloads as W
+    if name == "c2":
+        return (W.c2_program(seed=2, n=28, layers=40), 16,
+                {"workload": "28-qubit complex128 dynamic circuit: 40 U3+CX brickwork layers, "
+                             "4-qubit mid-circuit measurement, if (c == 0b1010) 3-gate block, "
+                             "if/else rx/rz on c[0], measure-all; 16 shots per step",
+                 "qubits": 28, "layers": 40, "shots_per_step": 16})
+    if name == "c1":
+        return (W.c1_program(seed=1), 1000,
+                {"workload": "10-qubit complex128 dynamic circuit: 20 U3+CX layers with 3 "
+                             "measure/if/reset sites, measure-all; 1000 shots per step",
+                 "qubits": 10, "layers": 20, "shots_per_step": 1000})
+    if name == "c3":
+        return (W.c3_program(seed=3, n=16), 4096,
+                {"workload": "16-qubit complex128: 12 random layers, then a repeat-until-success "
+                             "loop of at most 8 iterations; measure-all; 4096 shots per step",
+                 "qubits": 16, "layers": 12, "shots_per_step": 4096})
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "qsv_types.h"):
+        with open(os.path.join(ROOT, "paper_2604_11599_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(name):
+    """HBM bytes per tile-pass launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"tile_pass_{name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(src, budget_s=15.0):
+    """The oracle, as it stands, on the first operations of one shot of the workload;
+    the per-operation time is extrapolated to a whole shot."""
+    import numpy as np
+
+    from oracle import sim
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    prog = sim.Program(src)
+    ops_per_shot = 0
+    for st in prog.body:
+        if st[0] in ("gate",):
+            ops_per_shot += 1
+        elif st[0] == "measure":
+            ops_per_shot += prog.qregs["q"][1] if st[1][2] is None else 1
+        elif st[0] == "if":
+            ops_per_shot += max(len(st[2]), len(st[3]))
+    gates = [st for st in prog.body if st[0] == "gate"]
+    it = sim.Interpreter(prog)
+    t0 = time.perf_counter()
+    it.eng = sim.TensorEngine(prog.n_qubits)
+    it.cbits, it.gate_count, it.tape, it.shift = [0] * prog.n_clbits, 0, None, {}
+    t_alloc = time.perf_counter() - t0
+    done = 0
+    t1 = time.perf_counter()
+    while done < len(gates) and (done < 2 or time.perf_counter() - t1 < budget_s):
+        it.exec_stmt(gates[done], {})
+        done += 1
+    dt = time.perf_counter() - t1
+    per_op = dt / done
+    shot_s = per_op * ops_per_shot + t_alloc
+    del it
+    _ = np
+    return {"value": 1.0 / shot_s, "unit": "shots/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} of {ops_per_shot} state operations of one shot "
+                      f"({prog.n_qubits} qubits), {dt:.1f} s; extrapolated linearly to a whole shot"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_11599_amd import Context
+
+    src, shots, cfg = workload(args.workload)
+    log("workload", args.workload, cfg["workload"])
+    ctx = Context(0, profile=True)
+    prog = ctx.load(src)
+    log(f"planned {prog.info.n_passes} passes, {prog.info.n_sites} measurement sub-sites")
+    for w in range(args.warmup):
+        prog.run_shots(shots, seed=1000 + w)
+        log(f"warmup {w} done")
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        prog.run_shots(shots, seed=s)
+        log(f"step {s} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile()
+    ms_per_step = 1e3 * dt / args.steps
+    value = shots * args.steps / dt
+
+    launches = prof["pass_uncond_launches"]
+    t_pass = prof["pass_uncond_ms"] / 1e3
+    gbs = prof["pass_uncond_bytes"] / t_pass / 1e9 if t_pass else 0.0
+    tfl = prof["pass_uncond_flops"] / t_pass / 1e12 if t_pass else 0.0
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    alu = {"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": tfl / FP64_PEAK_TFLOPS}
+    roof = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
+    per_launch = prof["pass_uncond_bytes"] / launches if launches else 0.0
+    tr = traffic_from_profiles(args.workload)
+    roof["traffic"] = tr
+    roof["kernel"] = "k_tile_pass"
+    roof["launches"] = launches
+    roof["avg_launch_ms"] = prof["pass_uncond_ms"] / launches if launches else 0.0
+    roof["algorithmic_bytes_per_launch"] = per_launch
+    roof["other_bound"] = alu if roof["bound"] == "hbm" else hbm
+    roof["time_share"] = {"tile_pass_ms": prof["pass_ms"], "site_ms": prof["site_ms"],
+                          "other_ms": prof["other_ms"], "wall_ms": 1e3 * dt}
+
+    out = {"metric": "shots/s + achieved HBM GB/s on 16q/28q dynamic circuits; p50/p99 request latency",
+           "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof}
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample of the workload")
+        out["cpu_baseline"] = cpu_baseline(src)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+"""Python binding of libqsv with the C ABI's names (argument marshalling only)."""
+import ctypes as C
+
+import numpy as np
+
+from . import _abi as A
+from .lower import LoweredProgram, lower
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{A.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _desc(lp):
+    instr = np.ascontiguousarray(lp.instr)
+    pred = np.ascontiguousarray(lp.pred)
+    d = A.ProgramDesc(lp.n_qubits, lp.n_clbits, lp.n_params, len(instr), len(pred), 0,
+                      instr.ctypes.data if len(instr) else None, pred.ctypes.data if len(pred) else None)
+    return d, (instr, pred)
+
+
+def plan_inspect(source, tile_bits=0):
+    """Host-only planner statistics (no GPU needed)."""
+    lp = source if isinstance(source, LoweredProgram) else lower(source)
+    d, keep = _desc(lp)
+    st = A.PlanStats()
+    rc = A.lib().qsv_plan_inspect(C.byref(d), tile_bits, C.byref(st))
+    if rc:
+        raise QsvError(rc, "planning failed")
+    return st
+
+
+class Context:
+    """qsv_create / qsv_destroy. `stream` may be a torch.cuda.Stream or a raw hipStream_t."""
+
+    def __init__(self, device=0, stream=None, arena=None, arena_bytes=0, device_ptrs=False, profile=False):
+        raw = None
+        if stream is not None:
+            raw = getattr(stream, "cuda_stream", stream)
+        flags = (A.QSV_FLAG_DEVICE_PTRS if device_ptrs else 0) | (A.QSV_FLAG_PROFILE if profile else 0)
+        cfg = A.Config(device, raw, arena, arena_bytes, flags)
+        h = C.c_void_p()
+        rc = A.lib().qsv_create(C.byref(cfg), C.byref(h))
+        if rc:
+            raise QsvError(rc, "qsv_create failed")
+        self.handle = h
+        self.device_ptrs = device_ptrs
+
+    def close(self):
+        if self.handle:
+            A.lib().qsv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        msg = A.lib().qsv_last_error(self.handle)
+        return msg.decode() if msg else ""
+
+    def check(self, rc):
+        if rc:
+            raise QsvError(rc, self.last_error())
+
+    def profile(self):
+        """qsv_profile_read as a dict (context created with profile=True)."""
+        p = A.Profile()
+        self.check(A.lib().qsv_profile_read(self.handle, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in A.Profile._fields_}
+
+    def profile_reset(self):
+        self.check(A.lib().qsv_profile_reset(self.handle))
+
+    def load(self, source):
+        """qsv_load_program on OpenQASM 3 text or a LoweredProgram."""
+        return Program(self, source)
+
+
+class ShotResultArrays:
+    def __init__(self, creg, record, n_events, record_prob, shot_status, state, n_clbits):
+        self.creg, self.record, self.n_events = creg, record, n_events
+        self.record_prob, self.shot_status, self.state = record_prob, shot_status, state
+        self.n_clbits = n_clbits
+
+    def bits(self):
+        """Classical bits as an [n_shots, n_clbits] uint8 array."""
+        out = np.zeros((self.creg.shape[0], self.n_clbits), dtype=np.uint8)
+        for i in range(self.n_clbits):
+            out[:, i] = (self.creg[:, i // 64] >> np.uint64(i % 64)) & np.uint64(1)
+        return out
+
+
+class Program:
+    def __init__(self, ctx, source):
+        self.ctx = ctx
+        self.lowered = source if isinstance(source, LoweredProgram) else lower(source)
+        d, keep = _desc(self.lowered)
+        h = C.c_void_p()
+        ctx.check(A.lib().qsv_load_program(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+        info = A.ProgramInfo()
+        A.lib().qsv_program_info_get(h, C.byref(info))
+        self.info = info
+
+    def free(self):
+        if self.handle:
+            A.lib().qsv_program_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def n_qubits(self):
+        return self.info.n_qubits
+
+    def _theta(self, theta, batch=None):
+        p = self.info.n_params
+        if p == 0:
+            return np.zeros(max(1, batch or 1) * 1, dtype=np.float64)
+        t = np.ascontiguousarray(theta, dtype=np.float64)
+        if batch is None:
+            if t.size != p:
+                raise ValueError(f"theta must hold {p} values")
+        elif t.size != p * batch:
+            raise ValueError(f"theta must be [{batch}, {p}]")
+        return t
+
+    def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
+                  share_prefix=False):
+        """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses."""
+        lp = self.lowered
+        cw = max(1, (lp.n_clbits + 63) // 64)
+        mr = self.info.max_events
+        creg = np.zeros((n_shots, cw), dtype=np.uint64)
+        record = np.zeros((n_shots, max(1, mr)), dtype=np.uint8)
+        nev = np.zeros(n_shots, dtype=np.uint32)
+        prob = np.zeros(n_shots, dtype=np.float64)
+        status = np.zeros(n_shots, dtype=np.int32)
+        if theta is None and self.info.n_params:
+            raise ValueError(f"this program takes {self.info.n_params} input parameters")
+        th = self._theta(theta if theta is not None else np.zeros(self.info.n_params))
+        f = None
+        flen = 0
+        if forced is not None:
+            f = np.ascontiguousarray(forced, dtype=np.uint8)
+            if f.ndim == 1:
+                f = np.broadcast_to(f, (n_shots, f.size)).copy()
+            if f.shape[0] != n_shots:
+                raise ValueError("forced must have one row per shot")
+            flen = f.shape[1]
+        st = np.zeros((1 << lp.n_qubits, 2), dtype=np.float64) if state_out else None
+        opts = A.RunOpts(seed & 0xFFFFFFFFFFFFFFFF, shot_offset, _ptr(f), flen,
+                         A.QSV_RUN_SHARE_PREFIX if share_prefix else 0, _ptr(st))
+        res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
+        self.ctx.check(A.lib().qsv_run_shots(self.ctx.handle, self.handle, _ptr(th), n_shots,
+                                             C.byref(opts), C.byref(res)))
+        state = None if st is None else st[:, 0] + 1j * st[:, 1]
+        return ShotResultArrays(creg, record[:, :mr], nev, prob, status, state, lp.n_clbits)
+
+    def _pauli(self, coeffs, codes):
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        k = np.ascontiguousarray(codes, dtype=np.uint8).reshape(len(c), self.info.n_qubits)
+        return A.PauliSum(len(c), 0, _ptr(c), _ptr(k)), (c, k)
+
+    def expval(self, thetas, coeffs, codes):
+        """qsv_expval over a batch of parameter vectors thetas[B, P] (host arrays)."""
+        th = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
+        b = th.shape[0] if self.info.n_params else max(1, th.shape[0])
+        th = self._theta(th, b)
+        h, keep = self._pauli(coeffs, codes)
+        e = np.zeros(b, dtype=np.float64)
+        self.ctx.check(A.lib().qsv_expval(self.ctx.handle, self.handle, _ptr(th), b, C.byref(h), _ptr(e)))
+        return e
+
+    def expval_grad(self, thetas, coeffs, codes):
+        """qsv_expval_grad: energies [B] and gradients [B, P]."""
+        th = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
+        b = th.shape[0]
+        th = self._theta(th, b)
+        h, keep = self._pauli(coeffs, codes)
+        e = np.zeros(b, dtype=np.float64)
+        g = np.zeros((b, max(1, self.info.n_params)), dtype=np.float64)
+        self.ctx.check(A.lib().qsv_expval_grad(self.ctx.handle, self.handle, _ptr(th), b, C.byref(h),
+                                               _ptr(e), _ptr(g)))
+        return e, g[:, :self.info.n_params]
+
+    def expval_grad_device(self, theta_ptr, batch, pauli_sum, energy_ptr, grad_ptr):
+        """qsv_expval_grad with device pointers (context created with device_ptrs=True)."""
+        self.ctx.check(A.lib().qsv_expval_grad(self.ctx.handle, self.handle, C.c_void_p(theta_ptr), batch,
+                                               C.byref(pauli_sum), C.c_void_p(energy_ptr),
+                                               C.c_void_p(grad_ptr)))

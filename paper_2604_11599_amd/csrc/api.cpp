@@ -1,0 +1,638 @@
+// C ABI of libqsv (see include/qsv.h): contexts, program loading, shot
+// execution, expectation values and adjoint gradients on one GPU.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "planner.h"
+#include "qsv.h"
+#include "qsv_plan.h"
+
+using namespace qsv;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qsv_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint32_t flags = 0;
+  uint8_t* arena = nullptr;
+  size_t arena_bytes = 0;
+  size_t arena_top = 0;
+  std::string err;
+  std::vector<DevBuf> cache;  // grow-only scratch slots (used when no arena is given)
+  size_t slot = 0;
+  // profiling (QSV_FLAG_PROFILE): events around every launch, harvested after each sync
+  struct Rec {
+    hipEvent_t a, b;
+    int kind;  // 0 pass, 1 site, 2 other
+    bool uncond;
+    double bytes, flops;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<Rec> recs;
+  qsv_profile prof{};
+  bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0; }
+};
+
+struct qsv_program {
+  qsv_context* ctx = nullptr;
+  qsv_program_desc desc{};
+  std::vector<qsv_instr> instr;
+  std::vector<qsv_pred> pred;
+  Plan plan;
+  // device copies of the static plan
+  DGate* d_gates = nullptr;
+  GateSrc* d_src = nullptr;
+  SiteEvent* d_events = nullptr;
+  DPred* d_preds = nullptr;
+  uint32_t* d_csr_off = nullptr;
+  uint32_t* d_csr_sj = nullptr;
+  double* d_csr_scale = nullptr;
+  uint32_t pblocks = 1;
+};
+
+namespace {
+
+#define HIP_TRY(call)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+      return e_ == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_DEVICE;          \
+    }                                                                             \
+  } while (0)
+
+qsv_status set_err(qsv_context* ctx, qsv_status st, const std::string& m) {
+  if (ctx) ctx->err = m;
+  return st;
+}
+
+// Scratch allocation for one call: from the caller's arena (bump pointer,
+// reset per call) or from grow-only cached hipMalloc slots.
+struct Scratch {
+  qsv_context* ctx;
+  explicit Scratch(qsv_context* c) : ctx(c) {
+    ctx->arena_top = 0;
+    ctx->slot = 0;
+  }
+  hipError_t get(size_t bytes, void** out) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    if (ctx->arena) {
+      if (ctx->arena_top + bytes > ctx->arena_bytes) return hipErrorOutOfMemory;
+      *out = ctx->arena + ctx->arena_top;
+      ctx->arena_top += bytes;
+      return hipSuccess;
+    }
+    if (ctx->slot == ctx->cache.size()) ctx->cache.push_back(DevBuf{});
+    DevBuf& b = ctx->cache[ctx->slot++];
+    if (b.bytes < bytes) {
+      if (b.p) (void)hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+      hipError_t e = hipMalloc(&b.p, bytes);
+      if (e != hipSuccess) return e;
+      b.bytes = bytes;
+    }
+    *out = b.p;
+    return hipSuccess;
+  }
+  template <class T>
+  hipError_t get(size_t count, T** out) {
+    return get(count * sizeof(T), reinterpret_cast<void**>(out));
+  }
+};
+
+template <class T>
+hipError_t upload(const std::vector<T>& v, T** out) {
+  *out = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(out), v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Brackets one launch with profiling events when the context profiles.
+struct Prof {
+  qsv_context* ctx;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Prof(qsv_context* c, hipStream_t s) : ctx(c), st(s) {
+    if (!ctx->profiling()) return;
+    a = next();
+    (void)hipEventRecord(a, st);
+  }
+  hipEvent_t next() {
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ctx->ev_used++];
+  }
+  void done(int kind, bool uncond = false, double bytes = 0, double flops = 0) {
+    if (!ctx->profiling() || !a) return;
+    hipEvent_t b = next();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    ctx->recs.push_back({a, b, kind, uncond, bytes, flops});
+  }
+};
+
+// After a stream sync: fold the recorded launch times into the counters.
+void harvest(qsv_context* ctx) {
+  if (!ctx->profiling()) return;
+  for (const auto& r : ctx->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    qsv_profile& p = ctx->prof;
+    if (r.kind == 0) {
+      p.pass_launches++;
+      p.pass_ms += ms;
+      if (r.uncond) {
+        p.pass_uncond_launches++;
+        p.pass_uncond_ms += ms;
+        p.pass_uncond_bytes += r.bytes;
+        p.pass_uncond_flops += r.flops;
+      }
+    } else if (r.kind == 1) {
+      p.site_launches++;
+      p.site_ms += ms;
+    } else {
+      p.other_launches++;
+      p.other_ms += ms;
+    }
+  }
+  ctx->recs.clear();
+  ctx->ev_used = 0;
+}
+
+size_t free_device_bytes() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
+  return fr;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_create(const qsv_config* cfg, qsv_context** out) {
+  if (!out) return QSV_ERR_ARG;
+  *out = nullptr;
+  std::unique_ptr<qsv_context> ctx(new qsv_context());
+  qsv_config def{};
+  if (!cfg) cfg = &def;
+  ctx->device = cfg->device;
+  ctx->flags = cfg->flags;
+  ctx->arena = static_cast<uint8_t*>(cfg->arena);
+  ctx->arena_bytes = cfg->arena ? cfg->arena_bytes : 0;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return QSV_ERR_DEVICE;
+  if (cfg->device < 0 || cfg->device >= count) return QSV_ERR_ARG;
+  if (hipSetDevice(cfg->device) != hipSuccess) return QSV_ERR_DEVICE;
+  if (cfg->stream) {
+    ctx->stream = static_cast<hipStream_t>(cfg->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) return QSV_ERR_DEVICE;
+    ctx->own_stream = true;
+  }
+  *out = ctx.release();
+  return QSV_OK;
+}
+
+void qsv_destroy(qsv_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (auto& b : ctx->cache)
+    if (b.p) (void)hipFree(b.p);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* qsv_last_error(const qsv_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_program** out) {
+  if (!ctx || !desc || !out) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (desc->n_qubits > (uint32_t)kMaxQubits)
+    return set_err(ctx, QSV_ERR_LIMIT, "more than 34 qubits do not fit one GPU's HBM");
+  std::string err;
+  if (!validate_program(*desc, &err)) return set_err(ctx, QSV_ERR_ARG, err);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, QSV_ERR_DEVICE, "hipSetDevice failed");
+  std::unique_ptr<qsv_program> p(new qsv_program());
+  p->ctx = ctx;
+  p->instr.assign(desc->instr, desc->instr + desc->n_instr);
+  p->pred.assign(desc->pred, desc->pred + desc->n_pred);
+  p->desc = *desc;
+  p->desc.instr = p->instr.data();
+  p->desc.pred = p->pred.data();
+  p->plan = build_plan(p->desc, PlanOptions());
+  const Plan& pl = p->plan;
+  for (const SiteArgs& s : pl.sites) p->pblocks = std::max(p->pblocks, s.blocks);
+  std::vector<DPred> dp;
+  for (const qsv_pred& q : p->pred) {
+    DPred d{};
+    d.lo = q.lo;
+    d.width = q.width;
+    d.value = q.value;
+    d.cmp = q.cmp;
+    dp.push_back(d);
+  }
+  // parameter -> (slot*3 + angle, scale) lists for the gradient chain rule
+  std::vector<uint32_t> off(desc->n_params + 1, 0), sj;
+  std::vector<double> sc;
+  {
+    std::vector<std::vector<std::pair<uint32_t, double>>> lists(desc->n_params);
+    for (uint32_t s = 0; s < pl.gate_src.size(); ++s)
+      for (int j = 0; j < 3; ++j)
+        if (pl.gate_src[s].param[j] != QSV_NONE)
+          lists[pl.gate_src[s].param[j]].push_back({s * 3 + j, pl.gate_src[s].scale[j]});
+    for (uint32_t k = 0; k < desc->n_params; ++k) {
+      off[k + 1] = off[k] + (uint32_t)lists[k].size();
+      for (auto& e : lists[k]) {
+        sj.push_back(e.first);
+        sc.push_back(e.second);
+      }
+    }
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(pl.gates, &p->d_gates);
+  if (e == hipSuccess) e = upload(pl.gate_src, &p->d_src);
+  if (e == hipSuccess) e = upload(pl.events, &p->d_events);
+  if (e == hipSuccess) e = upload(dp, &p->d_preds);
+  if (e == hipSuccess) e = upload(off, &p->d_csr_off);
+  if (e == hipSuccess) e = upload(sj, &p->d_csr_sj);
+  if (e == hipSuccess) e = upload(sc, &p->d_csr_scale);
+  if (e != hipSuccess) {
+    qsv_program_free(p.release());
+    return set_err(ctx, e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_DEVICE,
+                   std::string("program upload: ") + hipGetErrorString(e));
+  }
+  *out = p.release();
+  return QSV_OK;
+}
+
+qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) {
+  if (!prog || !out) return QSV_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->n_qubits = prog->desc.n_qubits;
+  out->n_clbits = prog->desc.n_clbits;
+  out->n_params = prog->desc.n_params;
+  out->max_events = prog->plan.max_record;
+  out->n_passes = (uint32_t)prog->plan.passes.size();
+  out->n_sites = (uint32_t)prog->plan.sites.size();
+  out->is_unitary = prog->plan.unitary ? 1 : 0;
+  return QSV_OK;
+}
+
+void qsv_program_free(qsv_program* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->ctx->device);
+  void* ptrs[] = {p->d_gates, p->d_src, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double* theta, uint64_t n_shots,
+                         const qsv_run_opts* opts, qsv_shot_results* out) {
+  if (!ctx || !prog || !out) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  if (prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
+  if (!out->creg) return set_err(ctx, QSV_ERR_ARG, "creg output is required");
+  const qsv_run_opts def{};
+  if (!opts) opts = &def;
+  if (opts->forced_len && !opts->forced) return set_err(ctx, QSV_ERR_ARG, "forced_len without forced");
+  if (prog->desc.n_params && !theta) return set_err(ctx, QSV_ERR_ARG, "theta is required");
+  if (n_shots == 0) return QSV_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const Plan& pl = prog->plan;
+  const uint32_t n = prog->desc.n_qubits;
+  const uint32_t cw = std::max<uint32_t>(1, (prog->desc.n_clbits + 63) / 64);
+  const uint32_t maxrec = std::max<uint32_t>(1, pl.max_record);
+  const uint64_t dim = 1ull << n;
+  const size_t state_bytes = dim * sizeof(double2);
+  // shots per batch: what fits in the arena / free memory after the per-shot scratch
+  size_t per_shot = state_bytes + sizeof(ShotCtl) + cw * 8 + maxrec + opts->forced_len +
+                    (size_t)prog->pblocks * kSiteBins * 8 + 4 * 256;
+  size_t budget = ctx->arena ? ctx->arena_bytes : (free_device_bytes() / 10) * 8;
+  size_t fixed = pl.gate_src.size() * kMatStride * 8 + prog->desc.n_params * 8 + (1u << 20);
+  if (budget <= fixed + per_shot) {
+    if (ctx->arena) return set_err(ctx, QSV_ERR_NOMEM, "arena too small for one shot");
+    budget = fixed + per_shot;  // try anyway; hipMalloc reports the failure
+  }
+  uint64_t batch = std::min<uint64_t>(n_shots, (budget - fixed) / per_shot);
+  batch = std::max<uint64_t>(1, std::min<uint64_t>(batch, 65535));
+  Scratch scr(ctx);
+  hipStream_t st = ctx->stream;
+  double* d_theta = nullptr;
+  double* d_mats = nullptr;
+  const uint32_t n_slots = (uint32_t)pl.gate_src.size();
+  HIP_TRY(scr.get(std::max<uint32_t>(1, prog->desc.n_params), &d_theta));
+  HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride, &d_mats));
+  if (prog->desc.n_params)
+    HIP_TRY(hipMemcpyAsync(d_theta, theta, prog->desc.n_params * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, prog->desc.n_params, 1, d_mats, nullptr, st));
+  RunBuffers rb{};
+  HIP_TRY(scr.get(batch * dim, &rb.state));
+  HIP_TRY(scr.get(batch, &rb.ctl));
+  HIP_TRY(scr.get(batch * cw, &rb.creg));
+  HIP_TRY(scr.get(batch * maxrec, &rb.record));
+  HIP_TRY(scr.get(batch * prog->pblocks * kSiteBins, &rb.partials));
+  uint8_t* d_forced = nullptr;
+  if (opts->forced_len) HIP_TRY(scr.get(batch * opts->forced_len, &d_forced));
+  double2* d_out = nullptr;
+  if (opts->state_out) HIP_TRY(scr.get(dim, &d_out));
+  rb.stride = dim;
+  rb.cw = cw;
+  rb.max_record = maxrec;
+  rb.pblocks = prog->pblocks;
+  rb.forced = d_forced;
+  rb.forced_len = opts->forced_len;
+  rb.seed = opts->seed;
+  std::vector<ShotCtl> hctl(batch);
+  for (uint64_t s0 = 0; s0 < n_shots; s0 += batch) {
+    const uint32_t bs = (uint32_t)std::min<uint64_t>(batch, n_shots - s0);
+    rb.shots = bs;
+    rb.shot_base = opts->shot_offset + s0;
+    if (opts->forced_len)
+      HIP_TRY(hipMemcpyAsync(d_forced, opts->forced + s0 * opts->forced_len, (size_t)bs * opts->forced_len,
+                             hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, bs, st));
+    for (const Step& step : pl.steps) {
+      Prof pr(ctx, st);
+      if (step.kind == Step::INIT) {
+        HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st));
+        pr.done(2);
+      } else if (step.kind == Step::PASS) {
+        HIP_TRY(launch_tile_pass(rb, prog->d_gates, d_mats, 0, pl.passes[step.index], st));
+        const double amps = (double)dim * bs;
+        pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * amps, pl.pass_flops_per_amp[step.index] * amps);
+      } else {
+        HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, st));
+        pr.done(1);
+      }
+    }
+    if (s0 == 0 && opts->state_out) {
+      HIP_TRY(launch_materialize(rb, n, 0, d_out, st));
+      HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, state_bytes, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipMemcpyAsync(out->creg + s0 * cw, rb.creg, (size_t)bs * cw * 8, hipMemcpyDeviceToHost, st));
+    if (out->record && pl.max_record) {
+      if (maxrec == pl.max_record) {
+        HIP_TRY(hipMemcpyAsync(out->record + s0 * pl.max_record, rb.record, (size_t)bs * maxrec,
+                               hipMemcpyDeviceToHost, st));
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(hctl.data(), rb.ctl, (size_t)bs * sizeof(ShotCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    harvest(ctx);
+    for (uint32_t s = 0; s < bs; ++s) {
+      if (out->n_events) out->n_events[s0 + s] = hctl[s].n_events;
+      if (out->record_prob) out->record_prob[s0 + s] = hctl[s].record_prob;
+      if (out->shot_status) out->shot_status[s0 + s] = hctl[s].status;
+    }
+  }
+  return QSV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct HamDev {
+  uint64_t* x = nullptr;
+  uint64_t* z = nullptr;
+  uint32_t* ny = nullptr;
+  double* c = nullptr;
+};
+
+qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* theta, uint32_t batch,
+                       const qsv_pauli_sum* h, double* energy, double* grad) {
+  if (!ctx || !prog || !h || !energy) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  if (prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
+  if (!prog->plan.unitary)
+    return set_err(ctx, QSV_ERR_UNSUPPORTED, "expectation values need a program without measurement or control flow");
+  if (h->n_terms && (!h->coeff || !h->pauli)) return set_err(ctx, QSV_ERR_ARG, "null Hamiltonian arrays");
+  if (prog->desc.n_params && !theta) return set_err(ctx, QSV_ERR_ARG, "theta is required");
+  if (batch == 0) return QSV_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const Plan& pl = prog->plan;
+  const uint32_t n = prog->desc.n_qubits, P = prog->desc.n_params, T = h->n_terms;
+  const uint64_t dim = 1ull << n;
+  const uint32_t n_slots = (uint32_t)pl.gate_src.size();
+  const bool dev = (ctx->flags & QSV_FLAG_DEVICE_PTRS) != 0;
+  hipStream_t st = ctx->stream;
+  // Pauli strings as (x mask, z mask, #Y)
+  std::vector<uint64_t> xm(T), zm(T);
+  std::vector<uint32_t> ny(T);
+  for (uint32_t t = 0; t < T; ++t) {
+    uint64_t x = 0, z = 0;
+    uint32_t y = 0;
+    for (uint32_t q = 0; q < n; ++q) {
+      uint8_t c = h->pauli[(size_t)t * n + q];
+      if (c > 3) return set_err(ctx, QSV_ERR_ARG, "Pauli code must be 0..3");
+      if (c == 1 || c == 2) x |= 1ull << q;
+      if (c == 3 || c == 2) z |= 1ull << q;
+      if (c == 2) ++y;
+    }
+    xm[t] = x;
+    zm[t] = z;
+    ny[t] = y & 3u;
+  }
+  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, dim / 4096));
+  // vectors per chunk: states (x2 with a gradient) must fit
+  size_t per = dim * 16 * (grad ? 2 : 1) + (size_t)n_slots * kMatStride * 8 * (grad ? 4 : 1) +
+               (size_t)T * blocks * 8 + P * 16 + 4096;
+  if (grad) {
+    size_t maxg = 0;
+    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)a.tiles * a.gate_count * 3);
+    per += maxg * 8 + (size_t)n_slots * 3 * 8;
+  }
+  size_t budget = ctx->arena ? ctx->arena_bytes : (free_device_bytes() / 10) * 8;
+  uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(batch, (budget > 65536 ? budget - 65536 : 0) / per));
+  chunk = std::min<uint64_t>(chunk, 65535);
+  Scratch scr(ctx);
+  HamDev hd;
+  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.x));
+  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.z));
+  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.ny));
+  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.c));
+  if (T) {
+    HIP_TRY(hipMemcpyAsync(hd.x, xm.data(), T * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(hd.z, zm.data(), T * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(hd.ny, ny.data(), T * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(hd.c, h->coeff, T * 8, hipMemcpyHostToDevice, st));
+  }
+  double *d_theta, *d_mats, *d_dmats = nullptr, *d_tp, *d_energy, *d_dEda = nullptr, *d_gpart = nullptr,
+                            *d_grad = nullptr;
+  RunBuffers rb{};
+  double2* d_lam = nullptr;
+  HIP_TRY(scr.get(chunk * std::max<uint32_t>(P, 1), &d_theta));
+  HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * kMatStride, &d_mats));
+  HIP_TRY(scr.get(chunk * std::max<uint32_t>(T, 1) * blocks, &d_tp));
+  HIP_TRY(scr.get(chunk, &d_energy));
+  HIP_TRY(scr.get(chunk * dim, &rb.state));
+  HIP_TRY(scr.get(chunk, &rb.ctl));
+  HIP_TRY(scr.get(chunk, &rb.creg));
+  if (grad) {
+    size_t maxg = 1;
+    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)a.tiles * a.gate_count * 3);
+    HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * 3 * kMatStride, &d_dmats));
+    HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * 3, &d_dEda));
+    HIP_TRY(scr.get(chunk * maxg, &d_gpart));
+    HIP_TRY(scr.get(chunk * std::max<uint32_t>(P, 1), &d_grad));
+    HIP_TRY(scr.get(chunk * dim, &d_lam));
+  }
+  rb.stride = dim;
+  rb.cw = 1;
+  const uint64_t ms = (uint64_t)n_slots * kMatStride;
+  for (uint64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const uint32_t bs = (uint32_t)std::min<uint64_t>(chunk, batch - b0);
+    rb.shots = bs;
+    if (P)
+      HIP_TRY(hipMemcpyAsync(d_theta, theta + b0 * P, (size_t)bs * P * 8,
+                             dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, P, bs, d_mats, d_dmats, st));
+    HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, 1, bs, st));
+    for (const Step& step : pl.steps) {
+      Prof pr(ctx, st);
+      if (step.kind == Step::INIT) {
+        HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st));
+        pr.done(2);
+      } else if (step.kind == Step::PASS) {
+        HIP_TRY(launch_tile_pass(rb, prog->d_gates, d_mats, ms, pl.passes[step.index], st));
+        const double amps = (double)dim * bs;
+        pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * amps, pl.pass_flops_per_amp[step.index] * amps);
+      }
+    }
+    if (T) {
+      HIP_TRY(launch_pauli_terms(rb.state, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, d_tp, blocks, st));
+      HIP_TRY(launch_energy_reduce(d_tp, T, blocks, hd.c, bs, d_energy, st));
+    } else {
+      HIP_TRY(hipMemsetAsync(d_energy, 0, bs * 8, st));
+    }
+    if (grad) {
+      HIP_TRY(launch_apply_hamiltonian(rb.state, d_lam, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, st));
+      HIP_TRY(hipMemsetAsync(d_dEda, 0, (size_t)bs * std::max<uint32_t>(n_slots, 1) * 3 * 8, st));
+      for (size_t k = pl.steps.size(); k-- > 0;) {
+        const Step& step = pl.steps[k];
+        if (step.kind != Step::PASS) continue;
+        const PassArgs& a = pl.passes[step.index];
+        HIP_TRY(launch_backward_pass(rb.state, d_lam, dim, bs, prog->d_gates, d_mats, d_dmats, ms, a, d_gpart, st));
+        HIP_TRY(launch_grad_reduce(d_gpart, a.tiles, a.gate_count, 0, prog->d_gates + a.gate_begin, bs,
+                                   std::max<uint32_t>(n_slots, 1), d_dEda, st));
+      }
+      HIP_TRY(launch_grad_chain(d_dEda, std::max<uint32_t>(n_slots, 1), prog->d_csr_off, prog->d_csr_sj,
+                                prog->d_csr_scale, P, bs, d_grad, st));
+      if (P)
+        HIP_TRY(hipMemcpyAsync(grad + b0 * P, d_grad, (size_t)bs * P * 8,
+                               dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipMemcpyAsync(energy + b0, d_energy, (size_t)bs * 8,
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (!dev) {
+      HIP_TRY(hipStreamSynchronize(st));
+      harvest(ctx);
+    }
+  }
+  if (dev) {
+    HIP_TRY(hipStreamSynchronize(st));
+    harvest(ctx);
+  }
+  return QSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_expval(qsv_context* ctx, const qsv_program* prog, const double* theta, uint32_t batch,
+                      const qsv_pauli_sum* h, double* energy) {
+  return expval_impl(ctx, prog, theta, batch, h, energy, nullptr);
+}
+
+qsv_status qsv_expval_grad(qsv_context* ctx, const qsv_program* prog, const double* theta, uint32_t batch,
+                           const qsv_pauli_sum* h, double* energy, double* grad) {
+  if (!grad) return set_err(ctx, QSV_ERR_ARG, "grad is required");
+  return expval_impl(ctx, prog, theta, batch, h, energy, grad);
+}
+
+qsv_status qsv_profile_read(qsv_context* ctx, qsv_profile* out) {
+  if (!ctx || !out) return QSV_ERR_ARG;
+  if (!ctx->profiling()) return set_err(ctx, QSV_ERR_ARG, "context was created without QSV_FLAG_PROFILE");
+  *out = ctx->prof;
+  return QSV_OK;
+}
+
+qsv_status qsv_profile_reset(qsv_context* ctx) {
+  if (!ctx) return QSV_ERR_ARG;
+  std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+  return QSV_OK;
+}
+
+// Host-only planner inspection (no device calls).
+qsv_status qsv_plan_inspect(const qsv_program_desc* desc, uint32_t tile_bits, qsv_plan_stats* out) {
+  if (!desc || !out) return QSV_ERR_ARG;
+  if (desc->n_qubits > (uint32_t)kMaxQubits) return QSV_ERR_LIMIT;
+  std::string err;
+  if (!validate_program(*desc, &err)) return QSV_ERR_ARG;
+  PlanOptions o;
+  if (tile_bits) o.tile_bits = std::min<uint32_t>(tile_bits, kTileMaxBits);
+  Plan pl = build_plan(*desc, o);
+  std::memset(out, 0, sizeof(*out));
+  out->n_steps = (uint32_t)pl.steps.size();
+  out->n_passes = (uint32_t)pl.passes.size();
+  out->n_sites = (uint32_t)pl.sites.size();
+  out->n_gates = (uint32_t)pl.gates.size();
+  out->n_events = (uint32_t)pl.events.size();
+  out->max_record = pl.max_record;
+  out->is_unitary = pl.unitary ? 1 : 0;
+  out->init_step = (!pl.steps.empty() && pl.steps[0].kind == Step::INIT) ? 1 : 0;
+  uint32_t k = 0;
+  for (const Step& s : pl.steps) {
+    if (k >= QSV_PLAN_MAX_STEPS) break;
+    out->step_kind[k] = s.kind;
+    if (s.kind == Step::PASS) {
+      const PassArgs& a = pl.passes[s.index];
+      out->step_mask[k] = a.tile_mask;
+      out->step_count[k] = a.gate_count;
+    } else if (s.kind == Step::SITE) {
+      const SiteArgs& a = pl.sites[s.index];
+      uint64_t m = 0;
+      for (uint32_t j = 0; j < a.nq; ++j) m |= 1ull << a.q[j];
+      out->step_mask[k] = m;
+      out->step_count[k] = a.ev_count;
+    }
+    ++k;
+  }
+  // instruction index of every planned gate, in execution order
+  uint32_t g = 0;
+  for (const Step& s : pl.steps) {
+    if (s.kind != Step::PASS) continue;
+    const PassArgs& a = pl.passes[s.index];
+    for (uint32_t i = 0; i < a.gate_count && g < QSV_PLAN_MAX_GATES; ++i, ++g)
+      out->gate_instr[g] = pl.slot_instr[pl.gates[a.gate_begin + i].mat];
+  }
+  return QSV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Launchers of the gfx950 kernels (host-callable, C++ linkage, internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qsv_types.h"
+
+namespace qsv {
+
+struct RunBuffers {
+  double2* state;          // [shots][2^n]
+  uint64_t stride;         // amplitudes between consecutive shots
+  ShotCtl* ctl;            // [shots]
+  uint64_t* creg;          // [shots][cw]
+  uint32_t cw;
+  uint8_t* record;         // [shots][max_record]
+  uint32_t max_record;
+  double* partials;        // [shots][pblocks][kSiteBins]
+  uint32_t pblocks;        // reduction workgroups per shot in the partials layout
+  const uint8_t* forced;   // [shots][forced_len] or null
+  uint32_t forced_len;
+  uint64_t seed, shot_base;   // Philox key (seed, shot_base + shot)
+  uint32_t shots;
+};
+
+hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
+                                uint32_t n_params, uint32_t batch, double* mats, double* dmats,
+                                hipStream_t st);
+hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots, hipStream_t st);
+hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st);
+hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const double* mats,
+                            uint64_t mat_stride, const PassArgs& a, hipStream_t st);
+hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
+                       const DPred* preds, hipStream_t st);
+hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out,
+                              hipStream_t st);
+
+// Expectation values and adjoint gradients over a batch of parameter vectors.
+hipError_t launch_pauli_terms(const double2* psi, uint64_t stride, uint32_t n, uint32_t batch,
+                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny,
+                              const double* coeff, uint32_t n_terms, double* term_partials,
+                              uint32_t blocks, hipStream_t st);
+hipError_t launch_energy_reduce(const double* term_partials, uint32_t n_terms, uint32_t blocks,
+                                const double* coeff, uint32_t batch, double* energy, hipStream_t st);
+hipError_t launch_apply_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n,
+                                    uint32_t batch, const uint64_t* xmask, const uint64_t* zmask,
+                                    const uint32_t* ny, const double* coeff, uint32_t n_terms,
+                                    hipStream_t st);
+hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uint32_t batch,
+                                const DGate* gates, const double* mats, const double* dmats,
+                                uint64_t mat_stride, const PassArgs& a, double* gpart,
+                                hipStream_t st);
+hipError_t launch_grad_reduce(const double* gpart, uint32_t tiles, uint32_t gate_count,
+                              uint32_t slot_begin_of_pass, const DGate* gates, uint32_t batch,
+                              uint32_t n_slots, double* dEda, hipStream_t st);
+hipError_t launch_grad_chain(const double* dEda, uint32_t n_slots, const uint32_t* csr_off,
+                             const uint32_t* csr_slot, const double* csr_scale, uint32_t n_params,
+                             uint32_t batch, double* grad, hipStream_t st);
+
+}  // namespace qsv

@@ -1,0 +1,911 @@
+// gfx950 kernels of the dynamic-circuit state-vector path (complex128).
+//
+// State layout: shot s holds its 2^n amplitudes contiguously at
+// state + s * stride (double2 = re, im; index i = sum_q b_q 2^q).
+//
+// Kernels:
+//   k_bind_matrices   2x2 gate matrices (and their angle derivatives) from theta
+//   k_init_state      |0...0> for every shot
+//   k_tile_pass       one fused gate pass: each workgroup stages a 2^t tile in
+//                     LDS, applies the pending collapse, the pass's guarded
+//                     gates (in the shot's qubit-flip frame) and stores it back
+//   k_site_reduce     per-workgroup probability histogram over <= 4 qubits
+//   k_site_finalize   per shot: fixed-order sum of the histograms, Philox draws,
+//                     outcomes, classical bits, flags, record, new pending collapse
+//   k_materialize     the logical state of one shot (collapse + frame applied)
+//   k_pauli_terms / k_energy_reduce / k_apply_hamiltonian   <psi|H|psi>, H psi
+//   k_backward_pass   adjoint sweep of one pass on (psi, lambda) with gradient partials
+//   k_grad_reduce / k_grad_chain   fixed-order gradient reductions
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "qsv.h"
+
+namespace qsv {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// u * a + v * b
+__device__ __forceinline__ double2 cmac2(double2 u, double2 a, double2 v, double2 b) {
+  double re = u.x * a.x - u.y * a.y + v.x * b.x - v.y * b.y;
+  double im = u.x * a.y + u.y * a.x + v.x * b.y + v.y * b.x;
+  return make_double2(re, im);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t b) {
+  return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
+}
+__device__ __forceinline__ uint64_t ins0_64(uint64_t x, uint32_t b) {
+  return ((x >> b) << (b + 1)) | (x & ((1ull << b) - 1ull));
+}
+
+// Philox4x64-10 (Salmon et al., SC'11): multipliers and Weyl increments of Philox4x64.
+__device__ __forceinline__ uint64_t philox_word(uint64_t seed, uint64_t shot, uint64_t event) {
+  uint64_t c0 = event / 4 + 1, c1 = 0, c2 = 0, c3 = 0;
+  uint64_t k0 = seed, k1 = shot;
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  switch (event & 3) {
+    case 0: return c0;
+    case 1: return c1;
+    case 2: return c2;
+    default: return c3;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix binding (compile once, run many: angles are affine in theta)
+// ---------------------------------------------------------------------------
+__device__ void set2(double* m, double2 a, double2 b, double2 c, double2 d) {
+  m[0] = a.x; m[1] = a.y; m[2] = b.x; m[3] = b.y; m[4] = c.x; m[5] = c.y; m[6] = d.x; m[7] = d.y;
+}
+__device__ __forceinline__ double2 cexpi(double t) {
+  double s, c;
+  sincos(t, &s, &c);
+  return make_double2(c, s);
+}
+
+__global__ void k_bind_matrices(const GateSrc* __restrict__ src, uint32_t n_slots,
+                                const double* __restrict__ theta, uint32_t n_params, uint32_t batch,
+                                double* __restrict__ mats, double* __restrict__ dmats) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n_slots * batch) return;
+  uint32_t b = (uint32_t)(idx / n_slots), slot = (uint32_t)(idx % n_slots);
+  const GateSrc& g = src[slot];
+  double a[3];
+  for (int k = 0; k < 3; ++k) {
+    a[k] = g.offset[k];
+    if (g.param[k] != QSV_NONE) a[k] += g.scale[k] * theta[(uint64_t)b * n_params + g.param[k]];
+  }
+  double* m = mats + idx * kMatStride;
+  double* dm = dmats ? dmats + idx * 3 * kMatStride : nullptr;
+  const double2 Z0 = make_double2(0, 0), O1 = make_double2(1, 0), I1 = make_double2(0, 1);
+  const double r2 = 0.70710678118654752440;
+  if (dm)
+    for (int k = 0; k < 3 * kMatStride; ++k) dm[k] = 0.0;
+  switch (g.kind) {
+    case QSV_G_X: case QSV_G_CX: set2(m, Z0, O1, O1, Z0); break;
+    case QSV_G_Y: case QSV_G_CY: set2(m, Z0, make_double2(0, -1), I1, Z0); break;
+    case QSV_G_Z: case QSV_G_CZ: set2(m, O1, Z0, Z0, make_double2(-1, 0)); break;
+    case QSV_G_H: case QSV_G_CH:
+      set2(m, make_double2(r2, 0), make_double2(r2, 0), make_double2(r2, 0), make_double2(-r2, 0));
+      break;
+    case QSV_G_S: set2(m, O1, Z0, Z0, I1); break;
+    case QSV_G_SDG: set2(m, O1, Z0, Z0, make_double2(0, -1)); break;
+    case QSV_G_T: set2(m, O1, Z0, Z0, make_double2(r2, r2)); break;
+    case QSV_G_TDG: set2(m, O1, Z0, Z0, make_double2(r2, -r2)); break;
+    case QSV_G_SX:
+      set2(m, make_double2(0.5, 0.5), make_double2(0.5, -0.5), make_double2(0.5, -0.5), make_double2(0.5, 0.5));
+      break;
+    case QSV_G_SXDG:
+      set2(m, make_double2(0.5, -0.5), make_double2(0.5, 0.5), make_double2(0.5, 0.5), make_double2(0.5, -0.5));
+      break;
+    case QSV_G_RX: case QSV_G_CRX: {
+      double s, c;
+      sincos(0.5 * a[0], &s, &c);
+      set2(m, make_double2(c, 0), make_double2(0, -s), make_double2(0, -s), make_double2(c, 0));
+      if (dm) set2(dm, make_double2(-0.5 * s, 0), make_double2(0, -0.5 * c), make_double2(0, -0.5 * c),
+                   make_double2(-0.5 * s, 0));
+      break;
+    }
+    case QSV_G_RY: case QSV_G_CRY: {
+      double s, c;
+      sincos(0.5 * a[0], &s, &c);
+      set2(m, make_double2(c, 0), make_double2(-s, 0), make_double2(s, 0), make_double2(c, 0));
+      if (dm) set2(dm, make_double2(-0.5 * s, 0), make_double2(-0.5 * c, 0), make_double2(0.5 * c, 0),
+                   make_double2(-0.5 * s, 0));
+      break;
+    }
+    case QSV_G_RZ: case QSV_G_CRZ: {
+      double2 e0 = cexpi(-0.5 * a[0]), e1 = cexpi(0.5 * a[0]);
+      set2(m, e0, Z0, Z0, e1);
+      if (dm) set2(dm, make_double2(0.5 * e0.y, -0.5 * e0.x), Z0, Z0, make_double2(-0.5 * e1.y, 0.5 * e1.x));
+      break;
+    }
+    case QSV_G_P: case QSV_G_CP: {
+      double2 e = cexpi(a[0]);
+      set2(m, O1, Z0, Z0, e);
+      if (dm) set2(dm, Z0, Z0, Z0, make_double2(-e.y, e.x));
+      break;
+    }
+    case QSV_G_U: {
+      double s, c;
+      sincos(0.5 * a[0], &s, &c);
+      double2 ep = cexpi(a[1]), el = cexpi(a[2]), epl = cexpi(a[1] + a[2]);
+      set2(m, make_double2(c, 0), cscale(el, -s), cscale(ep, s), cscale(epl, c));
+      if (dm) {
+        // d/dtheta, d/dphi, d/dlambda of U(theta, phi, lambda)
+        set2(dm, make_double2(-0.5 * s, 0), cscale(el, -0.5 * c), cscale(ep, 0.5 * c), cscale(epl, -0.5 * s));
+        set2(dm + kMatStride, Z0, Z0, cmul(I1, cscale(ep, s)), cmul(I1, cscale(epl, c)));
+        set2(dm + 2 * kMatStride, Z0, cmul(I1, cscale(el, -s)), Z0, cmul(I1, cscale(epl, c)));
+      }
+      break;
+    }
+    default: set2(m, O1, Z0, Z0, O1); break;  // ID, SWAP (unused)
+  }
+}
+
+hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
+                                uint32_t n_params, uint32_t batch, double* mats, double* dmats,
+                                hipStream_t st) {
+  uint64_t total = (uint64_t)n_slots * batch;
+  if (total == 0) return hipSuccess;
+  uint32_t blocks = (uint32_t)((total + 255) / 256);
+  hipLaunchKernelGGL(k_bind_matrices, dim3(blocks), dim3(256), 0, st, src, n_slots, theta, n_params,
+                     batch, mats, dmats);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Control blocks and state initialisation
+// ---------------------------------------------------------------------------
+__global__ void k_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= shots) return;
+  ShotCtl c;
+  c.flags = 0;
+  c.pend_mask = 0;
+  c.pend_val = 0;
+  c.frame = 0;
+  c.pend_scale = 1.0;
+  c.record_prob = 1.0;
+  c.n_events = 0;
+  c.n_record = 0;
+  c.status = 0;
+  c.wg_done = 0;
+  ctl[s] = c;
+  for (uint32_t w = 0; w < cw; ++w) creg[(uint64_t)s * cw + w] = 0;
+}
+
+hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots, hipStream_t st) {
+  if (!shots) return hipSuccess;
+  hipLaunchKernelGGL(k_init_ctl, dim3((shots + 255) / 256), dim3(256), 0, st, ctl, creg, cw, shots);
+  return hipGetLastError();
+}
+
+__global__ void k_init_state(double2* __restrict__ state, uint64_t stride, uint64_t dim, uint32_t shots) {
+  uint64_t total = dim * shots;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t s = i / dim, j = i % dim;
+    state[s * stride + j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
+  }
+}
+
+hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st) {
+  uint64_t total = (1ull << n) * shots;
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_init_state, dim3((uint32_t)blocks), dim3(256), 0, st, state, stride, 1ull << n, shots);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tile pass
+// ---------------------------------------------------------------------------
+// 2x2 matrix of a slot, conjugated by X when the frame flips its qubit.
+struct M2 {
+  double2 a, b, c, d;
+};
+__device__ __forceinline__ M2 load_m2(const double* m, uint32_t flip) {
+  M2 r;
+  r.a = make_double2(m[0], m[1]);
+  r.b = make_double2(m[2], m[3]);
+  r.c = make_double2(m[4], m[5]);
+  r.d = make_double2(m[6], m[7]);
+  if (flip) {
+    double2 t = r.a;
+    r.a = r.d;
+    r.d = t;
+    t = r.b;
+    r.b = r.c;
+    r.c = t;
+  }
+  return r;
+}
+
+// Applies one gate to the LDS tile. f0/f1: frame flips of the gate's qubits.
+__device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t t, const DGate& g,
+                                           const double* __restrict__ m, uint32_t f0, uint32_t f1) {
+  const uint32_t tid = threadIdx.x;
+  switch (g.type) {
+    case GT_DENSE1: case GT_DIAG1: {
+      M2 u = load_m2(m, f0);
+      const uint32_t np = 1u << (t - 1), bit = 1u << g.b0;
+      if (g.type == GT_DIAG1) {
+        for (uint32_t p = tid; p < np; p += kTileThreads) {
+          uint32_t i0 = ins0(p, g.b0), i1 = i0 | bit;
+          tile[i0] = cmul(u.a, tile[i0]);
+          tile[i1] = cmul(u.d, tile[i1]);
+        }
+      } else {
+        for (uint32_t p = tid; p < np; p += kTileThreads) {
+          uint32_t i0 = ins0(p, g.b0), i1 = i0 | bit;
+          double2 x0 = tile[i0], x1 = tile[i1];
+          tile[i0] = cmac2(u.a, x0, u.b, x1);
+          tile[i1] = cmac2(u.c, x0, u.d, x1);
+        }
+      }
+      break;
+    }
+    case GT_X1: {
+      const uint32_t np = 1u << (t - 1), bit = 1u << g.b0;
+      for (uint32_t p = tid; p < np; p += kTileThreads) {
+        uint32_t i0 = ins0(p, g.b0), i1 = i0 | bit;
+        double2 x0 = tile[i0];
+        tile[i0] = tile[i1];
+        tile[i1] = x0;
+      }
+      break;
+    }
+    default: {  // two-qubit gates
+      const uint32_t lo = g.b0 < g.b1 ? g.b0 : g.b1, hi = g.b0 < g.b1 ? g.b1 : g.b0;
+      const uint32_t nq = 1u << (t - 2);
+      const uint32_t B0 = 1u << g.b0, B1 = 1u << g.b1;
+      const uint32_t cset = f0 ? 0u : B0;  // memory value of the control bit that means |1>
+      if (g.type == GT_CX) {
+        for (uint32_t p = tid; p < nq; p += kTileThreads) {
+          uint32_t i = ins0(ins0(p, lo), hi) | cset;
+          double2 x = tile[i];
+          tile[i] = tile[i | B1];
+          tile[i | B1] = x;
+        }
+      } else if (g.type == GT_CTRL1) {
+        M2 u = load_m2(m, f1);
+        for (uint32_t p = tid; p < nq; p += kTileThreads) {
+          uint32_t i = ins0(ins0(p, lo), hi) | cset;
+          double2 x0 = tile[i], x1 = tile[i | B1];
+          tile[i] = cmac2(u.a, x0, u.b, x1);
+          tile[i | B1] = cmac2(u.c, x0, u.d, x1);
+        }
+      } else if (g.type == GT_CPHASE) {
+        double2 ph = make_double2(m[6], m[7]);
+        uint32_t sel = cset | (f1 ? 0u : B1);
+        for (uint32_t p = tid; p < nq; p += kTileThreads) {
+          uint32_t i = ins0(ins0(p, lo), hi) | sel;
+          tile[i] = cmul(ph, tile[i]);
+        }
+      } else {  // GT_SWAP: exchange 01<->10, or 00<->11 when exactly one operand is flipped
+        uint32_t ea = (f0 == f1) ? B0 : 0u, eb = (f0 == f1) ? B1 : (B0 | B1);
+        for (uint32_t p = tid; p < nq; p += kTileThreads) {
+          uint32_t i = ins0(ins0(p, lo), hi);
+          double2 x = tile[i | ea];
+          tile[i | ea] = tile[i | eb];
+          tile[i | eb] = x;
+        }
+      }
+      break;
+    }
+  }
+}
+
+__device__ __forceinline__ bool guard_ok(uint64_t flags, uint64_t guard) { return (flags & guard) == guard; }
+
+// Global index of tile-local element l.
+__device__ __forceinline__ uint64_t local_to_global(uint32_t l, const PassArgs& a) {
+  uint64_t g = 0;
+  for (uint32_t k = 0; k < a.t; ++k) g |= (uint64_t)((l >> k) & 1u) << a.tq[k];
+  return g;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass(
+    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
+    const DGate* __restrict__ gates, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a) {
+  extern __shared__ double2 tile[];
+  const uint32_t shot = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+  ShotCtl* c = ctl + shot;
+  if (c->status != 0) return;
+  const uint64_t flags = c->flags, M = c->pend_mask, F = c->frame;
+  const double s = c->pend_scale;
+  const bool pending = M != 0 || s != 1.0;
+  bool any = false;
+  for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, gates[a.gate_begin + i].guard);
+  if (!a.init && !any) return;  // the pending collapse stays owed to a later pass
+  const uint64_t Vm = c->pend_val ^ (F & M);   // restriction in memory coordinates
+
+  // base index of this tile: w's bits scattered over the non-tile qubits
+  uint64_t base = 0;
+  {
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < a.n; ++q)
+      if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
+  }
+  double2* st = state + (uint64_t)shot * stride;
+  const uint32_t T = 1u << a.t;
+  for (uint32_t l = tid; l < T; l += kTileThreads) {
+    uint64_t gi = base | local_to_global(l, a);
+    double2 v;
+    if (a.init) {
+      v = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
+    } else if ((gi & M) != Vm) {
+      v = make_double2(0.0, 0.0);
+    } else {
+      v = st[gi];
+      if (pending) v = cscale(v, s);
+    }
+    tile[l] = v;
+  }
+  __syncthreads();
+  const double* mb = mats + (uint64_t)shot * mat_stride;
+  for (uint32_t i = 0; i < a.gate_count; ++i) {
+    DGate g = gates[a.gate_begin + i];
+    if (!guard_ok(flags, g.guard)) continue;
+    uint32_t f0 = (uint32_t)((F >> a.tq[g.b0]) & 1ull), f1 = (uint32_t)((F >> a.tq[g.b1]) & 1ull);
+    tile_apply(tile, a.t, g, mb + (uint64_t)g.mat * kMatStride, f0, f1);
+    __syncthreads();
+  }
+  for (uint32_t l = tid; l < T; l += kTileThreads) st[base | local_to_global(l, a)] = tile[l];
+  if (pending) {
+    // the last workgroup of this shot to finish clears the pending collapse
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      uint32_t done = atomicAdd(&c->wg_done, 1u);
+      if (done == a.tiles - 1) {
+        c->pend_mask = 0;
+        c->pend_val = 0;
+        c->pend_scale = 1.0;
+        c->wg_done = 0;
+      }
+    }
+  }
+}
+
+hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const double* mats,
+                            uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
+  dim3 grid(a.tiles, rb.shots);
+  size_t lds = (size_t)sizeof(double2) << a.t;
+  hipLaunchKernelGGL(k_tile_pass, grid, dim3(kTileThreads), lds, st, rb.state, rb.stride, rb.ctl, gates,
+                     mats, mat_stride, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Measurement sites
+// ---------------------------------------------------------------------------
+// Histogram of |psi|^2 over the site's qubits (logical values), restricted to
+// the pending collapse. Each workgroup covers a contiguous slice of the free
+// (unrestricted) index space; every thread keeps its own 16 bins in LDS and
+// the bins are summed in a fixed order, so the result does not depend on how
+// many shots share the launch.
+__global__ __launch_bounds__(kRedThreads) void k_site_reduce(
+    const double2* __restrict__ state, uint64_t stride, const ShotCtl* __restrict__ ctl, SiteArgs a,
+    double* __restrict__ partials, uint32_t pblocks) {
+  __shared__ double bins[kSiteBins][kRedThreads];
+  __shared__ double red[kRedThreads / kSiteBins][kSiteBins];
+  const uint32_t shot = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  const ShotCtl* c = ctl + shot;
+  double* out = partials + ((uint64_t)shot * pblocks + blk) * kSiteBins;
+  for (int b = 0; b < kSiteBins; ++b) bins[b][tid] = 0.0;
+  if (c->status == 0) {
+    const uint64_t M = c->pend_mask, F = c->frame, Vm = c->pend_val ^ (F & M);
+    const double s2 = c->pend_scale * c->pend_scale;
+    const uint32_t r = (uint32_t)__popcll(M);
+    const uint64_t nfree = 1ull << (a.n - r);
+    const uint64_t per = (nfree + a.blocks - 1) / a.blocks;
+    const uint64_t j0 = per * blk, j1 = (j0 + per < nfree) ? j0 + per : nfree;
+    const double2* st = state + (uint64_t)shot * stride;
+    uint32_t qbit[kSiteQubits];
+    uint32_t fq = 0;
+    for (uint32_t k = 0; k < a.nq; ++k) {
+      qbit[k] = a.q[k];
+      fq |= (uint32_t)((F >> a.q[k]) & 1ull) << k;
+    }
+    for (uint64_t j = j0 + tid; j < j1; j += kRedThreads) {
+      uint64_t gi = j;
+      if (M) {
+        uint64_t mm = M;
+        while (mm) {
+          uint32_t b = __ffsll((long long)mm) - 1;
+          mm &= mm - 1;
+          gi = ins0_64(gi, b);
+        }
+        gi |= Vm;
+      }
+      double2 v = st[gi];
+      double p = (v.x * v.x + v.y * v.y) * s2;
+      uint32_t bin = 0;
+      for (uint32_t k = 0; k < a.nq; ++k) bin |= (uint32_t)((gi >> qbit[k]) & 1ull) << k;
+      bin ^= fq;
+      bins[bin][tid] += p;
+    }
+  }
+  __syncthreads();
+  {
+    const uint32_t b = tid & (kSiteBins - 1), part = tid / kSiteBins;
+    double acc = 0.0;
+    for (uint32_t k = 0; k < kSiteBins; ++k) acc += bins[b][part * kSiteBins + k];
+    red[part][b] = acc;
+  }
+  __syncthreads();
+  if (tid < kSiteBins) {
+    double acc = 0.0;
+    for (uint32_t part = 0; part < kRedThreads / kSiteBins; ++part) acc += red[part][tid];
+    out[tid] = acc;
+  }
+}
+
+__device__ bool eval_pred(const DPred& p, const uint64_t* creg) {
+  if (p.cmp == QSV_CMP_TRUE) return true;
+  uint64_t v = 0;
+  for (uint32_t i = 0; i < p.width; ++i) {
+    uint32_t bit = p.lo + i;
+    v |= ((creg[bit >> 6] >> (bit & 63)) & 1ull) << i;
+  }
+  switch (p.cmp) {
+    case QSV_CMP_EQ: return v == p.value;
+    case QSV_CMP_NE: return v != p.value;
+    case QSV_CMP_LT: return v < p.value;
+    case QSV_CMP_GT: return v > p.value;
+    case QSV_CMP_LE: return v <= p.value;
+    default: return v >= p.value;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_site_finalize(
+    ShotCtl* __restrict__ ctl, SiteArgs a, const SiteEvent* __restrict__ ev,
+    const DPred* __restrict__ preds, const double* __restrict__ partials, uint32_t pblocks,
+    uint64_t* __restrict__ creg,
+    uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record, const uint8_t* __restrict__ forced,
+    uint32_t forced_len, uint64_t seed, uint64_t shot_base) {
+  __shared__ double part[4][kSiteBins];
+  const uint32_t shot = blockIdx.x, tid = threadIdx.x;
+  ShotCtl* c = ctl + shot;
+  if (a.nq) {
+    const double* pp = partials + (uint64_t)shot * pblocks * kSiteBins;
+    const uint32_t b = tid & (kSiteBins - 1), q = tid / kSiteBins;
+    double acc = 0.0;
+    for (uint32_t k = q; k < a.blocks; k += 4) acc += pp[(uint64_t)k * kSiteBins + b];
+    part[q][b] = acc;
+  }
+  __syncthreads();
+  if (tid != 0 || c->status != 0) return;
+  double bins[kSiteBins];
+  for (int b = 0; b < kSiteBins; ++b) bins[b] = a.nq ? ((part[0][b] + part[1][b]) + part[2][b]) + part[3][b] : 0.0;
+
+  ShotCtl cc = *c;
+  uint64_t* cr = creg + (uint64_t)shot * cw;
+  uint32_t rm = 0, rv = 0;  // restriction on the bins (pre-site logical values)
+  uint64_t xf = 0;          // flips applied during this site
+  const double kZero = 0x1p-60;
+  for (uint32_t e = 0; e < a.ev_count; ++e) {
+    const SiteEvent E = ev[a.ev_begin + e];
+    const bool active = guard_ok(cc.flags, E.guard);
+    if (E.op == SE_SETF) {
+      bool v = active && eval_pred(preds[E.pred], cr);
+      cc.flags = (cc.flags & ~(1ull << E.flag)) | ((uint64_t)v << E.flag);
+      continue;
+    }
+    if (!active) continue;
+    if (E.op == SE_CLRF) {
+      cc.flags &= ~(1ull << E.flag);
+    } else if (E.op == SE_X) {
+      xf ^= 1ull << E.q;
+    } else {  // measure or reset
+      const uint32_t k = E.k, fq = (uint32_t)((xf >> E.q) & 1ull);
+      double p[2] = {0.0, 0.0};
+      for (uint32_t b = 0; b < (uint32_t)kSiteBins; ++b)
+        if ((b & rm) == rv) p[((b >> k) & 1u) ^ fq] += bins[b];
+      const double norm = p[0] + p[1];
+      const uint64_t word = philox_word(seed, shot_base + shot, cc.n_events);
+      const double u = (double)(word >> 11) * 0x1p-53;
+      cc.n_events++;
+      uint32_t o;
+      if (E.op == SE_MEASURE && forced && cc.n_record < forced_len) {
+        o = forced[(uint64_t)shot * forced_len + cc.n_record] ? 1u : 0u;
+        if (p[o] / norm < kZero) {
+          cc.status = QSV_ERR_FORCED_ZERO_PROB;
+          break;
+        }
+      } else {
+        o = (u < p[0] / norm) ? 0u : 1u;
+      }
+      cc.record_prob *= p[o] / norm;
+      rm |= 1u << k;
+      rv |= (o ^ fq) << k;
+      if (E.op == SE_MEASURE) {
+        if (cc.n_record < max_record) record[(uint64_t)shot * max_record + cc.n_record] = (uint8_t)o;
+        cc.n_record++;
+        if (E.cbit != 0xFFFFFFFFu) {
+          uint64_t bitm = 1ull << (E.cbit & 63);
+          cr[E.cbit >> 6] = o ? (cr[E.cbit >> 6] | bitm) : (cr[E.cbit >> 6] & ~bitm);
+        }
+      } else if (o) {
+        xf ^= 1ull << E.q;  // reset: flip the qubit back to |0>
+      }
+    }
+  }
+  if (cc.status == 0) {
+    // compose the site's collapse with the incoming one (all in logical frames)
+    uint64_t R = 0, RV = 0;
+    double mass = 0.0;
+    for (uint32_t k = 0; k < a.nq; ++k)
+      if (rm >> k & 1u) {
+        R |= 1ull << a.q[k];
+        RV |= (uint64_t)((rv >> k) & 1u) << a.q[k];
+      }
+    if (rm) {
+      for (uint32_t b = 0; b < (uint32_t)kSiteBins; ++b)
+        if ((b & rm) == rv) mass += bins[b];
+      cc.pend_scale = cc.pend_scale / sqrt(mass);
+    }
+    const uint64_t M = cc.pend_mask;
+    cc.pend_val = ((cc.pend_val ^ (xf & M)) & M) | ((RV ^ (xf & R)) & R);
+    cc.pend_mask = M | R;
+    cc.frame ^= xf;
+  }
+  *c = cc;
+}
+
+hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev, const DPred* preds,
+                       hipStream_t st) {
+  if (a.nq) {
+    hipLaunchKernelGGL(k_site_reduce, dim3(a.blocks, rb.shots), dim3(kRedThreads), 0, st, rb.state,
+                       rb.stride, rb.ctl, a, rb.partials, rb.pblocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_site_finalize, dim3(rb.shots), dim3(64), 0, st, rb.ctl, a, ev, preds, rb.partials,
+                     rb.pblocks, rb.creg, rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len, rb.seed,
+                     rb.shot_base);
+  return hipGetLastError();
+}
+
+// The logical state of one shot: psi[i] = cond(i) ? mem[i ^ frame] * scale : 0.
+__global__ void k_materialize(const double2* __restrict__ state, uint64_t stride, const ShotCtl* ctl,
+                              uint32_t shot, uint64_t dim, double2* __restrict__ out) {
+  const ShotCtl c = ctl[shot];
+  const double2* st = state + (uint64_t)shot * stride;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    if ((i & c.pend_mask) == c.pend_val) v = cscale(st[i ^ c.frame], c.pend_scale);
+    out[i] = v;
+  }
+}
+
+hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out, hipStream_t st) {
+  uint64_t dim = 1ull << n;
+  uint64_t blocks = (dim + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_materialize, dim3((uint32_t)blocks), dim3(256), 0, st, rb.state, rb.stride, rb.ctl,
+                     shot, dim, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Expectation values: <psi|P|psi> for P = i^ny X^x Z^z (Y = i X Z)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 ipow(uint32_t k) {
+  switch (k & 3u) {
+    case 0: return make_double2(1, 0);
+    case 1: return make_double2(0, 1);
+    case 2: return make_double2(-1, 0);
+    default: return make_double2(0, -1);
+  }
+}
+
+// Block partials of Re sum_i conj(psi[i ^ x]) * phase(i) * psi[i] per term.
+__global__ __launch_bounds__(256) void k_pauli_terms(const double2* __restrict__ psi, uint64_t stride, uint32_t n,
+                                                    const uint64_t* __restrict__ xmask,
+                                                    const uint64_t* __restrict__ zmask,
+                                                    const uint32_t* __restrict__ ny, uint32_t n_terms,
+                                                    double* __restrict__ out, uint32_t blocks) {
+  __shared__ double red[256];
+  const uint32_t blk = blockIdx.x % blocks, tb = blockIdx.x / blocks, tid = threadIdx.x;
+  const uint32_t term = tb % n_terms, b = tb / n_terms;
+  const double2* st = psi + (uint64_t)b * stride;
+  const uint64_t dim = 1ull << n, per = (dim + blocks - 1) / blocks;
+  const uint64_t j0 = per * blk, j1 = (j0 + per < dim) ? j0 + per : dim;
+  const uint64_t x = xmask[term], z = zmask[term];
+  const double2 ph = ipow(ny[term]);
+  double acc = 0.0;
+  for (uint64_t i = j0 + tid; i < j1; i += 256) {
+    double2 a = st[i], bb = st[i ^ x];
+    double sgn = (__popcll(i & z) & 1) ? -1.0 : 1.0;
+    double2 pa = cmul(ph, cscale(a, sgn));
+    acc += bb.x * pa.x + bb.y * pa.y;  // Re(conj(bb) * pa)
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (uint32_t s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) out[((uint64_t)b * n_terms + term) * blocks + blk] = red[0];
+}
+
+hipError_t launch_pauli_terms(const double2* psi, uint64_t stride, uint32_t n, uint32_t batch,
+                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny,
+                              const double* coeff, uint32_t n_terms, double* term_partials, uint32_t blocks,
+                              hipStream_t st) {
+  (void)coeff;
+  hipLaunchKernelGGL(k_pauli_terms, dim3(blocks * batch * n_terms), dim3(256), 0, st, psi, stride, n, xmask,
+                     zmask, ny, n_terms, term_partials, blocks);
+  return hipGetLastError();
+}
+
+__global__ void k_energy_reduce(const double* __restrict__ tp, uint32_t n_terms, uint32_t blocks,
+                                const double* __restrict__ coeff, uint32_t batch, double* __restrict__ energy) {
+  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double e = 0.0;
+  for (uint32_t t = 0; t < n_terms; ++t) {
+    double v = 0.0;
+    for (uint32_t k = 0; k < blocks; ++k) v += tp[((uint64_t)b * n_terms + t) * blocks + k];
+    e += coeff[t] * v;
+  }
+  energy[b] = e;
+}
+
+hipError_t launch_energy_reduce(const double* term_partials, uint32_t n_terms, uint32_t blocks,
+                                const double* coeff, uint32_t batch, double* energy, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3((batch + 63) / 64), dim3(64), 0, st, term_partials, n_terms, blocks,
+                     coeff, batch, energy);
+  return hipGetLastError();
+}
+
+// lam = sum_j c_j P_j psi, terms accumulated in a fixed order per element:
+// (P psi)[i] = phase(i ^ x) * psi[i ^ x].
+__global__ void k_apply_hamiltonian(const double2* __restrict__ psi, double2* __restrict__ lam, uint64_t stride,
+                                    uint32_t n, const uint64_t* __restrict__ xmask,
+                                    const uint64_t* __restrict__ zmask, const uint32_t* __restrict__ ny,
+                                    const double* __restrict__ coeff, uint32_t n_terms, uint32_t batch) {
+  const uint64_t dim = 1ull << n, total = dim * batch;
+  for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = idx / dim, i = idx % dim;
+    const double2* st = psi + b * stride;
+    double2 acc = make_double2(0.0, 0.0);
+    for (uint32_t t = 0; t < n_terms; ++t) {
+      uint64_t src = i ^ xmask[t];
+      double2 v = st[src];
+      double sgn = (__popcll(src & zmask[t]) & 1) ? -1.0 : 1.0;
+      acc = cadd(acc, cscale(cmul(ipow(ny[t]), v), coeff[t] * sgn));
+    }
+    lam[b * stride + i] = acc;
+  }
+}
+
+hipError_t launch_apply_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
+                                    const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny,
+                                    const double* coeff, uint32_t n_terms, hipStream_t st) {
+  uint64_t total = (1ull << n) * batch;
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_apply_hamiltonian, dim3((uint32_t)blocks), dim3(256), 0, st, psi, lam, stride, n, xmask,
+                     zmask, ny, coeff, n_terms, batch);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep of one pass: for the pass's gates in reverse order,
+//   psi <- U^dag psi ; g_j = 2 Re <lam| dU/da_j |psi> ; lam <- U^dag lam
+// Partial gradient sums per workgroup: gpart[b][tile][gate][angle].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cdot_conj(double2 l, double2 v) {  // conj(l) * v
+  return make_double2(l.x * v.x + l.y * v.y, l.x * v.y - l.y * v.x);
+}
+
+__device__ double block_sum(double v, double* red) {
+  const uint32_t tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (uint32_t s = kTileThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_backward_pass(
+    double2* __restrict__ psi, double2* __restrict__ lam, uint64_t stride, const DGate* __restrict__ gates,
+    const double* __restrict__ mats, const double* __restrict__ dmats, uint64_t mat_stride, PassArgs a,
+    double* __restrict__ gpart) {
+  extern __shared__ double2 sm[];
+  __shared__ double red[kTileThreads];
+  const uint32_t T = 1u << a.t;
+  double2* tp = sm;
+  double2* tl = sm + T;
+  const uint32_t b = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+  uint64_t base = 0;
+  {
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < a.n; ++q)
+      if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
+  }
+  double2* sp = psi + (uint64_t)b * stride;
+  double2* sl = lam + (uint64_t)b * stride;
+  for (uint32_t l = tid; l < T; l += kTileThreads) {
+    uint64_t gi = base | local_to_global(l, a);
+    tp[l] = sp[gi];
+    tl[l] = sl[gi];
+  }
+  __syncthreads();
+  const double* mb = mats + (uint64_t)b * mat_stride;
+  const double* db = dmats + (uint64_t)b * mat_stride * 3;
+  for (int32_t gi = (int32_t)a.gate_count - 1; gi >= 0; --gi) {
+    const DGate g = gates[a.gate_begin + gi];
+    const double* m = mb + (uint64_t)g.mat * kMatStride;
+    const double* dm = db + (uint64_t)g.mat * 3 * kMatStride;
+    // U^dag on psi
+    M2 u = load_m2(m, 0);
+    M2 ud;
+    ud.a = cconj(u.a);
+    ud.b = cconj(u.c);
+    ud.c = cconj(u.b);
+    ud.d = cconj(u.d);
+    const bool one = (g.type == GT_DENSE1 || g.type == GT_DIAG1 || g.type == GT_X1);
+    const uint32_t B0 = 1u << g.b0, B1 = 1u << g.b1;
+    const uint32_t lo = g.b0 < g.b1 ? g.b0 : g.b1, hi = g.b0 < g.b1 ? g.b1 : g.b0;
+    const uint32_t cnt = one ? (T >> 1) : (T >> 2);
+    // indices of the 2-vector the gate acts on
+    auto pair = [&](uint32_t p, uint32_t* i0, uint32_t* i1) {
+      if (one) {
+        *i0 = ins0(p, g.b0);
+        *i1 = *i0 | B0;
+      } else {
+        uint32_t i = ins0(ins0(p, lo), hi) | B0;
+        *i0 = i;
+        *i1 = i | B1;
+      }
+    };
+    if (g.type == GT_SWAP) {
+      for (uint32_t p = tid; p < cnt; p += kTileThreads) {
+        uint32_t i = ins0(ins0(p, lo), hi);
+        double2 x = tp[i | B0];
+        tp[i | B0] = tp[i | B1];
+        tp[i | B1] = x;
+        x = tl[i | B0];
+        tl[i | B0] = tl[i | B1];
+        tl[i | B1] = x;
+      }
+      __syncthreads();
+      continue;
+    }
+    // psi <- U^dag psi
+    for (uint32_t p = tid; p < cnt; p += kTileThreads) {
+      uint32_t i0, i1;
+      pair(p, &i0, &i1);
+      double2 x0 = tp[i0], x1 = tp[i1];
+      tp[i0] = cmac2(ud.a, x0, ud.b, x1);
+      tp[i1] = cmac2(ud.c, x0, ud.d, x1);
+    }
+    __syncthreads();
+    // gradient partials for each angle the gate depends on (at most 3)
+    const uint32_t nang = (g.pad & 3u);
+    for (uint32_t j = 0; j < nang; ++j) {
+      M2 d = load_m2(dm + j * kMatStride, 0);
+      double acc = 0.0;
+      for (uint32_t p = tid; p < cnt; p += kTileThreads) {
+        uint32_t i0, i1;
+        pair(p, &i0, &i1);
+        double2 x0 = tp[i0], x1 = tp[i1];
+        double2 y0 = cmac2(d.a, x0, d.b, x1), y1 = cmac2(d.c, x0, d.d, x1);
+        acc += cdot_conj(tl[i0], y0).x + cdot_conj(tl[i1], y1).x;
+      }
+      double tot = block_sum(acc, red);
+      if (tid == 0)
+        gpart[(((uint64_t)b * a.tiles + w) * a.gate_count + gi) * 3 + j] = 2.0 * tot;
+    }
+    // lam <- U^dag lam
+    for (uint32_t p = tid; p < cnt; p += kTileThreads) {
+      uint32_t i0, i1;
+      pair(p, &i0, &i1);
+      double2 x0 = tl[i0], x1 = tl[i1];
+      tl[i0] = cmac2(ud.a, x0, ud.b, x1);
+      tl[i1] = cmac2(ud.c, x0, ud.d, x1);
+    }
+    __syncthreads();
+  }
+  for (uint32_t l = tid; l < T; l += kTileThreads) {
+    uint64_t gi = base | local_to_global(l, a);
+    sp[gi] = tp[l];
+    sl[gi] = tl[l];
+  }
+}
+
+hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uint32_t batch, const DGate* gates,
+                                const double* mats, const double* dmats, uint64_t mat_stride, const PassArgs& a,
+                                double* gpart, hipStream_t st) {
+  dim3 grid(a.tiles, batch);
+  size_t lds = (size_t)2 * sizeof(double2) << a.t;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_backward_pass),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_backward_pass, grid, dim3(kTileThreads), lds, st, psi, lam, stride, gates, mats, dmats,
+                     mat_stride, a, gpart);
+  return hipGetLastError();
+}
+
+// dEda[b][slot][j] = sum over tiles (fixed order) of the pass's partials.
+__global__ void k_grad_reduce(const double* __restrict__ gpart, uint32_t tiles, uint32_t gate_count,
+                              const DGate* __restrict__ gates, uint32_t batch, uint32_t n_slots,
+                              double* __restrict__ dEda) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)batch * gate_count * 3) return;
+  uint32_t j = idx % 3, gi = (idx / 3) % gate_count, b = (uint32_t)(idx / 3 / gate_count);
+  if (j >= (gates[gi].pad & 3u)) return;
+  double acc = 0.0;
+  for (uint32_t w = 0; w < tiles; ++w) acc += gpart[(((uint64_t)b * tiles + w) * gate_count + gi) * 3 + j];
+  dEda[((uint64_t)b * n_slots + gates[gi].mat) * 3 + j] = acc;
+}
+
+hipError_t launch_grad_reduce(const double* gpart, uint32_t tiles, uint32_t gate_count, uint32_t slot_begin_of_pass,
+                              const DGate* gates, uint32_t batch, uint32_t n_slots, double* dEda, hipStream_t st) {
+  (void)slot_begin_of_pass;
+  uint64_t total = (uint64_t)batch * gate_count * 3;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, gpart, tiles,
+                     gate_count, gates, batch, n_slots, dEda);
+  return hipGetLastError();
+}
+
+// grad[b][p] = sum over (slot, j) feeding parameter p of scale * dEda[b][slot][j], in CSR order.
+__global__ void k_grad_chain(const double* __restrict__ dEda, uint32_t n_slots, const uint32_t* __restrict__ off,
+                             const uint32_t* __restrict__ sj, const double* __restrict__ scale, uint32_t n_params,
+                             uint32_t batch, double* __restrict__ grad) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)batch * n_params) return;
+  uint32_t p = idx % n_params, b = (uint32_t)(idx / n_params);
+  double acc = 0.0;
+  for (uint32_t k = off[p]; k < off[p + 1]; ++k)
+    acc += scale[k] * dEda[(uint64_t)b * n_slots * 3 + sj[k]];
+  grad[idx] = acc;
+}
+
+hipError_t launch_grad_chain(const double* dEda, uint32_t n_slots, const uint32_t* csr_off, const uint32_t* csr_slot,
+                             const double* csr_scale, uint32_t n_params, uint32_t batch, double* grad, hipStream_t st) {
+  uint64_t total = (uint64_t)batch * n_params;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_chain, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, dEda, n_slots, csr_off,
+                     csr_slot, csr_scale, n_params, batch, grad);
+  return hipGetLastError();
+}
+
+}  // namespace qsv

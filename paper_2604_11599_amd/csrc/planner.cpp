@@ -1,0 +1,352 @@
+// Planner: validated instruction stream -> GPU steps.
+//
+// The stream is cut into maximal runs of gates and runs of non-unitary events
+// (measure, reset, flag updates; X gates adjacent to them are folded in as
+// relabelings of the index space). Gate runs become tile passes, each covering
+// at most 2^t amplitudes per workgroup: the tile's qubit set T always holds
+// the lowest qubits (contiguous 256-byte runs in HBM) and is grown greedily
+// along the gate list, taking every gate whose qubits fit in T and whose
+// earlier dependencies were taken too. Event runs become measurement
+// sub-sites of at most kSiteQubits histogrammed qubits each.
+#include "planner.h"
+
+#include <algorithm>
+#include <cstring>
+#include <set>
+
+namespace qsv {
+
+namespace {
+
+int angle_count(uint32_t kind) {
+  switch (kind) {
+    case QSV_G_RX: case QSV_G_RY: case QSV_G_RZ: case QSV_G_P:
+    case QSV_G_CP: case QSV_G_CRX: case QSV_G_CRY: case QSV_G_CRZ:
+      return 1;
+    case QSV_G_U:
+      return 3;
+    default:
+      return 0;
+  }
+}
+
+bool two_qubit(uint32_t kind) { return kind >= QSV_G_CX && kind < QSV_G_COUNT; }
+
+// Algorithmic flops per amplitude of a gate as applied in a tile: a dense 2x2
+// complex matrix-vector product costs 2 complex multiplies (6 flops each) and
+// one complex add (2) per output amplitude.
+double gate_flops_per_amp(GateType t) {
+  switch (t) {
+    case GT_DENSE1: return 14.0;
+    case GT_DIAG1: return 6.0;
+    case GT_CTRL1: return 7.0;
+    case GT_CPHASE: return 1.5;
+    default: return 0.0;
+  }
+}
+
+GateType gate_type(uint32_t kind) {
+  switch (kind) {
+    case QSV_G_X: return GT_X1;
+    case QSV_G_Z: case QSV_G_S: case QSV_G_SDG: case QSV_G_T: case QSV_G_TDG:
+    case QSV_G_RZ: case QSV_G_P:
+      return GT_DIAG1;
+    case QSV_G_CX: return GT_CX;
+    case QSV_G_CY: case QSV_G_CH: case QSV_G_CRX: case QSV_G_CRY: case QSV_G_CRZ:
+      return GT_CTRL1;
+    case QSV_G_CZ: case QSV_G_CP: return GT_CPHASE;
+    case QSV_G_SWAP: return GT_SWAP;
+    default: return GT_DENSE1;
+  }
+}
+
+struct GateRef {
+  uint32_t instr;
+  uint64_t qmask;
+};
+
+// Greedy growth of a tile qubit set from `start` along the gate list.
+uint64_t grow(const std::vector<GateRef>& rem, uint64_t start, uint32_t tmax,
+              std::vector<uint8_t>* taken, uint32_t* count) {
+  uint64_t T = start, blocked = 0;
+  uint32_t c = 0;
+  taken->assign(rem.size(), 0);
+  for (size_t i = 0; i < rem.size(); ++i) {
+    uint64_t m = rem[i].qmask;
+    if (m & blocked) {
+      blocked |= m;
+      continue;
+    }
+    uint64_t u = T | m;
+    if ((uint32_t)__builtin_popcountll(u) <= tmax) {
+      T = u;
+      (*taken)[i] = 1;
+      ++c;
+    } else {
+      blocked |= m;
+    }
+  }
+  *count = c;
+  return T;
+}
+
+}  // namespace
+
+bool validate_program(const qsv_program_desc& d, std::string* err) {
+  auto fail = [&](const std::string& m) {
+    *err = m;
+    return false;
+  };
+  if (d.n_qubits < 1) return fail("program has no qubits");
+  if (d.n_instr && !d.instr) return fail("instr is NULL");
+  if (d.n_pred && !d.pred) return fail("pred is NULL");
+  if (d.n_clbits > (1u << 20)) return fail("too many classical bits");
+  for (uint32_t i = 0; i < d.n_pred; ++i) {
+    const qsv_pred& p = d.pred[i];
+    if (p.cmp > QSV_CMP_TRUE) return fail("predicate " + std::to_string(i) + ": bad comparison");
+    if (p.cmp != QSV_CMP_TRUE) {
+      if (p.width < 1 || p.width > 64) return fail("predicate " + std::to_string(i) + ": width must be 1..64");
+      if ((uint64_t)p.lo + p.width > d.n_clbits)
+        return fail("predicate " + std::to_string(i) + ": bits out of range");
+    }
+  }
+  for (uint32_t i = 0; i < d.n_instr; ++i) {
+    const qsv_instr& in = d.instr[i];
+    std::string at = "instruction " + std::to_string(i) + ": ";
+    switch (in.op) {
+      case QSV_OP_GATE: {
+        if (in.kind >= QSV_G_COUNT) return fail(at + "unknown gate kind");
+        if (in.q0 >= d.n_qubits) return fail(at + "qubit out of range");
+        if (two_qubit(in.kind) && (in.q1 >= d.n_qubits || in.q1 == in.q0))
+          return fail(at + "second qubit out of range or repeated");
+        for (int k = 0; k < angle_count(in.kind); ++k)
+          if (in.param[k] != QSV_NONE && in.param[k] >= d.n_params)
+            return fail(at + "parameter index out of range");
+        break;
+      }
+      case QSV_OP_MEASURE:
+        if (in.q0 >= d.n_qubits) return fail(at + "qubit out of range");
+        if (in.cbit != QSV_NONE && in.cbit >= d.n_clbits) return fail(at + "classical bit out of range");
+        break;
+      case QSV_OP_RESET:
+        if (in.q0 >= d.n_qubits) return fail(at + "qubit out of range");
+        break;
+      case QSV_OP_SETF:
+        if (in.pred >= d.n_pred) return fail(at + "predicate out of range");
+        if (in.flag >= 64) return fail(at + "flag out of range");
+        break;
+      case QSV_OP_CLRF:
+        if (in.flag >= 64) return fail(at + "flag out of range");
+        break;
+      default:
+        return fail(at + "unknown op");
+    }
+  }
+  return true;
+}
+
+Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
+  Plan plan;
+  const uint32_t n = d.n_qubits;
+  plan.n = n;
+  const uint32_t tmax = std::min<uint32_t>(opt.tile_bits, n);
+  const uint32_t low = std::min<uint32_t>(opt.low_bits, tmax);
+  const uint64_t low_mask = (low >= 64) ? ~0ull : ((1ull << low) - 1);
+
+  for (uint32_t i = 0; i < d.n_instr; ++i) {
+    const qsv_instr& in = d.instr[i];
+    if (in.op == QSV_OP_MEASURE) ++plan.max_record, ++plan.max_events;
+    if (in.op == QSV_OP_RESET) ++plan.max_events;
+    if (in.op != QSV_OP_GATE) plan.unitary = false;
+  }
+
+  auto add_slot = [&](uint32_t i) {
+    const qsv_instr& in = d.instr[i];
+    GateSrc s;
+    std::memset(&s, 0, sizeof(s));
+    s.kind = in.kind;
+    for (int k = 0; k < 3; ++k) {
+      s.param[k] = in.param[k];
+      s.scale[k] = in.scale[k];
+      s.offset[k] = in.offset[k];
+    }
+    plan.gate_src.push_back(s);
+    plan.slot_instr.push_back(i);
+    return (uint32_t)(plan.gate_src.size() - 1);
+  };
+
+  auto emit_gate_run = [&](const std::vector<uint32_t>& run) {
+    std::vector<GateRef> rem;
+    for (uint32_t i : run) {
+      const qsv_instr& in = d.instr[i];
+      if (in.kind == QSV_G_ID) continue;
+      uint64_t m = 1ull << in.q0;
+      if (two_qubit(in.kind)) m |= 1ull << in.q1;
+      rem.push_back({i, m});
+    }
+    std::vector<uint8_t> taken, best_taken;
+    while (!rem.empty()) {
+      uint32_t best = 0;
+      uint64_t bestT = 0;
+      // candidate seeds: the low qubits alone, then low qubits + each early gate
+      std::vector<uint64_t> seeds{low_mask};
+      for (size_t i = 0; i < rem.size() && seeds.size() <= opt.candidates; ++i) {
+        uint64_t s = low_mask | rem[i].qmask;
+        if (std::find(seeds.begin(), seeds.end(), s) == seeds.end()) seeds.push_back(s);
+      }
+      for (uint64_t s : seeds) {
+        if ((uint32_t)__builtin_popcountll(s) > tmax) continue;
+        uint32_t c = 0;
+        uint64_t T = grow(rem, s, tmax, &taken, &c);
+        if (c > best) {
+          best = c;
+          bestT = T;
+          best_taken = taken;
+        }
+      }
+      if (best == 0) {  // cannot happen for validated streams: every gate fits a fresh tile
+        bestT = low_mask | rem[0].qmask;
+        best_taken.assign(rem.size(), 0);
+        best_taken[0] = 1;
+      }
+      // pad the tile with the lowest unused qubits up to tmax bits
+      for (uint32_t q = 0; q < n && (uint32_t)__builtin_popcountll(bestT) < tmax; ++q)
+        bestT |= 1ull << q;
+      PassArgs pa;
+      std::memset(&pa, 0, sizeof(pa));
+      pa.t = tmax;
+      pa.n = n;
+      pa.tile_mask = bestT;
+      pa.tiles = 1u << (n - tmax);
+      int pos[64];
+      uint32_t k = 0;
+      for (uint32_t q = 0; q < n; ++q)
+        if (bestT >> q & 1) {
+          pa.tq[k] = (uint8_t)q;
+          pos[q] = (int)k++;
+        }
+      pa.gate_begin = (uint32_t)plan.gates.size();
+      std::vector<GateRef> next;
+      for (size_t i = 0; i < rem.size(); ++i) {
+        if (!best_taken[i]) {
+          next.push_back(rem[i]);
+          continue;
+        }
+        const qsv_instr& in = d.instr[rem[i].instr];
+        DGate g;
+        std::memset(&g, 0, sizeof(g));
+        g.type = gate_type(in.kind);
+        g.b0 = (uint8_t)pos[in.q0];
+        g.b1 = two_qubit(in.kind) ? (uint8_t)pos[in.q1] : 0;
+        g.guard = in.guard;
+        g.mat = add_slot(rem[i].instr);
+        bool has_param = false;
+        for (int k = 0; k < angle_count(in.kind); ++k) has_param |= in.param[k] != QSV_NONE;
+        g.pad = has_param ? (uint8_t)angle_count(in.kind) : 0;  // angles the adjoint differentiates
+        plan.gates.push_back(g);
+      }
+      pa.gate_count = (uint32_t)plan.gates.size() - pa.gate_begin;
+      uint8_t uncond = 1;
+      double fl = 0.0;
+      for (uint32_t g = pa.gate_begin; g < pa.gate_begin + pa.gate_count; ++g) {
+        if (plan.gates[g].guard) uncond = 0;
+        fl += gate_flops_per_amp((GateType)plan.gates[g].type);
+      }
+      plan.steps.push_back({Step::PASS, (uint32_t)plan.passes.size()});
+      plan.passes.push_back(pa);
+      plan.pass_uncond.push_back(uncond);
+      plan.pass_flops_per_amp.push_back(fl);
+      rem.swap(next);
+    }
+  };
+
+  auto emit_site_run = [&](const std::vector<uint32_t>& run) {
+    SiteArgs cur;
+    std::memset(&cur, 0, sizeof(cur));
+    cur.n = n;
+    cur.ev_begin = (uint32_t)plan.events.size();
+    auto close = [&]() {
+      cur.ev_count = (uint32_t)plan.events.size() - cur.ev_begin;
+      if (cur.ev_count == 0) return;
+      uint64_t free_elems = 1ull << n;
+      uint64_t blocks = free_elems / (kRedThreads * 64ull);
+      cur.blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, kRedMaxBlocks));
+      if (cur.nq == 0) cur.blocks = 0;
+      plan.steps.push_back({Step::SITE, (uint32_t)plan.sites.size()});
+      plan.sites.push_back(cur);
+      std::memset(&cur, 0, sizeof(cur));
+      cur.n = n;
+      cur.ev_begin = (uint32_t)plan.events.size();
+    };
+    for (uint32_t i : run) {
+      const qsv_instr& in = d.instr[i];
+      SiteEvent e;
+      std::memset(&e, 0, sizeof(e));
+      e.guard = in.guard;
+      e.cbit = 0xFFFFFFFFu;
+      if (in.op == QSV_OP_MEASURE || in.op == QSV_OP_RESET) {
+        int k = -1;
+        for (uint32_t j = 0; j < cur.nq; ++j)
+          if (cur.q[j] == in.q0) k = (int)j;
+        if (k < 0) {
+          if (cur.nq == (uint32_t)kSiteQubits) close();
+          k = (int)cur.nq;
+          cur.q[cur.nq++] = (uint8_t)in.q0;
+        }
+        e.op = in.op == QSV_OP_MEASURE ? SE_MEASURE : SE_RESET;
+        e.k = (uint8_t)k;
+        e.q = in.q0;
+        if (in.op == QSV_OP_MEASURE) e.cbit = in.cbit;
+      } else if (in.op == QSV_OP_SETF) {
+        e.op = SE_SETF;
+        e.flag = (uint8_t)in.flag;
+        e.pred = in.pred;
+      } else if (in.op == QSV_OP_CLRF) {
+        e.op = SE_CLRF;
+        e.flag = (uint8_t)in.flag;
+      } else {  // an X gate folded into the site
+        e.op = SE_X;
+        e.q = in.q0;
+      }
+      plan.events.push_back(e);
+    }
+    close();
+  };
+
+  // Cut the stream into gate runs and event runs.
+  std::vector<uint32_t> run;
+  bool in_site = false;
+  for (uint32_t i = 0; i < d.n_instr; ++i) {
+    const qsv_instr& in = d.instr[i];
+    bool event = in.op != QSV_OP_GATE;
+    bool foldable_x = in.op == QSV_OP_GATE && in.kind == QSV_G_X && in_site;
+    if (event || foldable_x) {
+      if (!in_site && !run.empty()) {
+        emit_gate_run(run);
+        run.clear();
+      }
+      in_site = true;
+      run.push_back(i);
+    } else {
+      if (in_site && !run.empty()) {
+        emit_site_run(run);
+        run.clear();
+      }
+      in_site = false;
+      run.push_back(i);
+    }
+  }
+  if (!run.empty()) {
+    if (in_site) emit_site_run(run);
+    else emit_gate_run(run);
+  }
+  // State initialisation: folded into the first pass when the program starts with gates.
+  if (!plan.steps.empty() && plan.steps[0].kind == Step::PASS) {
+    plan.passes[plan.steps[0].index].init = 1;
+  } else {
+    plan.steps.insert(plan.steps.begin(), Step{Step::INIT, 0});
+  }
+  return plan;
+}
+
+}  // namespace qsv

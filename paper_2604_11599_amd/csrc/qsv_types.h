@@ -1,0 +1,102 @@
+// Internal plan and control-block types shared by the host planner and the
+// gfx950 kernels. Plain-old-data only: these structs are copied to the device
+// verbatim.
+#pragma once
+#include <stdint.h>
+
+namespace qsv {
+
+constexpr int kMaxQubits = 34;      // 2^34 complex128 = 256 GiB, the HBM ceiling of one MI355X
+constexpr int kTileMaxBits = 12;    // tile = 2^12 complex128 = 64 KiB of LDS per workgroup
+constexpr int kTileThreads = 256;   // workgroup size of the tile pass
+constexpr int kSiteQubits = 4;      // qubits histogrammed per measurement sub-site (16 bins)
+constexpr int kSiteBins = 1 << kSiteQubits;
+constexpr int kMatStride = 8;       // doubles per gate matrix slot (2x2 complex)
+constexpr int kRedThreads = 256;    // workgroup size of the probability reduction
+constexpr int kRedMaxBlocks = 1024; // reduction workgroups per shot (upper bound)
+
+// How a gate is applied inside a tile. Local bit positions refer to the tile's
+// qubit list (bit k of the tile-local index <-> tile qubit k).
+enum GateType : uint8_t {
+  GT_DENSE1 = 0,  // 2x2 matrix on b0
+  GT_DIAG1 = 1,   // diag(d0, d1) on b0 (matrix slot holds d0, d1)
+  GT_X1 = 2,      // swap the b0 halves
+  GT_CX = 3,      // swap the b1 halves where b0 is set
+  GT_CTRL1 = 4,   // 2x2 matrix on b1 where b0 is set
+  GT_CPHASE = 5,  // multiply by phase where b0 and b1 are both set (slot holds the phase)
+  GT_SWAP = 6,    // exchange bits b0 and b1
+};
+
+struct DGate {      // 16 bytes
+  uint8_t type, b0, b1, pad;
+  uint32_t mat;     // matrix slot = index of the gate in the program's gate table
+  uint64_t guard;   // active iff (flags & guard) == guard
+};
+
+// Source of a gate matrix: rebuilt on the device from theta at every call.
+struct GateSrc {    // 64 bytes
+  uint32_t kind;    // QSV_G_*
+  uint32_t param[3];
+  double scale[3];
+  double offset[3];
+};
+
+// A tile pass: every workgroup loads the 2^t amplitudes that share the values
+// of the non-tile qubits, applies the pass's gates and stores them back.
+struct PassArgs {
+  uint32_t t;                    // tile bits (tile = 2^t amplitudes)
+  uint32_t n;                    // qubits of the state
+  uint32_t gate_begin, gate_count;
+  uint32_t init;                 // 1: the state is |0...0>; generate instead of loading
+  uint32_t tiles;                // workgroups per shot = 2^(n - t)
+  uint64_t tile_mask;            // global bits covered by the tile
+  uint8_t tq[kTileMaxBits];      // global qubit of local bit k (ascending)
+};
+
+// Sequential events of a measurement site, replayed per shot by one thread.
+enum SiteOp : uint8_t { SE_MEASURE = 1, SE_RESET = 2, SE_SETF = 3, SE_CLRF = 4, SE_X = 5 };
+
+struct SiteEvent {  // 24 bytes
+  uint8_t op;       // SE_*
+  uint8_t k;        // index of the qubit in the site's qubit list (MEASURE/RESET)
+  uint8_t flag;     // SETF/CLRF flag bit
+  uint8_t pad;
+  uint32_t q;       // global qubit (MEASURE/RESET/X)
+  uint32_t cbit;    // MEASURE target bit or 0xFFFFFFFF
+  uint32_t pred;    // SETF predicate index
+  uint64_t guard;
+};
+
+struct SiteArgs {
+  uint32_t nq;                   // qubits histogrammed (0 = control-only site)
+  uint32_t n;
+  uint32_t ev_begin, ev_count;
+  uint32_t blocks;               // reduction workgroups per shot
+  uint32_t pad;
+  uint8_t q[kSiteQubits];        // global qubits of the histogram bins
+};
+
+struct DPred {      // device copy of qsv_pred
+  uint32_t lo, width;
+  uint64_t value;
+  uint32_t cmp, pad;
+};
+
+// Per-shot control block. The stored amplitudes `mem` relate to the logical
+// state by a qubit-flip frame and a pending collapse:
+//   psi[i] = ((i & pend_mask) == pend_val) ? mem[i ^ frame] * pend_scale : 0.
+// X gates next to measurements and the flip of a reset only update `frame`
+// (no data moves); the next tile pass that runs for the shot applies and
+// clears the pending collapse.
+struct ShotCtl {
+  uint64_t flags;
+  uint64_t pend_mask, pend_val, frame;
+  double pend_scale;
+  double record_prob;
+  uint32_t n_events;     // measure + reset events consumed (Philox word index)
+  uint32_t n_record;     // measure events recorded
+  int32_t status;
+  uint32_t wg_done;      // workgroups of the current pass finished for this shot
+};
+
+}  // namespace qsv

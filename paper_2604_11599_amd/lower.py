@@ -1,0 +1,424 @@
+"""Lowering of the OpenQASM 3 syntax tree to libqsv's guarded instruction stream.
+
+Follows the paper's translation scheme (Methodology): standard gates map one
+to one onto gate instructions; an ``if`` becomes a predicate evaluated at run
+time on the measured bits, guarding its body instead of expanding both
+branches statically; ``input`` variables become runtime parameter slots, so a
+program is lowered and loaded once and run with many parameter vectors.
+
+Symbol handling (Methodology, parsing and semantic analysis):
+  * compile-time constants and loop variables are folded to numbers;
+  * ``input`` parameters become slots of one flat theta vector (declaration
+    order, arrays contiguous); a gate angle must be affine in at most one slot:
+    angle = scale * theta[slot] + offset;
+  * classical bits of all ``bit`` registers form one flat array in declaration
+    order; a register's value is sum_i c[i] 2^i.
+
+Control flow becomes flags (64 per shot) and guard masks:
+  if (p) A else B   ->  SETF t <- p ; SETF e <- !p ; A guarded by t ; B guarded by e
+  for i in [a:b] S  ->  SETF l <- true ; S unrolled for each i, guarded by l
+  break / continue  ->  CLRF l / CLRF c (under the enclosing guards)
+Custom ``gate`` definitions are inlined.
+"""
+import math
+
+import numpy as np
+
+from . import frontend as F
+
+# instruction ops, gate kinds and predicate comparisons of include/qsv.h
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF = 1, 2, 3, 4, 5
+(G_ID, G_X, G_Y, G_Z, G_H, G_S, G_SDG, G_T, G_TDG, G_SX, G_SXDG, G_RX, G_RY, G_RZ, G_P, G_U,
+ G_CX, G_CY, G_CZ, G_CH, G_SWAP, G_CP, G_CRX, G_CRY, G_CRZ) = range(25)
+CMP_EQ, CMP_NE, CMP_LT, CMP_GT, CMP_LE, CMP_GE, CMP_TRUE = range(7)
+NONE32 = 0xFFFFFFFF
+MAX_QUBITS = 34
+MAX_INSTRUCTIONS = 20_000_000
+
+INSTR_DTYPE = np.dtype({
+    "names": ["op", "kind", "reserved", "q0", "q1", "cbit", "pred", "flag", "guard", "param",
+              "reserved2", "scale", "offset"],
+    "formats": [np.uint8, np.uint8, np.uint16, np.uint32, np.uint32, np.uint32, np.uint32, np.uint32,
+                np.uint64, (np.uint32, 3), np.uint32, (np.float64, 3), (np.float64, 3)],
+    "offsets": [0, 1, 2, 4, 8, 12, 16, 20, 24, 32, 44, 48, 72],
+    "itemsize": 96})
+PRED_DTYPE = np.dtype({"names": ["lo", "width", "value", "cmp", "reserved"],
+                       "formats": [np.uint32, np.uint32, np.uint64, np.uint32, np.uint32],
+                       "offsets": [0, 4, 8, 16, 20], "itemsize": 24})
+
+# name -> (kind, qubits, angles); u2 is U with theta fixed to pi/2
+_GATES = {
+    "id": (G_ID, 1, 0), "x": (G_X, 1, 0), "y": (G_Y, 1, 0), "z": (G_Z, 1, 0), "h": (G_H, 1, 0),
+    "s": (G_S, 1, 0), "sdg": (G_SDG, 1, 0), "t": (G_T, 1, 0), "tdg": (G_TDG, 1, 0),
+    "sx": (G_SX, 1, 0), "sxdg": (G_SXDG, 1, 0),
+    "rx": (G_RX, 1, 1), "ry": (G_RY, 1, 1), "rz": (G_RZ, 1, 1),
+    "p": (G_P, 1, 1), "phase": (G_P, 1, 1), "u1": (G_P, 1, 1),
+    "u": (G_U, 1, 3), "U": (G_U, 1, 3), "u3": (G_U, 1, 3), "u2": (G_U, 1, 2),
+    "cx": (G_CX, 2, 0), "CX": (G_CX, 2, 0), "cnot": (G_CX, 2, 0), "cy": (G_CY, 2, 0),
+    "cz": (G_CZ, 2, 0), "ch": (G_CH, 2, 0), "swap": (G_SWAP, 2, 0),
+    "cp": (G_CP, 2, 1), "cphase": (G_CP, 2, 1), "crx": (G_CRX, 2, 1), "cry": (G_CRY, 2, 1),
+    "crz": (G_CRZ, 2, 1),
+}
+_NAMED_CONSTANTS = {"pi": math.pi, "π": math.pi, "tau": 2.0 * math.pi, "τ": 2.0 * math.pi,
+                    "euler": math.e, "ℇ": math.e}
+_NEGATE = {CMP_EQ: CMP_NE, CMP_NE: CMP_EQ, CMP_LT: CMP_GE, CMP_GE: CMP_LT, CMP_GT: CMP_LE,
+           CMP_LE: CMP_GT}
+_CMP = {"==": CMP_EQ, "!=": CMP_NE, "<": CMP_LT, ">": CMP_GT, "<=": CMP_LE, ">=": CMP_GE}
+
+
+class Affine:
+    """c + sum_k coef_k * theta[k] (only affine dependence on parameters is representable)."""
+
+    __slots__ = ("c", "terms")
+
+    def __init__(self, c=0.0, terms=None):
+        self.c = c
+        self.terms = terms or {}
+
+    def is_const(self):
+        return not self.terms
+
+    def __repr__(self):
+        return f"Affine({self.c}, {self.terms})"
+
+
+def _aff_add(a, b, sign):
+    terms = dict(a.terms)
+    for k, v in b.terms.items():
+        terms[k] = terms.get(k, 0.0) + sign * v
+    return Affine(a.c + sign * b.c if sign > 0 else a.c - b.c, {k: v for k, v in terms.items()})
+
+
+class LoweredProgram:
+    """The flat instruction stream plus the symbol layout it was lowered with."""
+
+    def __init__(self, n_qubits, n_clbits, n_params, instr, pred, qregs, cregs, inputs):
+        self.n_qubits, self.n_clbits, self.n_params = n_qubits, n_clbits, n_params
+        self.instr, self.pred = instr, pred
+        self.qregs, self.cregs, self.inputs = qregs, cregs, inputs
+
+    @property
+    def is_unitary(self):
+        return bool(np.all(self.instr["op"] == OP_GATE)) if len(self.instr) else True
+
+    @property
+    def n_measure(self):
+        return int(np.sum(self.instr["op"] == OP_MEASURE))
+
+
+class _LoopCtx:
+    def __init__(self, brk, cont):
+        self.brk, self.cont = brk, cont
+
+
+class _Lowerer:
+    def __init__(self):
+        self.rows = []
+        self.preds, self.pred_ids = [], {}
+        self.qregs, self.cregs, self.inputs = {}, {}, {}
+        self.consts, self.gatedefs = {}, {}
+        self.nq = self.nc = self.npar = 0
+        self.free = list(range(63, -1, -1))
+
+    # -- flags --
+    def _alloc(self):
+        if not self.free:
+            raise F.QasmError("control flow nested too deeply (more than 64 live flags)")
+        return self.free.pop()
+
+    def _release(self, f):
+        self.free.append(f)
+
+    # -- emission --
+    def _emit(self, op, guard, kind=0, q0=NONE32, q1=NONE32, cbit=NONE32, pred=NONE32, flag=0,
+              angles=()):
+        if len(self.rows) >= MAX_INSTRUCTIONS:
+            raise F.QasmError("program unrolls to too many instructions")
+        param, scale, offset = [NONE32] * 3, [0.0] * 3, [0.0] * 3
+        for k, a in enumerate(angles):
+            if len(a.terms) > 1:
+                raise F.QasmError("a gate angle may depend on at most one input parameter")
+            offset[k] = float(a.c)
+            for slot, coef in a.terms.items():
+                param[k], scale[k] = slot, float(coef)
+        self.rows.append((op, kind, 0, q0, q1, cbit, pred, flag, guard, tuple(param), 0,
+                          tuple(scale), tuple(offset)))
+
+    def _pred(self, lo, width, value, cmp):
+        key = (lo, width, value, cmp)
+        if key not in self.pred_ids:
+            self.pred_ids[key] = len(self.preds)
+            self.preds.append((lo, width, value, cmp, 0))
+        return self.pred_ids[key]
+
+    # -- expressions --
+    def value(self, e, env):
+        if isinstance(e, F.Num):
+            return Affine(e.value)
+        if isinstance(e, F.Name):
+            if e.ident in env:
+                v = env[e.ident]
+                if isinstance(v, Affine):
+                    return v
+                if isinstance(v, (int, float)):
+                    return Affine(v)
+                raise F.QasmError(f"{e.ident} is a qubit, not a value")
+            if e.ident in self.consts:
+                return self.consts[e.ident]
+            if e.ident in _NAMED_CONSTANTS:
+                return Affine(_NAMED_CONSTANTS[e.ident])
+            if e.ident in self.inputs:
+                off, size, scalar = self.inputs[e.ident]
+                if not scalar:
+                    raise F.QasmError(f"input array {e.ident} needs an index")
+                return Affine(0.0, {off: 1.0})
+            raise F.QasmError(f"undefined name {e.ident}")
+        if isinstance(e, F.Subscript):
+            if e.ident not in self.inputs:
+                raise F.QasmError(f"{e.ident} cannot be indexed in an expression")
+            off, size, scalar = self.inputs[e.ident]
+            i = self.const_int(e.index, env)
+            if not 0 <= i < size:
+                raise F.QasmError(f"index {i} out of range for {e.ident}")
+            return Affine(0.0, {off + i: 1.0})
+        if isinstance(e, F.Unary):
+            a = self.value(e.arg, env)
+            return Affine(-a.c, {k: -v for k, v in a.terms.items()})
+        if isinstance(e, F.Binary):
+            a, b = self.value(e.lhs, env), self.value(e.rhs, env)
+            if e.op == "+":
+                return _aff_add(a, b, +1)
+            if e.op == "-":
+                return _aff_add(a, b, -1)
+            if e.op == "*":
+                if a.is_const():
+                    return Affine(a.c * b.c, {k: a.c * v for k, v in b.terms.items()})
+                if b.is_const():
+                    return Affine(a.c * b.c, {k: v * b.c for k, v in a.terms.items()})
+                raise F.QasmError("product of two parameter-dependent values is not affine")
+            if e.op == "/":
+                if not b.is_const():
+                    raise F.QasmError("division by a parameter-dependent value is not affine")
+                return Affine(a.c / b.c, {k: v / b.c for k, v in a.terms.items()})
+            if not (a.is_const() and b.is_const()):
+                raise F.QasmError(f"operator {e.op} needs constant operands")
+            return Affine(a.c % b.c if e.op == "%" else a.c ** b.c)
+        if isinstance(e, F.Call):
+            a = self.value(e.args[0], env)
+            if not a.is_const():
+                raise F.QasmError(f"{e.fn} of a parameter-dependent value is not affine")
+            fn = {"sin": math.sin, "cos": math.cos, "tan": math.tan, "exp": math.exp, "ln": math.log,
+                  "sqrt": math.sqrt, "arcsin": math.asin, "arccos": math.acos, "arctan": math.atan}[e.fn]
+            return Affine(fn(a.c))
+        raise F.QasmError(f"unsupported expression {e!r}")
+
+    def const_int(self, e, env):
+        a = self.value(e, env)
+        if not a.is_const():
+            raise F.QasmError("expected a compile-time integer")
+        v = a.c
+        if float(v) != float(int(round(v))):
+            raise F.QasmError(f"expected an integer, got {v}")
+        return int(round(v))
+
+    # -- operands --
+    def qubits(self, opd, env):
+        if opd.reg in env and isinstance(env[opd.reg], tuple) and env[opd.reg][0] == "q":
+            if opd.index is not None:
+                raise F.QasmError("gate arguments cannot be indexed")
+            return [env[opd.reg][1]]
+        if opd.reg not in self.qregs:
+            raise F.QasmError(f"unknown qubit register {opd.reg}")
+        off, size = self.qregs[opd.reg]
+        if opd.index is None:
+            return list(range(off, off + size))
+        i = self.const_int(opd.index, env)
+        if not 0 <= i < size:
+            raise F.QasmError(f"qubit index {i} out of range for {opd.reg}")
+        return [off + i]
+
+    def clbits(self, opd, env):
+        if opd.reg not in self.cregs:
+            raise F.QasmError(f"unknown classical register {opd.reg}")
+        off, size = self.cregs[opd.reg]
+        if opd.index is None:
+            return list(range(off, off + size))
+        i = self.const_int(opd.index, env)
+        if not 0 <= i < size:
+            raise F.QasmError(f"bit index {i} out of range for {opd.reg}")
+        return [off + i]
+
+    # -- conditions --
+    def condition(self, c, env):
+        if c.kind == "not":
+            lo, width, value, cmp = self.condition(c.inner, env)
+            return lo, width, value, _NEGATE[cmp]
+        bits = self.clbits(c.operand, env)
+        if len(bits) > 64:
+            raise F.QasmError("conditions read at most 64 bits")
+        if any(b != bits[0] + i for i, b in enumerate(bits)):
+            raise F.QasmError("condition bits must be contiguous")
+        if c.kind == "truth":
+            return bits[0], len(bits), 0, CMP_NE
+        v = self.const_int(c.rhs, env)
+        if v < 0:
+            raise F.QasmError("comparison with a negative value")
+        return bits[0], len(bits), v & 0xFFFFFFFFFFFFFFFF, _CMP[c.op]
+
+    # -- statements --
+    def program(self, stmts):
+        body = []
+        for st in stmts:
+            if isinstance(st, F.Declare):
+                table = self.qregs if st.kind == "qubit" else self.cregs
+                if st.name in table:
+                    raise F.QasmError(f"{st.name} declared twice")
+                size = 1 if st.size is None else st.size
+                if st.kind == "qubit":
+                    table[st.name] = (self.nq, size)
+                    self.nq += size
+                else:
+                    table[st.name] = (self.nc, size)
+                    self.nc += size
+            elif isinstance(st, F.InputDecl):
+                size = 1 if st.size is None else st.size
+                self.inputs[st.name] = (self.npar, size, st.size is None)
+                self.npar += size
+            elif isinstance(st, F.ConstDecl):
+                self.consts[st.name] = self.value(st.value, {})
+            elif isinstance(st, F.GateDef):
+                self.gatedefs[st.name] = st
+            else:
+                body.append(st)
+        if self.nq < 1:
+            raise F.QasmError("program declares no qubits")
+        if self.nq > MAX_QUBITS:
+            raise F.QasmError(f"{self.nq} qubits exceed the {MAX_QUBITS}-qubit limit of one GPU")
+        self.block(body, {}, 0, None)
+
+    def block(self, body, env, guard, loop):
+        for st in body:
+            self.statement(st, env, guard, loop)
+
+    def statement(self, st, env, guard, loop):
+        if isinstance(st, F.GateCall):
+            self.gate(st, env, guard)
+        elif isinstance(st, F.Measure):
+            qs = self.qubits(st.qubits, env)
+            cs = self.clbits(st.target, env) if st.target is not None else [NONE32] * len(qs)
+            if len(qs) != len(cs):
+                raise F.QasmError("measure: register sizes differ")
+            for q, c in zip(qs, cs):
+                self._emit(OP_MEASURE, guard, q0=q, cbit=c)
+        elif isinstance(st, F.Reset):
+            for q in self.qubits(st.qubits, env):
+                self._emit(OP_RESET, guard, q0=q)
+        elif isinstance(st, F.IfStmt):
+            lo, width, value, cmp = self.condition(st.cond, env)
+            ft = self._alloc()
+            self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, cmp), flag=ft)
+            fe = None
+            if st.else_body:
+                fe = self._alloc()
+                self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, _NEGATE[cmp]), flag=fe)
+            self.block(st.then_body, env, guard | (1 << ft), loop)
+            if fe is not None:
+                self.block(st.else_body, env, guard | (1 << fe), loop)
+                self._release(fe)
+            self._release(ft)
+        elif isinstance(st, F.ForStmt):
+            self.for_loop(st, env, guard)
+        elif isinstance(st, F.Break):
+            if loop is None:
+                raise F.QasmError("break outside a loop")
+            self._emit(OP_CLRF, guard, flag=loop.brk)
+        elif isinstance(st, F.Continue):
+            if loop is None:
+                raise F.QasmError("continue outside a loop")
+            self._emit(OP_CLRF, guard, flag=loop.cont)
+        elif isinstance(st, (F.Declare, F.InputDecl, F.GateDef, F.ConstDecl)):
+            raise F.QasmError("declarations are only allowed at the top level")
+        else:
+            raise F.QasmError(f"unsupported statement {type(st).__name__}")
+
+    def for_loop(self, st, env, guard):
+        a, step, b = (self.const_int(x, env) for x in (st.start, st.step, st.stop))
+        if step == 0:
+            raise F.QasmError("for loop with a zero step")
+        values = list(range(a, b + 1, step)) if step > 0 else list(range(a, b - 1, step))
+        has_brk, has_cont = _contains(st.body, F.Break), _contains(st.body, F.Continue)
+        fb = self._alloc() if has_brk else None
+        fc = self._alloc() if has_cont else None
+        g = guard
+        if fb is not None:
+            self._emit(OP_SETF, guard, pred=self._pred(0, 0, 0, CMP_TRUE), flag=fb)
+            g |= 1 << fb
+        for v in values:
+            inner = dict(env)
+            inner[st.var] = v
+            gi = g
+            if fc is not None:
+                self._emit(OP_SETF, g, pred=self._pred(0, 0, 0, CMP_TRUE), flag=fc)
+                gi |= 1 << fc
+            self.block(st.body, inner, gi, _LoopCtx(fb, fc))
+        for f in (fc, fb):
+            if f is not None:
+                self._release(f)
+
+    def gate(self, st, env, guard):
+        angles = [self.value(a, env) for a in st.args]
+        lists = [self.qubits(o, env) for o in st.operands]
+        width = max(len(x) for x in lists)
+        if any(len(x) not in (1, width) for x in lists):
+            raise F.QasmError(f"gate {st.name}: register operands of different sizes")
+        for j in range(width):
+            qs = [x[j] if len(x) > 1 else x[0] for x in lists]
+            if len(set(qs)) != len(qs):
+                raise F.QasmError(f"gate {st.name}: a qubit appears twice")
+            self.apply(st.name, angles, qs, guard)
+
+    def apply(self, name, angles, qs, guard):
+        if name in self.gatedefs:
+            d = self.gatedefs[name]
+            if len(d.params) != len(angles) or len(d.qargs) != len(qs):
+                raise F.QasmError(f"gate {name}: wrong number of arguments")
+            env = {p: a for p, a in zip(d.params, angles)}
+            env.update({qa: ("q", q) for qa, q in zip(d.qargs, qs)})
+            for st in d.body:
+                if not isinstance(st, F.GateCall):
+                    raise F.QasmError(f"gate {name}: only gate calls may appear in a gate body")
+                self.gate(st, env, guard)
+            return
+        if name not in _GATES:
+            raise F.QasmError(f"unknown gate {name}")
+        kind, nq, na = _GATES[name]
+        if len(qs) != nq:
+            raise F.QasmError(f"gate {name} acts on {nq} qubit(s)")
+        if len(angles) != na:
+            raise F.QasmError(f"gate {name} takes {na} parameter(s)")
+        if name == "u2":
+            angles = [Affine(math.pi / 2.0)] + angles
+        self._emit(OP_GATE, guard, kind=kind, q0=qs[0], q1=qs[1] if nq == 2 else NONE32, angles=angles)
+
+    def result(self):
+        instr = np.array(self.rows, dtype=INSTR_DTYPE) if self.rows else np.zeros(0, INSTR_DTYPE)
+        pred = np.array(self.preds, dtype=PRED_DTYPE) if self.preds else np.zeros(0, PRED_DTYPE)
+        return LoweredProgram(self.nq, self.nc, self.npar, instr, pred, dict(self.qregs),
+                              dict(self.cregs), dict(self.inputs))
+
+
+def _contains(body, cls):
+    for st in body:
+        if isinstance(st, cls):
+            return True
+        if isinstance(st, F.IfStmt) and (_contains(st.then_body, cls) or _contains(st.else_body, cls)):
+            return True
+    return False
+
+
+def lower(source):
+    """OpenQASM 3 text (or a parsed statement list) -> LoweredProgram."""
+    stmts = F.parse(source) if isinstance(source, str) else source
+    lw = _Lowerer()
+    lw.program(stmts)
+    return lw.result()

@@ -1,0 +1,76 @@
+"""Test-only interpreter of the lowered instruction stream.
+
+Executes the guarded stream the product's lowering emits, with the oracle's
+gate matrices and tensor engine, so that lowering can be compared with the
+oracle's direct walk of the syntax tree on the CPU.
+"""
+import math
+
+from oracle import gates as G
+from oracle.philox import ShotStream
+from oracle.sim import TensorEngine
+
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF = 1, 2, 3, 4, 5
+KIND_NAMES = ["id", "x", "y", "z", "h", "s", "sdg", "t", "tdg", "sx", "sxdg", "rx", "ry", "rz", "p", "U",
+              "cx", "cy", "cz", "ch", "swap", "cp", "crx", "cry", "crz"]
+N_ANGLES = {"rx": 1, "ry": 1, "rz": 1, "p": 1, "U": 3, "cp": 1, "crx": 1, "cry": 1, "crz": 1}
+
+
+def eval_pred(p, bits):
+    lo, width, value, cmp = int(p["lo"]), int(p["width"]), int(p["value"]), int(p["cmp"])
+    if cmp == 6:
+        return True
+    v = sum(bits[lo + i] << i for i in range(width))
+    return [v == value, v != value, v < value, v > value, v <= value, v >= value][cmp]
+
+
+def run(lp, theta=(), seed=0, shot=0, forced=None):
+    eng = TensorEngine(lp.n_qubits)
+    bits = [0] * lp.n_clbits
+    flags = 0
+    stream = ShotStream(seed, shot)
+    record, nmeas = [], 0
+    forced = list(forced or [])
+    for ins in lp.instr:
+        op, guard = int(ins["op"]), int(ins["guard"])
+        active = (flags & guard) == guard
+        if op == OP_SETF:
+            v = active and eval_pred(lp.pred[int(ins["pred"])], bits)
+            f = int(ins["flag"])
+            flags = (flags & ~(1 << f)) | (int(v) << f)
+            continue
+        if not active:
+            continue
+        if op == OP_CLRF:
+            flags &= ~(1 << int(ins["flag"]))
+        elif op == OP_GATE:
+            name = KIND_NAMES[int(ins["kind"])]
+            angles = []
+            for k in range(N_ANGLES.get(name, 0)):
+                a = float(ins["offset"][k])
+                if int(ins["param"][k]) != 0xFFFFFFFF:
+                    a += float(ins["scale"][k]) * float(theta[int(ins["param"][k])])
+                angles.append(a)
+            m, nq = G.gate_matrix(name, angles)
+            qs = [int(ins["q0"])] + ([int(ins["q1"])] if nq == 2 else [])
+            eng.apply(m, qs)
+        else:
+            q = int(ins["q0"])
+            p0, p1 = eng.probs(q)
+            u = stream.next_uniform()
+            if op == OP_MEASURE and nmeas < len(forced):
+                m = forced[nmeas]
+            else:
+                m = 0 if u < p0 / (p0 + p1) else 1
+            eng.collapse(q, m, p0 if m == 0 else p1)
+            if op == OP_MEASURE:
+                nmeas += 1
+                record.append(m)
+                if int(ins["cbit"]) != 0xFFFFFFFF:
+                    bits[int(ins["cbit"])] = m
+            elif m == 1:
+                eng.flip(q)
+    return eng.psi, bits, record
+
+
+_ = math

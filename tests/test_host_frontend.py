@@ -1,0 +1,178 @@
+"""CPU tests of the product's host side: ABI surface, lowering and planning."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sim
+from paper_2604_11599_amd import QasmError, lower
+from paper_2604_11599_amd import _abi
+from tests import ir_interp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+# ---------------------------------------------------------------------------
+# ABI surface
+# ---------------------------------------------------------------------------
+def _declared_functions():
+    names = set()
+    for h in ("qsv.h", "qsv_plan.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(qsv_[a-z_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_abi.LIB_PATH)
+    declared = _declared_functions()
+    assert {"qsv_create", "qsv_load_program", "qsv_run_shots", "qsv_expval", "qsv_expval_grad"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(_abi.SIGNATURES) == declared
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(_abi.Config) == 40
+    assert ctypes.sizeof(_abi.ProgramDesc) == 40
+    assert ctypes.sizeof(_abi.RunOpts) == 40
+    assert ctypes.sizeof(_abi.ShotResults) == 40
+    assert ctypes.sizeof(_abi.PauliSum) == 24
+    assert ctypes.sizeof(_abi.PlanStats) == 315424
+    from paper_2604_11599_amd.lower import INSTR_DTYPE, PRED_DTYPE
+    assert INSTR_DTYPE.itemsize == 96 and PRED_DTYPE.itemsize == 24
+
+
+# ---------------------------------------------------------------------------
+# Lowering == oracle (through a test-only interpreter of the instruction stream)
+# ---------------------------------------------------------------------------
+def _compare(src, theta=(), shots=3, seed=5, forced=None):
+    lp = lower(src)
+    for shot in range(shots):
+        o = sim.run_shot(src, theta if len(theta) else None, seed=seed, shot=shot, forced=forced)
+        psi, bits, record = ir_interp.run(lp, theta, seed=seed, shot=shot, forced=forced)
+        assert bits == o.cbits and record == o.record
+        assert np.max(np.abs(psi - o.psi)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_lowering_matches_oracle_random_dynamic(seed):
+    _compare(W.random_dynamic_program(seed, 2 + seed % 5, n_ops=40, final_measure=seed % 2 == 0))
+
+
+def test_lowering_protocols():
+    _compare(W.conditional_reset_program("plus"), shots=6)
+    _compare(W.teleport_program(0.3, 1.2, -0.7), shots=6)
+    _compare(W.if_else_program(0.77), shots=4)
+    for b in (0, 10, 5):
+        _compare(W.multibit_predicate_program(b), shots=1)
+    _compare(W.rus_program(2.0, 5), shots=8)
+    _compare(W.c1_program(1), shots=2)
+    _compare(W.c3_program(3, n=6, layers=2, max_iter=4), shots=5)
+    _compare(W.qft_program(4, 5), shots=1)
+
+
+def test_lowering_parameters_and_custom_gates():
+    src = ('OPENQASM 3.0; input array[float[64], 3] th; input float[64] s; qubit[3] q; bit[2] c;'
+           'const float[64] k = pi / 3;'
+           'gate rot(a, b) x, y { ry(a) x; cx x, y; rz(b - k) y; } '
+           'rot(2 * th[0] + 0.25, th[1] / 4) q[0], q[2]; u2(s, -th[2]) q[1]; U(th[0], s, k) q[2];'
+           'c[0] = measure q[0]; if (c[0] == 1) { crx(s * 3) q[1], q[2]; } else cp(th[1]) q[2], q[0];')
+    _compare(src, theta=np.array([0.3, -1.1, 2.2, 0.9]), shots=4)
+
+
+def test_nested_loops_break_continue():
+    src = ('qubit[3] q; bit[3] c;'
+           'for uint i in [0:2] { h q[i]; c[i] = measure q[i]; if (c[i] == 1) continue; '
+           '  for uint j in [1:2] { rx(0.3 * j) q[(i + j) % 3]; if (c[0]) break; } x q[i]; }'
+           'for int k in [2:-1:0] { ry(0.1 * k) q[k]; }')
+    _compare(src, shots=8)
+
+
+def test_lowering_errors():
+    for bad in ["qubit[2] q; while (true) { x q[0]; }",
+                "qubit[2] q; foo q[0];",
+                "qubit[2] q; input float[64] a; input float[64] b; rx(a * b) q[0];",
+                "qubit[2] q; input float[64] a; input float[64] b; rx(a + b) q[0];",
+                "qubit[2] q; break;",
+                "qubit[2] q; cx q[0], q[0];",
+                "qubit[35] q;",
+                "qubit[2] q; x q[2];",
+                "bit[2] c;"]:
+        with pytest.raises(QasmError):
+            lower(bad)
+
+
+def test_flag_layout_of_if_else():
+    lp = lower("qubit[2] q; bit[2] c; c[0] = measure q[0]; if (c == 2) x q[1]; else h q[1];")
+    ops = list(lp.instr["op"])
+    assert ops == [2, 4, 4, 1, 1]
+    t, e = lp.instr[1], lp.instr[2]
+    assert lp.pred[int(t["pred"])]["cmp"] == 0 and lp.pred[int(e["pred"])]["cmp"] == 1
+    assert int(lp.instr[3]["guard"]) == 1 << int(t["flag"])
+    assert int(lp.instr[4]["guard"]) == 1 << int(e["flag"])
+
+
+# ---------------------------------------------------------------------------
+# Planner (host-only inspection through the C ABI)
+# ---------------------------------------------------------------------------
+def _qubits_of(ins):
+    qs = [int(ins["q0"])]
+    if int(ins["q1"]) != 0xFFFFFFFF:
+        qs.append(int(ins["q1"]))
+    return qs
+
+
+def _check_plan(src, tile_bits=0):
+    from paper_2604_11599_amd.api import plan_inspect
+    lp = lower(src)
+    st = plan_inspect(lp, tile_bits)
+    gates = [i for i, ins in enumerate(lp.instr) if ins["op"] == 1 and ins["kind"] != 0]
+    order = list(st.gate_instr[:st.n_gates])
+    site_x = sorted(set(gates) - set(order))
+    # every gate is planned exactly once, or folded into a measurement site (X gates only)
+    assert len(order) == len(set(order))
+    assert all(int(lp.instr[i]["kind"]) == 1 for i in site_x)
+    # per qubit, gates keep their program order
+    pos = {g: k for k, g in enumerate(order)}
+    for q in range(lp.n_qubits):
+        seq = [pos[i] for i in gates if i in pos and q in _qubits_of(lp.instr[i])]
+        assert seq == sorted(seq)
+    # every pass's tile holds the qubits of its gates
+    k = 0
+    for s in range(st.n_steps):
+        if st.step_kind[s] == 1:
+            mask = st.step_mask[s]
+            assert bin(mask).count("1") == min(tile_bits or 12, lp.n_qubits)
+            for g in order[k:k + st.step_count[s]]:
+                for q in _qubits_of(lp.instr[g]):
+                    assert mask >> q & 1
+            k += st.step_count[s]
+    return st
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_plan_invariants_random(seed):
+    n = [3, 8, 13, 16, 20, 14, 17, 28][seed]
+    _check_plan(W.random_dynamic_program(seed, n, n_ops=120, final_measure=True))
+
+
+def test_plan_of_configs():
+    st = _check_plan(W.c2_program(2, n=28, layers=40))
+    assert st.n_passes <= 60
+    st = _check_plan(W.c1_program(1))
+    # one pass per gate run: the whole 10-qubit state is one tile
+    assert st.n_passes == 4 and st.init_step == 0
+    st = _check_plan(W.c3_program(3, n=16))
+    _check_plan(W.c4_ansatz(20, 6))
+    _check_plan(W.brickwork_program(7, n=28, layers=6), tile_bits=10)
+
+
+def test_plan_starts_with_init_when_program_starts_with_measurement():
+    st = _check_plan("qubit[3] q; bit c; c = measure q[1]; h q[0];")
+    assert st.init_step == 1 and st.step_kind[0] == 0 and st.step_kind[1] == 2
