@@ -90,7 +90,7 @@ def test_static_multi_tile_gates_on_every_qubit(ctx):
         lines = [W.circuits.HEADER, f"qubit[{n}] q;"]
         for _ in range(6 * n):
             a, b = (int(x) for x in rng.choice(n, 2, replace=False))
-            t = rng.uniform(0, 6.283, 3)
+            t = [float(x) for x in rng.uniform(0, 6.283, 3)]
             lines += [f"U({t[0]!r}, {t[1]!r}, {t[2]!r}) q[{a}];", f"cx q[{a}], q[{b}];",
                       f"cp({t[0]!r}) q[{b}], q[{a}];", f"swap q[{b}], q[{(a + 1) % n if (a + 1) % n != b else a}];"]
         src = "\n".join(lines) + "\n"
