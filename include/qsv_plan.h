@@ -31,6 +31,10 @@ typedef struct {
   uint64_t step_mask[QSV_PLAN_MAX_STEPS];    /* pass: tile qubit mask; site: histogrammed qubits */
   uint32_t step_count[QSV_PLAN_MAX_STEPS];   /* pass: gates; site: events */
   uint32_t gate_instr[QSV_PLAN_MAX_GATES];   /* instruction index of each planned gate, in order */
+  uint64_t gate_regs[QSV_PLAN_MAX_GATES];    /* qubits held in registers while the gate runs
+                                                (0: LDS-only pass) */
+  uint32_t n_phases;                         /* register phases over all passes */
+  uint32_t reserved2;
 } qsv_plan_stats;
 
 /* tile_bits = 0 uses the default tile width (12 bits). */

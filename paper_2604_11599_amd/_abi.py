@@ -57,7 +57,8 @@ class PlanStats(C.Structure):
                 ("n_gates", C.c_uint32), ("n_events", C.c_uint32), ("max_record", C.c_uint32),
                 ("is_unitary", C.c_uint8), ("init_step", C.c_uint8), ("reserved", C.c_uint8 * 6),
                 ("step_kind", C.c_uint8 * PLAN_MAX_STEPS), ("step_mask", C.c_uint64 * PLAN_MAX_STEPS),
-                ("step_count", C.c_uint32 * PLAN_MAX_STEPS), ("gate_instr", C.c_uint32 * PLAN_MAX_GATES)]
+                ("step_count", C.c_uint32 * PLAN_MAX_STEPS), ("gate_instr", C.c_uint32 * PLAN_MAX_GATES),
+                ("gate_regs", C.c_uint64 * PLAN_MAX_GATES), ("n_phases", C.c_uint32), ("reserved2", C.c_uint32)]
 
 
 class Profile(C.Structure):

@@ -58,6 +58,7 @@ struct qsv_program {
   Plan plan;
   // device copies of the static plan
   DGate* d_gates = nullptr;
+  Phase* d_phases = nullptr;
   GateSrc* d_src = nullptr;
   SiteEvent* d_events = nullptr;
   DPred* d_preds = nullptr;
@@ -276,6 +277,7 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
   }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(pl.gates, &p->d_gates);
+  if (e == hipSuccess) e = upload(pl.phases, &p->d_phases);
   if (e == hipSuccess) e = upload(pl.gate_src, &p->d_src);
   if (e == hipSuccess) e = upload(pl.events, &p->d_events);
   if (e == hipSuccess) e = upload(dp, &p->d_preds);
@@ -307,7 +309,7 @@ qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) 
 void qsv_program_free(qsv_program* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
-  void* ptrs[] = {p->d_gates, p->d_src, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
+  void* ptrs[] = {p->d_gates, p->d_phases, p->d_src, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -383,7 +385,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
         HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st));
         pr.done(2);
       } else if (step.kind == Step::PASS) {
-        HIP_TRY(launch_tile_pass(rb, prog->d_gates, d_mats, 0, pl.passes[step.index], st));
+        HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
         const double amps = (double)dim * bs;
         pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * amps, pl.pass_flops_per_amp[step.index] * amps);
       } else {
@@ -519,7 +521,7 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
         HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st));
         pr.done(2);
       } else if (step.kind == Step::PASS) {
-        HIP_TRY(launch_tile_pass(rb, prog->d_gates, d_mats, ms, pl.passes[step.index], st));
+        HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, ms, pl.passes[step.index], st));
         const double amps = (double)dim * bs;
         pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * amps, pl.pass_flops_per_amp[step.index] * amps);
       }
@@ -624,13 +626,23 @@ qsv_status qsv_plan_inspect(const qsv_program_desc* desc, uint32_t tile_bits, qs
     }
     ++k;
   }
-  // instruction index of every planned gate, in execution order
+  // instruction index of every planned gate, in execution order, with its phase's register qubits
   uint32_t g = 0;
+  out->n_phases = (uint32_t)pl.phases.size();
   for (const Step& s : pl.steps) {
     if (s.kind != Step::PASS) continue;
     const PassArgs& a = pl.passes[s.index];
-    for (uint32_t i = 0; i < a.gate_count && g < QSV_PLAN_MAX_GATES; ++i, ++g)
-      out->gate_instr[g] = pl.slot_instr[pl.gates[a.gate_begin + i].mat];
+    for (uint32_t i = 0; i < a.gate_count && g < QSV_PLAN_MAX_GATES; ++i, ++g) {
+      const uint32_t gi = a.gate_begin + i;
+      out->gate_instr[g] = pl.slot_instr[pl.gates[gi].mat];
+      uint64_t regs = 0;
+      for (uint32_t p = a.phase_begin; p < a.phase_begin + a.phase_count; ++p) {
+        const Phase& ph = pl.phases[p];
+        if (gi >= ph.gate_begin && gi < ph.gate_begin + ph.gate_count)
+          for (int k = 0; k < kRegBits; ++k) regs |= 1ull << a.tq[ph.r[k]];
+      }
+      out->gate_regs[g] = regs;
+    }
   }
   return QSV_OK;
 }

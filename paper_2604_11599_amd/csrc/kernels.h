@@ -28,7 +28,7 @@ hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const doub
                                 hipStream_t st);
 hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots, hipStream_t st);
 hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st);
-hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const double* mats,
+hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st);
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
                        const DPred* preds, hipStream_t st);

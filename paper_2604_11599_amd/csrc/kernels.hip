@@ -245,13 +245,13 @@ __device__ __forceinline__ M2 load_m2(const double* m, uint32_t flip) {
   return r;
 }
 
-// Applies one gate to the LDS tile. f0/f1: frame flips of the gate's qubits.
+// Applies one gate to the LDS tile (tile-local logical indices).
 __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t t, const DGate& g,
-                                           const double* __restrict__ m, uint32_t f0, uint32_t f1) {
+                                           const double* __restrict__ m) {
   const uint32_t tid = threadIdx.x;
   switch (g.type) {
     case GT_DENSE1: case GT_DIAG1: {
-      M2 u = load_m2(m, f0);
+      const M2 u = load_m2(m, 0);
       const uint32_t np = 1u << (t - 1), bit = 1u << g.b0;
       if (g.type == GT_DIAG1) {
         for (uint32_t p = tid; p < np; p += kTileThreads) {
@@ -283,36 +283,33 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
       const uint32_t lo = g.b0 < g.b1 ? g.b0 : g.b1, hi = g.b0 < g.b1 ? g.b1 : g.b0;
       const uint32_t nq = 1u << (t - 2);
       const uint32_t B0 = 1u << g.b0, B1 = 1u << g.b1;
-      const uint32_t cset = f0 ? 0u : B0;  // memory value of the control bit that means |1>
       if (g.type == GT_CX) {
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
-          uint32_t i = ins0(ins0(p, lo), hi) | cset;
+          uint32_t i = ins0(ins0(p, lo), hi) | B0;
           double2 x = tile[i];
           tile[i] = tile[i | B1];
           tile[i | B1] = x;
         }
       } else if (g.type == GT_CTRL1) {
-        M2 u = load_m2(m, f1);
+        const M2 u = load_m2(m, 0);
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
-          uint32_t i = ins0(ins0(p, lo), hi) | cset;
+          uint32_t i = ins0(ins0(p, lo), hi) | B0;
           double2 x0 = tile[i], x1 = tile[i | B1];
           tile[i] = cmac2(u.a, x0, u.b, x1);
           tile[i | B1] = cmac2(u.c, x0, u.d, x1);
         }
       } else if (g.type == GT_CPHASE) {
-        double2 ph = make_double2(m[6], m[7]);
-        uint32_t sel = cset | (f1 ? 0u : B1);
+        const double2 ph = make_double2(m[6], m[7]);
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
-          uint32_t i = ins0(ins0(p, lo), hi) | sel;
+          uint32_t i = ins0(ins0(p, lo), hi) | B0 | B1;
           tile[i] = cmul(ph, tile[i]);
         }
-      } else {  // GT_SWAP: exchange 01<->10, or 00<->11 when exactly one operand is flipped
-        uint32_t ea = (f0 == f1) ? B0 : 0u, eb = (f0 == f1) ? B1 : (B0 | B1);
+      } else {  // GT_SWAP
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
           uint32_t i = ins0(ins0(p, lo), hi);
-          double2 x = tile[i | ea];
-          tile[i | ea] = tile[i | eb];
-          tile[i | eb] = x;
+          double2 x = tile[i | B0];
+          tile[i | B0] = tile[i | B1];
+          tile[i | B1] = x;
         }
       }
       break;
@@ -342,9 +339,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
   bool any = false;
   for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, gates[a.gate_begin + i].guard);
   if (!a.init && !any) return;  // the pending collapse stays owed to a later pass
-  const uint64_t Vm = c->pend_val ^ (F & M);   // restriction in memory coordinates
-
-  // base index of this tile: w's bits scattered over the non-tile qubits
+  const uint64_t V = c->pend_val;
+  // Tile w holds the logical indices whose non-tile bits spell w; amplitude i is
+  // stored at memory index i ^ F (the shot's flip frame), so a workgroup reads
+  // and writes one memory tile and gates act on logical indices.
   uint64_t base = 0;
   {
     uint32_t k = 0;
@@ -358,10 +356,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
     double2 v;
     if (a.init) {
       v = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
-    } else if ((gi & M) != Vm) {
+    } else if ((gi & M) != V) {
       v = make_double2(0.0, 0.0);
     } else {
-      v = st[gi];
+      v = st[gi ^ F];
       if (pending) v = cscale(v, s);
     }
     tile[l] = v;
@@ -371,11 +369,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
   for (uint32_t i = 0; i < a.gate_count; ++i) {
     DGate g = gates[a.gate_begin + i];
     if (!guard_ok(flags, g.guard)) continue;
-    uint32_t f0 = (uint32_t)((F >> a.tq[g.b0]) & 1ull), f1 = (uint32_t)((F >> a.tq[g.b1]) & 1ull);
-    tile_apply(tile, a.t, g, mb + (uint64_t)g.mat * kMatStride, f0, f1);
+    tile_apply(tile, a.t, g, mb + (uint64_t)g.mat * kMatStride);
     __syncthreads();
   }
-  for (uint32_t l = tid; l < T; l += kTileThreads) st[base | local_to_global(l, a)] = tile[l];
+  for (uint32_t l = tid; l < T; l += kTileThreads) st[(base | local_to_global(l, a)) ^ F] = tile[l];
   if (pending) {
     // the last workgroup of this shot to finish clears the pending collapse
     __syncthreads();
@@ -392,13 +389,298 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
   }
 }
 
-hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const double* mats,
+__global__ void k_tile_pass_r(double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
+                              const DGate* __restrict__ gates, const Phase* __restrict__ phases,
+                              const double* __restrict__ mats, uint64_t mat_stride, PassArgs a);
+
+hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
   dim3 grid(a.tiles, rb.shots);
   size_t lds = (size_t)sizeof(double2) << a.t;
-  hipLaunchKernelGGL(k_tile_pass, grid, dim3(kTileThreads), lds, st, rb.state, rb.stride, rb.ctl, gates,
-                     mats, mat_stride, a);
+  if (a.phase_count) {
+    hipLaunchKernelGGL(k_tile_pass_r, grid, dim3(1u << (a.t - kRegBits)), lds, st, rb.state, rb.stride, rb.ctl,
+                       gates, phases, mats, mat_stride, a);
+  } else {
+    hipLaunchKernelGGL(k_tile_pass, grid, dim3(kTileThreads), lds, st, rb.state, rb.stride, rb.ctl, gates,
+                       mats, mat_stride, a);
+  }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Register-blocked tile pass
+//
+// Each thread owns the 16 amplitudes of the tile that differ only in the
+// phase's 4 register bits, applies the phase's gates to them in registers and
+// hands them back through LDS, where the next phase picks up a different set
+// of 4 bits. One LDS round trip per phase instead of one per gate.
+// LDS slots are XOR-swizzled (bits 4..11 folded onto bits 0..3) so that the
+// lanes of a wave spread over the banks for any choice of register bits.
+// ---------------------------------------------------------------------------
+constexpr int kR = 1 << kRegBits;
+
+__device__ __forceinline__ uint32_t swz(uint32_t l) { return l ^ ((l >> 4) & 15u) ^ ((l >> 8) & 15u); }
+
+template <int J>
+__device__ __forceinline__ void r_dense(double2 (&a)[kR], const M2& u) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    const double2 x0 = a[k], x1 = a[k1];
+    a[k] = cmac2(u.a, x0, u.b, x1);
+    a[k1] = cmac2(u.c, x0, u.d, x1);
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void r_diag(double2 (&a)[kR], const M2& u) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) a[k] = cmul((k & (1 << J)) ? u.d : u.a, a[k]);
+}
+
+template <int J>
+__device__ __forceinline__ void r_x(double2 (&a)[kR]) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (k & (1 << J)) continue;
+    const double2 x = a[k];
+    a[k] = a[k | (1 << J)];
+    a[k | (1 << J)] = x;
+  }
+}
+
+// memory value CV of the control bit C selects the pairs along T
+template <int C, int T, int CV>
+__device__ __forceinline__ void r_cx(double2 (&a)[kR]) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (((k >> C) & 1) != CV || (k & (1 << T))) continue;
+    const double2 x = a[k];
+    a[k] = a[k | (1 << T)];
+    a[k | (1 << T)] = x;
+  }
+}
+
+template <int C, int T, int CV>
+__device__ __forceinline__ void r_ctrl(double2 (&a)[kR], const M2& u) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (((k >> C) & 1) != CV || (k & (1 << T))) continue;
+    const int k1 = k | (1 << T);
+    const double2 x0 = a[k], x1 = a[k1];
+    a[k] = cmac2(u.a, x0, u.b, x1);
+    a[k1] = cmac2(u.c, x0, u.d, x1);
+  }
+}
+
+template <int C, int T, int SC, int ST>
+__device__ __forceinline__ void r_cphase(double2 (&a)[kR], double2 ph) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k)
+    if (((k >> C) & 1) == SC && ((k >> T) & 1) == ST) a[k] = cmul(ph, a[k]);
+}
+
+// SWAP in the flip frame: exchange 01<->10, or 00<->11 when one operand is flipped
+template <int A, int B, int ANTI>
+__device__ __forceinline__ void r_swap(double2 (&a)[kR]) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (ANTI) {
+      if ((k & (1 << A)) || (k & (1 << B))) continue;
+      const int k2 = k | (1 << A) | (1 << B);
+      const double2 x = a[k];
+      a[k] = a[k2];
+      a[k2] = x;
+    } else {
+      if (!(k & (1 << A)) || (k & (1 << B))) continue;
+      const int k2 = (k ^ (1 << A)) | (1 << B);
+      const double2 x = a[k];
+      a[k] = a[k2];
+      a[k2] = x;
+    }
+  }
+}
+
+template <int C, int T>
+__device__ __forceinline__ void r_two(double2 (&a)[kR], uint8_t type, const double* m) {
+  switch (type) {
+    case GT_CX: r_cx<C, T, 1>(a); break;
+    case GT_CTRL1: r_ctrl<C, T, 1>(a, load_m2(m, 0)); break;
+    case GT_CPHASE: r_cphase<C, T, 1, 1>(a, make_double2(m[6], m[7])); break;
+    default: r_swap<C, T, 0>(a); break;
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void r_one(double2 (&a)[kR], uint8_t type, const double* m) {
+  if (type == GT_X1) {
+    r_x<J>(a);
+    return;
+  }
+  const M2 u = load_m2(m, 0);
+  if (type == GT_DIAG1) r_diag<J>(a, u);
+  else r_dense<J>(a, u);
+}
+
+__device__ __forceinline__ void r_apply(double2 (&a)[kR], uint8_t type, int j0, int j1, const double* m) {
+  if (type <= GT_X1) {
+    switch (j0) {
+      case 0: r_one<0>(a, type, m); break;
+      case 1: r_one<1>(a, type, m); break;
+      case 2: r_one<2>(a, type, m); break;
+      default: r_one<3>(a, type, m); break;
+    }
+    return;
+  }
+#define QSV_R2(C, T) \
+  case (C * 4 + T): r_two<C, T>(a, type, m); break;
+  switch (j0 * 4 + j1) {
+    QSV_R2(0, 1) QSV_R2(0, 2) QSV_R2(0, 3)
+    QSV_R2(1, 0) QSV_R2(1, 2) QSV_R2(1, 3)
+    QSV_R2(2, 0) QSV_R2(2, 1) QSV_R2(2, 3)
+    QSV_R2(3, 0) QSV_R2(3, 1) QSV_R2(3, 2)
+    default: break;
+  }
+#undef QSV_R2
+}
+
+// scatter the low bits of x over the set bits of mask (ascending)
+__device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask) {
+  uint32_t r = 0;
+  while (mask) {
+    const uint32_t b = mask & (0u - mask);
+    if (x & 1u) r |= b;
+    x >>= 1;
+    mask ^= b;
+  }
+  return r;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
+    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const DGate* __restrict__ gates,
+    const Phase* __restrict__ phases, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a) {
+  extern __shared__ double2 tile[];
+  const uint32_t shot = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+  const uint32_t nthr = 1u << (a.t - kRegBits);
+  ShotCtl* c = ctl + shot;
+  if (c->status != 0) return;
+  const uint64_t flags = c->flags, M = c->pend_mask, F = c->frame;
+  const double s = c->pend_scale;
+  const bool pending = M != 0 || s != 1.0;
+  bool any = false;
+  for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, gates[a.gate_begin + i].guard);
+  if (!a.init && !any) return;
+  const uint64_t V = c->pend_val;
+  uint64_t base = 0;
+  {
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < a.n; ++q)
+      if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
+  }
+  double2* st = state + (uint64_t)shot * stride;
+  const uint32_t T = 1u << a.t;
+  // Logical amplitude i is stored at memory index i ^ F (the shot's flip frame):
+  // the workgroup reads and writes one memory tile, gates act on logical indices.
+  // element k of this thread is tile-local index l = tid + k * nthr: its global index is
+  // base | (tid's bits scattered over tq[0..t-5]) | (k's bits scattered over tq[t-4..t-1])
+  uint64_t gthr = base;
+  for (uint32_t b = 0; b + kRegBits < a.t; ++b) gthr |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
+  const uint64_t h0 = 1ull << a.tq[a.t - 4], h1 = 1ull << a.tq[a.t - 3], h2 = 1ull << a.tq[a.t - 2],
+                 h3 = 1ull << a.tq[a.t - 1];
+  double2 r[kR];
+  // all 16 loads are issued before the first use, so each thread keeps 16 requests in flight
+  if (a.init) {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                          ((k & 8) ? h3 : 0ull);
+      r[k] = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
+    }
+  } else if (M == 0) {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                          ((k & 8) ? h3 : 0ull);
+      r[k] = st[gi ^ F];
+    }
+  } else {
+    // a collapse is owed: amplitudes outside the kept outcome are zero and not read
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                          ((k & 8) ? h3 : 0ull);
+      r[k] = ((gi & M) == V) ? st[gi ^ F] : make_double2(0.0, 0.0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kR; ++k) tile[swz(tid + (uint32_t)k * nthr)] = pending ? cscale(r[k], s) : r[k];
+  __syncthreads();
+  const double* mb = mats + (uint64_t)shot * mat_stride;
+  __syncthreads();
+  for (uint32_t p = 0; p < a.phase_count; ++p) {
+    const Phase ph = phases[a.phase_begin + p];
+    bool act = false;
+    for (uint32_t i = 0; i < ph.gate_count && !act; ++i) act = guard_ok(flags, gates[ph.gate_begin + i].guard);
+    if (!act) continue;
+    const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
+    const uint32_t lb = pdep32(tid, (T - 1u) & ~(o0 | o1 | o2 | o3));
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
+      r[k] = tile[swz(l)];
+    }
+    // gate records and matrices are wave-uniform scalar loads; the next gate's
+    // are requested before the current gate is applied
+    // DGate words: [0] type | b0 | b1 | nang | j0 | j1 | q0 | q1, [1] mat | pad, [2] guard
+    const uint64_t* gw = reinterpret_cast<const uint64_t*>(gates + ph.gate_begin);
+    const double* mp = mb + (uint64_t)ph.gate_begin * kMatStride;
+    uint64_t w0n = gw[0], gdn = gw[2];
+    double mn[kMatStride];
+#pragma unroll
+    for (int e = 0; e < kMatStride; ++e) mn[e] = mp[e];
+    for (uint32_t i = 0; i < ph.gate_count; ++i) {
+      const uint64_t w0 = w0n, gd = gdn;
+      double m[kMatStride];
+#pragma unroll
+      for (int e = 0; e < kMatStride; ++e) m[e] = mn[e];
+      if (i + 1 < ph.gate_count) {
+        w0n = gw[(uint64_t)(i + 1) * 4];
+        gdn = gw[(uint64_t)(i + 1) * 4 + 2];
+#pragma unroll
+        for (int e = 0; e < kMatStride; ++e) mn[e] = mp[(uint64_t)(i + 1) * kMatStride + e];
+      }
+      if (!guard_ok(flags, gd)) continue;
+      r_apply(r, (uint8_t)(w0 & 0xFFu), (int)((w0 >> 32) & 0xFFu), (int)((w0 >> 40) & 0xFFu), m);
+    }
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
+      tile[swz(l)] = r[k];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kR; ++k) r[k] = tile[swz(tid + (uint32_t)k * nthr)];
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                        ((k & 8) ? h3 : 0ull);
+    st[gi ^ F] = r[k];
+  }
+  if (pending) {
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const uint32_t done = atomicAdd(&c->wg_done, 1u);
+      if (done == a.tiles - 1) {
+        c->pend_mask = 0;
+        c->pend_val = 0;
+        c->pend_scale = 1.0;
+        c->wg_done = 0;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -816,7 +1098,7 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_pass(
     }
     __syncthreads();
     // gradient partials for each angle the gate depends on (at most 3)
-    const uint32_t nang = (g.pad & 3u);
+    const uint32_t nang = g.nang;
     for (uint32_t j = 0; j < nang; ++j) {
       M2 d = load_m2(dm + j * kMatStride, 0);
       double acc = 0.0;
@@ -870,7 +1152,7 @@ __global__ void k_grad_reduce(const double* __restrict__ gpart, uint32_t tiles, 
   uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)batch * gate_count * 3) return;
   uint32_t j = idx % 3, gi = (idx / 3) % gate_count, b = (uint32_t)(idx / 3 / gate_count);
-  if (j >= (gates[gi].pad & 3u)) return;
+  if (j >= gates[gi].nang) return;
   double acc = 0.0;
   for (uint32_t w = 0; w < tiles; ++w) acc += gpart[(((uint64_t)b * tiles + w) * gate_count + gi) * 3 + j];
   dEda[((uint64_t)b * n_slots + gates[gi].mat) * 3 + j] = acc;

@@ -90,6 +90,73 @@ uint64_t grow(const std::vector<GateRef>& rem, uint64_t start, uint32_t tmax,
   return T;
 }
 
+// Reorders the gates of pass *pa into phases whose gates touch at most
+// kRegBits tile-local bits, greedily (same growth rule as the tile chooser,
+// on local bit masks), and records the phases.
+void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
+  std::vector<GateRef> rem;
+  std::vector<DGate> src(plan->gates.begin() + pa->gate_begin,
+                         plan->gates.begin() + pa->gate_begin + pa->gate_count);
+  for (uint32_t i = 0; i < src.size(); ++i) {
+    uint64_t m = 1ull << src[i].b0;
+    if (src[i].type >= GT_CX) m |= 1ull << src[i].b1;
+    rem.push_back({i, m});
+  }
+  std::vector<DGate> out;
+  pa->phase_begin = (uint32_t)plan->phases.size();
+  std::vector<uint8_t> taken, best_taken;
+  while (!rem.empty()) {
+    uint32_t best = 0;
+    uint64_t bestR = 0;
+    std::vector<uint64_t> seeds{0};
+    for (size_t i = 0; i < rem.size() && seeds.size() <= candidates; ++i)
+      if (std::find(seeds.begin(), seeds.end(), rem[i].qmask) == seeds.end()) seeds.push_back(rem[i].qmask);
+    for (uint64_t s : seeds) {
+      uint32_t c = 0;
+      uint64_t R = grow(rem, s, kRegBits, &taken, &c);
+      if (c > best) {
+        best = c;
+        bestR = R;
+        best_taken = taken;
+      }
+    }
+    // pad with the highest unused local bits (keeps the low bits on lanes)
+    for (int b = (int)pa->t - 1; b >= 0 && __builtin_popcountll(bestR) < kRegBits; --b) bestR |= 1ull << b;
+    Phase ph;
+    std::memset(&ph, 0, sizeof(ph));
+    uint32_t k = 0;
+    for (uint32_t b = 0; b < pa->t; ++b)
+      if (bestR >> b & 1) ph.r[k++] = (uint8_t)b;
+    auto pos = [&](uint8_t b) {
+      for (int j = 0; j < kRegBits; ++j)
+        if (ph.r[j] == b) return (uint8_t)j;
+      return (uint8_t)0;
+    };
+    std::vector<GateRef> next;
+    std::vector<DGate> chunk;
+    for (size_t i = 0; i < rem.size(); ++i) {
+      if (!best_taken[i]) {
+        next.push_back(rem[i]);
+        continue;
+      }
+      DGate g = src[rem[i].instr];
+      g.j0 = pos(g.b0);
+      g.j1 = g.type >= GT_CX ? pos(g.b1) : g.j0;
+      chunk.push_back(g);
+    }
+    // phases longer than kPhaseMaxGates are split into consecutive phases on the same bits
+    for (size_t c0 = 0; c0 < chunk.size(); c0 += kPhaseMaxGates) {
+      ph.gate_begin = pa->gate_begin + (uint32_t)out.size();
+      for (size_t c = c0; c < chunk.size() && c < c0 + kPhaseMaxGates; ++c) out.push_back(chunk[c]);
+      ph.gate_count = pa->gate_begin + (uint32_t)out.size() - ph.gate_begin;
+      plan->phases.push_back(ph);
+    }
+    rem.swap(next);
+  }
+  std::copy(out.begin(), out.end(), plan->gates.begin() + pa->gate_begin);
+  pa->phase_count = (uint32_t)plan->phases.size() - pa->phase_begin;
+}
+
 }  // namespace
 
 bool validate_program(const qsv_program_desc& d, std::string* err) {
@@ -242,10 +309,13 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
         g.mat = add_slot(rem[i].instr);
         bool has_param = false;
         for (int k = 0; k < angle_count(in.kind); ++k) has_param |= in.param[k] != QSV_NONE;
-        g.pad = has_param ? (uint8_t)angle_count(in.kind) : 0;  // angles the adjoint differentiates
+        g.nang = has_param ? (uint8_t)angle_count(in.kind) : 0;
+        g.q0 = (uint8_t)in.q0;
+        g.q1 = two_qubit(in.kind) ? (uint8_t)in.q1 : (uint8_t)in.q0;
         plan.gates.push_back(g);
       }
       pa.gate_count = (uint32_t)plan.gates.size() - pa.gate_begin;
+      if (opt.register_phases && pa.t >= (uint32_t)kRegBits) split_phases(&plan, &pa, opt.candidates);
       uint8_t uncond = 1;
       double fl = 0.0;
       for (uint32_t g = pa.gate_begin; g < pa.gate_begin + pa.gate_count; ++g) {
@@ -339,6 +409,19 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
   if (!run.empty()) {
     if (in_site) emit_site_run(run);
     else emit_gate_run(run);
+  }
+  // Matrix slots in plan order: gate i of the plan reads slot i, so a pass's
+  // matrices are contiguous and can be staged without an indirection.
+  {
+    std::vector<GateSrc> src(plan.gates.size());
+    std::vector<uint32_t> instr(plan.gates.size());
+    for (size_t i = 0; i < plan.gates.size(); ++i) {
+      src[i] = plan.gate_src[plan.gates[i].mat];
+      instr[i] = plan.slot_instr[plan.gates[i].mat];
+      plan.gates[i].mat = (uint32_t)i;
+    }
+    plan.gate_src.swap(src);
+    plan.slot_instr.swap(instr);
   }
   // State initialisation: folded into the first pass when the program starts with gates.
   if (!plan.steps.empty() && plan.steps[0].kind == Step::PASS) {

@@ -22,7 +22,8 @@ struct Plan {
   std::vector<PassArgs> passes;
   std::vector<uint8_t> pass_uncond;        // 1: no gate of the pass is guarded
   std::vector<double> pass_flops_per_amp;  // algorithmic flops per amplitude of each pass
-  std::vector<DGate> gates;       // gates of all passes, pass by pass
+  std::vector<DGate> gates;       // gates of all passes, pass by pass (phase order)
+  std::vector<Phase> phases;      // register phases of all passes
   std::vector<SiteArgs> sites;
   std::vector<SiteEvent> events;  // events of all sites, site by site
   std::vector<GateSrc> gate_src;  // one matrix slot per planned gate
@@ -37,6 +38,7 @@ struct PlanOptions {
   uint32_t tile_bits = kTileMaxBits;  // t_max
   uint32_t low_bits = 4;              // tile always holds qubits 0..low_bits-1 (256 B runs)
   uint32_t candidates = 8;            // seeds tried per pass by the greedy tile chooser
+  bool register_phases = true;        // split passes into 4-qubit register phases
 };
 
 // Checks ranges and structure; on failure returns false and sets *err.

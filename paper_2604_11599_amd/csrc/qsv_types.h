@@ -8,7 +8,9 @@ namespace qsv {
 
 constexpr int kMaxQubits = 34;      // 2^34 complex128 = 256 GiB, the HBM ceiling of one MI355X
 constexpr int kTileMaxBits = 12;    // tile = 2^12 complex128 = 64 KiB of LDS per workgroup
-constexpr int kTileThreads = 256;   // workgroup size of the tile pass
+constexpr int kTileThreads = 256;   // workgroup size of the LDS-only tile pass
+constexpr int kRegBits = 4;         // register-blocked pass: 2^4 amplitudes per thread
+constexpr int kPhaseMaxGates = 32;  // gates per register phase (staged in LDS)
 constexpr int kSiteQubits = 4;      // qubits histogrammed per measurement sub-site (16 bins)
 constexpr int kSiteBins = 1 << kSiteQubits;
 constexpr int kMatStride = 8;       // doubles per gate matrix slot (2x2 complex)
@@ -27,10 +29,15 @@ enum GateType : uint8_t {
   GT_SWAP = 6,    // exchange bits b0 and b1
 };
 
-struct DGate {      // 16 bytes
-  uint8_t type, b0, b1, pad;
-  uint32_t mat;     // matrix slot = index of the gate in the program's gate table
-  uint64_t guard;   // active iff (flags & guard) == guard
+struct DGate {      // 32 bytes (one scalar 8-dword load)
+  uint8_t type, b0, b1;  // GateType; tile-local bits of the operands
+  uint8_t nang;          // angles the adjoint differentiates (0 for parameter-free gates)
+  uint8_t j0, j1;        // positions of b0, b1 among the register bits of the gate's phase
+  uint8_t q0, q1;        // global qubits of the operands
+  uint32_t mat;          // matrix slot (= index of the gate in the plan's gate array)
+  uint32_t pad;
+  uint64_t guard;        // active iff (flags & guard) == guard
+  uint64_t pad2;
 };
 
 // Source of a gate matrix: rebuilt on the device from theta at every call.
@@ -39,6 +46,15 @@ struct GateSrc {    // 64 bytes
   uint32_t param[3];
   double scale[3];
   double offset[3];
+};
+
+// A phase of a register-blocked pass: the gates of the phase act only on the
+// 4 tile-local bits r[0..3]; every thread holds the 16 amplitudes that differ
+// in those bits.
+struct Phase {      // 16 bytes
+  uint8_t r[kRegBits];
+  uint32_t gate_begin, gate_count;
+  uint32_t pad;
 };
 
 // A tile pass: every workgroup loads the 2^t amplitudes that share the values
@@ -51,6 +67,7 @@ struct PassArgs {
   uint32_t tiles;                // workgroups per shot = 2^(n - t)
   uint64_t tile_mask;            // global bits covered by the tile
   uint8_t tq[kTileMaxBits];      // global qubit of local bit k (ascending)
+  uint32_t phase_begin, phase_count;  // register-blocked phases (phase_count = 0: LDS-only pass)
 };
 
 // Sequential events of a measurement site, replayed per shot by one thread.

@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.RunOpts) == 40
     assert ctypes.sizeof(_abi.ShotResults) == 40
     assert ctypes.sizeof(_abi.PauliSum) == 24
-    assert ctypes.sizeof(_abi.PlanStats) == 315424
+    assert ctypes.sizeof(_abi.PlanStats) == 315424 + 8 * 65536 + 8
     from paper_2604_11599_amd.lower import INSTR_DTYPE, PRED_DTYPE
     assert INSTR_DTYPE.itemsize == 96 and PRED_DTYPE.itemsize == 24
 
@@ -143,6 +143,12 @@ def _check_plan(src, tile_bits=0):
     for q in range(lp.n_qubits):
         seq = [pos[i] for i in gates if i in pos and q in _qubits_of(lp.instr[i])]
         assert seq == sorted(seq)
+    # register-blocked passes: every gate acts on qubits its phase holds in registers
+    for k, g in enumerate(order):
+        regs = st.gate_regs[k]
+        if lp.n_qubits >= 4:
+            assert bin(regs).count("1") == 4
+            assert all(regs >> q & 1 for q in _qubits_of(lp.instr[g]))
     # every pass's tile holds the qubits of its gates
     k = 0
     for s in range(st.n_steps):
