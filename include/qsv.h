@@ -162,6 +162,10 @@ void qsv_program_free(qsv_program* prog);
 /* ------------------------------------------------------------------------ */
 /* Shots                                                                     */
 /* ------------------------------------------------------------------------ */
+/* QSV_RUN_SHARE_PREFIX: the steps before the first measurement or reset draw no
+   randomness and are identical for every shot; run them once per batch and copy
+   the state to the other shots (shot branching). Results are bit-identical to
+   running every shot in full. */
 enum { QSV_RUN_SHARE_PREFIX = 1u };
 
 typedef struct {
@@ -189,6 +193,30 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
                          uint64_t n_shots, const qsv_run_opts* opts, qsv_shot_results* out);
 
 /* ------------------------------------------------------------------------ */
+/* Batches of requests in one persistent launch                              */
+/* ------------------------------------------------------------------------ */
+/* A request: every shot of one loaded program with its own parameters, Philox
+   key and outputs (sized as for qsv_run_shots; opts.flags and opts.state_out are
+   ignored). qsv_run_batch runs the shots of all requests as work items of one
+   persistent launch: workgroups take items from a queue, so circuits of
+   different widths and trajectories of different lengths (loop exits, taken
+   branches) share the GPU. States of up to 12 qubits stay in LDS for the whole
+   program; states of 13..20 qubits live in a per-workgroup HBM slot; requests
+   with more qubits run through qsv_run_shots after the launch. Every item is
+   computed the same way whatever else is in the batch, so a request's results
+   do not depend on the batch it is part of. Errors: QSV_ERR_ARG for a null or
+   foreign program or missing outputs, QSV_ERR_NOMEM when the slots do not fit. */
+typedef struct {
+  const qsv_program* prog;
+  const double* theta;     /* host [n_params], may be NULL when n_params == 0 */
+  uint64_t n_shots;
+  qsv_run_opts opts;
+  qsv_shot_results out;
+} qsv_request;
+
+qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_reqs);
+
+/* ------------------------------------------------------------------------ */
 /* Expectation values and gradients (unitary programs only)                  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -207,6 +235,40 @@ qsv_status qsv_expval(qsv_context* ctx, const qsv_program* prog, const double* t
 /* As qsv_expval, plus grad[b][k] = dE_b / dtheta_b[k] by the adjoint method. */
 qsv_status qsv_expval_grad(qsv_context* ctx, const qsv_program* prog, const double* theta,
                            uint32_t batch, const qsv_pauli_sum* h, double* energy, double* grad);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of requests                                  */
+/* ------------------------------------------------------------------------ */
+/* A server owns a queue of requests. qsv_server_step runs one scheduling tick:
+   waiting requests are admitted in arrival order while the HBM footprint of
+   the admitted set stays within the budget (footprint of a shots request =
+   its per-tick shot slice x 16 x 2^n bytes, where the slice is shots_per_tick
+   for n <= 16 and shots_per_tick / 2^(n-16) (at least 1) above; of an
+   energy+gradient request 2 x 16 x 2^n bytes); then one slice of every admitted shots request runs in
+   a single persistent launch (qsv_run_batch) and every admitted
+   energy+gradient request is evaluated; requests that finish are retired and
+   their memory is released, so requests that arrive while others run join at
+   the next tick. A shot's results depend only on (program, theta, seed, shot
+   index), never on the other requests. Programs must stay loaded until their
+   requests are fetched. */
+typedef struct qsv_server qsv_server;
+
+qsv_status qsv_server_create(qsv_context* ctx, size_t hbm_budget, uint32_t shots_per_tick, qsv_server** out);
+void qsv_server_destroy(qsv_server* srv);
+/* Shots request: n_shots shots of prog with theta (copied), Philox seed. */
+qsv_status qsv_submit(qsv_server* srv, const qsv_program* prog, const double* theta, uint64_t n_shots,
+                      uint64_t seed, uint64_t* ticket);
+/* Energy + gradient request for one parameter vector (theta and h are copied). */
+qsv_status qsv_submit_expval_grad(qsv_server* srv, const qsv_program* prog, const double* theta,
+                                  const qsv_pauli_sum* h, uint64_t* ticket);
+/* One tick; reports how many requests are admitted (running) and waiting. */
+qsv_status qsv_server_step(qsv_server* srv, uint32_t* n_running, uint32_t* n_waiting);
+/* done = 1 once the request has finished (its results can be fetched). */
+qsv_status qsv_poll(qsv_server* srv, uint64_t ticket, int32_t* done);
+/* Copies a finished request's results (buffers sized as for qsv_run_shots /
+   energy[1] and grad[n_params]) and forgets the request. */
+qsv_status qsv_fetch_shots(qsv_server* srv, uint64_t ticket, qsv_shot_results* out);
+qsv_status qsv_fetch_expval_grad(qsv_server* srv, uint64_t ticket, double* energy, double* grad);
 
 /* ------------------------------------------------------------------------ */
 /* Profiling (contexts created with QSV_FLAG_PROFILE)                        */

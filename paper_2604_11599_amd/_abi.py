@@ -47,6 +47,11 @@ class ShotResults(C.Structure):
                 ("record_prob", C.c_void_p), ("shot_status", C.c_void_p)]
 
 
+class Request(C.Structure):
+    _fields_ = [("prog", C.c_void_p), ("theta", C.c_void_p), ("n_shots", C.c_uint64),
+                ("opts", RunOpts), ("out", ShotResults)]
+
+
 class PauliSum(C.Structure):
     _fields_ = [("n_terms", C.c_uint32), ("reserved", C.c_uint32), ("coeff", C.c_void_p),
                 ("pauli", C.c_void_p)]
@@ -79,11 +84,22 @@ SIGNATURES = {
     "qsv_program_free": (None, [C.c_void_p]),
     "qsv_run_shots": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(RunOpts),
                                   C.POINTER(ShotResults)]),
+    "qsv_run_batch": (C.c_int32, [C.c_void_p, C.POINTER(Request), C.c_uint32]),
     "qsv_expval": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(PauliSum),
                                C.c_void_p]),
     "qsv_expval_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(PauliSum),
                                     C.c_void_p, C.c_void_p]),
     "qsv_plan_inspect": (C.c_int32, [C.POINTER(ProgramDesc), C.c_uint32, C.POINTER(PlanStats)]),
+    "qsv_server_create": (C.c_int32, [C.c_void_p, C.c_size_t, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "qsv_server_destroy": (None, [C.c_void_p]),
+    "qsv_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint64,
+                               C.POINTER(C.c_uint64)]),
+    "qsv_submit_expval_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PauliSum),
+                                           C.POINTER(C.c_uint64)]),
+    "qsv_server_step": (C.c_int32, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]),
+    "qsv_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]),
+    "qsv_fetch_shots": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ShotResults)]),
+    "qsv_fetch_expval_grad": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "qsv_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
     "qsv_profile_reset": (C.c_int32, [C.c_void_p]),
 }

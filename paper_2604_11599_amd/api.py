@@ -84,6 +84,34 @@ class Context:
         """qsv_load_program on OpenQASM 3 text or a LoweredProgram."""
         return Program(self, source)
 
+    def run_batch(self, requests):
+        """qsv_run_batch: every shot of every request in one persistent launch.
+
+        requests: iterable of dicts with keys prog, shots and optionally theta,
+        seed, shot_offset, forced. Returns one ShotResultArrays per request."""
+        reqs = list(requests)
+        arr = (A.Request * max(1, len(reqs)))()
+        keep, results = [], []
+        for i, rq in enumerate(reqs):
+            prog, n = rq["prog"], int(rq["shots"])
+            bufs = prog._result_buffers(n)
+            th = prog._theta(rq.get("theta")) if prog.info.n_params else None
+            f, flen = prog._forced(rq.get("forced"), n)
+            keep += [th, f, bufs]
+            arr[i].prog = prog.handle
+            arr[i].theta = None if th is None else th.ctypes.data
+            arr[i].n_shots = n
+            arr[i].opts = A.RunOpts(int(rq.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF, int(rq.get("shot_offset", 0)),
+                                    _ptr(f), flen, 0, None)
+            arr[i].out = A.ShotResults(*[_ptr(b) for b in bufs])
+            results.append(bufs)
+        self.check(A.lib().qsv_run_batch(self.handle, arr, len(reqs)))
+        out = []
+        for rq, (creg, record, nev, prob, status) in zip(reqs, results):
+            mr = rq["prog"].info.max_events
+            out.append(ShotResultArrays(creg, record[:, :mr], nev, prob, status, None, rq["prog"].lowered.n_clbits))
+        return out
+
 
 class ShotResultArrays:
     def __init__(self, creg, record, n_events, record_prob, shot_status, state, n_clbits):
@@ -137,6 +165,23 @@ class Program:
         elif t.size != p * batch:
             raise ValueError(f"theta must be [{batch}, {p}]")
         return t
+
+    def _result_buffers(self, n_shots):
+        cw = max(1, (self.lowered.n_clbits + 63) // 64)
+        return (np.zeros((n_shots, cw), dtype=np.uint64),
+                np.zeros((n_shots, max(1, self.info.max_events)), dtype=np.uint8),
+                np.zeros(n_shots, dtype=np.uint32), np.zeros(n_shots, dtype=np.float64),
+                np.zeros(n_shots, dtype=np.int32))
+
+    def _forced(self, forced, n_shots):
+        if forced is None:
+            return None, 0
+        f = np.ascontiguousarray(forced, dtype=np.uint8)
+        if f.ndim == 1:
+            f = np.broadcast_to(f, (n_shots, f.size)).copy()
+        if f.shape[0] != n_shots:
+            raise ValueError("forced must have one row per shot")
+        return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
                   share_prefix=False):

@@ -59,6 +59,9 @@ struct qsv_program {
   // device copies of the static plan
   DGate* d_gates = nullptr;
   Phase* d_phases = nullptr;
+  DStep* d_steps = nullptr;
+  PassArgs* d_passes = nullptr;
+  SiteArgs* d_sites = nullptr;
   GateSrc* d_src = nullptr;
   SiteEvent* d_events = nullptr;
   DPred* d_preds = nullptr;
@@ -278,6 +281,13 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(pl.gates, &p->d_gates);
   if (e == hipSuccess) e = upload(pl.phases, &p->d_phases);
+  {
+    std::vector<DStep> ds;
+    for (const Step& st : pl.steps) ds.push_back(DStep{(uint32_t)st.kind, st.index});
+    if (e == hipSuccess) e = upload(ds, &p->d_steps);
+  }
+  if (e == hipSuccess) e = upload(pl.passes, &p->d_passes);
+  if (e == hipSuccess) e = upload(pl.sites, &p->d_sites);
   if (e == hipSuccess) e = upload(pl.gate_src, &p->d_src);
   if (e == hipSuccess) e = upload(pl.events, &p->d_events);
   if (e == hipSuccess) e = upload(dp, &p->d_preds);
@@ -309,7 +319,7 @@ qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) 
 void qsv_program_free(qsv_program* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
-  void* ptrs[] = {p->d_gates, p->d_phases, p->d_src, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
+  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -371,6 +381,15 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   rb.forced_len = opts->forced_len;
   rb.seed = opts->seed;
   std::vector<ShotCtl> hctl(batch);
+  // steps before the first site that draws randomness are identical for every shot
+  size_t prefix_end = 0;
+  if (opts->flags & QSV_RUN_SHARE_PREFIX) {
+    while (prefix_end < pl.steps.size()) {
+      const Step& s = pl.steps[prefix_end];
+      if (s.kind == Step::SITE && pl.sites[s.index].nq > 0) break;
+      ++prefix_end;
+    }
+  }
   for (uint64_t s0 = 0; s0 < n_shots; s0 += batch) {
     const uint32_t bs = (uint32_t)std::min<uint64_t>(batch, n_shots - s0);
     rb.shots = bs;
@@ -378,8 +397,33 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     if (opts->forced_len)
       HIP_TRY(hipMemcpyAsync(d_forced, opts->forced + s0 * opts->forced_len, (size_t)bs * opts->forced_len,
                              hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, bs, st));
-    for (const Step& step : pl.steps) {
+    HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, rb.record, maxrec, bs, st));
+    size_t first = 0;
+    if (prefix_end > 0 && bs > 1) {
+      // shot branching: the prefix runs once (shot 0) and is copied to the other shots
+      RunBuffers r1 = rb;
+      r1.shots = 1;
+      for (size_t k = 0; k < prefix_end; ++k) {
+        const Step& step = pl.steps[k];
+        Prof pr(ctx, st);
+        if (step.kind == Step::INIT) {
+          HIP_TRY(launch_init_state(r1.state, r1.stride, n, 1, st));
+          pr.done(2);
+        } else if (step.kind == Step::PASS) {
+          HIP_TRY(launch_tile_pass(r1, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
+          pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * dim, pl.pass_flops_per_amp[step.index] * dim);
+        } else {
+          HIP_TRY(launch_site(r1, pl.sites[step.index], prog->d_events, prog->d_preds, st));
+          pr.done(1);
+        }
+      }
+      Prof pr(ctx, st);
+      HIP_TRY(launch_copy_branch(rb, n, st));
+      pr.done(2);
+      first = prefix_end;
+    }
+    for (size_t k = first; k < pl.steps.size(); ++k) {
+      const Step& step = pl.steps[k];
       Prof pr(ctx, st);
       if (step.kind == Step::INIT) {
         HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st));
@@ -412,6 +456,143 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       if (out->record_prob) out->record_prob[s0 + s] = hctl[s].record_prob;
       if (out->shot_status) out->shot_status[s0 + s] = hctl[s].status;
     }
+  }
+  return QSV_OK;
+}
+
+qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_reqs) {
+  if (!ctx || (n_reqs && !reqs)) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::vector<uint32_t> pers, big;
+  uint32_t max_stream = 0, cw = 1, rec_max = 1;
+  uint64_t items = 0;
+  for (uint32_t r = 0; r < n_reqs; ++r) {
+    const qsv_request& q = reqs[r];
+    if (!q.prog || q.prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": bad program");
+    if (!q.out.creg) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": creg output is required");
+    if (q.prog->desc.n_params && !q.theta) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": theta is required");
+    if (q.opts.forced_len && !q.opts.forced) return set_err(ctx, QSV_ERR_ARG, "forced_len without forced");
+    const uint32_t n = q.prog->desc.n_qubits;
+    if (q.n_shots == 0) continue;
+    if (n > (uint32_t)kStreamMaxBits) {
+      big.push_back(r);
+      continue;
+    }
+    pers.push_back(r);
+    items += q.n_shots;
+    if (n > (uint32_t)kResidentMaxBits) max_stream = std::max(max_stream, n);
+    cw = std::max<uint32_t>(cw, (q.prog->desc.n_clbits + 63) / 64);
+    rec_max = std::max<uint32_t>(rec_max, q.prog->plan.max_record);
+  }
+  if (items > 0xFFFFFFFFull) return set_err(ctx, QSV_ERR_LIMIT, "too many work items in one batch");
+  hipStream_t st = ctx->stream;
+  if (!pers.empty()) {
+    // widest circuits first: long items start early and short ones fill in
+    std::stable_sort(pers.begin(), pers.end(), [&](uint32_t a, uint32_t b) {
+      return reqs[a].prog->desc.n_qubits > reqs[b].prog->desc.n_qubits;
+    });
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    const uint32_t wgs = (uint32_t)std::min<uint64_t>(items, (uint64_t)cus * 2);
+    const uint64_t slot_amps = max_stream ? (1ull << max_stream) : 1;
+    Scratch scr(ctx);
+    size_t mat_total = 0, theta_total = 0, forced_total = 0;
+    for (uint32_t r : pers) {
+      mat_total += std::max<size_t>(1, reqs[r].prog->plan.gate_src.size()) * kMatStride;
+      theta_total += std::max<uint32_t>(1, reqs[r].prog->desc.n_params);
+      forced_total += reqs[r].opts.forced_len ? reqs[r].n_shots * reqs[r].opts.forced_len : 0;
+    }
+    double *d_mats, *d_theta;
+    uint8_t* d_forced = nullptr;
+    ReqDev* d_reqs;
+    uint32_t *d_item_req, *d_queue;
+    double2* d_scratch;
+    ShotCtl* d_ctl;
+    uint64_t* d_creg;
+    uint8_t* d_rec;
+    HIP_TRY(scr.get(mat_total, &d_mats));
+    HIP_TRY(scr.get(theta_total, &d_theta));
+    if (forced_total) HIP_TRY(scr.get(forced_total, &d_forced));
+    HIP_TRY(scr.get(pers.size(), &d_reqs));
+    HIP_TRY(scr.get(items, &d_item_req));
+    HIP_TRY(scr.get(64, &d_queue));
+    HIP_TRY(scr.get((size_t)wgs * slot_amps, &d_scratch));
+    HIP_TRY(scr.get(items, &d_ctl));
+    HIP_TRY(scr.get(items * cw, &d_creg));
+    HIP_TRY(scr.get(items * rec_max, &d_rec));
+    std::vector<ReqDev> rd(pers.size());
+    std::vector<uint32_t> item_req(items);
+    size_t mo = 0, to = 0, fo = 0;
+    uint32_t ib = 0;
+    for (size_t i = 0; i < pers.size(); ++i) {
+      const qsv_request& q = reqs[pers[i]];
+      const qsv_program* p = q.prog;
+      const uint32_t P = p->desc.n_params, slots = (uint32_t)p->plan.gate_src.size();
+      if (P) HIP_TRY(hipMemcpyAsync(d_theta + to, q.theta, P * 8, hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_bind_matrices(p->d_src, slots, d_theta + to, P, 1, d_mats + mo, nullptr, st));
+      ReqDev& R = rd[i];
+      std::memset(&R, 0, sizeof(R));
+      R.steps = p->d_steps;
+      R.passes = p->d_passes;
+      R.phases = p->d_phases;
+      R.gates = p->d_gates;
+      R.sites = p->d_sites;
+      R.events = p->d_events;
+      R.preds = p->d_preds;
+      R.mats = d_mats + mo;
+      if (q.opts.forced_len) {
+        HIP_TRY(hipMemcpyAsync(d_forced + fo, q.opts.forced, q.n_shots * q.opts.forced_len, hipMemcpyHostToDevice, st));
+        R.forced = d_forced + fo;
+        fo += q.n_shots * q.opts.forced_len;
+      }
+      R.forced_len = q.opts.forced_len;
+      R.seed = q.opts.seed;
+      R.shot_offset = q.opts.shot_offset;
+      R.n = p->desc.n_qubits;
+      R.n_steps = (uint32_t)p->plan.steps.size();
+      R.item_begin = ib;
+      for (uint64_t k = 0; k < q.n_shots; ++k) item_req[ib + k] = (uint32_t)i;
+      ib += (uint32_t)q.n_shots;
+      mo += std::max<size_t>(1, slots) * kMatStride;
+      to += std::max<uint32_t>(1, P);
+    }
+    HIP_TRY(hipMemcpyAsync(d_reqs, rd.data(), rd.size() * sizeof(ReqDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_item_req, item_req.data(), items * 4, hipMemcpyHostToDevice, st));
+    {
+      Prof pr(ctx, st);
+      HIP_TRY(launch_persistent(d_reqs, d_item_req, (uint32_t)items, d_queue, d_scratch, slot_amps, wgs, d_ctl,
+                                d_creg, cw, d_rec, rec_max, st));
+      pr.done(2);
+    }
+    std::vector<ShotCtl> hctl(items);
+    std::vector<uint64_t> hcreg(items * cw);
+    std::vector<uint8_t> hrec(items * rec_max);
+    HIP_TRY(hipMemcpyAsync(hctl.data(), d_ctl, items * sizeof(ShotCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hcreg.data(), d_creg, items * cw * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hrec.data(), d_rec, items * rec_max, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    harvest(ctx);
+    for (size_t i = 0; i < pers.size(); ++i) {
+      const qsv_request& q = reqs[pers[i]];
+      const uint32_t qcw = std::max<uint32_t>(1, (q.prog->desc.n_clbits + 63) / 64);
+      const uint32_t mr = q.prog->plan.max_record;
+      for (uint64_t k = 0; k < q.n_shots; ++k) {
+        const uint64_t it = rd[i].item_begin + k;
+        std::memcpy(q.out.creg + k * qcw, &hcreg[it * cw], qcw * 8);
+        if (q.out.record && mr) std::memcpy(q.out.record + k * mr, &hrec[it * rec_max], mr);
+        if (q.out.n_events) q.out.n_events[k] = hctl[it].n_events;
+        if (q.out.record_prob) q.out.record_prob[k] = hctl[it].record_prob;
+        if (q.out.shot_status) q.out.shot_status[k] = hctl[it].status;
+      }
+    }
+  }
+  for (uint32_t r : big) {
+    qsv_run_opts o = reqs[r].opts;
+    o.state_out = nullptr;
+    qsv_shot_results out = reqs[r].out;
+    qsv_status rc = qsv_run_shots(ctx, reqs[r].prog, reqs[r].theta, reqs[r].n_shots, &o, &out);
+    if (rc != QSV_OK) return rc;
   }
   return QSV_OK;
 }
@@ -514,7 +695,7 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
       HIP_TRY(hipMemcpyAsync(d_theta, theta + b0 * P, (size_t)bs * P * 8,
                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, P, bs, d_mats, d_dmats, st));
-    HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, 1, bs, st));
+    HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, 1, nullptr, 0, bs, st));
     for (const Step& step : pl.steps) {
       Prof pr(ctx, st);
       if (step.kind == Step::INIT) {

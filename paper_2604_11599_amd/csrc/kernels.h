@@ -26,14 +26,21 @@ struct RunBuffers {
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);
-hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots, hipStream_t st);
+hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* record, uint32_t max_record,
+                           uint32_t shots, hipStream_t st);
 hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st);
 hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st);
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
                        const DPred* preds, hipStream_t st);
+hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st);
 hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out,
                               hipStream_t st);
+
+// Persistent interpreter over (request, shot) work items.
+hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint32_t n_items, uint32_t* queue,
+                             double2* scratch, uint64_t slot_amps, uint32_t workgroups, ShotCtl* out_ctl,
+                             uint64_t* out_creg, uint32_t cw, uint8_t* out_rec, uint32_t rec_max, hipStream_t st);
 
 // Expectation values and adjoint gradients over a batch of parameter vectors.
 hipError_t launch_pauli_terms(const double2* psi, uint64_t stride, uint32_t n, uint32_t batch,

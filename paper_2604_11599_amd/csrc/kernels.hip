@@ -180,7 +180,8 @@ hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const doub
 // ---------------------------------------------------------------------------
 // Control blocks and state initialisation
 // ---------------------------------------------------------------------------
-__global__ void k_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots) {
+__global__ void k_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* record, uint32_t max_record,
+                           uint32_t shots) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= shots) return;
   ShotCtl c;
@@ -196,11 +197,15 @@ __global__ void k_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t s
   c.wg_done = 0;
   ctl[s] = c;
   for (uint32_t w = 0; w < cw; ++w) creg[(uint64_t)s * cw + w] = 0;
+  if (record)
+    for (uint32_t w = 0; w < max_record; ++w) record[(uint64_t)s * max_record + w] = 0;
 }
 
-hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint32_t shots, hipStream_t st) {
+hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* record, uint32_t max_record,
+                           uint32_t shots, hipStream_t st) {
   if (!shots) return hipSuccess;
-  hipLaunchKernelGGL(k_init_ctl, dim3((shots + 255) / 256), dim3(256), 0, st, ctl, creg, cw, shots);
+  hipLaunchKernelGGL(k_init_ctl, dim3((shots + 255) / 256), dim3(256), 0, st, ctl, creg, cw, record, max_record,
+                     shots);
   return hipGetLastError();
 }
 
@@ -557,39 +562,73 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask) {
   return r;
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
-    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const DGate* __restrict__ gates,
-    const Phase* __restrict__ phases, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a) {
-  extern __shared__ double2 tile[];
-  const uint32_t shot = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
-  const uint32_t nthr = 1u << (a.t - kRegBits);
-  ShotCtl* c = ctl + shot;
-  if (c->status != 0) return;
-  const uint64_t flags = c->flags, M = c->pend_mask, F = c->frame;
-  const double s = c->pend_scale;
-  const bool pending = M != 0 || s != 1.0;
-  bool any = false;
-  for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, gates[a.gate_begin + i].guard);
-  if (!a.init && !any) return;
-  const uint64_t V = c->pend_val;
-  uint64_t base = 0;
-  {
-    uint32_t k = 0;
-    for (uint32_t q = 0; q < a.n; ++q)
-      if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
+// Runs the register phases of a pass on a tile of T amplitudes staged in LDS
+// (slot swz(l) holds tile-local index l). Threads tid < nthr own 16 amplitudes
+// per phase; every thread of the workgroup reaches the barriers.
+__device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t T, uint32_t tid, uint32_t nthr, uint64_t flags,
+                           const Phase* __restrict__ phases, uint32_t pb, uint32_t pc,
+                           const DGate* __restrict__ gates, const double* __restrict__ mb) {
+  double2 r[kR];
+  for (uint32_t p = 0; p < pc; ++p) {
+    const Phase ph = phases[pb + p];
+    bool act = false;
+    for (uint32_t i = 0; i < ph.gate_count && !act; ++i) act = guard_ok(flags, gates[ph.gate_begin + i].guard);
+    if (!act) continue;
+    if (tid < nthr) {
+      const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
+      const uint32_t lb = pdep32(tid, (T - 1u) & ~(o0 | o1 | o2 | o3));
+#pragma unroll
+      for (int k = 0; k < kR; ++k) {
+        const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
+        r[k] = tile[swz(l)];
+      }
+      // DGate words: [0] type | b0 | b1 | nang | j0 | j1 | q0 | q1, [1] mat | pad, [2] guard;
+      // gate words and matrices are wave-uniform scalar loads, the next gate's
+      // are requested before the current gate is applied
+      const uint64_t* gw = reinterpret_cast<const uint64_t*>(gates + ph.gate_begin);
+      const double* mp = mb + (uint64_t)ph.gate_begin * kMatStride;
+      uint64_t w0n = gw[0], gdn = gw[2];
+      double mn[kMatStride];
+#pragma unroll
+      for (int e = 0; e < kMatStride; ++e) mn[e] = mp[e];
+      for (uint32_t i = 0; i < ph.gate_count; ++i) {
+        const uint64_t w0 = w0n, gd = gdn;
+        double m[kMatStride];
+#pragma unroll
+        for (int e = 0; e < kMatStride; ++e) m[e] = mn[e];
+        if (i + 1 < ph.gate_count) {
+          w0n = gw[(uint64_t)(i + 1) * 4];
+          gdn = gw[(uint64_t)(i + 1) * 4 + 2];
+#pragma unroll
+          for (int e = 0; e < kMatStride; ++e) mn[e] = mp[(uint64_t)(i + 1) * kMatStride + e];
+        }
+        if (!guard_ok(flags, gd)) continue;
+        r_apply(r, (uint8_t)(w0 & 0xFFu), (int)((w0 >> 32) & 0xFFu), (int)((w0 >> 40) & 0xFFu), m);
+      }
+#pragma unroll
+      for (int k = 0; k < kR; ++k) {
+        const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
+        tile[swz(l)] = r[k];
+      }
+    }
+    __syncthreads();
   }
-  double2* st = state + (uint64_t)shot * stride;
-  const uint32_t T = 1u << a.t;
-  // Logical amplitude i is stored at memory index i ^ F (the shot's flip frame):
-  // the workgroup reads and writes one memory tile, gates act on logical indices.
-  // element k of this thread is tile-local index l = tid + k * nthr: its global index is
-  // base | (tid's bits scattered over tq[0..t-5]) | (k's bits scattered over tq[t-4..t-1])
+}
+
+// Tile-local index l = tid + k * 2^(t-4) (k = 0..15) of thread tid: its global
+// index is base | (tid's bits over tq[0..t-5]) | (k's bits over tq[t-4..t-1]).
+// Logical amplitude i is stored at memory index i ^ F (the shot's flip frame),
+// so a workgroup reads and writes one memory tile while gates see logical
+// indices. All 16 loads are issued before the first use.
+__device__ __forceinline__ void load_tile16(double2* __restrict__ tile, const double2* __restrict__ st,
+                                            const PassArgs& a, uint64_t base, uint32_t tid, uint64_t M, uint64_t V,
+                                            uint64_t F, double s, bool pending) {
+  const uint32_t nthr = 1u << (a.t - kRegBits);
   uint64_t gthr = base;
   for (uint32_t b = 0; b + kRegBits < a.t; ++b) gthr |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
   const uint64_t h0 = 1ull << a.tq[a.t - 4], h1 = 1ull << a.tq[a.t - 3], h2 = 1ull << a.tq[a.t - 2],
                  h3 = 1ull << a.tq[a.t - 1];
   double2 r[kR];
-  // all 16 loads are issued before the first use, so each thread keeps 16 requests in flight
   if (a.init) {
 #pragma unroll
     for (int k = 0; k < kR; ++k) {
@@ -615,51 +654,16 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
   }
 #pragma unroll
   for (int k = 0; k < kR; ++k) tile[swz(tid + (uint32_t)k * nthr)] = pending ? cscale(r[k], s) : r[k];
-  __syncthreads();
-  const double* mb = mats + (uint64_t)shot * mat_stride;
-  __syncthreads();
-  for (uint32_t p = 0; p < a.phase_count; ++p) {
-    const Phase ph = phases[a.phase_begin + p];
-    bool act = false;
-    for (uint32_t i = 0; i < ph.gate_count && !act; ++i) act = guard_ok(flags, gates[ph.gate_begin + i].guard);
-    if (!act) continue;
-    const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
-    const uint32_t lb = pdep32(tid, (T - 1u) & ~(o0 | o1 | o2 | o3));
-#pragma unroll
-    for (int k = 0; k < kR; ++k) {
-      const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
-      r[k] = tile[swz(l)];
-    }
-    // gate records and matrices are wave-uniform scalar loads; the next gate's
-    // are requested before the current gate is applied
-    // DGate words: [0] type | b0 | b1 | nang | j0 | j1 | q0 | q1, [1] mat | pad, [2] guard
-    const uint64_t* gw = reinterpret_cast<const uint64_t*>(gates + ph.gate_begin);
-    const double* mp = mb + (uint64_t)ph.gate_begin * kMatStride;
-    uint64_t w0n = gw[0], gdn = gw[2];
-    double mn[kMatStride];
-#pragma unroll
-    for (int e = 0; e < kMatStride; ++e) mn[e] = mp[e];
-    for (uint32_t i = 0; i < ph.gate_count; ++i) {
-      const uint64_t w0 = w0n, gd = gdn;
-      double m[kMatStride];
-#pragma unroll
-      for (int e = 0; e < kMatStride; ++e) m[e] = mn[e];
-      if (i + 1 < ph.gate_count) {
-        w0n = gw[(uint64_t)(i + 1) * 4];
-        gdn = gw[(uint64_t)(i + 1) * 4 + 2];
-#pragma unroll
-        for (int e = 0; e < kMatStride; ++e) mn[e] = mp[(uint64_t)(i + 1) * kMatStride + e];
-      }
-      if (!guard_ok(flags, gd)) continue;
-      r_apply(r, (uint8_t)(w0 & 0xFFu), (int)((w0 >> 32) & 0xFFu), (int)((w0 >> 40) & 0xFFu), m);
-    }
-#pragma unroll
-    for (int k = 0; k < kR; ++k) {
-      const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
-      tile[swz(l)] = r[k];
-    }
-    __syncthreads();
-  }
+}
+
+__device__ __forceinline__ void store_tile16(const double2* __restrict__ tile, double2* __restrict__ st,
+                                             const PassArgs& a, uint64_t base, uint32_t tid, uint64_t F) {
+  const uint32_t nthr = 1u << (a.t - kRegBits);
+  uint64_t gthr = base;
+  for (uint32_t b = 0; b + kRegBits < a.t; ++b) gthr |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
+  const uint64_t h0 = 1ull << a.tq[a.t - 4], h1 = 1ull << a.tq[a.t - 3], h2 = 1ull << a.tq[a.t - 2],
+                 h3 = 1ull << a.tq[a.t - 1];
+  double2 r[kR];
 #pragma unroll
   for (int k = 0; k < kR; ++k) r[k] = tile[swz(tid + (uint32_t)k * nthr)];
 #pragma unroll
@@ -668,6 +672,36 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
                         ((k & 8) ? h3 : 0ull);
     st[gi ^ F] = r[k];
   }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
+    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const DGate* __restrict__ gates,
+    const Phase* __restrict__ phases, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a) {
+  extern __shared__ double2 tile[];
+  const uint32_t shot = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+  const uint32_t nthr = 1u << (a.t - kRegBits);
+  ShotCtl* c = ctl + shot;
+  if (c->status != 0) return;
+  const uint64_t flags = c->flags, M = c->pend_mask, F = c->frame;
+  const double s = c->pend_scale;
+  const bool pending = M != 0 || s != 1.0;
+  bool any = false;
+  for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, gates[a.gate_begin + i].guard);
+  if (!a.init && !any) return;
+  const uint64_t V = c->pend_val;
+  uint64_t base = 0;
+  {
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < a.n; ++q)
+      if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
+  }
+  double2* st = state + (uint64_t)shot * stride;
+  const uint32_t T = 1u << a.t;
+  load_tile16(tile, st, a, base, tid, M, V, F, s, pending);
+  const double* mb = mats + (uint64_t)shot * mat_stride;
+  __syncthreads();
+  run_phases(tile, T, tid, nthr, flags, phases, a.phase_begin, a.phase_count, gates, mb);
+  store_tile16(tile, st, a, base, tid, F);
   if (pending) {
     __syncthreads();
     if (tid == 0) {
@@ -765,29 +799,14 @@ __device__ bool eval_pred(const DPred& p, const uint64_t* creg) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_site_finalize(
-    ShotCtl* __restrict__ ctl, SiteArgs a, const SiteEvent* __restrict__ ev,
-    const DPred* __restrict__ preds, const double* __restrict__ partials, uint32_t pblocks,
-    uint64_t* __restrict__ creg,
-    uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record, const uint8_t* __restrict__ forced,
-    uint32_t forced_len, uint64_t seed, uint64_t shot_base) {
-  __shared__ double part[4][kSiteBins];
-  const uint32_t shot = blockIdx.x, tid = threadIdx.x;
-  ShotCtl* c = ctl + shot;
-  if (a.nq) {
-    const double* pp = partials + (uint64_t)shot * pblocks * kSiteBins;
-    const uint32_t b = tid & (kSiteBins - 1), q = tid / kSiteBins;
-    double acc = 0.0;
-    for (uint32_t k = q; k < a.blocks; k += 4) acc += pp[(uint64_t)k * kSiteBins + b];
-    part[q][b] = acc;
-  }
-  __syncthreads();
-  if (tid != 0 || c->status != 0) return;
-  double bins[kSiteBins];
-  for (int b = 0; b < kSiteBins; ++b) bins[b] = a.nq ? ((part[0][b] + part[1][b]) + part[2][b]) + part[3][b] : 0.0;
-
-  ShotCtl cc = *c;
-  uint64_t* cr = creg + (uint64_t)shot * cw;
+// The sequential events of a measurement site for one shot, given the
+// histogram of |psi|^2 over the site's qubits (logical values, pending collapse
+// applied): Philox draws, outcomes (or forced ones), classical bits, flags,
+// record, trajectory probability; then the site's collapse and flips are
+// composed into the shot's pending collapse and flip frame.
+__device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, const SiteArgs& a, const SiteEvent* __restrict__ ev,
+                            const DPred* __restrict__ preds, uint64_t* cr, uint8_t* rec, uint32_t max_record,
+                            const uint8_t* frow, uint32_t forced_len, uint64_t seed, uint64_t key1) {
   uint32_t rm = 0, rv = 0;  // restriction on the bins (pre-site logical values)
   uint64_t xf = 0;          // flips applied during this site
   const double kZero = 0x1p-60;
@@ -810,15 +829,15 @@ __global__ __launch_bounds__(64) void k_site_finalize(
       for (uint32_t b = 0; b < (uint32_t)kSiteBins; ++b)
         if ((b & rm) == rv) p[((b >> k) & 1u) ^ fq] += bins[b];
       const double norm = p[0] + p[1];
-      const uint64_t word = philox_word(seed, shot_base + shot, cc.n_events);
+      const uint64_t word = philox_word(seed, key1, cc.n_events);
       const double u = (double)(word >> 11) * 0x1p-53;
       cc.n_events++;
       uint32_t o;
-      if (E.op == SE_MEASURE && forced && cc.n_record < forced_len) {
-        o = forced[(uint64_t)shot * forced_len + cc.n_record] ? 1u : 0u;
+      if (E.op == SE_MEASURE && frow && cc.n_record < forced_len) {
+        o = frow[cc.n_record] ? 1u : 0u;
         if (p[o] / norm < kZero) {
           cc.status = QSV_ERR_FORCED_ZERO_PROB;
-          break;
+          return;
         }
       } else {
         o = (u < p[0] / norm) ? 0u : 1u;
@@ -827,7 +846,7 @@ __global__ __launch_bounds__(64) void k_site_finalize(
       rm |= 1u << k;
       rv |= (o ^ fq) << k;
       if (E.op == SE_MEASURE) {
-        if (cc.n_record < max_record) record[(uint64_t)shot * max_record + cc.n_record] = (uint8_t)o;
+        if (cc.n_record < max_record) rec[cc.n_record] = (uint8_t)o;
         cc.n_record++;
         if (E.cbit != 0xFFFFFFFFu) {
           uint64_t bitm = 1ull << (E.cbit & 63);
@@ -838,25 +857,49 @@ __global__ __launch_bounds__(64) void k_site_finalize(
       }
     }
   }
-  if (cc.status == 0) {
-    // compose the site's collapse with the incoming one (all in logical frames)
-    uint64_t R = 0, RV = 0;
-    double mass = 0.0;
-    for (uint32_t k = 0; k < a.nq; ++k)
-      if (rm >> k & 1u) {
-        R |= 1ull << a.q[k];
-        RV |= (uint64_t)((rv >> k) & 1u) << a.q[k];
-      }
-    if (rm) {
-      for (uint32_t b = 0; b < (uint32_t)kSiteBins; ++b)
-        if ((b & rm) == rv) mass += bins[b];
-      cc.pend_scale = cc.pend_scale / sqrt(mass);
+  // compose the site's collapse with the incoming one (all in logical frames)
+  uint64_t R = 0, RV = 0;
+  double mass = 0.0;
+  for (uint32_t k = 0; k < a.nq; ++k)
+    if (rm >> k & 1u) {
+      R |= 1ull << a.q[k];
+      RV |= (uint64_t)((rv >> k) & 1u) << a.q[k];
     }
-    const uint64_t M = cc.pend_mask;
-    cc.pend_val = ((cc.pend_val ^ (xf & M)) & M) | ((RV ^ (xf & R)) & R);
-    cc.pend_mask = M | R;
-    cc.frame ^= xf;
+  if (rm) {
+    for (uint32_t b = 0; b < (uint32_t)kSiteBins; ++b)
+      if ((b & rm) == rv) mass += bins[b];
+    cc.pend_scale = cc.pend_scale / sqrt(mass);
   }
+  const uint64_t M = cc.pend_mask;
+  cc.pend_val = ((cc.pend_val ^ (xf & M)) & M) | ((RV ^ (xf & R)) & R);
+  cc.pend_mask = M | R;
+  cc.frame ^= xf;
+}
+
+__global__ __launch_bounds__(64) void k_site_finalize(
+    ShotCtl* __restrict__ ctl, SiteArgs a, const SiteEvent* __restrict__ ev,
+    const DPred* __restrict__ preds, const double* __restrict__ partials, uint32_t pblocks,
+    uint64_t* __restrict__ creg,
+    uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record, const uint8_t* __restrict__ forced,
+    uint32_t forced_len, uint64_t seed, uint64_t shot_base) {
+  __shared__ double part[4][kSiteBins];
+  const uint32_t shot = blockIdx.x, tid = threadIdx.x;
+  ShotCtl* c = ctl + shot;
+  if (a.nq) {
+    const double* pp = partials + (uint64_t)shot * pblocks * kSiteBins;
+    const uint32_t b = tid & (kSiteBins - 1), q = tid / kSiteBins;
+    double acc = 0.0;
+    for (uint32_t k = q; k < a.blocks; k += 4) acc += pp[(uint64_t)k * kSiteBins + b];
+    part[q][b] = acc;
+  }
+  __syncthreads();
+  if (tid != 0 || c->status != 0) return;
+  double bins[kSiteBins];
+  for (int b = 0; b < kSiteBins; ++b) bins[b] = a.nq ? ((part[0][b] + part[1][b]) + part[2][b]) + part[3][b] : 0.0;
+  ShotCtl cc = *c;
+  site_events(cc, bins, a, ev, preds, creg + (uint64_t)shot * cw, record + (uint64_t)shot * max_record,
+              max_record, forced ? forced + (uint64_t)shot * forced_len : nullptr, forced_len, seed,
+              shot_base + shot);
   *c = cc;
 }
 
@@ -871,6 +914,33 @@ hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent*
   hipLaunchKernelGGL(k_site_finalize, dim3(rb.shots), dim3(64), 0, st, rb.ctl, a, ev, preds, rb.partials,
                      rb.pblocks, rb.creg, rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len, rb.seed,
                      rb.shot_base);
+  return hipGetLastError();
+}
+
+// Shot branching: shots 1..S-1 of a batch take over shot 0's state, control
+// block and classical bits (after a prefix that draws no randomness).
+__global__ void k_copy_branch(double2* __restrict__ state, uint64_t stride, uint64_t dim, uint32_t shots,
+                              ShotCtl* __restrict__ ctl, uint64_t* __restrict__ creg, uint32_t cw) {
+  const uint64_t total = dim * (shots - 1);
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t i = gid; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t s = i / dim + 1, j = i % dim;
+    state[s * stride + j] = state[j];
+  }
+  if (gid > 0 && gid < shots) {
+    ctl[gid] = ctl[0];
+    for (uint32_t w = 0; w < cw; ++w) creg[(uint64_t)gid * cw + w] = creg[w];
+  }
+}
+
+hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st) {
+  if (rb.shots < 2) return hipSuccess;
+  const uint64_t total = (1ull << n) * (rb.shots - 1);
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks * 256 < rb.shots) blocks = (rb.shots + 255) / 256;
+  hipLaunchKernelGGL(k_copy_branch, dim3((uint32_t)blocks), dim3(256), 0, st, rb.state, rb.stride, 1ull << n,
+                     rb.shots, rb.ctl, rb.creg, rb.cw);
   return hipGetLastError();
 }
 
@@ -893,6 +963,219 @@ hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, d
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_materialize, dim3((uint32_t)blocks), dim3(256), 0, st, rb.state, rb.stride, rb.ctl,
                      shot, dim, out);
+  return hipGetLastError();
+}
+
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent interpreter: one launch runs every shot of every request.
+//
+// Workgroups pop work items (request, shot) from an atomic counter until the
+// queue is empty, so trajectories of uneven length (loop exits, taken
+// branches) and circuits of different widths share one launch. A state of
+// n <= 12 qubits stays in LDS from the first gate to the last measurement; a
+// larger one lives in the workgroup's HBM slot and every pass streams it tile
+// by tile. Each item is processed by one workgroup in a fixed order, so its
+// results do not depend on what else is in the batch.
+// ---------------------------------------------------------------------------
+// Deterministic workgroup sum of 16 per-thread bins (wave shuffles, then waves in order).
+__device__ void wg_bins(double (&acc)[kSiteBins], double* red /* [4][16] in LDS */, double* out /* [16] */) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+#pragma unroll
+  for (int b = 0; b < kSiteBins; ++b) {
+    double v = acc[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave * kSiteBins + b] = v;
+  }
+  __syncthreads();
+  if (tid < (uint32_t)kSiteBins) {
+    double v = 0.0;
+    for (uint32_t w = 0; w < blockDim.x / 64u; ++w) v += red[w * kSiteBins + tid];
+    out[tid] = v;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_persistent(
+    const ReqDev* __restrict__ reqs, const uint32_t* __restrict__ item_req, uint32_t n_items,
+    uint32_t* __restrict__ queue, double2* __restrict__ scratch, uint64_t slot_amps, ShotCtl* __restrict__ out_ctl,
+    uint64_t* __restrict__ out_creg, uint32_t cw, uint8_t* __restrict__ out_rec, uint32_t rec_max) {
+  extern __shared__ double2 tile[];
+  __shared__ ShotCtl cs;
+  __shared__ uint32_t item_s;
+  __shared__ double red[4 * kSiteBins];
+  __shared__ double bins[kSiteBins];
+  const uint32_t tid = threadIdx.x;
+  double2* slot = scratch + (uint64_t)blockIdx.x * slot_amps;
+  for (;;) {
+    if (tid == 0) item_s = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t item = item_s;
+    if (item >= n_items) break;  // every workgroup reaches this once the queue is drained
+    const ReqDev R = reqs[item_req[item]];
+    const uint32_t shot = item - R.item_begin, n = R.n;
+    const bool resident = n <= (uint32_t)kResidentMaxBits;
+    uint64_t* cr = out_creg + (uint64_t)item * cw;
+    uint8_t* rec = out_rec + (uint64_t)item * rec_max;
+    for (uint32_t w = tid; w < cw; w += blockDim.x) cr[w] = 0;
+    for (uint32_t w = tid; w < rec_max; w += blockDim.x) rec[w] = 0;
+    if (tid == 0) {
+      ShotCtl c;
+      c.flags = 0;
+      c.pend_mask = 0;
+      c.pend_val = 0;
+      c.frame = 0;
+      c.pend_scale = 1.0;
+      c.record_prob = 1.0;
+      c.n_events = 0;
+      c.n_record = 0;
+      c.status = 0;
+      c.wg_done = 0;
+      cs = c;
+    }
+    __syncthreads();
+    const uint64_t dim = 1ull << n;
+    for (uint32_t k = 0; k < R.n_steps; ++k) {
+      if (cs.status != 0) break;
+      const DStep stp = R.steps[k];
+      const uint64_t flags = cs.flags;
+      if (stp.kind == 0) {  // |0...0>
+        if (resident) {
+          for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) tile[swz(l)] = make_double2(l == 0 ? 1.0 : 0.0, 0.0);
+        } else {
+          for (uint64_t j = tid; j < dim; j += blockDim.x) slot[j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+      } else if (stp.kind == 1) {  // gate pass
+        const PassArgs a = R.passes[stp.index];
+        bool any = a.init != 0;
+        for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, R.gates[a.gate_begin + i].guard);
+        if (!any) continue;
+        if (resident) {
+          if (a.init) {
+            for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) tile[swz(l)] = make_double2(l == 0 ? 1.0 : 0.0, 0.0);
+            __syncthreads();
+          }
+          if (a.phase_count) {
+            run_phases(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
+                       a.phase_count, R.gates, R.mats);
+          } else {
+            // fewer than 4 qubits: one LDS sweep per gate (slots are unswizzled for T < 16)
+            for (uint32_t i = 0; i < a.gate_count; ++i) {
+              const DGate g = R.gates[a.gate_begin + i];
+              if (!guard_ok(flags, g.guard)) continue;
+              tile_apply(tile, a.t, g, R.mats + (uint64_t)g.mat * kMatStride);
+              __syncthreads();
+            }
+          }
+        } else {
+          // stream the HBM slot tile by tile; the pending collapse and frame apply on load
+          const uint64_t M = cs.pend_mask, V = cs.pend_val, F = cs.frame;
+          const double sc = cs.pend_scale;
+          const bool pending = M != 0 || sc != 1.0;
+          const uint32_t T = 1u << a.t, nthr = T >> kRegBits;
+          for (uint32_t w = 0; w < a.tiles; ++w) {
+            uint64_t base = 0;
+            {
+              uint32_t kk = 0;
+              for (uint32_t q = 0; q < n; ++q)
+                if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> kk++) & 1u) << q;
+            }
+            load_tile16(tile, slot, a, base, tid, M, V, F, sc, pending);
+            __syncthreads();
+            run_phases(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
+            store_tile16(tile, slot, a, base, tid, F);
+            __syncthreads();
+          }
+          if (tid == 0) {
+            cs.pend_mask = 0;
+            cs.pend_val = 0;
+            cs.pend_scale = 1.0;
+          }
+          __syncthreads();
+        }
+      } else {  // measurement site
+        const SiteArgs sa = R.sites[stp.index];
+        if (sa.nq) {
+          double acc[kSiteBins];
+#pragma unroll
+          for (int b = 0; b < kSiteBins; ++b) acc[b] = 0.0;
+          const uint64_t M = cs.pend_mask, V = cs.pend_val, F = cs.frame;
+          const double s2 = cs.pend_scale * cs.pend_scale;
+          const uint32_t r = (uint32_t)__popcll(M);
+          const uint64_t nfree = 1ull << (n - r);
+          for (uint64_t j = tid; j < nfree; j += blockDim.x) {
+            uint64_t gi = j;
+            if (M) {
+              uint64_t mm = M;
+              while (mm) {
+                const uint32_t b = __ffsll((long long)mm) - 1;
+                mm &= mm - 1;
+                gi = ins0_64(gi, b);
+              }
+              gi |= V;
+            }
+            const double2 v = resident ? tile[swz((uint32_t)(gi ^ F))] : slot[gi ^ F];
+            const double p = (v.x * v.x + v.y * v.y) * s2;
+            uint32_t bin = 0;
+            for (uint32_t q = 0; q < sa.nq; ++q) bin |= (uint32_t)((gi >> sa.q[q]) & 1ull) << q;
+#pragma unroll
+            for (int b = 0; b < kSiteBins; ++b) acc[b] += (bin == (uint32_t)b) ? p : 0.0;
+          }
+          wg_bins(acc, red, bins);
+        }
+        if (tid == 0) {
+          double hb[kSiteBins];
+          for (int b = 0; b < kSiteBins; ++b) hb[b] = sa.nq ? bins[b] : 0.0;
+          ShotCtl c = cs;
+          site_events(c, hb, sa, R.events, R.preds, cr, rec, rec_max,
+                      R.forced ? R.forced + (uint64_t)shot * R.forced_len : nullptr, R.forced_len, R.seed,
+                      R.shot_offset + shot);
+          cs = c;
+        }
+        __syncthreads();
+        if (resident && (cs.pend_mask != 0 || cs.pend_scale != 1.0 || cs.frame != 0)) {
+          // materialise the collapse and the flips in LDS: psi[i] = cond(i) ? mem[i ^ F] * s : 0
+          const uint64_t M = cs.pend_mask, V = cs.pend_val, F = cs.frame;
+          const double sc = cs.pend_scale;
+          for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) {
+            const uint32_t m = l ^ (uint32_t)F;
+            if (m < l) continue;  // each pair (l, l ^ F) is handled by its smaller index
+            const double2 a0 = tile[swz(l)], a1 = tile[swz(m)];
+            tile[swz(l)] = ((l & M) == V) ? cscale(a1, sc) : make_double2(0.0, 0.0);
+            if (m != l) tile[swz(m)] = ((m & M) == V) ? cscale(a0, sc) : make_double2(0.0, 0.0);
+          }
+          __syncthreads();
+          if (tid == 0) {
+            cs.pend_mask = 0;
+            cs.pend_val = 0;
+            cs.pend_scale = 1.0;
+            cs.frame = 0;
+          }
+          __syncthreads();
+        }
+      }
+    }
+    if (tid == 0) out_ctl[item] = cs;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint32_t n_items, uint32_t* queue,
+                             double2* scratch, uint64_t slot_amps, uint32_t workgroups, ShotCtl* out_ctl,
+                             uint64_t* out_creg, uint32_t cw, uint8_t* out_rec, uint32_t rec_max, hipStream_t st) {
+  if (!n_items) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queue, 1u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = sizeof(double2) << kResidentMaxBits;
+  hipLaunchKernelGGL(k_persistent, dim3(workgroups), dim3(kTileThreads), lds, st, reqs, item_req, n_items, queue,
+                     scratch, slot_amps, out_ctl, out_creg, cw, out_rec, rec_max);
   return hipGetLastError();
 }
 

@@ -116,4 +116,29 @@ struct ShotCtl {
   uint32_t wg_done;      // workgroups of the current pass finished for this shot
 };
 
+// Device copy of a plan step (Step in planner.h).
+struct DStep {
+  uint32_t kind, index;   // 0 init, 1 pass, 2 site
+};
+
+constexpr int kResidentMaxBits = 12;  // persistent kernel keeps states up to 2^12 amplitudes in LDS
+constexpr int kStreamMaxBits = 20;    // larger states (up to 2^20) live in a per-workgroup HBM slot
+
+// One request of a persistent batch: a loaded program, its bound matrices and
+// where its shots' results go. Work item i belongs to the request whose
+// [item_begin, item_begin + shots) range contains it.
+struct ReqDev {
+  const DStep* steps;
+  const PassArgs* passes;
+  const Phase* phases;
+  const DGate* gates;
+  const SiteArgs* sites;
+  const SiteEvent* events;
+  const DPred* preds;
+  const double* mats;
+  const uint8_t* forced;  // [shots][forced_len] or null
+  uint64_t seed, shot_offset;
+  uint32_t n, n_steps, forced_len, item_begin;
+};
+
 }  // namespace qsv

@@ -204,6 +204,16 @@ def test_determinism_and_batch_independence(ctx):
         assert one.record_prob[0] == a.record_prob[k]
 
 
+def test_shared_prefix_is_bit_identical(ctx):
+    for src in (W.c2_program(2, n=14, layers=8), W.c1_program(4), W.c3_program(6, n=13, layers=3)):
+        prog = ctx.load(src)
+        a = prog.run_shots(24, seed=5, state_out=True)
+        b = prog.run_shots(24, seed=5, state_out=True, share_prefix=True)
+        assert np.array_equal(a.creg, b.creg) and np.array_equal(a.record, b.record)
+        assert np.array_equal(a.record_prob, b.record_prob) and np.array_equal(a.n_events, b.n_events)
+        assert np.array_equal(a.state, b.state)
+
+
 # ---------------------------------------------------------------------------
 # Expectation values and gradients
 # ---------------------------------------------------------------------------
