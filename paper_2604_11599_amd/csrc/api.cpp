@@ -647,7 +647,7 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
                (size_t)T * blocks * 8 + P * 16 + 4096;
   if (grad) {
     size_t maxg = 0;
-    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)a.tiles * a.gate_count * 3);
+    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)backward_parts(a) * a.gate_count * 3);
     per += maxg * 8 + (size_t)n_slots * 3 * 8;
   }
   size_t budget = ctx->arena ? ctx->arena_bytes : (free_device_bytes() / 10) * 8;
@@ -678,7 +678,7 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   HIP_TRY(scr.get(chunk, &rb.creg));
   if (grad) {
     size_t maxg = 1;
-    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)a.tiles * a.gate_count * 3);
+    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)backward_parts(a) * a.gate_count * 3);
     HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * 3 * kMatStride, &d_dmats));
     HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * 3, &d_dEda));
     HIP_TRY(scr.get(chunk * maxg, &d_gpart));
@@ -720,9 +720,12 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
         const Step& step = pl.steps[k];
         if (step.kind != Step::PASS) continue;
         const PassArgs& a = pl.passes[step.index];
-        HIP_TRY(launch_backward_pass(rb.state, d_lam, dim, bs, prog->d_gates, d_mats, d_dmats, ms, a, d_gpart, st));
-        HIP_TRY(launch_grad_reduce(d_gpart, a.tiles, a.gate_count, 0, prog->d_gates + a.gate_begin, bs,
+        Prof pr(ctx, st);
+        HIP_TRY(launch_backward_pass(rb.state, d_lam, dim, bs, prog->d_gates, prog->d_phases, d_mats, d_dmats, ms, a,
+                                     d_gpart, st));
+        HIP_TRY(launch_grad_reduce(d_gpart, backward_parts(a), a.gate_count, 0, prog->d_gates + a.gate_begin, bs,
                                    std::max<uint32_t>(n_slots, 1), d_dEda, st));
+        pr.done(2);
       }
       HIP_TRY(launch_grad_chain(d_dEda, std::max<uint32_t>(n_slots, 1), prog->d_csr_off, prog->d_csr_sj,
                                 prog->d_csr_scale, P, bs, d_grad, st));

@@ -54,10 +54,10 @@ hipError_t launch_apply_hamiltonian(const double2* psi, double2* lam, uint64_t s
                                     const uint32_t* ny, const double* coeff, uint32_t n_terms,
                                     hipStream_t st);
 hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uint32_t batch,
-                                const DGate* gates, const double* mats, const double* dmats,
-                                uint64_t mat_stride, const PassArgs& a, double* gpart,
-                                hipStream_t st);
-hipError_t launch_grad_reduce(const double* gpart, uint32_t tiles, uint32_t gate_count,
+                                const DGate* gates, const Phase* phases, const double* mats, const double* dmats,
+                                uint64_t mat_stride, const PassArgs& a, double* gpart, hipStream_t st);
+uint32_t backward_parts(const PassArgs& a);
+hipError_t launch_grad_reduce(const double* gpart, uint32_t parts, uint32_t gate_count,
                               uint32_t slot_begin_of_pass, const DGate* gates, uint32_t batch,
                               uint32_t n_slots, double* dEda, hipStream_t st);
 hipError_t launch_grad_chain(const double* dEda, uint32_t n_slots, const uint32_t* csr_off,
