@@ -15,7 +15,6 @@ bounded sample of the same workload.
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c2|c1|c3]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -53,14 +52,6 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "qsv_types.h"):
-        with open(os.path.join(ROOT, "paper_2604_11599_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(name):
     """HBM bytes per tile-pass launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel source; else None."""
@@ -69,6 +60,7 @@ def traffic_from_profiles(name):
         return None
     with open(path) as f:
         d = json.load(f)
+    from paper_2604_11599_amd.traffic_summary import kernel_hash
     if d.get("kernel_hash") != kernel_hash():
         return None
     return d.get("bytes_per_launch")

@@ -34,7 +34,7 @@ typedef struct {
   uint64_t gate_regs[QSV_PLAN_MAX_GATES];    /* qubits held in registers while the gate runs
                                                 (0: LDS-only pass) */
   uint32_t n_phases;                         /* register phases over all passes */
-  uint32_t reserved2;
+  uint32_t n_dense_phases;                   /* phases applied as one composed 16x16 matrix */
 } qsv_plan_stats;
 
 /* tile_bits = 0 uses the default tile width (12 bits). */

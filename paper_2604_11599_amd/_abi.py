@@ -63,7 +63,7 @@ class PlanStats(C.Structure):
                 ("is_unitary", C.c_uint8), ("init_step", C.c_uint8), ("reserved", C.c_uint8 * 6),
                 ("step_kind", C.c_uint8 * PLAN_MAX_STEPS), ("step_mask", C.c_uint64 * PLAN_MAX_STEPS),
                 ("step_count", C.c_uint32 * PLAN_MAX_STEPS), ("gate_instr", C.c_uint32 * PLAN_MAX_GATES),
-                ("gate_regs", C.c_uint64 * PLAN_MAX_GATES), ("n_phases", C.c_uint32), ("reserved2", C.c_uint32)]
+                ("gate_regs", C.c_uint64 * PLAN_MAX_GATES), ("n_phases", C.c_uint32), ("n_dense_phases", C.c_uint32)]
 
 
 class Profile(C.Structure):
@@ -101,6 +101,7 @@ SIGNATURES = {
     "qsv_fetch_shots": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ShotResults)]),
     "qsv_fetch_expval_grad": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "qsv_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
+    "qsv_diag_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "qsv_profile_reset": (C.c_int32, [C.c_void_p]),
 }
 

@@ -12,6 +12,7 @@
 #include "kernels.h"
 #include "planner.h"
 #include "qsv.h"
+#include "qsv_diag.h"
 #include "qsv_plan.h"
 
 using namespace qsv;
@@ -63,6 +64,7 @@ struct qsv_program {
   PassArgs* d_passes = nullptr;
   SiteArgs* d_sites = nullptr;
   GateSrc* d_src = nullptr;
+  uint32_t* d_dense = nullptr;  // indices of the dense phases
   SiteEvent* d_events = nullptr;
   DPred* d_preds = nullptr;
   uint32_t* d_csr_off = nullptr;
@@ -187,6 +189,10 @@ void harvest(qsv_context* ctx) {
   ctx->ev_used = 0;
 }
 
+// algorithmic HBM bytes per amplitude of a tile pass: read and write of one
+// complex128, or the write alone for the pass that also initialises |0...0>
+double pass_bytes_per_amp(const PassArgs& a) { return a.init ? 16.0 : 32.0; }
+
 size_t free_device_bytes() {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
@@ -289,6 +295,7 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
   if (e == hipSuccess) e = upload(pl.passes, &p->d_passes);
   if (e == hipSuccess) e = upload(pl.sites, &p->d_sites);
   if (e == hipSuccess) e = upload(pl.gate_src, &p->d_src);
+  if (e == hipSuccess) e = upload(pl.dense_phases, &p->d_dense);
   if (e == hipSuccess) e = upload(pl.events, &p->d_events);
   if (e == hipSuccess) e = upload(dp, &p->d_preds);
   if (e == hipSuccess) e = upload(off, &p->d_csr_off);
@@ -319,7 +326,7 @@ qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) 
 void qsv_program_free(qsv_program* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
-  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
+  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -363,6 +370,8 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   if (prog->desc.n_params)
     HIP_TRY(hipMemcpyAsync(d_theta, theta, prog->desc.n_params * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, prog->desc.n_params, 1, d_mats, nullptr, st));
+  HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, 1, 0,
+                               d_mats, st));
   RunBuffers rb{};
   HIP_TRY(scr.get(batch * dim, &rb.state));
   HIP_TRY(scr.get(batch, &rb.ctl));
@@ -411,7 +420,8 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
           pr.done(2);
         } else if (step.kind == Step::PASS) {
           HIP_TRY(launch_tile_pass(r1, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
-          pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * dim, pl.pass_flops_per_amp[step.index] * dim);
+          pr.done(0, pl.pass_uncond[step.index] != 0, pass_bytes_per_amp(pl.passes[step.index]) * dim,
+                  pl.pass_flops_per_amp[step.index] * dim);
         } else {
           HIP_TRY(launch_site(r1, pl.sites[step.index], prog->d_events, prog->d_preds, st));
           pr.done(1);
@@ -431,7 +441,8 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       } else if (step.kind == Step::PASS) {
         HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
         const double amps = (double)dim * bs;
-        pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * amps, pl.pass_flops_per_amp[step.index] * amps);
+        pr.done(0, pl.pass_uncond[step.index] != 0, pass_bytes_per_amp(pl.passes[step.index]) * amps,
+                pl.pass_flops_per_amp[step.index] * amps);
       } else {
         HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, st));
         pr.done(1);
@@ -695,6 +706,8 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
       HIP_TRY(hipMemcpyAsync(d_theta, theta + b0 * P, (size_t)bs * P * 8,
                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, P, bs, d_mats, d_dmats, st));
+    HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, bs,
+                                 ms, d_mats, st));
     HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, 1, nullptr, 0, bs, st));
     for (const Step& step : pl.steps) {
       Prof pr(ctx, st);
@@ -704,7 +717,8 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
       } else if (step.kind == Step::PASS) {
         HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, ms, pl.passes[step.index], st));
         const double amps = (double)dim * bs;
-        pr.done(0, pl.pass_uncond[step.index] != 0, 32.0 * amps, pl.pass_flops_per_amp[step.index] * amps);
+        pr.done(0, pl.pass_uncond[step.index] != 0, pass_bytes_per_amp(pl.passes[step.index]) * amps,
+                pl.pass_flops_per_amp[step.index] * amps);
       }
     }
     if (T) {
@@ -762,6 +776,14 @@ qsv_status qsv_expval_grad(qsv_context* ctx, const qsv_program* prog, const doub
   return expval_impl(ctx, prog, theta, batch, h, energy, grad);
 }
 
+qsv_status qsv_diag_copy(qsv_context* ctx, void* dst, const void* src, size_t bytes) {
+  if (!ctx || !dst || !src || bytes % 16) return set_err(ctx, QSV_ERR_ARG, "bad copy arguments");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_copy(dst, src, bytes, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return QSV_OK;
+}
+
 qsv_status qsv_profile_read(qsv_context* ctx, qsv_profile* out) {
   if (!ctx || !out) return QSV_ERR_ARG;
   if (!ctx->profiling()) return set_err(ctx, QSV_ERR_ARG, "context was created without QSV_FLAG_PROFILE");
@@ -813,6 +835,7 @@ qsv_status qsv_plan_inspect(const qsv_program_desc* desc, uint32_t tile_bits, qs
   // instruction index of every planned gate, in execution order, with its phase's register qubits
   uint32_t g = 0;
   out->n_phases = (uint32_t)pl.phases.size();
+  out->n_dense_phases = (uint32_t)pl.dense_phases.size();
   for (const Step& s : pl.steps) {
     if (s.kind != Step::PASS) continue;
     const PassArgs& a = pl.passes[s.index];

@@ -26,6 +26,8 @@ struct RunBuffers {
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);
+hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint32_t n_dense, const DGate* gates,
+                                uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st);
 hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* record, uint32_t max_record,
                            uint32_t shots, hipStream_t st);
 hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st);
@@ -33,6 +35,7 @@ hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phas
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st);
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
                        const DPred* preds, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
 hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st);
 hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out,
                               hipStream_t st);

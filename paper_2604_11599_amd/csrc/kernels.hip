@@ -550,6 +550,50 @@ __device__ __forceinline__ void r_apply(double2 (&a)[kR], uint8_t type, int j0, 
 #undef QSV_R2
 }
 
+// Composes every dense phase: column c of the phase's complex matrix M is the
+// phase's gate list applied, in order, to the basis vector e_c (one thread per
+// batch element, phase and column); it is written as columns c and 16 + c of
+// the real 32x32 form, in matrix-core fragment order.
+__device__ __forceinline__ uint32_t dense_index(uint32_t i, uint32_t k) {
+  return ((i >> 4) * 8u + (k >> 2)) * 64u + (i & 15u) + 16u * (k & 3u);
+}
+
+__global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t* __restrict__ dense,
+                                uint32_t n_dense, const DGate* __restrict__ gates, uint32_t batch,
+                                uint64_t mat_stride, double* __restrict__ mats) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n_dense * kR * batch) return;
+  const uint32_t c = (uint32_t)(idx % kR);
+  const uint64_t rest = idx / kR;
+  const uint32_t d = (uint32_t)(rest % n_dense), b = (uint32_t)(rest / n_dense);
+  const Phase ph = phases[dense[d]];
+  double* mb = mats + (uint64_t)b * mat_stride;
+  double2 a[kR];
+#pragma unroll
+  for (int k = 0; k < kR; ++k) a[k] = make_double2(k == (int)c ? 1.0 : 0.0, 0.0);
+  for (uint32_t i = 0; i < ph.gate_count; ++i) {
+    const DGate g = gates[ph.gate_begin + i];
+    r_apply(a, g.type, g.j0, g.j1, mb + (uint64_t)g.mat * kMatStride);
+  }
+  double* A = mb + (uint64_t)ph.dense * kMatStride;
+#pragma unroll
+  for (uint32_t r = 0; r < (uint32_t)kR; ++r) {
+    A[dense_index(r, c)] = a[r].x;
+    A[dense_index(16u + r, 16u + c)] = a[r].x;
+    A[dense_index(16u + r, c)] = a[r].y;
+    A[dense_index(r, 16u + c)] = -a[r].y;
+  }
+}
+
+hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint32_t n_dense, const DGate* gates,
+                                uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st) {
+  const uint64_t total = (uint64_t)n_dense * kR * batch;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_compose_dense, dim3((uint32_t)((total + 127) / 128)), dim3(128), 0, st, phases, dense,
+                     n_dense, gates, batch, mat_stride, mats);
+  return hipGetLastError();
+}
+
 // scatter the low bits of x over the set bits of mask (ascending)
 __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask) {
   uint32_t r = 0;
@@ -562,9 +606,56 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask) {
   return r;
 }
 
+typedef double qsv_d4 __attribute__((ext_vector_type(4)));
+
+// One dense phase on the matrix cores, for the 64 amplitude groups of this
+// thread's wave (group g = tile-local indices with the non-register bits set
+// to the bits of g). Y = A X with A the real 32x32 phase matrix and X the 32
+// real components of each group (16 real parts, then 16 imaginary parts);
+// v_mfma_f64_16x16x4f64 takes A[l % 16][l / 16] and B[l / 16][l % 16] from
+// lane l and returns D[4 v + l / 16][l % 16] in its result element v (the
+// double-precision form interleaves the rows). A lane reads the components
+// q + 4 jj (q = lane / 16) of its group in each block of 16 groups and writes
+// back the same components; the wave reads all of a block before it writes any
+// of it, and blocks of different waves are disjoint.
+__device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
+                                                 const Phase& ph, const double* __restrict__ A) {
+  const uint32_t lane = tid & 63u, wbase = tid & ~63u, q = lane >> 4, j = lane & 15u;
+  const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
+  const uint32_t lbmask = (T - 1u) & ~(o0 | o1 | o2 | o3);
+  double af[16];
+#pragma unroll
+  for (int f = 0; f < 16; ++f) af[f] = A[f * 64 + lane];
+  uint32_t cq[4];  // local offsets of components q + 4 k
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t ci = q + 4u * k;
+    cq[k] = ((ci & 1u) ? o0 : 0u) | ((ci & 2u) ? o1 : 0u) | ((ci & 4u) ? o2 : 0u) | ((ci & 8u) ? o3 : 0u);
+  }
+  const uint32_t lbl = pdep32(wbase | j, lbmask);
+#pragma unroll
+  for (uint32_t cb = 0; cb < 4; ++cb) {
+    const uint32_t lb = lbl | pdep32(16u * cb, lbmask);
+    double2 x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = tile[swz(lb | cq[k])];
+    qsv_d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const double bv = kb < 4 ? x[kb].x : x[kb - 4].y;
+      re = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kb], bv, re, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f64_16x16x4f64(af[8 + kb], bv, im, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tile[swz(lb | cq[v])] = make_double2(re[v], im[v]);
+  }
+}
+
 // Runs the register phases of a pass on a tile of T amplitudes staged in LDS
 // (slot swz(l) holds tile-local index l). Threads tid < nthr own 16 amplitudes
 // per phase; every thread of the workgroup reaches the barriers.
+// kDense: apply the composed matrix of dense phases (else always the gate list).
+template <bool kDense>
 __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t T, uint32_t tid, uint32_t nthr, uint64_t flags,
                            const Phase* __restrict__ phases, uint32_t pb, uint32_t pc,
                            const DGate* __restrict__ gates, const double* __restrict__ mb) {
@@ -574,7 +665,9 @@ __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t 
     bool act = false;
     for (uint32_t i = 0; i < ph.gate_count && !act; ++i) act = guard_ok(flags, gates[ph.gate_begin + i].guard);
     if (!act) continue;
-    if (tid < nthr) {
+    if (kDense && ph.dense != kNoDense && nthr >= 64u) {
+      if (tid < nthr) dense_phase_mfma(tile, T, tid, ph, mb + (uint64_t)ph.dense * kMatStride);
+    } else if (tid < nthr) {
       const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
       const uint32_t lb = pdep32(tid, (T - 1u) & ~(o0 | o1 | o2 | o3));
 #pragma unroll
@@ -582,28 +675,30 @@ __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t 
         const uint32_t l = lb | ((k & 1) ? o0 : 0u) | ((k & 2) ? o1 : 0u) | ((k & 4) ? o2 : 0u) | ((k & 8) ? o3 : 0u);
         r[k] = tile[swz(l)];
       }
+      {
       // DGate words: [0] type | b0 | b1 | nang | j0 | j1 | q0 | q1, [1] mat | pad, [2] guard;
       // gate words and matrices are wave-uniform scalar loads, the next gate's
       // are requested before the current gate is applied
       const uint64_t* gw = reinterpret_cast<const uint64_t*>(gates + ph.gate_begin);
       const double* mp = mb + (uint64_t)ph.gate_begin * kMatStride;
       uint64_t w0n = gw[0], gdn = gw[2];
-      double mn[kMatStride];
+      double mn[8];
 #pragma unroll
-      for (int e = 0; e < kMatStride; ++e) mn[e] = mp[e];
+      for (int e = 0; e < 8; ++e) mn[e] = mp[e];
       for (uint32_t i = 0; i < ph.gate_count; ++i) {
         const uint64_t w0 = w0n, gd = gdn;
-        double m[kMatStride];
+        double m[8];
 #pragma unroll
-        for (int e = 0; e < kMatStride; ++e) m[e] = mn[e];
+        for (int e = 0; e < 8; ++e) m[e] = mn[e];
         if (i + 1 < ph.gate_count) {
           w0n = gw[(uint64_t)(i + 1) * 4];
           gdn = gw[(uint64_t)(i + 1) * 4 + 2];
 #pragma unroll
-          for (int e = 0; e < kMatStride; ++e) mn[e] = mp[(uint64_t)(i + 1) * kMatStride + e];
+          for (int e = 0; e < 8; ++e) mn[e] = mp[(uint64_t)(i + 1) * kMatStride + e];
         }
         if (!guard_ok(flags, gd)) continue;
         r_apply(r, (uint8_t)(w0 & 0xFFu), (int)((w0 >> 32) & 0xFFu), (int)((w0 >> 40) & 0xFFu), m);
+      }
       }
 #pragma unroll
       for (int k = 0; k < kR; ++k) {
@@ -700,7 +795,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
   load_tile16(tile, st, a, base, tid, M, V, F, s, pending);
   const double* mb = mats + (uint64_t)shot * mat_stride;
   __syncthreads();
-  run_phases(tile, T, tid, nthr, flags, phases, a.phase_begin, a.phase_count, gates, mb);
+  run_phases<true>(tile, T, tid, nthr, flags, phases, a.phase_begin, a.phase_count, gates, mb);
   store_tile16(tile, st, a, base, tid, F);
   if (pending) {
     __syncthreads();
@@ -944,6 +1039,22 @@ hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st) 
   return hipGetLastError();
 }
 
+// Plain streaming copy (calibration of hardware byte counters).
+__global__ void k_copy(double2* __restrict__ dst, const double2* __restrict__ src, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st) {
+  const uint64_t n = bytes / 16;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (!blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, st, static_cast<double2*>(dst),
+                     static_cast<const double2*>(src), n);
+  return hipGetLastError();
+}
+
 // The logical state of one shot: psi[i] = cond(i) ? mem[i ^ frame] * scale : 0.
 __global__ void k_materialize(const double2* __restrict__ state, uint64_t stride, const ShotCtl* ctl,
                               uint32_t shot, uint64_t dim, double2* __restrict__ out) {
@@ -1062,7 +1173,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             __syncthreads();
           }
           if (a.phase_count) {
-            run_phases(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
+            run_phases<false>(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
                        a.phase_count, R.gates, R.mats);
           } else {
             // fewer than 4 qubits: one LDS sweep per gate (slots are unswizzled for T < 16)
@@ -1088,7 +1199,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             }
             load_tile16(tile, slot, a, base, tid, M, V, F, sc, pending);
             __syncthreads();
-            run_phases(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
+            run_phases<false>(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
             store_tile16(tile, slot, a, base, tid, F);
             __syncthreads();
           }
@@ -1557,7 +1668,7 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_r(
       const DGate g = gates[gi];
       const double* m = mb + (uint64_t)g.mat * kMatStride;
       // U^dag: conjugate transpose of the 2x2 (the phase of a controlled phase is conjugated)
-      double md[kMatStride] = {m[0], -m[1], m[4], -m[5], m[2], -m[3], m[6], -m[7]};
+      double md[8] = {m[0], -m[1], m[4], -m[5], m[2], -m[3], m[6], -m[7]};
       r_apply(x, g.type, g.j0, g.j1, md);
       for (uint32_t j = 0; j < g.nang; ++j) {
         const M2 d = load_m2(db + (uint64_t)g.mat * 3 * kMatStride + j * kMatStride, 0);

@@ -35,6 +35,17 @@ bool two_qubit(uint32_t kind) { return kind >= QSV_G_CX && kind < QSV_G_COUNT; }
 // Algorithmic flops per amplitude of a gate as applied in a tile: a dense 2x2
 // complex matrix-vector product costs 2 complex multiplies (6 flops each) and
 // one complex add (2) per output amplitude.
+// Relative cost of applying a gate from the gate list of a register phase, in
+// units of one dense 2x2 gate (8 FMA per amplitude plus dispatch); a dense
+// 16x16 phase product (64 FMA per amplitude, no dispatch) costs about 5.5.
+double gate_dispatch_cost(GateType t) {
+  switch (t) {
+    case GT_DENSE1: case GT_CTRL1: return 1.0;
+    case GT_DIAG1: return 0.8;
+    default: return 0.65;
+  }
+}
+
 double gate_flops_per_amp(GateType t) {
   switch (t) {
     case GT_DENSE1: return 14.0;
@@ -315,13 +326,13 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
         plan.gates.push_back(g);
       }
       pa.gate_count = (uint32_t)plan.gates.size() - pa.gate_begin;
-      if (opt.register_phases && pa.t >= (uint32_t)kRegBits) split_phases(&plan, &pa, opt.candidates);
       uint8_t uncond = 1;
       double fl = 0.0;
       for (uint32_t g = pa.gate_begin; g < pa.gate_begin + pa.gate_count; ++g) {
         if (plan.gates[g].guard) uncond = 0;
         fl += gate_flops_per_amp((GateType)plan.gates[g].type);
       }
+      if (opt.register_phases && pa.t >= (uint32_t)kRegBits) split_phases(&plan, &pa, opt.candidates);
       plan.steps.push_back({Step::PASS, (uint32_t)plan.passes.size()});
       plan.passes.push_back(pa);
       plan.pass_uncond.push_back(uncond);
@@ -422,6 +433,37 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
     }
     plan.gate_src.swap(src);
     plan.slot_instr.swap(instr);
+  }
+  // Dense phases: an unguarded phase (of a pass with full-wave tiles) whose
+  // gates would cost more than one dense 16x16 product gets its composed
+  // matrix in kDenseSlots consecutive slots after the gate slots (composed on
+  // the device after the gate matrices are bound); the forward pass applies it
+  // instead of the gate list.
+  for (Phase& ph : plan.phases) ph.dense = kNoDense;
+  std::vector<uint8_t> dense_ok(plan.phases.size(), 0);
+  for (const PassArgs& pa : plan.passes)
+    if (pa.t >= kDenseMinTileBits)
+      for (uint32_t p = pa.phase_begin; p < pa.phase_begin + pa.phase_count; ++p) dense_ok[p] = 1;
+  for (uint32_t p = 0; p < plan.phases.size(); ++p) {
+    Phase& ph = plan.phases[p];
+    if (opt.dense_min_cost <= 0.0 || !dense_ok[p]) continue;
+    double cost = 0.0;
+    bool guarded = false;
+    for (uint32_t g = ph.gate_begin; g < ph.gate_begin + ph.gate_count; ++g) {
+      guarded |= plan.gates[g].guard != 0;
+      cost += gate_dispatch_cost((GateType)plan.gates[g].type);
+    }
+    if (guarded || cost < opt.dense_min_cost) continue;
+    ph.dense = (uint32_t)plan.gate_src.size();
+    GateSrc id;
+    std::memset(&id, 0, sizeof(id));
+    id.kind = QSV_G_ID;
+    for (int k = 0; k < 3; ++k) id.param[k] = QSV_NONE;
+    for (int k = 0; k < kDenseSlots; ++k) {
+      plan.gate_src.push_back(id);
+      plan.slot_instr.push_back(UINT32_MAX);
+    }
+    plan.dense_phases.push_back(p);
   }
   // State initialisation: folded into the first pass when the program starts with gates.
   if (!plan.steps.empty() && plan.steps[0].kind == Step::PASS) {

@@ -28,17 +28,23 @@ struct Plan {
   std::vector<SiteEvent> events;  // events of all sites, site by site
   std::vector<GateSrc> gate_src;  // one matrix slot per planned gate
   std::vector<uint32_t> slot_instr;  // instruction index of each matrix slot
+  std::vector<uint32_t> dense_phases;  // phases applied as one composed 16x16 matrix
   uint32_t max_record = 0;        // measure instructions in the stream
   uint32_t max_events = 0;        // measure + reset instructions
   bool unitary = true;
   double pass_bytes_per_amp = 32.0;  // HBM bytes per amplitude per pass (read + write)
 };
 
+#ifndef QSV_DENSE_MIN_COST
+#define QSV_DENSE_MIN_COST 5.5
+#endif
+
 struct PlanOptions {
   uint32_t tile_bits = kTileMaxBits;  // t_max
   uint32_t low_bits = 4;              // tile always holds qubits 0..low_bits-1 (256 B runs)
   uint32_t candidates = 8;            // seeds tried per pass by the greedy tile chooser
   bool register_phases = true;        // split passes into 4-qubit register phases
+  double dense_min_cost = QSV_DENSE_MIN_COST;        // compose a phase into a 16x16 matrix from this gate cost on (0: never)
 };
 
 // Checks ranges and structure; on failure returns false and sets *err.

@@ -13,7 +13,7 @@ constexpr int kRegBits = 4;         // register-blocked pass: 2^4 amplitudes per
 constexpr int kPhaseMaxGates = 32;  // gates per register phase (staged in LDS)
 constexpr int kSiteQubits = 4;      // qubits histogrammed per measurement sub-site (16 bins)
 constexpr int kSiteBins = 1 << kSiteQubits;
-constexpr int kMatStride = 8;       // doubles per gate matrix slot (2x2 complex)
+constexpr int kMatStride = 8;       // doubles per gate matrix slot (2x2 complex, row-major re, im)
 constexpr int kRedThreads = 256;    // workgroup size of the probability reduction
 constexpr int kRedMaxBlocks = 1024; // reduction workgroups per shot (upper bound)
 
@@ -50,11 +50,20 @@ struct GateSrc {    // 64 bytes
 
 // A phase of a register-blocked pass: the gates of the phase act only on the
 // 4 tile-local bits r[0..3]; every thread holds the 16 amplitudes that differ
-// in those bits.
+// in those bits (register k <-> local index with bit j of k on bit r[j]).
+// A dense phase also has its gates' product M (16x16 complex) stored as the
+// real 32x32 matrix [[Re M, -Im M], [Im M, Re M]] in matrix-core fragment
+// order: element (i, k) at double ((i / 16) * 8 + k / 4) * 64 + i % 16 + 16 (k % 4),
+// in kDenseSlots consecutive matrix slots from slot `dense`; the forward pass
+// applies it on the matrix cores instead of the gate list.
+constexpr uint32_t kNoDense = 0xFFFFFFFFu;
+constexpr int kDenseDoubles = 32 * 32;
+constexpr int kDenseSlots = kDenseDoubles / kMatStride;
+constexpr uint32_t kDenseMinTileBits = 10;  // full 64-lane waves of amplitude groups
 struct Phase {      // 16 bytes
   uint8_t r[kRegBits];
   uint32_t gate_begin, gate_count;
-  uint32_t pad;
+  uint32_t dense;   // first matrix slot of the composed matrix, or kNoDense
 };
 
 // A tile pass: every workgroup loads the 2^t amplitudes that share the values

@@ -1,0 +1,43 @@
+"""Workload for the hardware byte-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE).
+
+Runs, in one process: one plain device copy of 4 GiB (qsv_diag_copy, the
+calibration: it reads and writes exactly 4 GiB), then one step of the 28-qubit
+benchmark workload (16 shots) with the same launch configuration as bench.py.
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- python3 -m paper_2604_11599_amd.traffic_probe
+"""
+import ctypes as C
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+COPY_BYTES = 4 << 30
+
+
+def main():
+    import torch
+
+    import workloads as W
+    from paper_2604_11599_amd import Context
+    from paper_2604_11599_amd import _abi as A
+    from paper_2604_11599_amd.traffic_summary import kernel_hash
+    print(f"kernel_hash={kernel_hash()}", flush=True)
+    ctx = Context(0)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ctx.check(A.lib().qsv_diag_copy(ctx.handle, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                                    COPY_BYTES))
+    del src, dst
+    torch.cuda.empty_cache()
+    print("copy done", flush=True)
+    prog = ctx.load(W.c2_program(seed=2, n=28, layers=40))
+    prog.run_shots(16, seed=0)
+    print("step done", flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,112 @@
+"""Turns the two hardware byte-counter runs of traffic_probe.py into HBM bytes per
+tile-pass launch.
+
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each scaled by the factor that
+maps the same counter on a plain device copy of known size (4 GiB read, 4 GiB
+written) to its true byte count. Writes profiles/tile_pass_c2_traffic.json (read
+by bench.py while the kernel source hash matches) and a short text summary.
+
+    python -m paper_2604_11599_amd.traffic_summary FETCH_CSV WRITE_CSV PROBE_LOG [COMMAND]
+
+PROBE_LOG is the output of the probe run; its kernel_hash line names the kernel
+source the counters were taken on.
+"""
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 4 << 30
+PASS_KERNEL = "k_tile_pass"
+COPY_KERNEL = "k_copy"
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "qsv_types.h"):
+        with open(os.path.join(ROOT, "paper_2604_11599_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name):
+    return name.split("(")[0].split("<")[0].strip().split("::")[-1]
+
+
+def read_counter(path, counter):
+    """[(dispatch id, kernel name, KiB)] in dispatch order."""
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            key = {k.lower(): k for k in r}
+            if r[key["counter_name"]] != counter:
+                continue
+            rows.append((int(r[key["dispatch_id"]]), _short(r[key["kernel_name"]]), float(r[key["counter_value"]])))
+    rows.sort()
+    return rows
+
+
+def probe_hash(log):
+    with open(log) as f:
+        for line in f:
+            if line.startswith("kernel_hash="):
+                return line.strip().split("=", 1)[1]
+    raise SystemExit("no kernel_hash line in the probe log")
+
+
+def summarize(fetch_csv, write_csv, khash):
+    fe = read_counter(fetch_csv, "FETCH_SIZE")
+    wr = read_counter(write_csv, "WRITE_SIZE")
+    cf = [v for _, k, v in fe if k == COPY_KERNEL]
+    cw = [v for _, k, v in wr if k == COPY_KERNEL]
+    if len(cf) != 1 or len(cw) != 1:
+        raise SystemExit("expected exactly one calibration copy per run")
+    f_fac = COPY_BYTES / (cf[0] * 1024.0)
+    w_fac = COPY_BYTES / (cw[0] * 1024.0)
+    pf = [v for _, k, v in fe if k.startswith(PASS_KERNEL)]
+    pw = [v for _, k, v in wr if k.startswith(PASS_KERNEL)]
+    if not pf or len(pf) != len(pw):
+        raise SystemExit("tile-pass dispatch counts differ between the two runs")
+    per = [a * 1024.0 * f_fac + b * 1024.0 * w_fac for a, b in zip(pf, pw)]
+    return {
+        "kernel_hash": khash,
+        "workload": "28 qubits, 40 brickwork layers, 16 shots in one launch per pass",
+        "launches": len(per),
+        "bytes_per_launch": sum(per) / len(per),
+        "fetch_bytes_per_launch": sum(pf) * 1024.0 * f_fac / len(pf),
+        "write_bytes_per_launch": sum(pw) * 1024.0 * w_fac / len(pw),
+        "calibration": {"copy_bytes_each_way": COPY_BYTES, "copy_fetch_kib": cf[0], "copy_write_kib": cw[0],
+                        "fetch_factor": f_fac, "write_factor": w_fac},
+        "per_launch_min": min(per), "per_launch_max": max(per),
+    }
+
+
+def main():
+    fetch_csv, write_csv, log = sys.argv[1], sys.argv[2], sys.argv[3]
+    cmd = sys.argv[4] if len(sys.argv) > 4 else ""
+    d = summarize(fetch_csv, write_csv, probe_hash(log))
+    d["command"] = cmd
+    out = os.path.join(ROOT, "profiles", "tile_pass_c2_traffic.json")
+    with open(out, "w") as f:
+        json.dump(d, f, indent=1)
+    amps = 16 * 2 ** 28
+    with open(os.path.join(ROOT, "profiles", "tile_pass_c2_28q_traffic.txt"), "w") as f:
+        f.write("HBM traffic of the tile pass, 28 qubits x 16 shots per launch (rocprofv3 --pmc)\n")
+        f.write(f"command: {cmd}\n")
+        f.write(f"kernel source hash: {d['kernel_hash']}\n")
+        c = d["calibration"]
+        f.write(f"calibration copy (4 GiB each way): FETCH_SIZE {c['copy_fetch_kib']:.0f} KiB "
+                f"(factor {c['fetch_factor']:.4f}), WRITE_SIZE {c['copy_write_kib']:.0f} KiB "
+                f"(factor {c['write_factor']:.4f})\n")
+        f.write(f"tile-pass launches: {d['launches']}\n")
+        f.write(f"scaled bytes per launch: fetch {d['fetch_bytes_per_launch']:.4e}, write "
+                f"{d['write_bytes_per_launch']:.4e}, total {d['bytes_per_launch']:.4e} "
+                f"(min {d['per_launch_min']:.4e}, max {d['per_launch_max']:.4e})\n")
+        f.write(f"per amplitude: {d['bytes_per_launch'] / amps:.2f} B (read + write of complex128 is 32 B)\n")
+    print(json.dumps(d))
+
+
+if __name__ == "__main__":
+    main()

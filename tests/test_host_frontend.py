@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # ---------------------------------------------------------------------------
 def _declared_functions():
     names = set()
-    for h in ("qsv.h", "qsv_plan.h"):
+    for h in ("qsv.h", "qsv_plan.h", "qsv_diag.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         for m in re.finditer(r"\b(qsv_[a-z_]+)\s*\(", text):
@@ -171,6 +171,8 @@ def test_plan_invariants_random(seed):
 def test_plan_of_configs():
     st = _check_plan(W.c2_program(2, n=28, layers=40))
     assert st.n_passes <= 60
+    # most brickwork phases are dense enough to run as one composed 16x16 product
+    assert 0 < st.n_dense_phases <= st.n_phases and st.n_dense_phases >= st.n_phases // 2
     st = _check_plan(W.c1_program(1))
     # one pass per gate run: the whole 10-qubit state is one tile
     assert st.n_passes == 4 and st.init_step == 0
