@@ -20,6 +20,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "qsv.h"
 
@@ -324,6 +326,25 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
 
 __device__ __forceinline__ bool guard_ok(uint64_t flags, uint64_t guard) { return (flags & guard) == guard; }
 
+// Reads through the constant address space: wave-uniform values that the
+// kernel reading them does not write become scalar loads, which keep the
+// vector-memory counter free for the loads that overlap the arithmetic.
+#define QSV_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const QSV_CONST T* cst(const T* p) {
+  return (const QSV_CONST T*)p;
+}
+
+__device__ __forceinline__ Phase load_phase(const Phase* p) {
+  static_assert(sizeof(Phase) == 16, "Phase is two 8-byte words");
+  const QSV_CONST uint64_t* w = (const QSV_CONST uint64_t*)p;
+  const uint64_t w0 = w[0], w1 = w[1];
+  Phase ph;
+  __builtin_memcpy(&ph, &w0, 8);
+  __builtin_memcpy(reinterpret_cast<char*>(&ph) + 8, &w1, 8);
+  return ph;
+}
+
 // Global index of tile-local element l.
 __device__ __forceinline__ uint64_t local_to_global(uint32_t l, const PassArgs& a) {
   uint64_t g = 0;
@@ -394,17 +415,64 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
   }
 }
 
-__global__ void k_tile_pass_r(double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
+template <bool kDenseOnly>
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
                               const DGate* __restrict__ gates, const Phase* __restrict__ phases,
-                              const double* __restrict__ mats, uint64_t mat_stride, PassArgs a);
+                              const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots);
+
+// Workgroups of the register tile pass (tile of 2^t amplitudes, `lds` bytes of
+// LDS: the tile and up to kLdsDensePhases staged matrices) that the device
+// holds at once, per device, variant and LDS size (cached).
+template <bool kDenseOnly>
+hipError_t resident_grid(uint32_t t, size_t lds, uint32_t* out) {
+  static uint32_t cache[64][kTileMaxBits + 1][kLdsDensePhases + 1] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64 || t > (uint32_t)kTileMaxBits || t < (uint32_t)kRegBits) return hipErrorInvalidValue;
+  const size_t tile_bytes = sizeof(double2) << t, mat_bytes = 256u * sizeof(double2);
+  if (lds < tile_bytes || (lds - tile_bytes) % mat_bytes || (lds - tile_bytes) / mat_bytes > kLdsDensePhases)
+    return hipErrorInvalidValue;
+  uint32_t& slot = cache[dev][t][(lds - tile_bytes) / mat_bytes];
+  if (!slot) {
+    const size_t max_lds = (sizeof(double2) << kTileMaxBits) + kLdsDensePhases * mat_bytes;
+    e = hipFuncSetAttribute((const void*)k_tile_pass_r<kDenseOnly>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)max_lds);
+    if (e != hipSuccess) return e;
+    int cus = 0, per = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tile_pass_r<kDenseOnly>,
+                                                     1 << (t - kRegBits), lds);
+    if (e != hipSuccess) return e;
+    slot = (uint32_t)std::max(1, cus) * (uint32_t)std::max(1, per);
+  }
+  *out = slot;
+  return hipSuccess;
+}
 
 hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
   dim3 grid(a.tiles, rb.shots);
   size_t lds = (size_t)sizeof(double2) << a.t;
   if (a.phase_count) {
-    hipLaunchKernelGGL(k_tile_pass_r, grid, dim3(1u << (a.t - kRegBits)), lds, st, rb.state, rb.stride, rb.ctl,
-                       gates, phases, mats, mat_stride, a);
+    const uint64_t total = (uint64_t)a.tiles * rb.shots;
+    // the dense-only variant stages the pass's matrices once per workgroup,
+    // so it runs where every shot of the launch shares them
+    const bool dense_only = a.all_dense && a.t >= kDenseMinTileBits && a.phase_count <= kLdsDensePhases &&
+                            mat_stride == 0;
+    if (dense_only) lds += (size_t)a.phase_count * 256u * sizeof(double2);
+    uint32_t g = 0;
+    hipError_t e = dense_only ? resident_grid<true>(a.t, lds, &g) : resident_grid<false>(a.t, lds, &g);
+    if (e != hipSuccess) return e;
+    if ((uint64_t)g > total) g = (uint32_t)total;
+    if (!g) return hipSuccess;
+    if (dense_only)
+      hipLaunchKernelGGL(k_tile_pass_r<true>, dim3(g), dim3(1u << (a.t - kRegBits)), lds, st, rb.state, rb.stride,
+                         rb.ctl, gates, phases, mats, mat_stride, a, rb.shots);
+    else
+      hipLaunchKernelGGL(k_tile_pass_r<false>, dim3(g), dim3(1u << (a.t - kRegBits)), lds, st, rb.state,
+                         rb.stride, rb.ctl, gates, phases, mats, mat_stride, a, rb.shots);
   } else {
     hipLaunchKernelGGL(k_tile_pass, grid, dim3(kTileThreads), lds, st, rb.state, rb.stride, rb.ctl, gates,
                        mats, mat_stride, a);
@@ -552,11 +620,8 @@ __device__ __forceinline__ void r_apply(double2 (&a)[kR], uint8_t type, int j0, 
 
 // Composes every dense phase: column c of the phase's complex matrix M is the
 // phase's gate list applied, in order, to the basis vector e_c (one thread per
-// batch element, phase and column); it is written as columns c and 16 + c of
-// the real 32x32 form, in matrix-core fragment order.
-__device__ __forceinline__ uint32_t dense_index(uint32_t i, uint32_t k) {
-  return ((i >> 4) * 8u + (k >> 2)) * 64u + (i & 15u) + 16u * (k & 3u);
-}
+// batch element, phase and column), stored in matrix-core operand order.
+__device__ __forceinline__ uint32_t dense_pos(uint32_t i, uint32_t c) { return (c >> 2) * 64u + i + 16u * (c & 3u); }
 
 __global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t* __restrict__ dense,
                                 uint32_t n_dense, const DGate* __restrict__ gates, uint32_t batch,
@@ -575,14 +640,9 @@ __global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t
     const DGate g = gates[ph.gate_begin + i];
     r_apply(a, g.type, g.j0, g.j1, mb + (uint64_t)g.mat * kMatStride);
   }
-  double* A = mb + (uint64_t)ph.dense * kMatStride;
+  double2* A = reinterpret_cast<double2*>(mb + (uint64_t)ph.dense * kMatStride);
 #pragma unroll
-  for (uint32_t r = 0; r < (uint32_t)kR; ++r) {
-    A[dense_index(r, c)] = a[r].x;
-    A[dense_index(16u + r, 16u + c)] = a[r].x;
-    A[dense_index(16u + r, c)] = a[r].y;
-    A[dense_index(r, 16u + c)] = -a[r].y;
-  }
+  for (uint32_t r = 0; r < (uint32_t)kR; ++r) A[dense_pos(r, c)] = a[r];
 }
 
 hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint32_t n_dense, const DGate* gates,
@@ -610,22 +670,31 @@ typedef double qsv_d4 __attribute__((ext_vector_type(4)));
 
 // One dense phase on the matrix cores, for the 64 amplitude groups of this
 // thread's wave (group g = tile-local indices with the non-register bits set
-// to the bits of g). Y = A X with A the real 32x32 phase matrix and X the 32
-// real components of each group (16 real parts, then 16 imaginary parts);
-// v_mfma_f64_16x16x4f64 takes A[l % 16][l / 16] and B[l / 16][l % 16] from
-// lane l and returns D[4 v + l / 16][l % 16] in its result element v (the
-// double-precision form interleaves the rows). A lane reads the components
-// q + 4 jj (q = lane / 16) of its group in each block of 16 groups and writes
-// back the same components; the wave reads all of a block before it writes any
-// of it, and blocks of different waves are disjoint.
+// to the bits of g). With M = A + iB and a block of 16 groups as X + iY (16
+// components x 16 groups), the product is formed from three real 16x16
+// products, P1 = A X, P2 = B Y, P3 = (A + B)(X + Y): real part P1 - P2,
+// imaginary part P3 - P1 - P2 (three real multiplications per complex one
+// instead of four). Each real product is 4 v_mfma_f64_16x16x4f64; that
+// instruction takes A[l % 16][l / 16] and B[l / 16][l % 16] from lane l and
+// returns D[4 v + l / 16][l % 16] in its result element v (the
+// double-precision form interleaves the rows). So lane l needs M[l % 16][4 kb +
+// l / 16] (kb = 0..3: the complex values at Mc[kb * 64 + l]), reads the
+// components q + 4 kb (q = l / 16) of its group in each block and writes back
+// the same components. The wave reads all of a block before it writes any of
+// it, and blocks of different waves are disjoint.
 __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
-                                                 const Phase& ph, const double* __restrict__ A) {
+                                                 const Phase& ph, const double2* __restrict__ Mc) {
   const uint32_t lane = tid & 63u, wbase = tid & ~63u, q = lane >> 4, j = lane & 15u;
   const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
   const uint32_t lbmask = (T - 1u) & ~(o0 | o1 | o2 | o3);
-  double af[16];
+  double fa[4], fb[4], fs[4];  // fragments of A, B and A + B
 #pragma unroll
-  for (int f = 0; f < 16; ++f) af[f] = A[f * 64 + lane];
+  for (int kb = 0; kb < 4; ++kb) {
+    const double2 m = Mc[kb * 64 + (int)lane];
+    fa[kb] = m.x;
+    fb[kb] = m.y;
+    fs[kb] = m.x + m.y;
+  }
   uint32_t cq[4];  // local offsets of components q + 4 k
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
@@ -639,35 +708,46 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
     double2 x[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[k] = tile[swz(lb | cq[k])];
-    qsv_d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+    qsv_d4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const double bv = kb < 4 ? x[kb].x : x[kb - 4].y;
-      re = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kb], bv, re, 0, 0, 0);
-      im = __builtin_amdgcn_mfma_f64_16x16x4f64(af[8 + kb], bv, im, 0, 0, 0);
+    for (int kb = 0; kb < 4; ++kb) {
+      p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[kb], x[kb].x, p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[kb].y, p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[kb].x + x[kb].y, p3, 0, 0, 0);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) tile[swz(lb | cq[v])] = make_double2(re[v], im[v]);
+    for (int v = 0; v < 4; ++v) tile[swz(lb | cq[v])] = make_double2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
   }
 }
 
 // Runs the register phases of a pass on a tile of T amplitudes staged in LDS
 // (slot swz(l) holds tile-local index l). Threads tid < nthr own 16 amplitudes
 // per phase; every thread of the workgroup reaches the barriers.
-// kDense: apply the composed matrix of dense phases (else always the gate list).
-template <bool kDense>
+// kDense: apply the composed matrix of dense phases on the matrix cores;
+// kGates: apply gate lists (of every phase when !kDense, else of the phases
+// that are not dense). A kernel built without kGates runs only passes whose
+// phases are all dense (unguarded, on tiles of at least 64 threads).
+// lds_mats: the pass's dense matrices staged in LDS (phase p at lds_mats + 256 p),
+// or null to read them from the matrix slots.
+template <bool kDense, bool kGates>
 __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t T, uint32_t tid, uint32_t nthr, uint64_t flags,
                            const Phase* __restrict__ phases, uint32_t pb, uint32_t pc,
-                           const DGate* __restrict__ gates, const double* __restrict__ mb) {
+                           const DGate* __restrict__ gates, const double* __restrict__ mb,
+                           const double2* __restrict__ lds_mats = nullptr) {
   double2 r[kR];
   for (uint32_t p = 0; p < pc; ++p) {
-    const Phase ph = phases[pb + p];
-    bool act = false;
-    for (uint32_t i = 0; i < ph.gate_count && !act; ++i) act = guard_ok(flags, gates[ph.gate_begin + i].guard);
-    if (!act) continue;
+    const Phase ph = load_phase(phases + pb + p);
+    if (kGates) {
+      bool act = false;
+      for (uint32_t i = 0; i < ph.gate_count && !act; ++i) act = guard_ok(flags, gates[ph.gate_begin + i].guard);
+      if (!act) continue;
+    }
     if (kDense && ph.dense != kNoDense && nthr >= 64u) {
-      if (tid < nthr) dense_phase_mfma(tile, T, tid, ph, mb + (uint64_t)ph.dense * kMatStride);
-    } else if (tid < nthr) {
+      if (tid < nthr)
+        dense_phase_mfma(tile, T, tid, ph,
+                         lds_mats ? lds_mats + (size_t)p * 256u
+                                  : reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride));
+    } else if (kGates && tid < nthr) {
       const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
       const uint32_t lb = pdep32(tid, (T - 1u) & ~(o0 | o1 | o2 | o3));
 #pragma unroll
@@ -769,46 +849,191 @@ __device__ __forceinline__ void store_tile16(const double2* __restrict__ tile, d
   }
 }
 
+// Whether the pass has work for a shot: the shot is alive and (the pass
+// initialises the state, or some gate of the pass is enabled by its flags).
+__device__ __forceinline__ bool pass_active(const ShotCtl* __restrict__ c, const PassArgs& a,
+                                            const DGate* __restrict__ gates) {
+  const QSV_CONST ShotCtl* cc = cst(c);
+  if (cc->status != 0) return false;
+  if (a.init || a.uncond) return true;
+  const uint64_t flags = cc->flags;
+  for (uint32_t i = 0; i < a.gate_count; ++i)
+    if (guard_ok(flags, cst(gates + a.gate_begin + i)->guard)) return true;
+  return false;
+}
+
+__device__ __forceinline__ uint64_t next_pass_item(uint64_t it, uint64_t total, uint64_t G, const ShotCtl* ctl,
+                                                   const PassArgs& a, const DGate* __restrict__ gates,
+                                                   uint32_t& last_shot, bool& last_active) {
+  for (; it < total; it += G) {
+    const uint32_t shot = (uint32_t)(it / a.tiles);
+    if (shot != last_shot) {
+      last_shot = shot;
+      last_active = pass_active(ctl + shot, a, gates);
+    }
+    if (last_active) break;
+  }
+  return it;
+}
+
+// global index bits of tile w: the bits of w scattered over the non-tile qubits
+__device__ __forceinline__ uint64_t tile_base(uint64_t w, uint64_t free_mask) {
+  uint64_t base = 0, m = free_mask;
+  while (m) {
+    const uint64_t bit = m & (0ull - m);
+    if (w & 1ull) base |= bit;
+    w >>= 1;
+    m ^= bit;
+  }
+  return base;
+}
+
+// The 16 amplitudes of a thread (address bits gthr | subsets of h0..h3) in the
+// load layout: logical amplitude i is stored at memory index i ^ F. Every
+// amplitude is read (one straight run of loads); those outside a pending
+// collapse are zeroed when staged.
+__device__ __forceinline__ void fetch16(double2 (&r)[kR], const double2* __restrict__ st, uint64_t gthr, uint64_t h0,
+                                        uint64_t h1, uint64_t h2, uint64_t h3, bool init, uint64_t F) {
+  if (init) {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                          ((k & 8) ? h3 : 0ull);
+      r[k] = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                          ((k & 8) ? h3 : 0ull);
+      r[k] = st[gi ^ F];
+    }
+  }
+}
+
+// the 16 amplitudes of a thread into LDS (load layout l = tid + k nthr), with
+// the pending collapse's scale applied
+__device__ __forceinline__ void stage16(double2* __restrict__ tile, const double2 (&r)[kR], uint32_t tid,
+                                        uint32_t nthr, uint64_t gthr, uint64_t h0, uint64_t h1, uint64_t h2,
+                                        uint64_t h3, uint64_t M, uint64_t V, double s) {
+  if (M == 0 && s == 1.0) {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) tile[swz(tid + (uint32_t)k * nthr)] = r[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                          ((k & 8) ? h3 : 0ull);
+      tile[swz(tid + (uint32_t)k * nthr)] = ((gi & M) == V) ? cscale(r[k], s) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Persistent register-blocked pass. The grid holds as many workgroups as fit
+// on the device at once; workgroup b takes the work items (shot, tile)
+// b, b + G, b + 2G, ... (item = shot * tiles + tile) of shots the pass has work
+// for. While it runs the phases of one tile, the 16 loads per thread of its
+// next tile are already in flight (held in registers), so HBM reads overlap
+// the gate arithmetic of the same workgroup. kDenseOnly: the variant for
+// passes whose phases are all dense (matrix cores only, fewer live registers).
+template <bool kDenseOnly>
 __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
     double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const DGate* __restrict__ gates,
-    const Phase* __restrict__ phases, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a) {
+    const Phase* __restrict__ phases, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a,
+    uint32_t shots) {
   extern __shared__ double2 tile[];
-  const uint32_t shot = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
-  const uint32_t nthr = 1u << (a.t - kRegBits);
-  ShotCtl* c = ctl + shot;
-  if (c->status != 0) return;
-  const uint64_t flags = c->flags, M = c->pend_mask, F = c->frame;
-  const double s = c->pend_scale;
-  const bool pending = M != 0 || s != 1.0;
-  bool any = false;
-  for (uint32_t i = 0; i < a.gate_count && !any; ++i) any = guard_ok(flags, gates[a.gate_begin + i].guard);
-  if (!a.init && !any) return;
-  const uint64_t V = c->pend_val;
-  uint64_t base = 0;
-  {
-    uint32_t k = 0;
-    for (uint32_t q = 0; q < a.n; ++q)
-      if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
-  }
-  double2* st = state + (uint64_t)shot * stride;
-  const uint32_t T = 1u << a.t;
-  load_tile16(tile, st, a, base, tid, M, V, F, s, pending);
-  const double* mb = mats + (uint64_t)shot * mat_stride;
-  __syncthreads();
-  run_phases<true>(tile, T, tid, nthr, flags, phases, a.phase_begin, a.phase_count, gates, mb);
-  store_tile16(tile, st, a, base, tid, F);
-  if (pending) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nthr = 1u << (a.t - kRegBits), T = 1u << a.t;
+  const uint64_t total = (uint64_t)a.tiles * shots, G = gridDim.x;
+  const uint64_t free_mask = ~a.tile_mask & ((a.n >= 64) ? ~0ull : ((1ull << a.n) - 1ull));
+  uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..t-5]
+  for (uint32_t b = 0; b + kRegBits < a.t; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
+  const uint64_t h0 = 1ull << a.tq[a.t - 4], h1 = 1ull << a.tq[a.t - 3], h2 = 1ull << a.tq[a.t - 2],
+                 h3 = 1ull << a.tq[a.t - 1];
+  // next item at or after `it` (in steps of G) whose shot the pass has work for;
+  // the answer for the last shot looked at is kept
+  uint32_t last_shot = 0xFFFFFFFFu;
+  bool last_active = false;
+  double2 nx[kR];
+  // the dense-only variant prefetches the next tile and keeps the pass's
+  // dense matrices in LDS after the tile (no vector loads but the prefetch
+  // while it computes); the gate-list variant (more live registers) loads each
+  // tile when it starts on it
+  constexpr bool kPrefetch = kDenseOnly;
+  double2* lds_mats = nullptr;
+  if (kDenseOnly) {
+    lds_mats = tile + T;
+    const double* mb0 = mats;  // dense matrices are per call (mat_stride 0 on this path)
+    for (uint32_t p = 0; p < a.phase_count; ++p) {
+      const double2* src = reinterpret_cast<const double2*>(mb0 + (uint64_t)cst(phases + a.phase_begin + p)->dense *
+                                                                      kMatStride);
+      for (uint32_t e = tid; e < 256u; e += nthr) lds_mats[p * 256u + e] = src[e];
+    }
     __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const uint32_t done = atomicAdd(&c->wg_done, 1u);
-      if (done == a.tiles - 1) {
-        c->pend_mask = 0;
-        c->pend_val = 0;
-        c->pend_scale = 1.0;
-        c->wg_done = 0;
+  }
+  // Loop order: prefetch the next tile, run the phases and store this tile,
+  // then stage the next tile in LDS. Staging comes after the stores are issued,
+  // so it waits for the prefetched loads only (the stores may still be in
+  // flight: the vector-memory counter completes in issue order).
+  uint64_t it = next_pass_item(blockIdx.x, total, G, ctl, a, gates, last_shot, last_active);
+  if (it < total) {
+    const uint32_t sh = (uint32_t)(it / a.tiles);
+    const QSV_CONST ShotCtl* cc = cst(ctl + sh);
+    const uint64_t g0 = tile_base(it % a.tiles, free_mask) | tb;
+    fetch16(nx, state + (uint64_t)sh * stride, g0, h0, h1, h2, h3, a.init, cc->frame);
+    stage16(tile, nx, tid, nthr, g0, h0, h1, h2, h3, cc->pend_mask, cc->pend_val, cc->pend_scale);
+    __syncthreads();
+  }
+  while (it < total) {
+    const uint32_t shot = (uint32_t)(it / a.tiles);
+    ShotCtl* c = ctl + shot;
+    const uint64_t flags = cst(c)->flags, F = cst(c)->frame;
+    const bool pending = cst(c)->pend_mask != 0 || cst(c)->pend_scale != 1.0;
+    const uint64_t base = tile_base(it % a.tiles, free_mask);
+    const uint64_t nit = next_pass_item(it + G, total, G, ctl, a, gates, last_shot, last_active);
+    const uint32_t nshot = (uint32_t)(nit / a.tiles);
+    const uint64_t ngthr = nit < total ? tile_base(nit % a.tiles, free_mask) | tb : 0ull;
+    if (kPrefetch && nit < total)
+      fetch16(nx, state + (uint64_t)nshot * stride, ngthr, h0, h1, h2, h3, a.init, cst(ctl + nshot)->frame);
+    run_phases<true, !kDenseOnly>(tile, T, tid, nthr, flags, phases, a.phase_begin, a.phase_count, gates,
+                                  mats + (uint64_t)shot * mat_stride, lds_mats);
+    {
+      // back to HBM in the load layout (address bits computed once, above)
+      double2* st = state + (uint64_t)shot * stride;
+      const uint64_t gthr = base | tb;
+      double2 r[kR];
+#pragma unroll
+      for (int k = 0; k < kR; ++k) r[k] = tile[swz(tid + (uint32_t)k * nthr)];
+#pragma unroll
+      for (int k = 0; k < kR; ++k) {
+        const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
+                            ((k & 8) ? h3 : 0ull);
+        st[gi ^ F] = r[k];
       }
     }
+    if (pending) {
+      __syncthreads();
+      if (tid == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&c->wg_done, 1u);
+        if (done == a.tiles - 1) {
+          c->pend_mask = 0;
+          c->pend_val = 0;
+          c->pend_scale = 1.0;
+          c->wg_done = 0;
+        }
+      }
+    }
+    __syncthreads();
+    if (nit < total) {
+      // nit is a tile its shot has not finished, so that shot's pending
+      // collapse is still in place
+      const QSV_CONST ShotCtl* cn = cst(ctl + nshot);
+      if (!kPrefetch) fetch16(nx, state + (uint64_t)nshot * stride, ngthr, h0, h1, h2, h3, a.init, cn->frame);
+      stage16(tile, nx, tid, nthr, ngthr, h0, h1, h2, h3, cn->pend_mask, cn->pend_val, cn->pend_scale);
+      __syncthreads();
+    }
+    it = nit;
   }
 }
 
@@ -1173,7 +1398,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             __syncthreads();
           }
           if (a.phase_count) {
-            run_phases<false>(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
+            run_phases<false, true>(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
                        a.phase_count, R.gates, R.mats);
           } else {
             // fewer than 4 qubits: one LDS sweep per gate (slots are unswizzled for T < 16)
@@ -1199,7 +1424,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             }
             load_tile16(tile, slot, a, base, tid, M, V, F, sc, pending);
             __syncthreads();
-            run_phases<false>(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
+            run_phases<false, true>(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
             store_tile16(tile, slot, a, base, tid, F);
             __syncthreads();
           }

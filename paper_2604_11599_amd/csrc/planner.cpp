@@ -37,7 +37,10 @@ bool two_qubit(uint32_t kind) { return kind >= QSV_G_CX && kind < QSV_G_COUNT; }
 // one complex add (2) per output amplitude.
 // Relative cost of applying a gate from the gate list of a register phase, in
 // units of one dense 2x2 gate (8 FMA per amplitude plus dispatch); a dense
-// 16x16 phase product (64 FMA per amplitude, no dispatch) costs about 5.5.
+// 16x16 phase product (64 FMA per amplitude on the matrix cores) costs about
+// as much as 5 of them, and passes made only of dense phases run a leaner
+// kernel that overlaps loads with arithmetic, so phases from a cost of 4 on
+// are made dense.
 double gate_dispatch_cost(GateType t) {
   switch (t) {
     case GT_DENSE1: case GT_CTRL1: return 1.0;
@@ -336,6 +339,7 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
       plan.steps.push_back({Step::PASS, (uint32_t)plan.passes.size()});
       plan.passes.push_back(pa);
       plan.pass_uncond.push_back(uncond);
+      plan.passes.back().uncond = uncond;
       plan.pass_flops_per_amp.push_back(fl);
       rem.swap(next);
     }
@@ -464,6 +468,11 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
       plan.slot_instr.push_back(UINT32_MAX);
     }
     plan.dense_phases.push_back(p);
+  }
+  for (PassArgs& pa : plan.passes) {
+    pa.all_dense = pa.phase_count > 0 ? 1u : 0u;
+    for (uint32_t p = pa.phase_begin; p < pa.phase_begin + pa.phase_count; ++p)
+      if (plan.phases[p].dense == kNoDense) pa.all_dense = 0;
   }
   // State initialisation: folded into the first pass when the program starts with gates.
   if (!plan.steps.empty() && plan.steps[0].kind == Step::PASS) {

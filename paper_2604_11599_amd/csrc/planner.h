@@ -36,7 +36,7 @@ struct Plan {
 };
 
 #ifndef QSV_DENSE_MIN_COST
-#define QSV_DENSE_MIN_COST 5.5
+#define QSV_DENSE_MIN_COST 4.0
 #endif
 
 struct PlanOptions {

@@ -51,15 +51,16 @@ struct GateSrc {    // 64 bytes
 // A phase of a register-blocked pass: the gates of the phase act only on the
 // 4 tile-local bits r[0..3]; every thread holds the 16 amplitudes that differ
 // in those bits (register k <-> local index with bit j of k on bit r[j]).
-// A dense phase also has its gates' product M (16x16 complex) stored as the
-// real 32x32 matrix [[Re M, -Im M], [Im M, Re M]] in matrix-core fragment
-// order: element (i, k) at double ((i / 16) * 8 + k / 4) * 64 + i % 16 + 16 (k % 4),
-// in kDenseSlots consecutive matrix slots from slot `dense`; the forward pass
-// applies it on the matrix cores instead of the gate list.
+// A dense phase also has its gates' product M (16x16 complex) in kDenseSlots
+// consecutive matrix slots from slot `dense`, as 256 complex values with
+// M[i][c] at position (c / 4) * 64 + i + 16 (c % 4): the order in which the
+// 64 lanes of a wave take their matrix-core operands. The forward pass applies
+// it on the matrix cores instead of the gate list.
 constexpr uint32_t kNoDense = 0xFFFFFFFFu;
-constexpr int kDenseDoubles = 32 * 32;
+constexpr int kDenseDoubles = 16 * 16 * 2;
 constexpr int kDenseSlots = kDenseDoubles / kMatStride;
 constexpr uint32_t kDenseMinTileBits = 10;  // full 64-lane waves of amplitude groups
+constexpr uint32_t kLdsDensePhases = 4;     // dense phases a pass keeps in LDS (4 KiB each)
 struct Phase {      // 16 bytes
   uint8_t r[kRegBits];
   uint32_t gate_begin, gate_count;
@@ -77,6 +78,8 @@ struct PassArgs {
   uint64_t tile_mask;            // global bits covered by the tile
   uint8_t tq[kTileMaxBits];      // global qubit of local bit k (ascending)
   uint32_t phase_begin, phase_count;  // register-blocked phases (phase_count = 0: LDS-only pass)
+  uint32_t uncond;               // 1: no gate of the pass is guarded
+  uint32_t all_dense;            // 1: every phase has a composed dense matrix
 };
 
 // Sequential events of a measurement site, replayed per shot by one thread.
