@@ -276,7 +276,8 @@ qsv_status qsv_fetch_expval_grad(qsv_server* srv, uint64_t ticket, double* energ
 /* Kernel time is measured with HIP events recorded on the context stream
    around every launch. "Algorithmic" bytes and flops count what the method
    needs, not what the hardware moved: a tile pass over S shots of n qubits
-   reads and writes 2 * 16 * 2^n * S bytes; its flops are the gate arithmetic
+   reads and writes 2 * 16 * 2^n * S bytes (the pass that also prepares
+   |0...0> only writes, 16 * 2^n * S bytes); its flops are the gate arithmetic
    (14 per amplitude for a dense 2x2 gate, 6 for a diagonal one, 7 for a
    controlled 2x2, 1.5 for a controlled phase, 0 for permutations). Only passes
    whose gates are unconditional are counted in the *_uncond figures, since a
