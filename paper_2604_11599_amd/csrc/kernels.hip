@@ -420,34 +420,37 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(double2* __restric
                               const DGate* __restrict__ gates, const Phase* __restrict__ phases,
                               const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots);
 
-// Workgroups of the register tile pass (tile of 2^t amplitudes, `lds` bytes of
-// LDS: the tile and up to kLdsDensePhases staged matrices) that the device
-// holds at once, per device, variant and LDS size (cached).
-template <bool kDenseOnly>
-hipError_t resident_grid(uint32_t t, size_t lds, uint32_t* out) {
-  static uint32_t cache[64][kTileMaxBits + 1][kLdsDensePhases + 1] = {};
+// Workgroups of `kernel` (threads per workgroup, bytes of dynamic LDS) that
+// the current device holds at once; the first query for a kernel also raises
+// its LDS limit to max_lds. Cached per device, kernel, size and LDS.
+hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_t max_lds, uint32_t* out) {
+  struct Entry {
+    int dev;
+    const void* kernel;
+    uint32_t threads;
+    size_t lds;
+    uint32_t grid;
+  };
+  static Entry cache[64];
+  static int used = 0;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= 64 || t > (uint32_t)kTileMaxBits || t < (uint32_t)kRegBits) return hipErrorInvalidValue;
-  const size_t tile_bytes = sizeof(double2) << t, mat_bytes = 256u * sizeof(double2);
-  if (lds < tile_bytes || (lds - tile_bytes) % mat_bytes || (lds - tile_bytes) / mat_bytes > kLdsDensePhases)
-    return hipErrorInvalidValue;
-  uint32_t& slot = cache[dev][t][(lds - tile_bytes) / mat_bytes];
-  if (!slot) {
-    const size_t max_lds = (sizeof(double2) << kTileMaxBits) + kLdsDensePhases * mat_bytes;
-    e = hipFuncSetAttribute((const void*)k_tile_pass_r<kDenseOnly>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)max_lds);
-    if (e != hipSuccess) return e;
-    int cus = 0, per = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tile_pass_r<kDenseOnly>,
-                                                     1 << (t - kRegBits), lds);
-    if (e != hipSuccess) return e;
-    slot = (uint32_t)std::max(1, cus) * (uint32_t)std::max(1, per);
-  }
-  *out = slot;
+  for (int i = 0; i < used; ++i)
+    if (cache[i].dev == dev && cache[i].kernel == kernel && cache[i].threads == threads && cache[i].lds == lds) {
+      *out = cache[i].grid;
+      return hipSuccess;
+    }
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+  if (e != hipSuccess) return e;
+  int cus = 0, per = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)threads, lds);
+  if (e != hipSuccess) return e;
+  const uint32_t grid = (uint32_t)std::max(1, cus) * (uint32_t)std::max(1, per);
+  if (used < 64) cache[used++] = Entry{dev, kernel, threads, lds, grid};
+  *out = grid;
   return hipSuccess;
 }
 
@@ -457,22 +460,27 @@ hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phas
   size_t lds = (size_t)sizeof(double2) << a.t;
   if (a.phase_count) {
     const uint64_t total = (uint64_t)a.tiles * rb.shots;
+    const size_t mat_lds = (size_t)a.phase_count * 256u * sizeof(double2);
+    const size_t max_lds = (sizeof(double2) << kTileMaxBits) + kLdsDensePhases * 256u * sizeof(double2);
+    const uint32_t nthr = 1u << (a.t - kRegBits);
+    uint32_t g = 0;
+    hipError_t e = hipSuccess;
     // the dense-only variant stages the pass's matrices once per workgroup,
     // so it runs where every shot of the launch shares them
     const bool dense_only = a.all_dense && a.t >= kDenseMinTileBits && a.phase_count <= kLdsDensePhases &&
                             mat_stride == 0;
-    if (dense_only) lds += (size_t)a.phase_count * 256u * sizeof(double2);
-    uint32_t g = 0;
-    hipError_t e = dense_only ? resident_grid<true>(a.t, lds, &g) : resident_grid<false>(a.t, lds, &g);
+    if (dense_only) lds += mat_lds;
+    e = dense_only ? resident_grid((const void*)k_tile_pass_r<true>, nthr, lds, max_lds, &g)
+                   : resident_grid((const void*)k_tile_pass_r<false>, nthr, lds, max_lds, &g);
     if (e != hipSuccess) return e;
     if ((uint64_t)g > total) g = (uint32_t)total;
     if (!g) return hipSuccess;
     if (dense_only)
-      hipLaunchKernelGGL(k_tile_pass_r<true>, dim3(g), dim3(1u << (a.t - kRegBits)), lds, st, rb.state, rb.stride,
-                         rb.ctl, gates, phases, mats, mat_stride, a, rb.shots);
+      hipLaunchKernelGGL(k_tile_pass_r<true>, dim3(g), dim3(nthr), lds, st, rb.state, rb.stride, rb.ctl, gates, phases,
+                         mats, mat_stride, a, rb.shots);
     else
-      hipLaunchKernelGGL(k_tile_pass_r<false>, dim3(g), dim3(1u << (a.t - kRegBits)), lds, st, rb.state,
-                         rb.stride, rb.ctl, gates, phases, mats, mat_stride, a, rb.shots);
+      hipLaunchKernelGGL(k_tile_pass_r<false>, dim3(g), dim3(nthr), lds, st, rb.state, rb.stride, rb.ctl, gates,
+                         phases, mats, mat_stride, a, rb.shots);
   } else {
     hipLaunchKernelGGL(k_tile_pass, grid, dim3(kTileThreads), lds, st, rb.state, rb.stride, rb.ctl, gates,
                        mats, mat_stride, a);
@@ -680,8 +688,9 @@ typedef double qsv_d4 __attribute__((ext_vector_type(4)));
 // double-precision form interleaves the rows). So lane l needs M[l % 16][4 kb +
 // l / 16] (kb = 0..3: the complex values at Mc[kb * 64 + l]), reads the
 // components q + 4 kb (q = l / 16) of its group in each block and writes back
-// the same components. The wave reads all of a block before it writes any of
-// it, and blocks of different waves are disjoint.
+// the same components. The wave reads kNB blocks before it writes any of
+// them, and blocks of different groups and waves are disjoint.
+template <int kNB>
 __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
                                                  const Phase& ph, const double2* __restrict__ Mc) {
   const uint32_t lane = tid & 63u, wbase = tid & ~63u, q = lane >> 4, j = lane & 15u;
@@ -702,21 +711,41 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
     cq[k] = ((ci & 1u) ? o0 : 0u) | ((ci & 2u) ? o1 : 0u) | ((ci & 4u) ? o2 : 0u) | ((ci & 8u) ? o3 : 0u);
   }
   const uint32_t lbl = pdep32(wbase | j, lbmask);
+  // kNB blocks at a time: their reads (one LDS round trip), then 3 kNB
+  // independent accumulation chains of 4 products, then their writes
 #pragma unroll
-  for (uint32_t cb = 0; cb < 4; ++cb) {
-    const uint32_t lb = lbl | pdep32(16u * cb, lbmask);
-    double2 x[4];
+  for (uint32_t c0 = 0; c0 < 4; c0 += kNB) {
+    uint32_t slot[kNB][4];
+    double2 x[kNB][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = tile[swz(lb | cq[k])];
-    qsv_d4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t c = 0; c < (uint32_t)kNB; ++c) {
+      const uint32_t lb = lbl | pdep32(16u * (c0 + c), lbmask);
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[kb], x[kb].x, p1, 0, 0, 0);
-      p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[kb].y, p2, 0, 0, 0);
-      p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[kb].x + x[kb].y, p3, 0, 0, 0);
+      for (int k = 0; k < 4; ++k) {
+        slot[c][k] = swz(lb | cq[k]);
+        x[c][k] = tile[slot[c][k]];
+      }
+    }
+    qsv_d4 p1[kNB], p2[kNB], p3[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) {
+      p1[c] = qsv_d4{0.0, 0.0, 0.0, 0.0};
+      p2[c] = qsv_d4{0.0, 0.0, 0.0, 0.0};
+      p3[c] = qsv_d4{0.0, 0.0, 0.0, 0.0};
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) tile[swz(lb | cq[v])] = make_double2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        p1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[kb], x[c][kb].x, p1[c], 0, 0, 0);
+        p2[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[c][kb].y, p2[c], 0, 0, 0);
+        p3[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[c][kb].x + x[c][kb].y, p3[c], 0, 0, 0);
+      }
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        tile[slot[c][v]] = make_double2(p1[c][v] - p2[c][v], p3[c][v] - p1[c][v] - p2[c][v]);
   }
 }
 
@@ -744,7 +773,7 @@ __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t 
     }
     if (kDense && ph.dense != kNoDense && nthr >= 64u) {
       if (tid < nthr)
-        dense_phase_mfma(tile, T, tid, ph,
+        dense_phase_mfma<kGates ? 1 : 2>(tile, T, tid, ph,
                          lds_mats ? lds_mats + (size_t)p * 256u
                                   : reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride));
     } else if (kGates && tid < nthr) {
