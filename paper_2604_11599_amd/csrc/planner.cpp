@@ -269,11 +269,20 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
     while (!rem.empty()) {
       uint32_t best = 0;
       uint64_t bestT = 0;
-      // candidate seeds: the low qubits alone, then low qubits + each early gate
+      // candidate seeds: the low qubits alone, then low qubits + each early
+      // gate, then the low qubits + every window of consecutive other qubits
+      // that fills the tile (nearest-neighbour circuits advance in such blocks)
       std::vector<uint64_t> seeds{low_mask};
       for (size_t i = 0; i < rem.size() && seeds.size() <= opt.candidates; ++i) {
         uint64_t s = low_mask | rem[i].qmask;
         if (std::find(seeds.begin(), seeds.end(), s) == seeds.end()) seeds.push_back(s);
+      }
+      if (opt.window_seeds && n > tmax) {
+        const uint32_t free_bits = tmax - (uint32_t)__builtin_popcountll(low_mask);
+        for (uint32_t a = low; a + free_bits <= n; ++a) {
+          const uint64_t s = low_mask | (((1ull << free_bits) - 1ull) << a);
+          if (std::find(seeds.begin(), seeds.end(), s) == seeds.end()) seeds.push_back(s);
+        }
       }
       for (uint64_t s : seeds) {
         if ((uint32_t)__builtin_popcountll(s) > tmax) continue;

@@ -43,6 +43,7 @@ struct PlanOptions {
   uint32_t tile_bits = kTileMaxBits;  // t_max
   uint32_t low_bits = 4;              // tile always holds qubits 0..low_bits-1 (256 B runs)
   uint32_t candidates = 8;            // seeds tried per pass by the greedy tile chooser
+  bool window_seeds = true;           // also try windows of consecutive qubits as tiles
   bool register_phases = true;        // split passes into 4-qubit register phases
   double dense_min_cost = QSV_DENSE_MIN_COST;        // compose a phase into a 16x16 matrix from this gate cost on (0: never)
 };
