@@ -688,9 +688,8 @@ typedef double qsv_d4 __attribute__((ext_vector_type(4)));
 // double-precision form interleaves the rows). So lane l needs M[l % 16][4 kb +
 // l / 16] (kb = 0..3: the complex values at Mc[kb * 64 + l]), reads the
 // components q + 4 kb (q = l / 16) of its group in each block and writes back
-// the same components. The wave reads kNB blocks before it writes any of
-// them, and blocks of different groups and waves are disjoint.
-template <int kNB>
+// the same components. The wave reads a block before it writes it, and the
+// blocks of different waves are disjoint.
 __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
                                                  const Phase& ph, const double2* __restrict__ Mc) {
   const uint32_t lane = tid & 63u, wbase = tid & ~63u, q = lane >> 4, j = lane & 15u;
@@ -711,41 +710,39 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
     cq[k] = ((ci & 1u) ? o0 : 0u) | ((ci & 2u) ? o1 : 0u) | ((ci & 4u) ? o2 : 0u) | ((ci & 8u) ? o3 : 0u);
   }
   const uint32_t lbl = pdep32(wbase | j, lbmask);
-  // kNB blocks at a time: their reads (one LDS round trip), then 3 kNB
-  // independent accumulation chains of 4 products, then their writes
+  // software-pipelined over the 4 blocks: the reads of block b + 1 are issued
+  // before the writes of block b, so the LDS round trip of the next block
+  // overlaps the tail of the current block's products
+  uint32_t slot[2][4];
+  double2 x[2][4];
+  {
+    const uint32_t lb = lbl | pdep32(0u, lbmask);
 #pragma unroll
-  for (uint32_t c0 = 0; c0 < 4; c0 += kNB) {
-    uint32_t slot[kNB][4];
-    double2 x[kNB][4];
+    for (int k = 0; k < 4; ++k) {
+      slot[0][k] = swz(lb | cq[k]);
+      x[0][k] = tile[slot[0][k]];
+    }
+  }
 #pragma unroll
-    for (uint32_t c = 0; c < (uint32_t)kNB; ++c) {
-      const uint32_t lb = lbl | pdep32(16u * (c0 + c), lbmask);
+  for (uint32_t cb = 0; cb < 4; ++cb) {
+    const uint32_t c = cb & 1u;
+    qsv_d4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[kb], x[c][kb].x, p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[c][kb].y, p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[c][kb].x + x[c][kb].y, p3, 0, 0, 0);
+    }
+    if (cb + 1 < 4) {
+      const uint32_t lb = lbl | pdep32(16u * (cb + 1), lbmask);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        slot[c][k] = swz(lb | cq[k]);
-        x[c][k] = tile[slot[c][k]];
+        slot[c ^ 1u][k] = swz(lb | cq[k]);
+        x[c ^ 1u][k] = tile[slot[c ^ 1u][k]];
       }
     }
-    qsv_d4 p1[kNB], p2[kNB], p3[kNB];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-      p1[c] = qsv_d4{0.0, 0.0, 0.0, 0.0};
-      p2[c] = qsv_d4{0.0, 0.0, 0.0, 0.0};
-      p3[c] = qsv_d4{0.0, 0.0, 0.0, 0.0};
-    }
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) {
-        p1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[kb], x[c][kb].x, p1[c], 0, 0, 0);
-        p2[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[c][kb].y, p2[c], 0, 0, 0);
-        p3[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[c][kb].x + x[c][kb].y, p3[c], 0, 0, 0);
-      }
-#pragma unroll
-    for (int c = 0; c < kNB; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        tile[slot[c][v]] = make_double2(p1[c][v] - p2[c][v], p3[c][v] - p1[c][v] - p2[c][v]);
+    for (int v = 0; v < 4; ++v) tile[slot[c][v]] = make_double2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
   }
 }
 
@@ -773,7 +770,7 @@ __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t 
     }
     if (kDense && ph.dense != kNoDense && nthr >= 64u) {
       if (tid < nthr)
-        dense_phase_mfma<kGates ? 1 : 2>(tile, T, tid, ph,
+        dense_phase_mfma(tile, T, tid, ph,
                          lds_mats ? lds_mats + (size_t)p * 256u
                                   : reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride));
     } else if (kGates && tid < nthr) {

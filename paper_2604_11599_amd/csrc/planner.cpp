@@ -125,6 +125,11 @@ void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
     std::vector<uint64_t> seeds{0};
     for (size_t i = 0; i < rem.size() && seeds.size() <= candidates; ++i)
       if (std::find(seeds.begin(), seeds.end(), rem[i].qmask) == seeds.end()) seeds.push_back(rem[i].qmask);
+    // windows of kRegBits consecutive local bits (consecutive qubits of the tile)
+    for (uint32_t a = 0; a + kRegBits <= pa->t; ++a) {
+      const uint64_t w = ((1ull << kRegBits) - 1ull) << a;
+      if (std::find(seeds.begin(), seeds.end(), w) == seeds.end()) seeds.push_back(w);
+    }
     for (uint64_t s : seeds) {
       uint32_t c = 0;
       uint64_t R = grow(rem, s, kRegBits, &taken, &c);
