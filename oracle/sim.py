@@ -312,11 +312,16 @@ class Interpreter:
         return [off + i]
 
     # -- running one shot --
-    def run(self, seed=0, shot=0, forced=None):
+    def run(self, seed=0, shot=0, forced=None, first_event=0):
+        """first_event: index in the shot's Philox stream of the first word this
+        program draws (0 for a whole program; a program that is one independent
+        block of a larger product-state program starts where the draws of the
+        blocks measured before it end)."""
         p = self.prog
         self.eng = self.engine_cls(p.n_qubits)
         self.cbits = [0] * p.n_clbits
         self.stream = ShotStream(seed, shot)
+        self.stream.event = int(first_event)
         self.record, self.events = [], []
         self.record_prob = 1.0
         self.forced = list(forced) if forced is not None else []
@@ -489,10 +494,10 @@ def _val(x):
 # --------------------------------------------------------------------------
 # Convenience entry points used by tests, the smoke check and the CPU baseline.
 # --------------------------------------------------------------------------
-def run_shot(source, theta=None, seed=0, shot=0, forced=None, engine_cls=TensorEngine):
+def run_shot(source, theta=None, seed=0, shot=0, forced=None, engine_cls=TensorEngine, first_event=0):
     """Run one shot; returns the finished interpreter (psi, cbits, record, ...)."""
     it = Interpreter(source if isinstance(source, Program) else Program(source), theta, engine_cls)
-    return it.run(seed, shot, forced)
+    return it.run(seed, shot, forced, first_event)
 
 
 def run_shots(source, n_shots, theta=None, seed=0, shot_offset=0, forced=None):

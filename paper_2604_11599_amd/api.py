@@ -212,7 +212,7 @@ class Program:
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
         self.ctx.check(A.lib().qsv_run_shots(self.ctx.handle, self.handle, _ptr(th), n_shots,
                                              C.byref(opts), C.byref(res)))
-        state = None if st is None else st[:, 0] + 1j * st[:, 1]
+        state = None if st is None else st.view(np.complex128).reshape(-1)
         return ShotResultArrays(creg, record[:, :mr], nev, prob, status, state, lp.n_clbits)
 
     def _pauli(self, coeffs, codes):

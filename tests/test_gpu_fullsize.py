@@ -1,0 +1,124 @@
+"""GPU checks at the benchmark's full size: 28 qubits (4 GiB per shot), 40
+brickwork layers, 16 shots in one launch as bench.py runs them.
+
+The oracle cannot simulate a 28-qubit shot of 40 layers in test time, so:
+* a block-separable 28-qubit brickwork (CX gates never cross block
+  boundaries, so the state is a product of 7-qubit blocks) is simulated by the
+  oracle block by block; sampled amplitudes, and every shot's measure-all record
+  (same Philox draws: block b starts at event offset_b), are compared exactly as
+  in the small-size parity tests;
+* the mirror circuit U U^dag must return |0...0>;
+* on the benchmark circuit itself, properties that hold at any size: forced
+  re-runs reproduce sampled shots bit for bit, a shot alone equals the same shot
+  inside the batch, the shared-prefix path is bit-identical, norms stay 1.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sim
+
+pytestmark = pytest.mark.gpu
+
+AMP_TOL = 1e-10
+PROB_TOL = 1e-12
+TIE = 1e-12
+N = 28
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2604_11599_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _width(src):
+    return int(src.split("qubit[")[1].split("]")[0])
+
+
+def test_separable_28q_amplitudes_and_shots(ctx):
+    full, blocks, offs = W.separable_brickwork(seed=5, n=N, blocks=4, layers=40)
+    say("separable 28q: oracle blocks")
+    psis = [sim.run_shot(b).psi for b in blocks]
+    say("separable 28q: GPU state of one shot")
+    st = ctx.load(full).run_shots(1, state_out=True).state
+    assert abs(np.vdot(st, st).real - 1.0) < 1e-10
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, 1 << N, size=200000, dtype=np.int64)
+    idx[:4] = [0, (1 << N) - 1, 12345, 1 << 27]
+    expect = np.ones(idx.shape, dtype=np.complex128)
+    for psi, src, off in zip(psis, blocks, offs):
+        w = _width(src)
+        expect *= psi[(idx >> off) & ((1 << w) - 1)]
+    assert np.max(np.abs(st[idx] - expect)) < AMP_TOL
+    del st
+
+    say("separable 28q: 16 sampled shots, measure-all")
+    meas = f"bit[{N}] f;\nf = measure q;\n"
+    seed = 17
+    res = ctx.load(full + meas).run_shots(16, seed=seed)
+    bits = res.bits()
+    skipped = 0
+    for s in range(16):
+        cb, rec, prob, near = [], [], 1.0, False
+        for src, off in zip(blocks, offs):
+            w = _width(src)
+            o = sim.run_shot(src + f"bit[{w}] f;\nf = measure q;\n", seed=seed, shot=s, first_event=off)
+            cb += o.cbits
+            rec += o.record
+            prob *= o.record_prob
+            near |= any(abs(e[3] - e[4]) < TIE for e in o.events)
+        if near:
+            skipped += 1
+            continue
+        assert list(bits[s]) == cb, f"shot {s}"
+        assert list(res.record[s, :N]) == rec
+        assert res.n_events[s] == N
+        assert abs(res.record_prob[s] - prob) < PROB_TOL
+    assert skipped <= 1
+
+
+def test_mirror_28q_returns_to_zero(ctx):
+    src = W.mirror_program(seed=6, n=N, layers=40) + f"bit[{N}] f;\nf = measure q;\n"
+    say("mirror 28q, 16 shots")
+    res = ctx.load(src).run_shots(16, seed=2)
+    assert not res.creg.any()
+    assert np.all(np.abs(res.record_prob - 1.0) < 1e-10)
+    assert np.all(res.shot_status == 0)
+
+
+def test_benchmark_circuit_properties(ctx):
+    src = W.c2_program(seed=2, n=N, layers=40)
+    prog = ctx.load(src)
+    say("c2 28q: 16 sampled shots (bench launch)")
+    a = prog.run_shots(16, seed=0)
+    assert np.all(a.shot_status == 0)
+    assert np.all((a.record_prob > 0) & (a.record_prob <= 1 + 1e-12))
+    width = int(a.n_events.max())
+    forced = np.zeros((16, width), dtype=np.uint8)
+    for s in range(16):
+        forced[s, :a.n_events[s]] = a.record[s, :a.n_events[s]]
+    say("c2 28q: forced re-run of the same records")
+    f = prog.run_shots(16, seed=0, forced=forced)
+    assert np.array_equal(f.creg, a.creg) and np.array_equal(f.n_events, a.n_events)
+    assert np.max(np.abs(f.record_prob - a.record_prob)) < PROB_TOL
+    say("c2 28q: shots alone vs in the batch")
+    for k in (0, 9):
+        one = prog.run_shots(1, seed=0, shot_offset=k)
+        assert np.array_equal(one.creg[0], a.creg[k]) and one.record_prob[0] == a.record_prob[k]
+    say("c2 28q: shared prefix")
+    b = prog.run_shots(16, seed=0, share_prefix=True)
+    assert np.array_equal(b.creg, a.creg) and np.array_equal(b.record, a.record)
+    assert np.array_equal(b.record_prob, a.record_prob)
+    say("c2 28q: norm of a shot's state after the mid-circuit site")
+    nomeas = src[:src.rindex("f = measure q;")]
+    st = ctx.load(nomeas).run_shots(1, seed=0, state_out=True).state
+    assert abs(np.vdot(st, st).real - 1.0) < 1e-10
