@@ -454,6 +454,10 @@ hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_
   return hipSuccess;
 }
 
+__global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
+    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
+    const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats);
+
 hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
   dim3 grid(a.tiles, rb.shots);
@@ -469,6 +473,18 @@ hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phas
     // so it runs where every shot of the launch shares them
     const bool dense_only = a.all_dense && a.t >= kDenseMinTileBits && a.phase_count <= kLdsDensePhases &&
                             mat_stride == 0;
+    // all-dense passes on full tiles: eight waves per tile
+    if (a.all_dense && a.t == (uint32_t)kTileMaxBits) {
+      const uint32_t staged = (a.phase_count <= kLdsDensePhases && mat_stride == 0) ? 1u : 0u;
+      const size_t l8 = lds + (staged ? mat_lds : 0);
+      e = resident_grid((const void*)k_tile_pass_d8, 2 * nthr, l8, max_lds, &g);
+      if (e != hipSuccess) return e;
+      if ((uint64_t)g > total) g = (uint32_t)total;
+      if (!g) return hipSuccess;
+      hipLaunchKernelGGL(k_tile_pass_d8, dim3(g), dim3(2 * nthr), l8, st, rb.state, rb.stride, rb.ctl, phases, mats,
+                         mat_stride, a, rb.shots, staged);
+      return hipGetLastError();
+    }
     if (dense_only) lds += mat_lds;
     e = dense_only ? resident_grid((const void*)k_tile_pass_r<true>, nthr, lds, max_lds, &g)
                    : resident_grid((const void*)k_tile_pass_r<false>, nthr, lds, max_lds, &g);
@@ -690,9 +706,11 @@ typedef double qsv_d4 __attribute__((ext_vector_type(4)));
 // components q + 4 kb (q = l / 16) of its group in each block and writes back
 // the same components. The wave reads a block before it writes it, and the
 // blocks of different waves are disjoint.
+template <int kBlocks>
 __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
                                                  const Phase& ph, const double2* __restrict__ Mc) {
-  const uint32_t lane = tid & 63u, wbase = tid & ~63u, q = lane >> 4, j = lane & 15u;
+  // this wave's groups: gbase + 16 cb + j, cb < kBlocks
+  const uint32_t lane = tid & 63u, wbase = (tid >> 6) * (16u * kBlocks), q = lane >> 4, j = lane & 15u;
   const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
   const uint32_t lbmask = (T - 1u) & ~(o0 | o1 | o2 | o3);
   double fa[4], fb[4], fs[4];  // fragments of A, B and A + B
@@ -710,7 +728,7 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
     cq[k] = ((ci & 1u) ? o0 : 0u) | ((ci & 2u) ? o1 : 0u) | ((ci & 4u) ? o2 : 0u) | ((ci & 8u) ? o3 : 0u);
   }
   const uint32_t lbl = pdep32(wbase | j, lbmask);
-  // software-pipelined over the 4 blocks: the reads of block b + 1 are issued
+  // software-pipelined over the blocks: the reads of block b + 1 are issued
   // before the writes of block b, so the LDS round trip of the next block
   // overlaps the tail of the current block's products
   uint32_t slot[2][4];
@@ -724,7 +742,7 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
     }
   }
 #pragma unroll
-  for (uint32_t cb = 0; cb < 4; ++cb) {
+  for (uint32_t cb = 0; cb < (uint32_t)kBlocks; ++cb) {
     const uint32_t c = cb & 1u;
     qsv_d4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -733,7 +751,7 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
       p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[c][kb].y, p2, 0, 0, 0);
       p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[c][kb].x + x[c][kb].y, p3, 0, 0, 0);
     }
-    if (cb + 1 < 4) {
+    if (cb + 1 < (uint32_t)kBlocks) {
       const uint32_t lb = lbl | pdep32(16u * (cb + 1), lbmask);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -770,7 +788,7 @@ __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t 
     }
     if (kDense && ph.dense != kNoDense && nthr >= 64u) {
       if (tid < nthr)
-        dense_phase_mfma(tile, T, tid, ph,
+        dense_phase_mfma<4>(tile, T, tid, ph,
                          lds_mats ? lds_mats + (size_t)p * 256u
                                   : reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride));
     } else if (kGates && tid < nthr) {
@@ -1060,6 +1078,90 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
       __syncthreads();
     }
     it = nit;
+  }
+}
+
+// Tile pass for passes made only of dense phases, on full tiles (2^12
+// amplitudes), with eight waves per tile: each thread stages and stores 8
+// amplitudes (load layout l = tid + k * 512), each wave applies the phases to
+// 2 blocks of 16 amplitude groups on the matrix cores, and at most 128
+// registers per thread let two workgroups (16 waves) share a CU, so that the
+// waits of one wave (LDS, barriers, HBM) are covered by the others. With
+// lds_mats the pass's matrices (shared by every shot: mat_stride 0, at most
+// kLdsDensePhases of them) are staged in LDS once; otherwise each phase reads
+// its matrix from the shot's matrix slots.
+__global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
+    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
+    const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats) {
+  extern __shared__ double2 tile[];
+  constexpr uint32_t kA = 8, kThreads = 2 * kTileThreads;
+  const uint32_t tid = threadIdx.x, T = 1u << a.t;
+  const uint64_t total = (uint64_t)a.tiles * shots, G = gridDim.x;
+  const uint64_t free_mask = ~a.tile_mask & ((a.n >= 64) ? ~0ull : ((1ull << a.n) - 1ull));
+  uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..8]
+  for (uint32_t b = 0; b < 9; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
+  const uint64_t h0 = 1ull << a.tq[9], h1 = 1ull << a.tq[10], h2 = 1ull << a.tq[11];
+  double2* const lmats = tile + T;
+  if (lds_mats)
+    for (uint32_t p = 0; p < a.phase_count; ++p) {
+      const double2* src =
+          reinterpret_cast<const double2*>(mats + (uint64_t)cst(phases + a.phase_begin + p)->dense * kMatStride);
+      for (uint32_t e = tid; e < 256u; e += kThreads) lmats[p * 256u + e] = src[e];
+    }
+  uint32_t last_shot = 0xFFFFFFFFu;
+  bool last_active = false;
+  uint64_t it = next_pass_item(blockIdx.x, total, G, ctl, a, nullptr, last_shot, last_active);
+  while (it < total) {
+    const uint32_t shot = (uint32_t)(it / a.tiles);
+    ShotCtl* c = ctl + shot;
+    const uint64_t F = cst(c)->frame, M = cst(c)->pend_mask, V = cst(c)->pend_val;
+    const double sc = cst(c)->pend_scale;
+    const bool pending = M != 0 || sc != 1.0;
+    const uint64_t gthr = tile_base(it % a.tiles, free_mask) | tb;
+    double2* st = state + (uint64_t)shot * stride;
+    double2 r[kA];
+#pragma unroll
+    for (int k = 0; k < (int)kA; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
+      r[k] = a.init ? make_double2(gi == 0 ? 1.0 : 0.0, 0.0) : st[gi ^ F];
+    }
+#pragma unroll
+    for (int k = 0; k < (int)kA; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
+      tile[swz(tid + (uint32_t)k * kThreads)] =
+          !pending ? r[k] : (((gi & M) == V) ? cscale(r[k], sc) : make_double2(0.0, 0.0));
+    }
+    __syncthreads();
+    for (uint32_t p = 0; p < a.phase_count; ++p) {
+      const Phase ph = load_phase(phases + a.phase_begin + p);
+      const double2* Mc = lds_mats ? lmats + (size_t)p * 256u
+                                   : reinterpret_cast<const double2*>(mats + (uint64_t)shot * mat_stride +
+                                                                      (uint64_t)ph.dense * kMatStride);
+      dense_phase_mfma<2>(tile, T, tid, ph, Mc);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < (int)kA; ++k) r[k] = tile[swz(tid + (uint32_t)k * kThreads)];
+#pragma unroll
+    for (int k = 0; k < (int)kA; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
+      st[gi ^ F] = r[k];
+    }
+    if (pending) {
+      __syncthreads();
+      if (tid == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&c->wg_done, 1u);
+        if (done == a.tiles - 1) {
+          c->pend_mask = 0;
+          c->pend_val = 0;
+          c->pend_scale = 1.0;
+          c->wg_done = 0;
+        }
+      }
+    }
+    __syncthreads();
+    it = next_pass_item(it + G, total, G, ctl, a, nullptr, last_shot, last_active);
   }
 }
 
