@@ -36,11 +36,11 @@ bool two_qubit(uint32_t kind) { return kind >= QSV_G_CX && kind < QSV_G_COUNT; }
 // complex matrix-vector product costs 2 complex multiplies (6 flops each) and
 // one complex add (2) per output amplitude.
 // Relative cost of applying a gate from the gate list of a register phase, in
-// units of one dense 2x2 gate (8 FMA per amplitude plus dispatch); a dense
-// 16x16 phase product (64 FMA per amplitude on the matrix cores) costs about
-// as much as 5 of them, and passes made only of dense phases run a leaner
-// kernel that overlaps loads with arithmetic, so phases from a cost of 4 on
-// are made dense.
+// units of one dense 2x2 gate (8 FMA per amplitude plus dispatch). A dense
+// 16x16 phase product (48 matrix-core products per wave) costs about as much
+// as 5 of them, but passes made only of dense phases run the eight-wave tile
+// pass, which more than pays for the few light phases it makes dense, so by
+// default every unguarded phase is made dense.
 double gate_dispatch_cost(GateType t) {
   switch (t) {
     case GT_DENSE1: case GT_CTRL1: return 1.0;

@@ -36,7 +36,7 @@ struct Plan {
 };
 
 #ifndef QSV_DENSE_MIN_COST
-#define QSV_DENSE_MIN_COST 4.0
+#define QSV_DENSE_MIN_COST 0.5
 #endif
 
 struct PlanOptions {
