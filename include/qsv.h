@@ -202,7 +202,9 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
    different widths and trajectories of different lengths (loop exits, taken
    branches) share the GPU. States of up to 12 qubits stay in LDS for the whole
    program; states of 13..20 qubits live in a per-workgroup HBM slot; requests
-   with more qubits run through qsv_run_shots after the launch. Every item is
+   with more qubits, and requests of 13..20 qubits with at least 64 shots, run
+   through qsv_run_shots (shots sharing the deterministic prefix) after the
+   launch. The path is chosen from the request alone. Every item is
    computed the same way whatever else is in the batch, so a request's results
    do not depend on the batch it is part of. Errors: QSV_ERR_ARG for a null or
    foreign program or missing outputs, QSV_ERR_NOMEM when the slots do not fit. */

@@ -485,7 +485,10 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     if (q.opts.forced_len && !q.opts.forced) return set_err(ctx, QSV_ERR_ARG, "forced_len without forced");
     const uint32_t n = q.prog->desc.n_qubits;
     if (q.n_shots == 0) continue;
-    if (n > (uint32_t)kStreamMaxBits) {
+    // wide states, and streamed states with many shots, run on the tile-pass
+    // path (decided from the request alone, so its results do not depend on
+    // the rest of the batch)
+    if (n > (uint32_t)kStreamMaxBits || (n > (uint32_t)kResidentMaxBits && q.n_shots >= kTilePathMinShots)) {
       big.push_back(r);
       continue;
     }
@@ -568,6 +571,65 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       mo += std::max<size_t>(1, slots) * kMatStride;
       to += std::max<uint32_t>(1, P);
     }
+    // Shot branching for streamed states: the deterministic prefix (every step
+    // before the first measurement) of a request with several shots runs once,
+    // as one item of a first launch, into a buffer of its own; the request's
+    // shots then start from that state and control block.
+    {
+      std::vector<ReqDev> pre;
+      std::vector<uint32_t> pre_of;  // index into rd
+      size_t pre_amps = 0;
+      for (size_t i = 0; i < pers.size(); ++i) {
+        const qsv_request& q = reqs[pers[i]];
+        const Plan& pl = q.prog->plan;
+        if (q.prog->desc.n_qubits <= (uint32_t)kResidentMaxBits || q.n_shots < 2) continue;
+        uint32_t prefix_end = 0;
+        for (const Step& s : pl.steps) {
+          if (s.kind == Step::SITE && pl.sites[s.index].nq > 0) break;
+          ++prefix_end;
+        }
+        if (prefix_end == 0) continue;
+        ReqDev P = rd[i];
+        P.n_steps = prefix_end;
+        P.item_begin = (uint32_t)pre.size();
+        P.forced = nullptr;
+        P.forced_len = 0;
+        pre.push_back(P);
+        pre_of.push_back((uint32_t)i);
+        rd[i].step_begin = prefix_end;
+        pre_amps += 1ull << q.prog->desc.n_qubits;
+      }
+      if (!pre.empty()) {
+        double2* d_pstate;
+        ShotCtl* d_pctl;
+        uint64_t* d_pcreg;
+        uint8_t* d_prec;
+        ReqDev* d_pre;
+        uint32_t* d_pitem;
+        HIP_TRY(scr.get(pre_amps, &d_pstate));
+        HIP_TRY(scr.get(pre.size(), &d_pctl));
+        HIP_TRY(scr.get(pre.size() * cw, &d_pcreg));
+        HIP_TRY(scr.get(pre.size() * rec_max, &d_prec));
+        HIP_TRY(scr.get(pre.size(), &d_pre));
+        HIP_TRY(scr.get(pre.size(), &d_pitem));
+        size_t off = 0;
+        std::vector<uint32_t> pitem(pre.size());
+        for (size_t k = 0; k < pre.size(); ++k) {
+          pre[k].state_out = reinterpret_cast<double*>(d_pstate + off);
+          rd[pre_of[k]].init_state = reinterpret_cast<const double*>(d_pstate + off);
+          rd[pre_of[k]].init_ctl = d_pctl + k;
+          off += 1ull << pre[k].n;
+          pitem[k] = (uint32_t)k;
+        }
+        HIP_TRY(hipMemcpyAsync(d_pre, pre.data(), pre.size() * sizeof(ReqDev), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_pitem, pitem.data(), pitem.size() * 4, hipMemcpyHostToDevice, st));
+        Prof pr(ctx, st);
+        HIP_TRY(launch_persistent(d_pre, d_pitem, (uint32_t)pre.size(), d_queue, d_scratch, slot_amps,
+                                  std::min<uint32_t>(wgs, (uint32_t)pre.size()), d_pctl, d_pcreg, cw, d_prec, rec_max,
+                                  st));
+        pr.done(2);
+      }
+    }
     HIP_TRY(hipMemcpyAsync(d_reqs, rd.data(), rd.size() * sizeof(ReqDev), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_item_req, item_req.data(), items * 4, hipMemcpyHostToDevice, st));
     {
@@ -601,6 +663,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
   for (uint32_t r : big) {
     qsv_run_opts o = reqs[r].opts;
     o.state_out = nullptr;
+    o.flags = QSV_RUN_SHARE_PREFIX;  // bit-identical to running every shot from |0...0>
     qsv_shot_results out = reqs[r].out;
     qsv_status rc = qsv_run_shots(ctx, reqs[r].prog, reqs[r].theta, reqs[r].n_shots, &o, &out);
     if (rc != QSV_OK) return rc;

@@ -1475,7 +1475,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
   __shared__ double red[4 * kSiteBins];
   __shared__ double bins[kSiteBins];
   const uint32_t tid = threadIdx.x;
-  double2* slot = scratch + (uint64_t)blockIdx.x * slot_amps;
+  double2* const wg_slot = scratch + (uint64_t)blockIdx.x * slot_amps;
   for (;;) {
     if (tid == 0) item_s = atomicAdd(queue, 1u);
     __syncthreads();
@@ -1484,27 +1484,40 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
     const ReqDev R = reqs[item_req[item]];
     const uint32_t shot = item - R.item_begin, n = R.n;
     const bool resident = n <= (uint32_t)kResidentMaxBits;
+    double2* const slot = R.state_out ? reinterpret_cast<double2*>(R.state_out) : wg_slot;
+    const double2* const init_state = reinterpret_cast<const double2*>(R.init_state);
     uint64_t* cr = out_creg + (uint64_t)item * cw;
     uint8_t* rec = out_rec + (uint64_t)item * rec_max;
     for (uint32_t w = tid; w < cw; w += blockDim.x) cr[w] = 0;
     for (uint32_t w = tid; w < rec_max; w += blockDim.x) rec[w] = 0;
     if (tid == 0) {
       ShotCtl c;
-      c.flags = 0;
-      c.pend_mask = 0;
-      c.pend_val = 0;
-      c.frame = 0;
-      c.pend_scale = 1.0;
-      c.record_prob = 1.0;
-      c.n_events = 0;
-      c.n_record = 0;
-      c.status = 0;
+      if (R.init_ctl) {
+        c = *R.init_ctl;
+      } else {
+        c.flags = 0;
+        c.pend_mask = 0;
+        c.pend_val = 0;
+        c.frame = 0;
+        c.pend_scale = 1.0;
+        c.record_prob = 1.0;
+        c.n_events = 0;
+        c.n_record = 0;
+        c.status = 0;
+      }
       c.wg_done = 0;
       cs = c;
     }
-    __syncthreads();
     const uint64_t dim = 1ull << n;
-    for (uint32_t k = 0; k < R.n_steps; ++k) {
+    if (init_state) {  // the request's shared prefix, computed once
+      if (resident) {
+        for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) tile[swz(l)] = init_state[l];
+      } else {
+        for (uint64_t j = tid; j < dim; j += blockDim.x) slot[j] = init_state[j];
+      }
+    }
+    __syncthreads();
+    for (uint32_t k = R.step_begin; k < R.n_steps; ++k) {
       if (cs.status != 0) break;
       const DStep stp = R.steps[k];
       const uint64_t flags = cs.flags;
@@ -1625,6 +1638,8 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
         }
       }
     }
+    if (R.state_out && resident)
+      for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) slot[l] = tile[swz(l)];
     if (tid == 0) out_ctl[item] = cs;
     __syncthreads();
   }

@@ -135,6 +135,7 @@ struct DStep {
 
 constexpr int kResidentMaxBits = 12;  // persistent kernel keeps states up to 2^12 amplitudes in LDS
 constexpr int kStreamMaxBits = 20;    // larger states (up to 2^20) live in a per-workgroup HBM slot
+constexpr uint64_t kTilePathMinShots = 64;  // streamed-state requests with this many shots use tile passes
 
 // One request of a persistent batch: a loaded program, its bound matrices and
 // where its shots' results go. Work item i belongs to the request whose
@@ -151,6 +152,15 @@ struct ReqDev {
   const uint8_t* forced;  // [shots][forced_len] or null
   uint64_t seed, shot_offset;
   uint32_t n, n_steps, forced_len, item_begin;
+  // Shot branching in a persistent launch: an item runs steps [step_begin,
+  // n_steps). With init_state set it starts from that state and control block
+  // (the deterministic prefix, computed once per request) instead of |0...0>;
+  // with state_out set (prefix items) it works in, and leaves its state in,
+  // that buffer instead of the workgroup's slot.
+  uint32_t step_begin, pad;
+  const double* init_state;  // complex128 amplitudes (re, im)
+  const ShotCtl* init_ctl;
+  double* state_out;         // complex128 amplitudes (re, im)
 };
 
 }  // namespace qsv
