@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "planner.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "planner.cpp", "api.cpp", "server.cpp"]
 OUT = os.path.join(HERE, "libqsv.so")
 
 

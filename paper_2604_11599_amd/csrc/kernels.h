@@ -23,6 +23,11 @@ struct RunBuffers {
   uint32_t shots;
 };
 
+// Workgroups of `kernel` (threads per workgroup, bytes of dynamic LDS) that the
+// current device holds at once; the first query for a kernel also raises its
+// LDS limit to max_lds. Cached per device, kernel, size and LDS.
+hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_t max_lds, uint32_t* out);
+
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);

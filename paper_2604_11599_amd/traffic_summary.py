@@ -26,7 +26,7 @@ COPY_KERNEL = "k_copy"
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "qsv_types.h"):
+    for f in ("kernels.hip", "device_common.h", "qsv_types.h"):
         with open(os.path.join(ROOT, "paper_2604_11599_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
