@@ -35,6 +35,9 @@ typedef struct {
                                                 (0: LDS-only pass) */
   uint32_t n_phases;                         /* register phases over all passes */
   uint32_t n_dense_phases;                   /* phases applied as one composed 16x16 matrix */
+  uint32_t n_mfma_sweep_passes;              /* passes whose adjoint sweep (qsv_expval_grad) runs on
+                                                the matrix cores: all phases dense, 2^10..2^12
+                                                amplitudes per tile */
 } qsv_plan_stats;
 
 /* tile_bits = 0 uses the default tile width (12 bits). */

@@ -63,7 +63,8 @@ class PlanStats(C.Structure):
                 ("is_unitary", C.c_uint8), ("init_step", C.c_uint8), ("reserved", C.c_uint8 * 6),
                 ("step_kind", C.c_uint8 * PLAN_MAX_STEPS), ("step_mask", C.c_uint64 * PLAN_MAX_STEPS),
                 ("step_count", C.c_uint32 * PLAN_MAX_STEPS), ("gate_instr", C.c_uint32 * PLAN_MAX_GATES),
-                ("gate_regs", C.c_uint64 * PLAN_MAX_GATES), ("n_phases", C.c_uint32), ("n_dense_phases", C.c_uint32)]
+                ("gate_regs", C.c_uint64 * PLAN_MAX_GATES), ("n_phases", C.c_uint32), ("n_dense_phases", C.c_uint32),
+                ("n_mfma_sweep_passes", C.c_uint32)]
 
 
 class Profile(C.Structure):

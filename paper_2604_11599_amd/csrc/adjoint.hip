@@ -1,9 +1,10 @@
 // gfx950 kernels of expectation values and adjoint gradients (complex128).
 //
 // A batch of parameter vectors b holds its states at psi + b * stride.
-//   k_pauli_terms / k_energy_reduce / k_apply_hamiltonian   <psi|H|psi>, H psi
+//   k_hamiltonian / k_energy_sum   H psi and <psi|H|psi> in one sweep
 //   k_backward_pass   adjoint sweep of one pass on (psi, lambda) with gradient partials
 //   k_backward_r      the same on register phases
+//   k_compose_grad / k_backward_mfma   the sweep of all-dense passes on the matrix cores
 //   k_grad_reduce / k_grad_chain   fixed-order gradient reductions
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -15,7 +16,9 @@
 namespace qsv {
 
 // ---------------------------------------------------------------------------
-// Expectation values: <psi|P|psi> for P = i^ny X^x Z^z (Y = i X Z)
+// Expectation values: H = sum_t c_t P_t with P_t = i^ny X^x Z^z (Y = i X Z).
+// (P psi)[i] = i^ny (-1)^popcount((i ^ x) & z) psi[i ^ x]; lambda = H psi and
+// E = Re <psi|lambda> in one sweep over the state.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double2 ipow(uint32_t k) {
   switch (k & 3u) {
@@ -26,96 +29,67 @@ __device__ __forceinline__ double2 ipow(uint32_t k) {
   }
 }
 
-// Block partials of Re sum_i conj(psi[i ^ x]) * phase(i) * psi[i] per term.
-__global__ __launch_bounds__(256) void k_pauli_terms(const double2* __restrict__ psi, uint64_t stride, uint32_t n,
-                                                    const uint64_t* __restrict__ xmask,
+// Block (blk, b) covers a contiguous slice of vector b: writes lambda there
+// (unless lam is null), terms accumulated in a fixed order per element, and
+// the slice's Re sum conj(psi) lambda to epart[b][blk] (fixed-order tree).
+__global__ __launch_bounds__(256) void k_hamiltonian(const double2* __restrict__ psi, double2* __restrict__ lam,
+                                                    uint64_t stride, uint32_t n, const uint64_t* __restrict__ xmask,
                                                     const uint64_t* __restrict__ zmask,
-                                                    const uint32_t* __restrict__ ny, uint32_t n_terms,
-                                                    double* __restrict__ out, uint32_t blocks) {
+                                                    const uint32_t* __restrict__ ny, const double* __restrict__ coeff,
+                                                    uint32_t n_terms, uint32_t blocks, double* __restrict__ epart) {
   __shared__ double red[256];
-  const uint32_t blk = blockIdx.x % blocks, tb = blockIdx.x / blocks, tid = threadIdx.x;
-  const uint32_t term = tb % n_terms, b = tb / n_terms;
-  const double2* st = psi + (uint64_t)b * stride;
+  const uint32_t tid = threadIdx.x, blk = blockIdx.x, b = blockIdx.y;
   const uint64_t dim = 1ull << n, per = (dim + blocks - 1) / blocks;
   const uint64_t j0 = per * blk, j1 = (j0 + per < dim) ? j0 + per : dim;
-  const uint64_t x = xmask[term], z = zmask[term];
-  const double2 ph = ipow(ny[term]);
-  double acc = 0.0;
+  const double2* st = psi + (uint64_t)b * stride;
+  double e = 0.0;
   for (uint64_t i = j0 + tid; i < j1; i += 256) {
-    double2 a = st[i], bb = st[i ^ x];
-    double sgn = (__popcll(i & z) & 1) ? -1.0 : 1.0;
-    double2 pa = cmul(ph, cscale(a, sgn));
-    acc += bb.x * pa.x + bb.y * pa.y;  // Re(conj(bb) * pa)
+    double2 acc = make_double2(0.0, 0.0);
+    for (uint32_t t = 0; t < n_terms; ++t) {
+      const uint64_t src = i ^ xmask[t];
+      const double sgn = (__popcll(src & zmask[t]) & 1) ? -1.0 : 1.0;
+      acc = cadd(acc, cscale(cmul(ipow(ny[t]), st[src]), coeff[t] * sgn));
+    }
+    if (lam) lam[(uint64_t)b * stride + i] = acc;
+    const double2 p = st[i];
+    e += p.x * acc.x + p.y * acc.y;
   }
-  red[tid] = acc;
+  red[tid] = e;
   __syncthreads();
   for (uint32_t s = 128; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) out[((uint64_t)b * n_terms + term) * blocks + blk] = red[0];
+  if (tid == 0) epart[(uint64_t)b * blocks + blk] = red[0];
 }
 
-hipError_t launch_pauli_terms(const double2* psi, uint64_t stride, uint32_t n, uint32_t batch,
-                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny,
-                              const double* coeff, uint32_t n_terms, double* term_partials, uint32_t blocks,
-                              hipStream_t st) {
-  (void)coeff;
-  hipLaunchKernelGGL(k_pauli_terms, dim3(blocks * batch * n_terms), dim3(256), 0, st, psi, stride, n, xmask,
-                     zmask, ny, n_terms, term_partials, blocks);
+hipError_t launch_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
+                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny, const double* coeff,
+                              uint32_t n_terms, uint32_t blocks, double* epart, hipStream_t st) {
+  hipLaunchKernelGGL(k_hamiltonian, dim3(blocks, batch), dim3(256), 0, st, psi, lam, stride, n, xmask, zmask, ny,
+                     coeff, n_terms, blocks, epart);
   return hipGetLastError();
 }
 
-__global__ void k_energy_reduce(const double* __restrict__ tp, uint32_t n_terms, uint32_t blocks,
-                                const double* __restrict__ coeff, uint32_t batch, double* __restrict__ energy) {
-  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  double e = 0.0;
-  for (uint32_t t = 0; t < n_terms; ++t) {
-    double v = 0.0;
-    for (uint32_t k = 0; k < blocks; ++k) v += tp[((uint64_t)b * n_terms + t) * blocks + k];
-    e += coeff[t] * v;
+// energy[b] = sum over blk of epart[b][blk]: one workgroup per vector, strided
+// partial sums then a tree, both in a fixed order
+__global__ __launch_bounds__(256) void k_energy_sum(const double* __restrict__ epart, uint32_t blocks,
+                                                   double* __restrict__ energy) {
+  __shared__ double red[256];
+  const uint32_t tid = threadIdx.x, b = blockIdx.x;
+  double v = 0.0;
+  for (uint32_t k = tid; k < blocks; k += 256) v += epart[(uint64_t)b * blocks + k];
+  red[tid] = v;
+  __syncthreads();
+  for (uint32_t s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
   }
-  energy[b] = e;
+  if (tid == 0) energy[b] = red[0];
 }
 
-hipError_t launch_energy_reduce(const double* term_partials, uint32_t n_terms, uint32_t blocks,
-                                const double* coeff, uint32_t batch, double* energy, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_reduce, dim3((batch + 63) / 64), dim3(64), 0, st, term_partials, n_terms, blocks,
-                     coeff, batch, energy);
-  return hipGetLastError();
-}
-
-// lam = sum_j c_j P_j psi, terms accumulated in a fixed order per element:
-// (P psi)[i] = phase(i ^ x) * psi[i ^ x].
-__global__ void k_apply_hamiltonian(const double2* __restrict__ psi, double2* __restrict__ lam, uint64_t stride,
-                                    uint32_t n, const uint64_t* __restrict__ xmask,
-                                    const uint64_t* __restrict__ zmask, const uint32_t* __restrict__ ny,
-                                    const double* __restrict__ coeff, uint32_t n_terms, uint32_t batch) {
-  const uint64_t dim = 1ull << n, total = dim * batch;
-  for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t b = idx / dim, i = idx % dim;
-    const double2* st = psi + b * stride;
-    double2 acc = make_double2(0.0, 0.0);
-    for (uint32_t t = 0; t < n_terms; ++t) {
-      uint64_t src = i ^ xmask[t];
-      double2 v = st[src];
-      double sgn = (__popcll(src & zmask[t]) & 1) ? -1.0 : 1.0;
-      acc = cadd(acc, cscale(cmul(ipow(ny[t]), v), coeff[t] * sgn));
-    }
-    lam[b * stride + i] = acc;
-  }
-}
-
-hipError_t launch_apply_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
-                                    const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny,
-                                    const double* coeff, uint32_t n_terms, hipStream_t st) {
-  uint64_t total = (1ull << n) * batch;
-  uint64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_apply_hamiltonian, dim3((uint32_t)blocks), dim3(256), 0, st, psi, lam, stride, n, xmask,
-                     zmask, ny, coeff, n_terms, batch);
+hipError_t launch_energy_sum(const double* epart, uint32_t blocks, uint32_t batch, double* energy, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_sum, dim3(batch), dim3(256), 0, st, epart, blocks, energy);
   return hipGetLastError();
 }
 
@@ -435,6 +409,380 @@ hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uin
   }
   hipLaunchKernelGGL(k_backward_pass, grid, dim3(kTileThreads), lds, st, psi, lam, stride, gates, mats, dmats,
                      mat_stride, a, gpart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep of an all-dense pass on the matrix cores.
+//
+// A phase with gates G_1..G_m has the composed matrix W = G_m..G_1. With psi_a
+// and lambda_a the states after the phase, the sweep forms psi_b = W^dag psi_a
+// and lambda_b = W^dag lambda_a, and the derivative along angle j of G_i is
+//   2 Re <lambda_a| G_m..G_{i+1} G_i' G_{i-1}..G_1 |psi_b>
+//     = 2 Re <lambda_b| S |psi_b> = 2 Re tr(S C),
+// with S = W^dag G_m..G_i'..G_1 = (G_{i-1}..G_1)^dag G_i^dag G_i' (G_{i-1}..G_1)
+// (composed once per call) and C[r][c] = sum over amplitude groups g of
+// psi_b[r][g] conj(lambda_b[c][g]), a 16 x 16 product over the groups.
+// ---------------------------------------------------------------------------
+
+// derivative of a controlled gate: zero where the control C is clear, the
+// 2x2 derivative on target T where it is set
+template <int C, int T>
+__device__ __forceinline__ void r_dctrl(double2 (&a)[kR], const M2& u) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (!((k >> C) & 1)) {
+      a[k] = make_double2(0.0, 0.0);
+      continue;
+    }
+    if (k & (1 << T)) continue;
+    const int k1 = k | (1 << T);
+    const double2 x0 = a[k], x1 = a[k1];
+    a[k] = cmac2(u.a, x0, u.b, x1);
+    a[k1] = cmac2(u.c, x0, u.d, x1);
+  }
+}
+
+// the derivative matrix dm of a gate (one angle) on a thread's 16 amplitudes
+__device__ __forceinline__ void r_apply_deriv(double2 (&a)[kR], uint8_t type, int j0, int j1, const double* dm) {
+  const M2 u = load_m2(dm, 0);
+  if (type <= GT_X1) {
+    switch (j0) {
+      case 0: r_dense<0>(a, u); break;
+      case 1: r_dense<1>(a, u); break;
+      case 2: r_dense<2>(a, u); break;
+      default: r_dense<3>(a, u); break;
+    }
+    return;
+  }
+#define QSV_D2(C, T) \
+  case (C * 4 + T): r_dctrl<C, T>(a, u); break;
+  switch (j0 * 4 + j1) {
+    QSV_D2(0, 1) QSV_D2(0, 2) QSV_D2(0, 3)
+    QSV_D2(1, 0) QSV_D2(1, 2) QSV_D2(1, 3)
+    QSV_D2(2, 0) QSV_D2(2, 1) QSV_D2(2, 3)
+    QSV_D2(3, 0) QSV_D2(3, 1) QSV_D2(3, 2)
+    default: break;
+  }
+#undef QSV_D2
+}
+
+// a gate's inverse: the conjugate transpose of its 2x2 (a controlled phase's phase is conjugated)
+__device__ __forceinline__ void r_apply_dag(double2 (&a)[kR], const DGate& g, const double* m) {
+  const double md[8] = {m[0], -m[1], m[4], -m[5], m[2], -m[3], m[6], -m[7]};
+  r_apply(a, g.type, g.j0, g.j1, md);
+}
+
+// Column c of S for every angle entry and parameter vector (one thread each),
+// stored in matrix-core operand order like a composed phase matrix.
+__global__ __launch_bounds__(128) void k_compose_grad(const DGate* __restrict__ gates, const AngEnt* __restrict__ ent, uint32_t n_ent,
+                               uint32_t batch, uint64_t mat_stride, const double* __restrict__ mats,
+                               const double* __restrict__ dmats, double* __restrict__ smats) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n_ent * kR * batch) return;
+  const uint32_t c = (uint32_t)(idx % kR);
+  const uint64_t rest = idx / kR;
+  const uint32_t e = (uint32_t)(rest % n_ent), b = (uint32_t)(rest / n_ent);
+  const AngEnt en = ent[e];
+  const double* mb = mats + (uint64_t)b * mat_stride;
+  const double* db = dmats + (uint64_t)b * mat_stride * 3;
+  const uint32_t g0 = en.gate - en.off;
+  double2 v[kR];
+#pragma unroll
+  for (int k = 0; k < kR; ++k) v[k] = make_double2(k == (int)c ? 1.0 : 0.0, 0.0);
+  for (uint32_t i = 0; i < en.off; ++i) {
+    const DGate g = gates[g0 + i];
+    r_apply(v, g.type, g.j0, g.j1, mb + (uint64_t)g.mat * kMatStride);
+  }
+  const DGate gi = gates[en.gate];
+  r_apply_deriv(v, gi.type, gi.j0, gi.j1, db + (uint64_t)gi.mat * 3 * kMatStride + (uint64_t)en.j * kMatStride);
+  r_apply_dag(v, gi, mb + (uint64_t)gi.mat * kMatStride);
+  for (uint32_t i = en.off; i-- > 0;) {
+    const DGate g = gates[g0 + i];
+    r_apply_dag(v, g, mb + (uint64_t)g.mat * kMatStride);
+  }
+  double2* S = reinterpret_cast<double2*>(smats) + ((uint64_t)b * n_ent + e) * 256u;
+#pragma unroll
+  for (uint32_t r = 0; r < (uint32_t)kR; ++r) S[dense_pos(r, c)] = v[r];
+}
+
+hipError_t launch_compose_grad(const DGate* gates, const AngEnt* ent, uint32_t n_ent, uint32_t batch,
+                               uint64_t mat_stride, const double* mats, const double* dmats, double* smats,
+                               hipStream_t st) {
+  const uint64_t total = (uint64_t)n_ent * kR * batch;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_compose_grad, dim3((uint32_t)((total + 127) / 128)), dim3(128), 0, st, gates, ent, n_ent,
+                     batch, mat_stride, mats, dmats, smats);
+  return hipGetLastError();
+}
+
+// LDS slots: the slot of tile-local index l is swz(l); swz and the scatter of
+// bits over a mask are both linear over GF(2) (swz(a ^ b) = swz(a) ^ swz(b)),
+// so every slot a lane touches in a phase is a per-lane part, formed once per
+// phase, XOR a wave-uniform part (scalar registers).
+
+// the set bits of a wave-uniform mask, lowest first, one bit each (0 past the last)
+struct UBits {
+  uint32_t b[8];
+};
+__device__ __forceinline__ UBits ubits(uint32_t m) {
+  UBits u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    u.b[k] = m & (0u - m);
+    m &= m - 1u;
+  }
+  return u;
+}
+
+// bits 0..kBits-1 of x scattered over the first kBits set bits of the mask
+template <int kBits>
+__device__ __forceinline__ uint32_t udep(const UBits& u, uint32_t x) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < kBits; ++k) r |= ((x >> k) & 1u) ? u.b[k] : 0u;
+  return r;
+}
+
+// lane l's matrix-core B operand of conj(W) over the 4 K chunks: conj(W[4 kb + l / 16][l % 16])
+__device__ __forceinline__ void load_wfrag(double2 (&wf)[4], const double2* __restrict__ Wc, uint32_t lane) {
+  const uint32_t q = lane >> 4, j = lane & 15u;
+#pragma unroll
+  for (uint32_t kb = 0; kb < 4; ++kb) wf[kb] = Wc[dense_pos(4u * kb + q, j)];
+}
+
+// One phase of the sweep for the 32 amplitude groups (2 blocks of 16) of this
+// thread's wave, on the matrix cores. psi_b^T = psi_a^T conj(W): as the A
+// operand, lane l supplies psi_a[component 4 kb + l / 16][group l % 16] (kb =
+// 0..3), the amplitudes the forward phase reads; as the B operand it supplies
+// conj(W[4 kb + l / 16][l % 16]) (wf). Result element v of lane l is then
+// psi_b[component l % 16][group 4 v + l / 16], which is both the A operand
+// (psi_b) and, conjugated for lambda, the B operand of C over the K chunk of
+// groups 4 v..4 v + 3; results are written back from that layout. Complex
+// products use three real ones (as in the forward phase). The reads of block
+// 1 are issued before the writes of block 0; waves own disjoint groups.
+__device__ __forceinline__ void adjoint_phase_mfma(double2* __restrict__ tp, double2* __restrict__ tl, uint32_t T,
+                                                   uint32_t lane, uint32_t wave, const Phase& ph,
+                                                   const double2 (&wf)[4], qsv_d4& c1, qsv_d4& c2, qsv_d4& c3) {
+  constexpr uint32_t kBlocks = 2;
+  const uint32_t q = lane >> 4, j = lane & 15u;
+  const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
+  const UBits u = ubits((T - 1u) & ~(o0 | o1 | o2 | o3));
+  // group of block cb, K chunk v, lane: 32 wave + 16 cb + 4 v + q (writes) or 32 wave + 16 cb + j (reads)
+  const uint32_t pw = (((wave >> 0) & 1u) ? u.b[5] : 0u) | (((wave >> 1) & 1u) ? u.b[6] : 0u) |
+                      (((wave >> 2) & 1u) ? u.b[7] : 0u);
+  const uint32_t cqq = ((q & 1u) ? o0 : 0u) | ((q & 2u) ? o1 : 0u);
+  const uint32_t cj = ((j & 1u) ? o0 : 0u) | ((j & 2u) ? o1 : 0u) | ((j & 4u) ? o2 : 0u) | ((j & 8u) ? o3 : 0u);
+  const uint32_t rl = swz(udep<4>(u, j) | cqq);  // per-lane part of the read slots
+  const uint32_t wl = swz(udep<2>(u, q) | cj);   // per-lane part of the write slots
+  double wa[4], wb[4], ws[4];  // conj(W) = wa + i wb, and wa + wb
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    wa[kb] = wf[kb].x;
+    wb[kb] = -wf[kb].y;
+    ws[kb] = wf[kb].x - wf[kb].y;
+  }
+  double2 x[2][4], y[2][4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t sl = rl ^ swz(pw | ((k & 1u) ? o2 : 0u) | ((k & 2u) ? o3 : 0u));
+    x[0][k] = tp[sl];
+    y[0][k] = tl[sl];
+  }
+#pragma unroll
+  for (uint32_t cb = 0; cb < kBlocks; ++cb) {
+    const uint32_t s = cb & 1u;
+    qsv_d4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = p1, p3 = p1, l1 = p1, l2 = p1, l3 = p1;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s][kb].x, wa[kb], p1, 0, 0, 0);
+      p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s][kb].y, wb[kb], p2, 0, 0, 0);
+      p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s][kb].x + x[s][kb].y, ws[kb], p3, 0, 0, 0);
+      l1 = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s][kb].x, wa[kb], l1, 0, 0, 0);
+      l2 = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s][kb].y, wb[kb], l2, 0, 0, 0);
+      l3 = __builtin_amdgcn_mfma_f64_16x16x4f64(y[s][kb].x + y[s][kb].y, ws[kb], l3, 0, 0, 0);
+    }
+    if (cb + 1 < kBlocks) {
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t sl = rl ^ swz(pw | u.b[4] | ((k & 1u) ? o2 : 0u) | ((k & 2u) ? o3 : 0u));
+        x[s ^ 1u][k] = tp[sl];
+        y[s ^ 1u][k] = tl[sl];
+      }
+    }
+#pragma unroll
+    for (uint32_t v = 0; v < 4; ++v) {
+      const double pr = p1[v] - p2[v], pi = p3[v] - p1[v] - p2[v];
+      const double lr = l1[v] - l2[v], li = l3[v] - l1[v] - l2[v];
+      // C += psi_b conj(lambda_b) over groups 4 v..4 v + 3 of the block
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, lr, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pi, -li, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(pr + pi, lr - li, c3, 0, 0, 0);
+      const uint32_t sl =
+          wl ^ swz(pw | (cb ? u.b[4] : 0u) | ((v & 1u) ? u.b[2] : 0u) | ((v & 2u) ? u.b[3] : 0u));
+      tp[sl] = make_double2(pr, pi);
+      tl[sl] = make_double2(lr, li);
+    }
+  }
+}
+
+// Sums a[0..7] over the 64 lanes of the wave; lane l returns the sum of
+// a[l >> 3]. Three exchange steps each hand half of the remaining values to
+// the partner lane (xor 32, 16, 8), then a butterfly over the last 3 bits:
+// 10 shuffles instead of 48.
+__device__ __forceinline__ double wave_sum8(const double (&a)[8], uint32_t lane) {
+  const bool h5 = (lane >> 5) & 1u, h4 = (lane >> 4) & 1u, h3 = (lane >> 3) & 1u;
+  double b[4], c[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = h5 ? a[4 + i] : a[i], send = h5 ? a[i] : a[4 + i];
+    b[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = h4 ? b[2 + i] : b[i], send = h4 ? b[i] : b[2 + i];
+    c[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  double d = (h3 ? c[1] : c[0]) + __shfl_xor(h3 ? c[0] : c[1], 8, 64);
+  d += __shfl_xor(d, 4, 64);
+  d += __shfl_xor(d, 2, 64);
+  d += __shfl_xor(d, 1, 64);
+  return d;
+}
+
+// Persistent workgroups of 2^(t-3) threads (8 amplitudes of psi and of lambda
+// per thread) over the items (vector, tile) of an all-dense pass with
+// 10 <= t <= 12. Phases run in reverse order; after each, every wave reduces
+// 2 Re tr(S C) per angle of the phase over its lanes, and the waves' values
+// are summed in a fixed order into gpart[vector][tile][gate][angle].
+__global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
+    double2* __restrict__ psi, double2* __restrict__ lam, uint64_t stride, const Phase* __restrict__ phases,
+    const uint32_t* __restrict__ ang_off, const AngEnt* __restrict__ ent, const double* __restrict__ mats,
+    uint64_t mat_stride, const double* __restrict__ smats, uint32_t n_ent, PassArgs a, uint32_t batch,
+    double* __restrict__ gpart) {
+  extern __shared__ double2 lds[];
+  const uint32_t tid = threadIdx.x, T = 1u << a.t, nthr = T >> 3, nwaves = nthr >> 6;
+  const uint32_t lane = tid & 63u, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double2* const tp = lds;
+  double2* const tl = lds + T;
+  double* const red = reinterpret_cast<double*>(lds + 2 * T);  // [2][kBwWaves][kMaxPhaseAngles]
+  const uint64_t total = (uint64_t)a.tiles * batch, G = gridDim.x;
+  const uint64_t free_mask = ~a.tile_mask & ((a.n >= 64) ? ~0ull : ((1ull << a.n) - 1ull));
+  uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..t-4]
+  for (uint32_t bb = 0; bb + 3 < a.t; ++bb) tb |= (uint64_t)((tid >> bb) & 1u) << a.tq[bb];
+  const uint64_t h0 = 1ull << a.tq[a.t - 3], h1 = 1ull << a.tq[a.t - 2], h2 = 1ull << a.tq[a.t - 1];
+  for (uint64_t it = blockIdx.x; it < total; it += G) {
+    const uint32_t b = (uint32_t)(it / a.tiles), w = (uint32_t)(it % a.tiles);
+    const uint64_t gthr = tile_base(w, free_mask) | tb;
+    double2* sp = psi + (uint64_t)b * stride;
+    double2* sl = lam + (uint64_t)b * stride;
+    double2 rp[8], rl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
+      rp[k] = sp[gi];
+      rl[k] = sl[gi];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      tp[swz(tid + (uint32_t)k * nthr)] = rp[k];
+      tl[swz(tid + (uint32_t)k * nthr)] = rl[k];
+    }
+    const double* mb = mats + (uint64_t)b * mat_stride;
+    const double2* sb = reinterpret_cast<const double2*>(smats) + (uint64_t)b * n_ent * 256u;
+    double* gp = gpart + ((uint64_t)b * a.tiles + w) * a.gate_count * 3;
+    double2 wf[4];
+    load_wfrag(wf, reinterpret_cast<const double2*>(
+                       mb + (uint64_t)load_phase(phases + a.phase_begin + a.phase_count - 1).dense * kMatStride),
+               lane);
+    __syncthreads();
+    for (uint32_t p = a.phase_count; p-- > 0;) {
+      const uint32_t pg = a.phase_begin + p;
+      const Phase ph = load_phase(phases + pg);
+      double2 wn[4];  // the next phase's operand, requested before this phase's products
+      if (p > 0)
+        load_wfrag(wn, reinterpret_cast<const double2*>(mb + (uint64_t)load_phase(phases + pg - 1).dense * kMatStride),
+                   lane);
+      const uint32_t e0 = cst(ang_off)[pg], ne = cst(ang_off)[pg + 1] - e0;
+      // the gradient slot this thread fills after the phase, requested before the products
+      uint32_t gslot = 0;
+      if (tid < ne) {
+        const AngEnt en = ent[e0 + tid];
+        gslot = (en.gate - a.gate_begin) * 3u + en.j;
+      }
+      qsv_d4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
+      adjoint_phase_mfma(tp, tl, T, lane, wave, ph, wf, c1, c2, c3);
+      double cr[4], ci[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cr[v] = c1[v] - c2[v];
+        ci[v] = c3[v] - c1[v] - c2[v];
+      }
+      double* rw = red + ((p & 1u) * kBwWaves + wave) * kMaxPhaseAngles;
+      for (uint32_t e = 0; e < ne; e += 8) {
+        double part[8];
+#pragma unroll
+        for (uint32_t uu = 0; uu < 8; ++uu) {
+          part[uu] = 0.0;
+          if (e + uu < ne) {
+            const double2* S = sb + (uint64_t)(e0 + e + uu) * 256u;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double2 sv = S[v * 64 + (int)lane];
+              part[uu] += sv.x * cr[v] - sv.y * ci[v];
+            }
+          }
+        }
+        const double tot = wave_sum8(part, lane);
+        if ((lane & 7u) == 0 && e + (lane >> 3) < ne) rw[e + (lane >> 3)] = tot;
+      }
+      __syncthreads();
+      // the waves' values of this phase, summed in wave order
+      if (tid < ne) {
+        const double* rp0 = red + (p & 1u) * kBwWaves * kMaxPhaseAngles;
+        double sum = 0.0;
+        for (uint32_t ww = 0; ww < nwaves; ++ww) sum += rp0[ww * kMaxPhaseAngles + tid];
+        gp[gslot] = 2.0 * sum;
+      }
+      if (p > 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wf[k] = wn[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      rp[k] = tp[swz(tid + (uint32_t)k * nthr)];
+      rl[k] = tl[swz(tid + (uint32_t)k * nthr)];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
+      sp[gi] = rp[k];
+      sl[gi] = rl[k];
+    }
+    __syncthreads();
+  }
+}
+
+// Dynamic LDS of k_backward_mfma for tiles of 2^t amplitudes.
+size_t backward_mfma_lds(uint32_t t) {
+  return (size_t)2 * sizeof(double2) * (1u << t) + (size_t)2 * kBwWaves * kMaxPhaseAngles * sizeof(double);
+}
+
+hipError_t launch_backward_mfma(double2* psi, double2* lam, uint64_t stride, uint32_t batch, const Phase* phases,
+                                const uint32_t* ang_off, const AngEnt* ent, const double* mats, uint64_t mat_stride,
+                                const double* smats, uint32_t n_ent, const PassArgs& a, double* gpart,
+                                hipStream_t st) {
+  const uint64_t total = (uint64_t)a.tiles * batch;
+  if (!total) return hipSuccess;
+  const size_t lds = backward_mfma_lds(a.t);
+  uint32_t g = 0;
+  hipError_t e = resident_grid((const void*)k_backward_mfma, 1u << (a.t - 3), lds,
+                               backward_mfma_lds(kTileMaxBits), &g);
+  if (e != hipSuccess) return e;
+  if ((uint64_t)g > total) g = (uint32_t)total;
+  hipLaunchKernelGGL(k_backward_mfma, dim3(g), dim3(1u << (a.t - 3)), lds, st, psi, lam, stride, phases, ang_off,
+                     ent, mats, mat_stride, smats, n_ent, a, batch, gpart);
   return hipGetLastError();
 }
 

@@ -71,6 +71,12 @@ struct qsv_program {
   uint32_t* d_csr_sj = nullptr;
   double* d_csr_scale = nullptr;
   uint32_t pblocks = 1;
+  // matrix-core adjoint sweep: angle entries of the dense phases of eligible
+  // passes, and per phase the first entry (ang_off[phase + 1] ends it)
+  AngEnt* d_ang_ent = nullptr;
+  uint32_t* d_ang_off = nullptr;
+  uint32_t n_ang_ent = 0;
+  std::vector<uint8_t> bw_mfma;  // per pass: swept on the matrix cores
 };
 
 namespace {
@@ -284,7 +290,36 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
       }
     }
   }
+  // angle entries for the matrix-core adjoint sweep (all-dense passes of
+  // 2^10..2^12-amplitude tiles whose phases have at most kMaxPhaseAngles angles)
+  std::vector<AngEnt> ang;
+  std::vector<uint32_t> ang_off(pl.phases.size() + 1, 0);
+  p->bw_mfma.assign(pl.passes.size(), 0);
+  {
+    std::vector<uint32_t> cnt(pl.phases.size(), 0);
+    for (size_t k = 0; k < pl.passes.size(); ++k) {
+      if (!mfma_sweep_pass(pl, k)) continue;
+      p->bw_mfma[k] = 1;
+      const PassArgs& a = pl.passes[k];
+      for (uint32_t q = 0; q < a.phase_count; ++q) {
+        const uint32_t pg = a.phase_begin + q;
+        const Phase& ph = pl.phases[pg];
+        for (uint32_t i = 0; i < ph.gate_count; ++i) cnt[pg] += pl.gates[ph.gate_begin + i].nang;
+      }
+    }
+    for (size_t pg = 0; pg < pl.phases.size(); ++pg) {
+      ang_off[pg + 1] = ang_off[pg] + cnt[pg];
+      const Phase& ph = pl.phases[pg];
+      if (!cnt[pg]) continue;
+      for (uint32_t i = 0; i < ph.gate_count; ++i)
+        for (uint32_t j = 0; j < pl.gates[ph.gate_begin + i].nang; ++j)
+          ang.push_back(AngEnt{ph.gate_begin + i, (uint16_t)i, (uint8_t)j, 0});
+    }
+  }
+  p->n_ang_ent = (uint32_t)ang.size();
   hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(ang, &p->d_ang_ent);
+  if (e == hipSuccess && std::count(p->bw_mfma.begin(), p->bw_mfma.end(), 1)) e = upload(ang_off, &p->d_ang_off);
   if (e == hipSuccess) e = upload(pl.gates, &p->d_gates);
   if (e == hipSuccess) e = upload(pl.phases, &p->d_phases);
   {
@@ -326,7 +361,7 @@ qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) 
 void qsv_program_free(qsv_program* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
-  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale};
+  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -718,11 +753,23 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, dim / 4096));
   // vectors per chunk: states (x2 with a gradient) must fit
   size_t per = dim * 16 * (grad ? 2 : 1) + (size_t)n_slots * kMatStride * 8 * (grad ? 4 : 1) +
-               (size_t)T * blocks * 8 + P * 16 + 4096;
+               (size_t)blocks * 8 + P * 16 + 4096;
+  // the matrix-core sweep needs its LDS on this device
+  bool lds_ok = false;
   if (grad) {
-    size_t maxg = 0;
-    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)backward_parts(a) * a.gate_count * 3);
-    per += maxg * 8 + (size_t)n_slots * 3 * 8;
+    int l1 = 0, l2 = 0;
+    HIP_TRY(hipDeviceGetAttribute(&l1, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    HIP_TRY(hipDeviceGetAttribute(&l2, hipDeviceAttributeSharedMemPerBlockOptin, ctx->device));
+    lds_ok = (size_t)std::max(l1, l2) >= backward_mfma_lds(kTileMaxBits);
+  }
+  auto on_mfma = [&](size_t k) { return lds_ok && prog->bw_mfma[k] != 0; };
+  auto parts_of = [&](size_t k) { return on_mfma(k) ? pl.passes[k].tiles : backward_parts(pl.passes[k]); };
+  const uint32_t n_ent = lds_ok ? prog->n_ang_ent : 0;
+  size_t maxg = 1;
+  if (grad) {
+    for (size_t k = 0; k < pl.passes.size(); ++k)
+      maxg = std::max<size_t>(maxg, (size_t)parts_of(k) * pl.passes[k].gate_count * 3);
+    per += maxg * 8 + (size_t)n_slots * 3 * 8 + (size_t)n_ent * 256 * 16;
   }
   size_t budget = ctx->arena ? ctx->arena_bytes : (free_device_bytes() / 10) * 8;
   uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(batch, (budget > 65536 ? budget - 65536 : 0) / per));
@@ -745,15 +792,15 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   double2* d_lam = nullptr;
   HIP_TRY(scr.get(chunk * std::max<uint32_t>(P, 1), &d_theta));
   HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * kMatStride, &d_mats));
-  HIP_TRY(scr.get(chunk * std::max<uint32_t>(T, 1) * blocks, &d_tp));
+  HIP_TRY(scr.get(chunk * blocks, &d_tp));
   HIP_TRY(scr.get(chunk, &d_energy));
   HIP_TRY(scr.get(chunk * dim, &rb.state));
   HIP_TRY(scr.get(chunk, &rb.ctl));
   HIP_TRY(scr.get(chunk, &rb.creg));
+  double* d_smats = nullptr;
   if (grad) {
-    size_t maxg = 1;
-    for (const PassArgs& a : pl.passes) maxg = std::max<size_t>(maxg, (size_t)backward_parts(a) * a.gate_count * 3);
     HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * 3 * kMatStride, &d_dmats));
+    if (n_ent) HIP_TRY(scr.get(chunk * n_ent * 512, &d_smats));
     HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * 3, &d_dEda));
     HIP_TRY(scr.get(chunk * maxg, &d_gpart));
     HIP_TRY(scr.get(chunk * std::max<uint32_t>(P, 1), &d_grad));
@@ -771,6 +818,8 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
     HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, P, bs, d_mats, d_dmats, st));
     HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, bs,
                                  ms, d_mats, st));
+    if (grad && n_ent)
+      HIP_TRY(launch_compose_grad(prog->d_gates, prog->d_ang_ent, n_ent, bs, ms, d_mats, d_dmats, d_smats, st));
     HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, 1, nullptr, 0, bs, st));
     for (const Step& step : pl.steps) {
       Prof pr(ctx, st);
@@ -784,23 +833,29 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
                 pl.pass_flops_per_amp[step.index] * amps);
       }
     }
+    // lambda = H psi (kept for the gradient) and the energy Re <psi|lambda> in one sweep
     if (T) {
-      HIP_TRY(launch_pauli_terms(rb.state, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, d_tp, blocks, st));
-      HIP_TRY(launch_energy_reduce(d_tp, T, blocks, hd.c, bs, d_energy, st));
+      HIP_TRY(launch_hamiltonian(rb.state, grad ? d_lam : nullptr, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, blocks,
+                                 d_tp, st));
+      HIP_TRY(launch_energy_sum(d_tp, blocks, bs, d_energy, st));
     } else {
       HIP_TRY(hipMemsetAsync(d_energy, 0, bs * 8, st));
+      if (grad) HIP_TRY(hipMemsetAsync(d_lam, 0, (size_t)bs * dim * sizeof(double2), st));
     }
     if (grad) {
-      HIP_TRY(launch_apply_hamiltonian(rb.state, d_lam, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, st));
       HIP_TRY(hipMemsetAsync(d_dEda, 0, (size_t)bs * std::max<uint32_t>(n_slots, 1) * 3 * 8, st));
       for (size_t k = pl.steps.size(); k-- > 0;) {
         const Step& step = pl.steps[k];
         if (step.kind != Step::PASS) continue;
         const PassArgs& a = pl.passes[step.index];
         Prof pr(ctx, st);
-        HIP_TRY(launch_backward_pass(rb.state, d_lam, dim, bs, prog->d_gates, prog->d_phases, d_mats, d_dmats, ms, a,
-                                     d_gpart, st));
-        HIP_TRY(launch_grad_reduce(d_gpart, backward_parts(a), a.gate_count, 0, prog->d_gates + a.gate_begin, bs,
+        if (on_mfma(step.index))
+          HIP_TRY(launch_backward_mfma(rb.state, d_lam, dim, bs, prog->d_phases, prog->d_ang_off, prog->d_ang_ent,
+                                       d_mats, ms, d_smats, n_ent, a, d_gpart, st));
+        else
+          HIP_TRY(launch_backward_pass(rb.state, d_lam, dim, bs, prog->d_gates, prog->d_phases, d_mats, d_dmats, ms,
+                                       a, d_gpart, st));
+        HIP_TRY(launch_grad_reduce(d_gpart, parts_of(step.index), a.gate_count, 0, prog->d_gates + a.gate_begin, bs,
                                    std::max<uint32_t>(n_slots, 1), d_dEda, st));
         pr.done(2);
       }
@@ -899,6 +954,7 @@ qsv_status qsv_plan_inspect(const qsv_program_desc* desc, uint32_t tile_bits, qs
   uint32_t g = 0;
   out->n_phases = (uint32_t)pl.phases.size();
   out->n_dense_phases = (uint32_t)pl.dense_phases.size();
+  for (size_t k = 0; k < pl.passes.size(); ++k) out->n_mfma_sweep_passes += mfma_sweep_pass(pl, k) ? 1u : 0u;
   for (const Step& s : pl.steps) {
     if (s.kind != Step::PASS) continue;
     const PassArgs& a = pl.passes[s.index];

@@ -51,20 +51,27 @@ hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint3
                              uint64_t* out_creg, uint32_t cw, uint8_t* out_rec, uint32_t rec_max, hipStream_t st);
 
 // Expectation values and adjoint gradients over a batch of parameter vectors.
-hipError_t launch_pauli_terms(const double2* psi, uint64_t stride, uint32_t n, uint32_t batch,
-                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny,
-                              const double* coeff, uint32_t n_terms, double* term_partials,
-                              uint32_t blocks, hipStream_t st);
-hipError_t launch_energy_reduce(const double* term_partials, uint32_t n_terms, uint32_t blocks,
-                                const double* coeff, uint32_t batch, double* energy, hipStream_t st);
-hipError_t launch_apply_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n,
-                                    uint32_t batch, const uint64_t* xmask, const uint64_t* zmask,
-                                    const uint32_t* ny, const double* coeff, uint32_t n_terms,
-                                    hipStream_t st);
+// lambda = H psi (lam may be null) and per-slice partials of Re <psi|H psi>
+// (epart[batch][blocks]); launch_energy_sum reduces them to energy[batch].
+hipError_t launch_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
+                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny, const double* coeff,
+                              uint32_t n_terms, uint32_t blocks, double* epart, hipStream_t st);
+hipError_t launch_energy_sum(const double* epart, uint32_t blocks, uint32_t batch, double* energy, hipStream_t st);
 hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uint32_t batch,
                                 const DGate* gates, const Phase* phases, const double* mats, const double* dmats,
                                 uint64_t mat_stride, const PassArgs& a, double* gpart, hipStream_t st);
 uint32_t backward_parts(const PassArgs& a);
+// Matrix-core adjoint sweep of all-dense passes with 10 <= t <= 12: S matrices
+// of the angle entries (per vector, 256 complex each), then the sweep, which
+// writes per-tile partials (backward_parts = tiles).
+hipError_t launch_compose_grad(const DGate* gates, const AngEnt* ent, uint32_t n_ent, uint32_t batch,
+                               uint64_t mat_stride, const double* mats, const double* dmats, double* smats,
+                               hipStream_t st);
+size_t backward_mfma_lds(uint32_t t);
+hipError_t launch_backward_mfma(double2* psi, double2* lam, uint64_t stride, uint32_t batch, const Phase* phases,
+                                const uint32_t* ang_off, const AngEnt* ent, const double* mats, uint64_t mat_stride,
+                                const double* smats, uint32_t n_ent, const PassArgs& a, double* gpart,
+                                hipStream_t st);
 hipError_t launch_grad_reduce(const double* gpart, uint32_t parts, uint32_t gate_count,
                               uint32_t slot_begin_of_pass, const DGate* gates, uint32_t batch,
                               uint32_t n_slots, double* dEda, hipStream_t st);

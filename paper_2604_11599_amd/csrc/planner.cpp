@@ -497,4 +497,18 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
   return plan;
 }
 
+bool mfma_sweep_pass(const Plan& pl, size_t k) {
+  const PassArgs& a = pl.passes[k];
+  if (!pl.unitary || !a.phase_count || !a.all_dense || a.t < kDenseMinTileBits || a.t > (uint32_t)kTileMaxBits)
+    return false;
+  for (uint32_t q = 0; q < a.phase_count; ++q) {
+    const Phase& ph = pl.phases[a.phase_begin + q];
+    if (ph.gate_count > 65535u) return false;
+    uint32_t na = 0;
+    for (uint32_t i = 0; i < ph.gate_count; ++i) na += pl.gates[ph.gate_begin + i].nang;
+    if (na > kMaxPhaseAngles) return false;
+  }
+  return true;
+}
+
 }  // namespace qsv

@@ -54,4 +54,9 @@ bool validate_program(const qsv_program_desc& d, std::string* err);
 // Builds the plan. The stream must have passed validate_program.
 Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt);
 
+// Whether the adjoint sweep of pass k can run on the matrix cores: a unitary
+// program, every phase of the pass dense, 2^10..2^12 amplitudes per tile and
+// at most kMaxPhaseAngles differentiated angles per phase.
+bool mfma_sweep_pass(const Plan& pl, size_t k);
+
 }  // namespace qsv

@@ -61,6 +61,19 @@ constexpr int kDenseDoubles = 16 * 16 * 2;
 constexpr int kDenseSlots = kDenseDoubles / kMatStride;
 constexpr uint32_t kDenseMinTileBits = 10;  // full 64-lane waves of amplitude groups
 constexpr uint32_t kLdsDensePhases = 4;     // dense phases a pass keeps in LDS (4 KiB each)
+// One differentiated angle of a gate inside a dense phase. For the phase's
+// gates G_1..G_m (applied in that order) and angle j of gate G_i, the adjoint
+// sweep uses S = (G_{i-1}..G_1)^dag G_i^dag (dG_i/d angle_j) (G_{i-1}..G_1),
+// composed per parameter vector and stored like a dense phase matrix.
+struct AngEnt {     // 8 bytes
+  uint32_t gate;    // index of G_i in the plan's gate array
+  uint16_t off;     // number of gates of the phase before G_i (they start at gate - off)
+  uint8_t j;        // angle of G_i
+  uint8_t pad;
+};
+constexpr uint32_t kMaxPhaseAngles = 3 * kPhaseMaxGates;  // angles of one phase (at most 3 per gate)
+constexpr uint32_t kBwWaves = 8;          // waves of that sweep's workgroup at 2^12 amplitudes
+
 struct Phase {      // 16 bytes
   uint8_t r[kRegBits];
   uint32_t gate_begin, gate_count;

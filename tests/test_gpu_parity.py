@@ -233,6 +233,28 @@ def test_expval_and_gradient_small(ctx):
     assert np.max(np.abs(g[0] - gp)) < 1e-11
 
 
+def test_gradient_matrix_core_sweep(ctx):
+    """Passes of 2^10..2^12-amplitude tiles whose phases are all dense take the
+    adjoint sweep on the matrix cores (tiles of 10, 11 and 12 bits, one to five
+    passes, U and controlled rotations and phases inside the dense phases)."""
+    from paper_2604_11599_amd import lower
+    from paper_2604_11599_amd.api import plan_inspect
+    cases = [(W.c4_ansatz(10, 2), 10, 40), (W.c4_ansatz(12, 3), 12, 72), (W.c4_ansatz(14, 4), 14, 112),
+             (W.param_program(5, 11, 70, 24), 11, 24), (W.param_program(7, 13, 120, 40), 13, 40),
+             (W.param_program(9, 14, 160, 50), 14, 50)]
+    for src, n, P in cases:
+        st = plan_inspect(lower(src), 0)
+        assert st.n_mfma_sweep_passes == st.n_passes > 0
+        coeffs, codes = W.c4_hamiltonian(seed=n, n=n, terms=16)
+        thetas = W.c4_thetas(seed=100 + n, batch=3, n_params=P)
+        say("matrix-core sweep case", n, "qubits", P, "params", st.n_passes, "passes")
+        e, g = ctx.load(src).expval_grad(thetas, coeffs, codes)
+        for b in range(3):
+            eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
+            assert abs(e[b] - eo) < 1e-12
+            assert np.max(np.abs(g[b] - go)) < 1e-11
+
+
 def test_expval_closed_form_and_general_gates(ctx):
     prog = ctx.load(W.hea2_program())
     ab = np.array([[0.3, 1.1], [2.0, -0.4]])

@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.RunOpts) == 40
     assert ctypes.sizeof(_abi.ShotResults) == 40
     assert ctypes.sizeof(_abi.PauliSum) == 24
-    assert ctypes.sizeof(_abi.PlanStats) == 315424 + 8 * 65536 + 8
+    assert ctypes.sizeof(_abi.PlanStats) == 315424 + 8 * 65536 + 16
     from paper_2604_11599_amd.lower import INSTR_DTYPE, PRED_DTYPE
     assert INSTR_DTYPE.itemsize == 96 and PRED_DTYPE.itemsize == 24
 

@@ -390,3 +390,31 @@ def hea2_program():
     """Two-qubit ansatz RY(a) q0, RY(b) q1, CX(0,1) with runtime inputs a, b."""
     return (HEADER + "input float[64] a;\ninput float[64] b;\nqubit[2] q;\n"
             "ry(a) q[0];\nry(b) q[1];\ncx q[0], q[1];\n")
+
+
+def param_program(seed, n, n_gates, n_params):
+    """Random parameterised unitary circuit over `n_params` runtime inputs t[k]:
+    U, rx, ry, rz, p, crx, cry, crz, cp with angles t[k], 2 * t[k], t[k] + 0.3
+    or -t[k], mixed with h, cx, swap and sx on uniform random qubits."""
+    rng = _rng(seed)
+    lines = [HEADER, f"input array[float[64], {n_params}] t;", f"qubit[{n}] q;"]
+
+    def ang():
+        k = int(rng.integers(n_params))
+        return (f"t[{k}]", f"2 * t[{k}]", f"t[{k}] + 0.3", f"-t[{k}]")[int(rng.integers(4))]
+
+    for _ in range(n_gates):
+        kind = int(rng.integers(13))
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        if kind == 0:
+            lines.append(f"U({ang()}, {ang()}, {ang()}) q[{a}];")
+        elif kind <= 4:
+            lines.append(f"{('rx', 'ry', 'rz', 'p')[kind - 1]}({ang()}) q[{a}];")
+        elif kind <= 8:
+            lines.append(f"{('crx', 'cry', 'crz', 'cp')[kind - 5]}({ang()}) q[{a}], q[{b}];")
+        elif kind <= 10:
+            lines.append(f"{('cx', 'swap')[kind - 9]} q[{a}], q[{b}];")
+        else:
+            lines.append(f"{('h', 'sx')[kind - 11]} q[{a}];")
+    return "\n".join(lines) + "\n"
+
