@@ -314,7 +314,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for s in range(args.steps):
-        prog.run_shots(shots, seed=s, share_prefix=True)
+        prog.run_shots(shots, seed=s, share=True)
     torch.cuda.synchronize()
     dt_sp = time.perf_counter() - t1
     shared = {"value": shots * args.steps / dt_sp, "unit": "shots/s", "ms_per_step": 1e3 * dt_sp / args.steps,

@@ -67,7 +67,8 @@ typedef struct {
   uint32_t flags;      /* QSV_FLAG_* */
 } qsv_config;
 
-/* Creates a context on cfg->device. *out is owned by the caller; free with qsv_destroy. */
+/* Creates a context on cfg->device. *out is owned by the caller; free with qsv_destroy
+   after every program loaded into it has been freed with qsv_program_free. */
 qsv_status qsv_create(const qsv_config* cfg, qsv_context** out);
 void qsv_destroy(qsv_context* ctx);
 /* Message of the last failed call on ctx; owned by ctx, valid until the next call. */
@@ -162,11 +163,14 @@ void qsv_program_free(qsv_program* prog);
 /* ------------------------------------------------------------------------ */
 /* Shots                                                                     */
 /* ------------------------------------------------------------------------ */
-/* QSV_RUN_SHARE_PREFIX: the steps before the first measurement or reset draw no
-   randomness and are identical for every shot; run them once per batch and copy
-   the state to the other shots (shot branching). Results are bit-identical to
-   running every shot in full. */
-enum { QSV_RUN_SHARE_PREFIX = 1u };
+/* QSV_RUN_SHARE_TRAJ: shots whose measurement and reset outcomes (and so
+   classical bits, flags and records) are identical so far share one state:
+   gate passes run once per distinct history, a site's histogram is taken once
+   per history and every shot still draws its own outcome from its own Philox
+   stream; a history splits where its shots' outcomes differ. A split copies the
+   state only before the next gate pass writes it, so a final measure-all adds
+   no copies. Results are bit-identical to running every shot on its own. */
+enum { QSV_RUN_SHARE_TRAJ = 1u };
 
 typedef struct {
   uint64_t seed;         /* Philox key word 0 */

@@ -1,5 +1,6 @@
 """Python binding of libqsv with the C ABI's names (argument marshalling only)."""
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -51,9 +52,14 @@ class Context:
             raise QsvError(rc, "qsv_create failed")
         self.handle = h
         self.device_ptrs = device_ptrs
+        self._programs = weakref.WeakSet()
 
     def close(self):
+        """Frees the context's programs that are still alive, then the context
+        (a program must not outlive its context)."""
         if self.handle:
+            for p in list(self._programs):
+                p.free()
             A.lib().qsv_destroy(self.handle)
             self.handle = None
 
@@ -135,13 +141,15 @@ class Program:
         h = C.c_void_p()
         ctx.check(A.lib().qsv_load_program(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
+        ctx._programs.add(self)
         info = A.ProgramInfo()
         A.lib().qsv_program_info_get(h, C.byref(info))
         self.info = info
 
     def free(self):
         if self.handle:
-            A.lib().qsv_program_free(self.handle)
+            if self.ctx.handle:
+                A.lib().qsv_program_free(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -184,7 +192,7 @@ class Program:
         return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
-                  share_prefix=False):
+                  share=False):
         """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses."""
         lp = self.lowered
         cw = max(1, (lp.n_clbits + 63) // 64)
@@ -208,7 +216,7 @@ class Program:
             flen = f.shape[1]
         st = np.zeros((1 << lp.n_qubits, 2), dtype=np.float64) if state_out else None
         opts = A.RunOpts(seed & 0xFFFFFFFFFFFFFFFF, shot_offset, _ptr(f), flen,
-                         A.QSV_RUN_SHARE_PREFIX if share_prefix else 0, _ptr(st))
+                         A.QSV_RUN_SHARE_TRAJ if share else 0, _ptr(st))
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
         self.ctx.check(A.lib().qsv_run_shots(self.ctx.handle, self.handle, _ptr(th), n_shots,
                                              C.byref(opts), C.byref(res)))

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <unordered_map>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -408,7 +409,11 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, 1, 0,
                                d_mats, st));
   RunBuffers rb{};
-  HIP_TRY(scr.get(batch * dim, &rb.state));
+  // state buffers: one per shot, or with trajectory sharing one per slot that
+  // owns its state, grown on demand (doubling) up to one per shot
+  const bool share_req = (opts->flags & QSV_RUN_SHARE_TRAJ) != 0;
+  uint64_t cap = (share_req && batch > 1) ? std::min<uint64_t>(batch, 8) : batch;
+  HIP_TRY(scr.get(cap * dim, &rb.state));
   HIP_TRY(scr.get(batch, &rb.ctl));
   HIP_TRY(scr.get(batch * cw, &rb.creg));
   HIP_TRY(scr.get(batch * maxrec, &rb.record));
@@ -425,65 +430,161 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   rb.forced_len = opts->forced_len;
   rb.seed = opts->seed;
   std::vector<ShotCtl> hctl(batch);
-  // steps before the first site that draws randomness are identical for every shot
-  size_t prefix_end = 0;
-  if (opts->flags & QSV_RUN_SHARE_PREFIX) {
-    while (prefix_end < pl.steps.size()) {
-      const Step& s = pl.steps[prefix_end];
-      if (s.kind == Step::SITE && pl.sites[s.index].nq > 0) break;
-      ++prefix_end;
-    }
+  // trajectory sharing: slot g holds one state (buffer buf_of[g]) and control
+  // block for every shot s with slot_of[s] == g, i.e. the same history so far
+  ShotCtl* d_slot_ctl = nullptr;
+  uint32_t *d_slot_of = nullptr, *d_buf_of = nullptr, *d_rep = nullptr, *d_pairs = nullptr;
+  if (share_req && batch > 1) {
+    HIP_TRY(scr.get(batch, &d_slot_ctl));
+    HIP_TRY(scr.get(batch, &d_slot_of));
+    HIP_TRY(scr.get(batch, &d_buf_of));
+    HIP_TRY(scr.get(batch, &d_rep));
+    HIP_TRY(scr.get(2 * batch, &d_pairs));
   }
+  std::vector<uint32_t> slot_of, buf_of, rep, pairs;
+  std::vector<uint64_t> hcreg;
+  std::vector<uint8_t> hrec;
+  // room for `need` state buffers; a larger allocation takes over the current ones
+  auto ensure_capacity = [&](uint64_t need) -> qsv_status {
+    if (need <= cap) return QSV_OK;
+    const uint64_t ncap = std::min<uint64_t>(batch, std::max<uint64_t>(2 * cap, need));
+    double2* ns = nullptr;
+    HIP_TRY(scr.get(ncap * dim, &ns));
+    HIP_TRY(hipMemcpyAsync(ns, rb.state, cap * state_bytes, hipMemcpyDeviceToDevice, st));
+    rb.state = ns;
+    cap = ncap;
+    return QSV_OK;
+  };
   for (uint64_t s0 = 0; s0 < n_shots; s0 += batch) {
     const uint32_t bs = (uint32_t)std::min<uint64_t>(batch, n_shots - s0);
+    const bool share = share_req && bs > 1;
     rb.shots = bs;
     rb.shot_base = opts->shot_offset + s0;
     if (opts->forced_len)
       HIP_TRY(hipMemcpyAsync(d_forced, opts->forced + s0 * opts->forced_len, (size_t)bs * opts->forced_len,
                              hipMemcpyHostToDevice, st));
     HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, rb.record, maxrec, bs, st));
-    size_t first = 0;
-    if (prefix_end > 0 && bs > 1) {
-      // shot branching: the prefix runs once (shot 0) and is copied to the other shots
-      RunBuffers r1 = rb;
-      r1.shots = 1;
-      for (size_t k = 0; k < prefix_end; ++k) {
-        const Step& step = pl.steps[k];
-        Prof pr(ctx, st);
-        if (step.kind == Step::INIT) {
-          HIP_TRY(launch_init_state(r1.state, r1.stride, n, 1, st));
-          pr.done(2);
-        } else if (step.kind == Step::PASS) {
-          HIP_TRY(launch_tile_pass(r1, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
-          pr.done(0, pl.pass_uncond[step.index] != 0, pass_bytes_per_amp(pl.passes[step.index]) * dim,
-                  pl.pass_flops_per_amp[step.index] * dim);
-        } else {
-          HIP_TRY(launch_site(r1, pl.sites[step.index], prog->d_events, prog->d_preds, st));
-          pr.done(1);
-        }
-      }
-      Prof pr(ctx, st);
-      HIP_TRY(launch_copy_branch(rb, n, st));
-      pr.done(2);
-      first = prefix_end;
+    // the view the passes run on: one state per slot with the slot's control block
+    RunBuffers rp = rb;
+    uint32_t n_slot = bs;
+    if (share) {
+      n_slot = 1;
+      slot_of.assign(bs, 0);
+      buf_of.assign(1, 0);
+      rep.assign(1, 0);
+      HIP_TRY(hipMemcpyAsync(d_slot_of, slot_of.data(), bs * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(d_buf_of, buf_of.data(), 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(d_rep, rep.data(), 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_ctl_gather(d_slot_ctl, rb.ctl, d_rep, 1, st));
+      rp.ctl = d_slot_ctl;
     }
-    for (size_t k = first; k < pl.steps.size(); ++k) {
+    for (size_t k = 0; k < pl.steps.size(); ++k) {
       const Step& step = pl.steps[k];
+      rp.shots = n_slot;
       Prof pr(ctx, st);
       if (step.kind == Step::INIT) {
-        HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st));
+        HIP_TRY(launch_init_state(rp.state, rp.stride, n, n_slot, st));
         pr.done(2);
       } else if (step.kind == Step::PASS) {
-        HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
-        const double amps = (double)dim * bs;
+        if (share) {
+          // copy on write: slots that still read a parent's buffer get their own
+          pairs.clear();
+          for (uint32_t g = 0; g < n_slot; ++g)
+            if (buf_of[g] != g) {
+              pairs.push_back(g);
+              pairs.push_back(buf_of[g]);
+              buf_of[g] = g;
+            }
+          if (!pairs.empty()) {
+            const qsv_status cs = ensure_capacity(n_slot);
+            if (cs != QSV_OK) return cs;
+            rp.state = rb.state;
+            HIP_TRY(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_buf_copy(rb.state, rb.stride, n, d_pairs, (uint32_t)pairs.size() / 2, st));
+            HIP_TRY(hipMemcpyAsync(d_buf_of, buf_of.data(), n_slot * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));  // the host tables change again after the uploads
+          }
+        }
+        HIP_TRY(launch_tile_pass(rp, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
+        const double amps = (double)dim * n_slot;
         pr.done(0, pl.pass_uncond[step.index] != 0, pass_bytes_per_amp(pl.passes[step.index]) * amps,
                 pl.pass_flops_per_amp[step.index] * amps);
-      } else {
+      } else if (!share) {
         HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, st));
         pr.done(1);
+      } else {
+        const SiteArgs& sa = pl.sites[step.index];
+        // every shot takes its slot's control block (passes change only its
+        // pending collapse), histograms per slot, outcomes per shot
+        HIP_TRY(launch_ctl_gather(rb.ctl, d_slot_ctl, d_slot_of, bs, st));
+        RunBuffers rs = rb;
+        rs.slot_of = d_slot_of;
+        rs.buf_of = d_buf_of;
+        rs.site_ctl = d_slot_ctl;
+        rs.site_slots = n_slot;
+        HIP_TRY(launch_site(rs, sa, prog->d_events, prog->d_preds, st));
+        pr.done(1);
+        if (sa.nq) {
+          // split the slots by the new histories
+          hcreg.resize((size_t)bs * cw);
+          hrec.resize((size_t)bs * maxrec);
+          HIP_TRY(hipMemcpyAsync(hctl.data(), rb.ctl, (size_t)bs * sizeof(ShotCtl), hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipMemcpyAsync(hcreg.data(), rb.creg, hcreg.size() * 8, hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipMemcpyAsync(hrec.data(), rb.record, hrec.size(), hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipStreamSynchronize(st));
+          std::unordered_map<std::string, uint32_t> seen;
+          std::vector<uint8_t> kept(n_slot, 0);
+          std::string key;
+          for (uint32_t sh = 0; sh < bs; ++sh) {
+            const uint32_t g = slot_of[sh];
+            ShotCtl c = hctl[sh];
+            c.wg_done = 0;
+            key.assign(reinterpret_cast<const char*>(&g), 4);
+            key.append(reinterpret_cast<const char*>(&c), sizeof(c));
+            key.append(reinterpret_cast<const char*>(&hcreg[(size_t)sh * cw]), (size_t)cw * 8);
+            key.append(reinterpret_cast<const char*>(&hrec[(size_t)sh * maxrec]),
+                       std::min<uint32_t>(c.n_record, maxrec));
+            auto it = seen.find(key);
+            if (it != seen.end()) {
+              slot_of[sh] = it->second;
+              continue;
+            }
+            uint32_t ng = g;
+            if (kept[g]) {
+              ng = n_slot++;
+              buf_of.push_back(buf_of[g]);
+              rep.push_back(sh);
+            } else {
+              kept[g] = 1;
+              rep[g] = sh;
+            }
+            seen.emplace(key, ng);
+            slot_of[sh] = ng;
+          }
+          HIP_TRY(hipMemcpyAsync(d_slot_of, slot_of.data(), bs * 4, hipMemcpyHostToDevice, st));
+          HIP_TRY(hipMemcpyAsync(d_buf_of, buf_of.data(), n_slot * 4, hipMemcpyHostToDevice, st));
+          HIP_TRY(hipMemcpyAsync(d_rep, rep.data(), n_slot * 4, hipMemcpyHostToDevice, st));
+          HIP_TRY(hipStreamSynchronize(st));
+        }
+        HIP_TRY(launch_ctl_gather(d_slot_ctl, rb.ctl, d_rep, n_slot, st));
       }
     }
-    if (s0 == 0 && opts->state_out) {
+    if (share && s0 == 0 && opts->state_out) {
+      // shot 0's slot reads its own buffer for the materialization
+      const uint32_t g = slot_of[0];
+      if (buf_of[g] != g) {
+        const qsv_status cs = ensure_capacity((uint64_t)g + 1);
+        if (cs != QSV_OK) return cs;
+        rp.state = rb.state;
+        pairs.assign({g, buf_of[g]});
+        buf_of[g] = g;
+        HIP_TRY(hipMemcpyAsync(d_pairs, pairs.data(), 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_buf_copy(rb.state, rb.stride, n, d_pairs, 1, st));
+      }
+      HIP_TRY(launch_materialize(rp, n, g, d_out, st));
+      HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, state_bytes, hipMemcpyDeviceToHost, st));
+    }
+    if (!share && s0 == 0 && opts->state_out) {
       HIP_TRY(launch_materialize(rb, n, 0, d_out, st));
       HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, state_bytes, hipMemcpyDeviceToHost, st));
     }
@@ -698,7 +799,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
   for (uint32_t r : big) {
     qsv_run_opts o = reqs[r].opts;
     o.state_out = nullptr;
-    o.flags = QSV_RUN_SHARE_PREFIX;  // bit-identical to running every shot from |0...0>
+    o.flags = QSV_RUN_SHARE_TRAJ;  // bit-identical to running every shot from |0...0>
     qsv_shot_results out = reqs[r].out;
     qsv_status rc = qsv_run_shots(ctx, reqs[r].prog, reqs[r].theta, reqs[r].n_shots, &o, &out);
     if (rc != QSV_OK) return rc;

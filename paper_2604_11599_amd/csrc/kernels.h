@@ -21,6 +21,12 @@ struct RunBuffers {
   uint32_t forced_len;
   uint64_t seed, shot_base;   // Philox key (seed, shot_base + shot)
   uint32_t shots;
+  // trajectory sharing (null: one state per shot): a site's histogram of
+  // slot g reads state buffer buf_of[g]; shot s finalises from slot slot_of[s]
+  const uint32_t* buf_of;
+  const uint32_t* slot_of;
+  const ShotCtl* site_ctl;  // slot control blocks the histograms follow
+  uint32_t site_slots;      // slots the site reduces over
 };
 
 // Workgroups of `kernel` (threads per workgroup, bytes of dynamic LDS) that the
@@ -41,6 +47,11 @@ hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phas
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
                        const DPred* preds, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
+// dst[i] = src[idx[i]] for i < count (control blocks of trajectory slots and shots)
+hipError_t launch_ctl_gather(ShotCtl* dst, const ShotCtl* src, const uint32_t* idx, uint32_t count, hipStream_t st);
+// state buffer pairs[2k] <- state buffer pairs[2k + 1] (2^n amplitudes each, k < n_pairs)
+hipError_t launch_buf_copy(double2* state, uint64_t stride, uint32_t n, const uint32_t* pairs, uint32_t n_pairs,
+                           hipStream_t st);
 hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st);
 hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out,
                               hipStream_t st);

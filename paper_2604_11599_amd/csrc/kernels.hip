@@ -943,7 +943,7 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
 // many shots share the launch.
 __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
     const double2* __restrict__ state, uint64_t stride, const ShotCtl* __restrict__ ctl, SiteArgs a,
-    double* __restrict__ partials, uint32_t pblocks) {
+    double* __restrict__ partials, uint32_t pblocks, const uint32_t* __restrict__ buf_of) {
   __shared__ double bins[kSiteBins][kRedThreads];
   __shared__ double red[kRedThreads / kSiteBins][kSiteBins];
   const uint32_t shot = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
@@ -957,7 +957,7 @@ __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
     const uint64_t nfree = 1ull << (a.n - r);
     const uint64_t per = (nfree + a.blocks - 1) / a.blocks;
     const uint64_t j0 = per * blk, j1 = (j0 + per < nfree) ? j0 + per : nfree;
-    const double2* st = state + (uint64_t)shot * stride;
+    const double2* st = state + (uint64_t)(buf_of ? buf_of[shot] : shot) * stride;
     uint32_t qbit[kSiteQubits];
     uint32_t fq = 0;
     for (uint32_t k = 0; k < a.nq; ++k) {
@@ -1097,12 +1097,12 @@ __global__ __launch_bounds__(64) void k_site_finalize(
     const DPred* __restrict__ preds, const double* __restrict__ partials, uint32_t pblocks,
     uint64_t* __restrict__ creg,
     uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record, const uint8_t* __restrict__ forced,
-    uint32_t forced_len, uint64_t seed, uint64_t shot_base) {
+    uint32_t forced_len, uint64_t seed, uint64_t shot_base, const uint32_t* __restrict__ slot_of) {
   __shared__ double part[4][kSiteBins];
   const uint32_t shot = blockIdx.x, tid = threadIdx.x;
   ShotCtl* c = ctl + shot;
   if (a.nq) {
-    const double* pp = partials + (uint64_t)shot * pblocks * kSiteBins;
+    const double* pp = partials + (uint64_t)(slot_of ? slot_of[shot] : shot) * pblocks * kSiteBins;
     const uint32_t b = tid & (kSiteBins - 1), q = tid / kSiteBins;
     double acc = 0.0;
     for (uint32_t k = q; k < a.blocks; k += 4) acc += pp[(uint64_t)k * kSiteBins + b];
@@ -1122,14 +1122,51 @@ __global__ __launch_bounds__(64) void k_site_finalize(
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev, const DPred* preds,
                        hipStream_t st) {
   if (a.nq) {
-    hipLaunchKernelGGL(k_site_reduce, dim3(a.blocks, rb.shots), dim3(kRedThreads), 0, st, rb.state,
-                       rb.stride, rb.ctl, a, rb.partials, rb.pblocks);
+    // with trajectory sharing the histograms are taken per slot (slot control
+    // blocks in site_ctl), the outcomes per shot
+    hipLaunchKernelGGL(k_site_reduce, dim3(a.blocks, rb.slot_of ? rb.site_slots : rb.shots), dim3(kRedThreads), 0,
+                       st, rb.state, rb.stride, rb.slot_of ? rb.site_ctl : rb.ctl, a, rb.partials, rb.pblocks,
+                       rb.buf_of);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_site_finalize, dim3(rb.shots), dim3(64), 0, st, rb.ctl, a, ev, preds, rb.partials,
                      rb.pblocks, rb.creg, rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len, rb.seed,
-                     rb.shot_base);
+                     rb.shot_base, rb.slot_of);
+  return hipGetLastError();
+}
+
+__global__ void k_ctl_gather(ShotCtl* __restrict__ dst, const ShotCtl* __restrict__ src,
+                             const uint32_t* __restrict__ idx, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[idx[i]];
+}
+
+hipError_t launch_ctl_gather(ShotCtl* dst, const ShotCtl* src, const uint32_t* idx, uint32_t count, hipStream_t st) {
+  if (!count) return hipSuccess;
+  hipLaunchKernelGGL(k_ctl_gather, dim3((count + 255) / 256), dim3(256), 0, st, dst, src, idx, count);
+  return hipGetLastError();
+}
+
+// Copy-on-write of trajectory slots: buffer pairs[2k] takes the amplitudes of
+// buffer pairs[2k + 1]. Sources are never destinations in one launch.
+__global__ void k_buf_copy(double2* __restrict__ state, uint64_t stride, uint64_t dim,
+                           const uint32_t* __restrict__ pairs, uint32_t n_pairs) {
+  const uint64_t total = dim * n_pairs;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = i / dim, j = i % dim;
+    state[(uint64_t)pairs[2 * k] * stride + j] = state[(uint64_t)pairs[2 * k + 1] * stride + j];
+  }
+}
+
+hipError_t launch_buf_copy(double2* state, uint64_t stride, uint32_t n, const uint32_t* pairs, uint32_t n_pairs,
+                           hipStream_t st) {
+  if (!n_pairs) return hipSuccess;
+  const uint64_t total = (1ull << n) * n_pairs;
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_buf_copy, dim3((uint32_t)blocks), dim3(256), 0, st, state, stride, 1ull << n, pairs, n_pairs);
   return hipGetLastError();
 }
 

@@ -55,6 +55,17 @@ qsv_status info_of(const qsv_program* p, qsv_program_info* info) {
   return qsv_program_info_get(p, info);
 }
 
+// state buffers a request of more than 2^16 amplitudes is charged for
+// (distinct histories are few)
+constexpr uint64_t kWideSlots = 16;
+
+// shots of a request per tick: states of more than 2^16 amplitudes all at once
+// (with many shots they run on the tile-pass path, where shots with equal
+// histories share one state); narrower ones a slice per tick
+uint64_t shots_per_tick(uint32_t n, uint64_t shots, uint32_t slice) {
+  return n > 16 ? shots : slice;
+}
+
 }  // namespace
 
 extern "C" {
@@ -93,8 +104,9 @@ qsv_status qsv_submit(qsv_server* srv, const qsv_program* prog, const double* th
   r->n_events.assign(n_shots, 0);
   r->record_prob.assign(n_shots, 0.0);
   r->status.assign(n_shots, 0);
-  const uint64_t per = r->n > 16 ? std::max<uint64_t>(1, srv->slice >> (r->n - 16)) : srv->slice;
-  r->footprint = (size_t)std::min<uint64_t>(n_shots, per) * (16ull << r->n);
+  const uint64_t per = shots_per_tick(r->n, n_shots, srv->slice);
+  r->footprint = (size_t)std::min<uint64_t>(std::min<uint64_t>(n_shots, per), r->n > 16 ? kWideSlots : per) *
+                 (16ull << r->n);
   *ticket = r->ticket;
   if (n_shots == 0) r->finished = true;
   else srv->waiting.push_back(r->ticket);
@@ -144,11 +156,7 @@ qsv_status qsv_server_step(qsv_server* srv, uint32_t* n_running, uint32_t* n_wai
   for (uint64_t t : srv->running) {
     Req& r = *srv->reqs[t];
     if (r.vqe || r.finished) continue;
-    // wide states get proportionally fewer shots per tick, so a tick moves about
-    // the same number of bytes whatever the mix
-    uint64_t per = srv->slice;
-    if (r.n > 16) per = std::max<uint64_t>(1, per >> (r.n - 16));
-    const uint64_t k = std::min<uint64_t>(per, r.shots - r.done_shots);
+    const uint64_t k = std::min<uint64_t>(shots_per_tick(r.n, r.shots, srv->slice), r.shots - r.done_shots);
     const uint64_t cw = std::max<uint32_t>(1, (r.n_clbits + 63) / 64);
     const uint64_t mr = std::max<uint32_t>(1, r.max_events);
     qsv_request q;

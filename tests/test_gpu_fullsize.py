@@ -115,7 +115,7 @@ def test_benchmark_circuit_properties(ctx):
         one = prog.run_shots(1, seed=0, shot_offset=k)
         assert np.array_equal(one.creg[0], a.creg[k]) and one.record_prob[0] == a.record_prob[k]
     say("c2 28q: shared prefix")
-    b = prog.run_shots(16, seed=0, share_prefix=True)
+    b = prog.run_shots(16, seed=0, share=True)
     assert np.array_equal(b.creg, a.creg) and np.array_equal(b.record, a.record)
     assert np.array_equal(b.record_prob, a.record_prob)
     say("c2 28q: norm of a shot's state after the mid-circuit site")

@@ -204,14 +204,55 @@ def test_determinism_and_batch_independence(ctx):
         assert one.record_prob[0] == a.record_prob[k]
 
 
-def test_shared_prefix_is_bit_identical(ctx):
-    for src in (W.c2_program(2, n=14, layers=8), W.c1_program(4), W.c3_program(6, n=13, layers=3)):
-        prog = ctx.load(src)
-        a = prog.run_shots(24, seed=5, state_out=True)
-        b = prog.run_shots(24, seed=5, state_out=True, share_prefix=True)
-        assert np.array_equal(a.creg, b.creg) and np.array_equal(a.record, b.record)
-        assert np.array_equal(a.record_prob, b.record_prob) and np.array_equal(a.n_events, b.n_events)
+def _same_results(a, b, state=True):
+    assert np.array_equal(a.creg, b.creg) and np.array_equal(a.record, b.record)
+    assert np.array_equal(a.record_prob, b.record_prob) and np.array_equal(a.n_events, b.n_events)
+    assert np.array_equal(a.shot_status, b.shot_status)
+    if state:
         assert np.array_equal(a.state, b.state)
+
+
+def test_trajectory_sharing_is_bit_identical(ctx):
+    """Shots with equal histories share one state; results equal running every
+    shot on its own, bit for bit (mid-circuit multi-qubit measurement with
+    feed-forward, resets, repeat-until-success loops, random dynamic programs,
+    forced records, many shots)."""
+    cases = [(W.c2_program(2, n=14, layers=8), 24), (W.c1_program(4), 40), (W.c3_program(6, n=13, layers=3), 200),
+             (W.random_dynamic_program(3, 13, n_ops=60), 64), (W.random_dynamic_program(8, 14, n_ops=50), 33)]
+    for src, shots in cases:
+        say("trajectory sharing case", src.splitlines()[2:3], shots, "shots")
+        prog = ctx.load(src)
+        a = prog.run_shots(shots, seed=5, state_out=True)
+        b = prog.run_shots(shots, seed=5, state_out=True, share=True)
+        _same_results(a, b)
+        c = prog.run_shots(shots, seed=9, shot_offset=7, share=True)
+        d = prog.run_shots(shots, seed=9, shot_offset=7)
+        _same_results(c, d, state=False)
+    # forced records: every shot its own forced row
+    src = W.c1_program(4)
+    prog = ctx.load(src)
+    forced = np.array([[(k >> j) & 1 for j in range(3)] for k in range(8)] * 3, dtype=np.uint8)
+    _same_results(prog.run_shots(24, seed=1, forced=forced), prog.run_shots(24, seed=1, forced=forced, share=True),
+                  state=False)
+
+
+def test_trajectory_sharing_runs_passes_once_per_history():
+    """The repeat-until-success loop of a 13-qubit circuit has at most 9
+    histories before the final measure-all: with 256 shots the shared run moves
+    at most 9/256 of the per-shot gate-pass bytes."""
+    from paper_2604_11599_amd import Context
+    c = Context(0, profile=True)
+    try:
+        prog = c.load(W.c3_program(6, n=13, layers=3))
+        c.profile_reset()
+        prog.run_shots(256, seed=3)
+        full = c.profile()["pass_uncond_bytes"]
+        c.profile_reset()
+        prog.run_shots(256, seed=3, share=True)
+        shared = c.profile()["pass_uncond_bytes"]
+        assert 0 < shared <= full * 9 / 256
+    finally:
+        c.close()
 
 
 # ---------------------------------------------------------------------------

@@ -184,3 +184,35 @@ def test_plan_of_configs():
 def test_plan_starts_with_init_when_program_starts_with_measurement():
     st = _check_plan("qubit[3] q; bit c; c = measure q[1]; h q[0];")
     assert st.init_step == 1 and st.step_kind[0] == 0 and st.step_kind[1] == 2
+
+
+def test_context_close_frees_live_programs_first(monkeypatch):
+    """A program must not outlive its context: Context.close frees the programs
+    still alive before qsv_destroy, and a later Program.free does nothing."""
+    import gc
+    import weakref
+
+    from paper_2604_11599_amd import api as api_mod
+    calls = []
+
+    class Stub:
+        def qsv_destroy(self, h):
+            calls.append(("destroy", h))
+
+        def qsv_program_free(self, h):
+            calls.append(("free", h))
+
+    monkeypatch.setattr(api_mod.A, "lib", lambda: Stub())
+    c = object.__new__(api_mod.Context)
+    c.handle, c.device_ptrs, c._programs = 1, False, weakref.WeakSet()
+    progs = []
+    for h in (7, 8):
+        p = object.__new__(api_mod.Program)
+        p.ctx, p.handle = c, h
+        c._programs.add(p)
+        progs.append(p)
+    c.close()
+    progs[0].free()
+    del progs
+    gc.collect()
+    assert sorted(calls[:2]) == [("free", 7), ("free", 8)] and calls[2:] == [("destroy", 1)]
