@@ -516,34 +516,6 @@ hipError_t launch_compose_grad(const DGate* gates, const AngEnt* ent, uint32_t n
   return hipGetLastError();
 }
 
-// LDS slots: the slot of tile-local index l is swz(l); swz and the scatter of
-// bits over a mask are both linear over GF(2) (swz(a ^ b) = swz(a) ^ swz(b)),
-// so every slot a lane touches in a phase is a per-lane part, formed once per
-// phase, XOR a wave-uniform part (scalar registers).
-
-// the set bits of a wave-uniform mask, lowest first, one bit each (0 past the last)
-struct UBits {
-  uint32_t b[8];
-};
-__device__ __forceinline__ UBits ubits(uint32_t m) {
-  UBits u;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    u.b[k] = m & (0u - m);
-    m &= m - 1u;
-  }
-  return u;
-}
-
-// bits 0..kBits-1 of x scattered over the first kBits set bits of the mask
-template <int kBits>
-__device__ __forceinline__ uint32_t udep(const UBits& u, uint32_t x) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int k = 0; k < kBits; ++k) r |= ((x >> k) & 1u) ? u.b[k] : 0u;
-  return r;
-}
-
 // lane l's matrix-core B operand of conj(W) over the 4 K chunks: conj(W[4 kb + l / 16][l % 16])
 __device__ __forceinline__ void load_wfrag(double2 (&wf)[4], const double2* __restrict__ Wc, uint32_t lane) {
   const uint32_t q = lane >> 4, j = lane & 15u;

@@ -472,6 +472,12 @@ hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint
   return hipGetLastError();
 }
 
+// group bits 4..7 of a wave-uniform group index, scattered over the mask bits
+__device__ __forceinline__ uint32_t udep_hi(const UBits& u, uint32_t g) {
+  return (((g >> 4) & 1u) ? u.b[4] : 0u) | (((g >> 5) & 1u) ? u.b[5] : 0u) | (((g >> 6) & 1u) ? u.b[6] : 0u) |
+         (((g >> 7) & 1u) ? u.b[7] : 0u);
+}
+
 // One dense phase on the matrix cores, for the 64 amplitude groups of this
 // thread's wave (group g = tile-local indices with the non-register bits set
 // to the bits of g). With M = A + iB and a block of 16 groups as X + iY (16
@@ -490,9 +496,10 @@ template <int kBlocks>
 __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
                                                  const Phase& ph, const double2* __restrict__ Mc) {
   // this wave's groups: gbase + 16 cb + j, cb < kBlocks
-  const uint32_t lane = tid & 63u, wbase = (tid >> 6) * (16u * kBlocks), q = lane >> 4, j = lane & 15u;
+  const uint32_t lane = tid & 63u, q = lane >> 4, j = lane & 15u;
+  const uint32_t wbase = __builtin_amdgcn_readfirstlane(tid >> 6) * (16u * kBlocks);
   const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
-  const uint32_t lbmask = (T - 1u) & ~(o0 | o1 | o2 | o3);
+  const UBits u = ubits((T - 1u) & ~(o0 | o1 | o2 | o3));
   double fa[4], fb[4], fs[4];  // fragments of A, B and A + B
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
@@ -501,23 +508,20 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
     fb[kb] = m.y;
     fs[kb] = m.x + m.y;
   }
-  uint32_t cq[4];  // local offsets of components q + 4 k
-#pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    const uint32_t ci = q + 4u * k;
-    cq[k] = ((ci & 1u) ? o0 : 0u) | ((ci & 2u) ? o1 : 0u) | ((ci & 4u) ? o2 : 0u) | ((ci & 8u) ? o3 : 0u);
-  }
-  const uint32_t lbl = pdep32(wbase | j, lbmask);
+  // slot of component q + 4 k of group gbase + 16 cb + j: a per-lane part (group
+  // bits 0..3, component bits of q) XOR a wave-uniform part (higher group bits,
+  // component bits of k)
+  const uint32_t rl = swz(udep<4>(u, j) | ((q & 1u) ? o0 : 0u) | ((q & 2u) ? o1 : 0u));
   // software-pipelined over the blocks: the reads of block b + 1 are issued
   // before the writes of block b, so the LDS round trip of the next block
   // overlaps the tail of the current block's products
   uint32_t slot[2][4];
   double2 x[2][4];
   {
-    const uint32_t lb = lbl | pdep32(0u, lbmask);
+    const uint32_t ug = udep_hi(u, wbase);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      slot[0][k] = swz(lb | cq[k]);
+    for (uint32_t k = 0; k < 4; ++k) {
+      slot[0][k] = rl ^ swz(ug | ((k & 1u) ? o2 : 0u) | ((k & 2u) ? o3 : 0u));
       x[0][k] = tile[slot[0][k]];
     }
   }
@@ -532,10 +536,10 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
       p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[c][kb].x + x[c][kb].y, p3, 0, 0, 0);
     }
     if (cb + 1 < (uint32_t)kBlocks) {
-      const uint32_t lb = lbl | pdep32(16u * (cb + 1), lbmask);
+      const uint32_t ug = udep_hi(u, wbase + 16u * (cb + 1));
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        slot[c ^ 1u][k] = swz(lb | cq[k]);
+      for (uint32_t k = 0; k < 4; ++k) {
+        slot[c ^ 1u][k] = rl ^ swz(ug | ((k & 1u) ? o2 : 0u) | ((k & 2u) ? o3 : 0u));
         x[c ^ 1u][k] = tile[slot[c ^ 1u][k]];
       }
     }
