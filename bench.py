@@ -310,7 +310,7 @@ def main():
     roof["time_share"] = {"tile_pass_ms": prof["pass_ms"], "site_ms": prof["site_ms"],
                           "other_ms": prof["other_ms"], "wall_ms": 1e3 * dt}
 
-    # the same steps with shot branching (prefix before the first measurement run once per batch)
+    # the same steps with trajectory sharing (shots with equal measurement histories share one state)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for s in range(args.steps):
@@ -318,14 +318,14 @@ def main():
     torch.cuda.synchronize()
     dt_sp = time.perf_counter() - t1
     shared = {"value": shots * args.steps / dt_sp, "unit": "shots/s", "ms_per_step": 1e3 * dt_sp / args.steps,
-              "note": "same shots, bit-identical results; gates before the first measurement are "
-                      "simulated once per step and the state is copied to every shot"}
-    log("shared-prefix steps done")
+              "note": "same shots, bit-identical results; shots with equal measurement histories "
+                      "share one state (gate passes once per distinct history)"}
+    log("shared-trajectory steps done")
 
     out = {"metric": "shots/s + achieved HBM GB/s on 16q/28q dynamic circuits; p50/p99 request latency",
            "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof, "shared_prefix": shared}
+           "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof, "shared_trajectories": shared}
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the workload")

@@ -10,7 +10,7 @@ The oracle cannot simulate a 28-qubit shot of 40 layers in test time, so:
 * the mirror circuit U U^dag must return |0...0>;
 * on the benchmark circuit itself, properties that hold at any size: forced
   re-runs reproduce sampled shots bit for bit, a shot alone equals the same shot
-  inside the batch, the shared-prefix path is bit-identical, norms stay 1.
+  inside the batch, the trajectory-sharing path is bit-identical, norms stay 1.
 """
 import sys
 
@@ -114,7 +114,7 @@ def test_benchmark_circuit_properties(ctx):
     for k in (0, 9):
         one = prog.run_shots(1, seed=0, shot_offset=k)
         assert np.array_equal(one.creg[0], a.creg[k]) and one.record_prob[0] == a.record_prob[k]
-    say("c2 28q: shared prefix")
+    say("c2 28q: shared trajectories")
     b = prog.run_shots(16, seed=0, share=True)
     assert np.array_equal(b.creg, a.creg) and np.array_equal(b.record, a.record)
     assert np.array_equal(b.record_prob, a.record_prob)
