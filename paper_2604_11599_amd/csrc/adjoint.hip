@@ -624,9 +624,11 @@ __device__ __forceinline__ double wave_sum8(const double (&a)[8], uint32_t lane)
 
 // Persistent workgroups of 2^(t-3) threads (8 amplitudes of psi and of lambda
 // per thread) over the items (vector, tile) of an all-dense pass with
-// 10 <= t <= 12. Phases run in reverse order; after each, every wave reduces
-// 2 Re tr(S C) per angle of the phase over its lanes, and the waves' values
-// are summed in a fixed order into gpart[vector][tile][gate][angle].
+// 10 <= t <= 12. Phases run in reverse order. After each, the waves' partial
+// C are summed in LDS in a fixed order; angle e of the phase is then taken by
+// wave e mod (waves), which reduces 2 Re tr(S C) over its lanes and writes
+// gpart[vector][tile][gate][angle]. Those traces overlap the next phase's
+// products (no barrier until that phase ends).
 __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
     double2* __restrict__ psi, double2* __restrict__ lam, uint64_t stride, const Phase* __restrict__ phases,
     const uint32_t* __restrict__ ang_off, const AngEnt* __restrict__ ent, const double* __restrict__ mats,
@@ -637,7 +639,7 @@ __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
   const uint32_t lane = tid & 63u, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   double2* const tp = lds;
   double2* const tl = lds + T;
-  double* const red = reinterpret_cast<double*>(lds + 2 * T);  // [2][kBwWaves][kMaxPhaseAngles]
+  double2* const cbuf = lds + 2 * T;  // [waves][256]: partial C per wave, then the sum in slot 0
   const uint64_t total = (uint64_t)a.tiles * batch, G = gridDim.x;
   const uint64_t free_mask = ~a.tile_mask & ((a.n >= 64) ? ~0ull : ((1ull << a.n) - 1ull));
   uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..t-4]
@@ -676,28 +678,47 @@ __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
         load_wfrag(wn, reinterpret_cast<const double2*>(mb + (uint64_t)load_phase(phases + pg - 1).dense * kMatStride),
                    lane);
       const uint32_t e0 = cst(ang_off)[pg], ne = cst(ang_off)[pg + 1] - e0;
-      // the gradient slot this thread fills after the phase, requested before the products
+      // this wave's angles: e = wave + k * waves; lane k holds the gradient slot of the k-th
+      const uint32_t my_n = ne > wave ? (ne - wave + nwaves - 1) / nwaves : 0u;
       uint32_t gslot = 0;
-      if (tid < ne) {
-        const AngEnt en = ent[e0 + tid];
+      if (lane < my_n) {
+        const AngEnt en = ent[e0 + wave + lane * nwaves];
         gslot = (en.gate - a.gate_begin) * 3u + en.j;
       }
       qsv_d4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
       adjoint_phase_mfma(tp, tl, T, lane, wave, ph, wf, c1, c2, c3);
-      double cr[4], ci[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cr[v] = c1[v] - c2[v];
-        ci[v] = c3[v] - c1[v] - c2[v];
+      for (int v = 0; v < 4; ++v)
+        cbuf[wave * 256u + (uint32_t)v * 64u + lane] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
+      __syncthreads();
+      // C of the tile: the waves' partials summed in wave order
+      for (uint32_t e = tid; e < 256u; e += nthr) {
+        double2 acc = cbuf[e];
+        for (uint32_t ww = 1; ww < nwaves; ++ww) {
+          const double2 v = cbuf[ww * 256u + e];
+          acc.x += v.x;
+          acc.y += v.y;
+        }
+        cbuf[e] = acc;
       }
-      double* rw = red + ((p & 1u) * kBwWaves + wave) * kMaxPhaseAngles;
-      for (uint32_t e = 0; e < ne; e += 8) {
+      __syncthreads();
+      double cr[4] = {0.0, 0.0, 0.0, 0.0}, ci[4] = {0.0, 0.0, 0.0, 0.0};
+      if (my_n) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double2 c = cbuf[(uint32_t)v * 64u + lane];
+          cr[v] = c.x;
+          ci[v] = c.y;
+        }
+      }
+      __syncthreads();  // every wave holds the sum before the next phase writes its partials
+      for (uint32_t k0 = 0; k0 < my_n; k0 += 8) {
         double part[8];
 #pragma unroll
         for (uint32_t uu = 0; uu < 8; ++uu) {
           part[uu] = 0.0;
-          if (e + uu < ne) {
-            const double2* S = sb + (uint64_t)(e0 + e + uu) * 256u;
+          if (k0 + uu < my_n) {
+            const double2* S = sb + (uint64_t)(e0 + wave + (k0 + uu) * nwaves) * 256u;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const double2 sv = S[v * 64 + (int)lane];
@@ -706,15 +727,9 @@ __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
           }
         }
         const double tot = wave_sum8(part, lane);
-        if ((lane & 7u) == 0 && e + (lane >> 3) < ne) rw[e + (lane >> 3)] = tot;
-      }
-      __syncthreads();
-      // the waves' values of this phase, summed in wave order
-      if (tid < ne) {
-        const double* rp0 = red + (p & 1u) * kBwWaves * kMaxPhaseAngles;
-        double sum = 0.0;
-        for (uint32_t ww = 0; ww < nwaves; ++ww) sum += rp0[ww * kMaxPhaseAngles + tid];
-        gp[gslot] = 2.0 * sum;
+        const uint32_t k = k0 + (lane >> 3);
+        const uint32_t slot = __shfl(gslot, (int)(k & 63u), 64);
+        if ((lane & 7u) == 0 && k < my_n) gp[slot] = 2.0 * tot;
       }
       if (p > 0) {
 #pragma unroll
@@ -736,9 +751,10 @@ __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
   }
 }
 
-// Dynamic LDS of k_backward_mfma for tiles of 2^t amplitudes.
+// Dynamic LDS of k_backward_mfma for tiles of 2^t amplitudes: the psi and
+// lambda tiles and one 16x16 complex C per wave (2^12 amplitudes: 160 KiB).
 size_t backward_mfma_lds(uint32_t t) {
-  return (size_t)2 * sizeof(double2) * (1u << t) + (size_t)2 * kBwWaves * kMaxPhaseAngles * sizeof(double);
+  return (size_t)2 * sizeof(double2) * (1u << t) + (size_t)((1u << t) / 512u) * 256u * sizeof(double2);
 }
 
 hipError_t launch_backward_mfma(double2* psi, double2* lam, uint64_t stride, uint32_t batch, const Phase* phases,
