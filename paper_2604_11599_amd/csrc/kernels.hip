@@ -492,9 +492,27 @@ __device__ __forceinline__ uint32_t udep_hi(const UBits& u, uint32_t g) {
 // components q + 4 kb (q = l / 16) of its group in each block and writes back
 // the same components. The wave reads a block before it writes it, and the
 // blocks of different waves are disjoint.
+// lane l's matrix-core operand of a phase matrix: Mc[kb * 64 + l], kb = 0..3;
+// from LDS when the pass's matrices are staged there, else from HBM (two
+// loops, so the compiler keeps the LDS reads as LDS reads)
+__device__ __forceinline__ void load_mfrag(double2 (&mf)[4], bool staged, const double2* __restrict__ lds_mats,
+                                           const double2* __restrict__ gmat, uint32_t lane) {
+  typedef __attribute__((address_space(3))) const double lds_d;
+  typedef __attribute__((address_space(1))) const double glb_d;
+  if (staged) {
+    const lds_d* l = (const lds_d*)lds_mats;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) mf[kb] = make_double2(l[2 * (kb * 64 + (int)lane)], l[2 * (kb * 64 + (int)lane) + 1]);
+  } else {
+    const glb_d* g = (const glb_d*)gmat;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) mf[kb] = make_double2(g[2 * (kb * 64 + (int)lane)], g[2 * (kb * 64 + (int)lane) + 1]);
+  }
+}
+
 template <int kBlocks>
 __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
-                                                 const Phase& ph, const double2* __restrict__ Mc) {
+                                                 const Phase& ph, const double2 (&mf)[4]) {
   // this wave's groups: gbase + 16 cb + j, cb < kBlocks
   const uint32_t lane = tid & 63u, q = lane >> 4, j = lane & 15u;
   const uint32_t wbase = __builtin_amdgcn_readfirstlane(tid >> 6) * (16u * kBlocks);
@@ -503,10 +521,9 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
   double fa[4], fb[4], fs[4];  // fragments of A, B and A + B
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
-    const double2 m = Mc[kb * 64 + (int)lane];
-    fa[kb] = m.x;
-    fb[kb] = m.y;
-    fs[kb] = m.x + m.y;
+    fa[kb] = mf[kb].x;
+    fb[kb] = mf[kb].y;
+    fs[kb] = mf[kb].x + mf[kb].y;
   }
   // slot of component q + 4 k of group gbase + 16 cb + j: a per-lane part (group
   // bits 0..3, component bits of q) XOR a wave-uniform part (higher group bits,
@@ -571,10 +588,12 @@ __device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t 
       if (!act) continue;
     }
     if (kDense && ph.dense != kNoDense && nthr >= 64u) {
-      if (tid < nthr)
-        dense_phase_mfma<4>(tile, T, tid, ph,
-                         lds_mats ? lds_mats + (size_t)p * 256u
-                                  : reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride));
+      if (tid < nthr) {
+        double2 mf[4];
+        load_mfrag(mf, lds_mats != nullptr, lds_mats + (size_t)p * 256u,
+                   reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride), tid & 63u);
+        dense_phase_mfma<4>(tile, T, tid, ph, mf);
+      }
     } else if (kGates && tid < nthr) {
       const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
       const uint32_t lb = pdep32(tid, (T - 1u) & ~(o0 | o1 | o2 | o3));
@@ -867,7 +886,7 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
     const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats) {
   extern __shared__ double2 tile[];
   constexpr uint32_t kA = 8, kThreads = 2 * kTileThreads;
-  const uint32_t tid = threadIdx.x, T = 1u << a.t;
+  const uint32_t tid = threadIdx.x, T = 1u << a.t, lane = tid & 63u;
   const uint64_t total = (uint64_t)a.tiles * shots, G = gridDim.x;
   const uint64_t free_mask = ~a.tile_mask & ((a.n >= 64) ? ~0ull : ((1ull << a.n) - 1ull));
   uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..8]
@@ -904,12 +923,13 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
           !pending ? r[k] : (((gi & M) == V) ? cscale(r[k], sc) : make_double2(0.0, 0.0));
     }
     __syncthreads();
+    const double* ms = mats + (uint64_t)shot * mat_stride;
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const Phase ph = load_phase(phases + a.phase_begin + p);
-      const double2* Mc = lds_mats ? lmats + (size_t)p * 256u
-                                   : reinterpret_cast<const double2*>(mats + (uint64_t)shot * mat_stride +
-                                                                      (uint64_t)ph.dense * kMatStride);
-      dense_phase_mfma<2>(tile, T, tid, ph, Mc);
+      double2 mf[4];
+      load_mfrag(mf, lds_mats != 0u, lmats + (size_t)p * 256u,
+                 reinterpret_cast<const double2*>(ms + (uint64_t)ph.dense * kMatStride), lane);
+      dense_phase_mfma<2>(tile, T, tid, ph, mf);
       __syncthreads();
     }
 #pragma unroll
