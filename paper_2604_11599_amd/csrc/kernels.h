@@ -52,7 +52,6 @@ hipError_t launch_ctl_gather(ShotCtl* dst, const ShotCtl* src, const uint32_t* i
 // state buffer pairs[2k] <- state buffer pairs[2k + 1] (2^n amplitudes each, k < n_pairs)
 hipError_t launch_buf_copy(double2* state, uint64_t stride, uint32_t n, const uint32_t* pairs, uint32_t n_pairs,
                            hipStream_t st);
-hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st);
 hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out,
                               hipStream_t st);
 

@@ -1194,33 +1194,6 @@ hipError_t launch_buf_copy(double2* state, uint64_t stride, uint32_t n, const ui
   return hipGetLastError();
 }
 
-// Shot branching: shots 1..S-1 of a batch take over shot 0's state, control
-// block and classical bits (after a prefix that draws no randomness).
-__global__ void k_copy_branch(double2* __restrict__ state, uint64_t stride, uint64_t dim, uint32_t shots,
-                              ShotCtl* __restrict__ ctl, uint64_t* __restrict__ creg, uint32_t cw) {
-  const uint64_t total = dim * (shots - 1);
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint64_t i = gid; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t s = i / dim + 1, j = i % dim;
-    state[s * stride + j] = state[j];
-  }
-  if (gid > 0 && gid < shots) {
-    ctl[gid] = ctl[0];
-    for (uint32_t w = 0; w < cw; ++w) creg[(uint64_t)gid * cw + w] = creg[w];
-  }
-}
-
-hipError_t launch_copy_branch(const RunBuffers& rb, uint32_t n, hipStream_t st) {
-  if (rb.shots < 2) return hipSuccess;
-  const uint64_t total = (1ull << n) * (rb.shots - 1);
-  uint64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks * 256 < rb.shots) blocks = (rb.shots + 255) / 256;
-  hipLaunchKernelGGL(k_copy_branch, dim3((uint32_t)blocks), dim3(256), 0, st, rb.state, rb.stride, 1ull << n,
-                     rb.shots, rb.ctl, rb.creg, rb.cw);
-  return hipGetLastError();
-}
-
 // Plain streaming copy (calibration of hardware byte counters).
 __global__ void k_copy(double2* __restrict__ dst, const double2* __restrict__ src, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
