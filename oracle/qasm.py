@@ -11,7 +11,7 @@ builds such an AST as plain tuples for the tree-walking interpreter in
   ('qubit', name, size|None)        ('bit', name, size|None)
   ('input', name, size|None)        ('const', name, expr)
   ('gatedef', name, params, qargs, body)
-  ('gate', name, [expr], [qref])    ('measure', qref, cref|None)
+  ('gate', name, [expr], [qref], mods)    ('measure', qref, cref|None)
   ('reset', qref)                   ('barrier',)
   ('if', cond, then_body, else_body) ('for', var, start, step, stop, body)
   ('break',)                        ('continue',)
@@ -251,7 +251,17 @@ class _Parser:
         return ("gatedef", name, params, qargs, body)
 
     def gate_call(self):
+        # gate modifiers, outermost first: inv @, pow(k) @, ctrl @, ctrl(n) @, negctrl @, negctrl(n) @
+        mods = []
         name = self.ident()
+        while name in ("inv", "pow", "ctrl", "negctrl") and self.peek(0)[1] in ("@", "("):
+            arg = None
+            if self.accept("("):
+                arg = self.expr()
+                self.expect(")")
+            self.expect("@")
+            mods.append((name, arg))
+            name = self.ident()
         args = []
         if self.accept("("):
             if not self.accept(")"):
@@ -263,7 +273,7 @@ class _Parser:
         while self.accept(","):
             qs.append(self.ref())
         self.expect(";")
-        return ("gate", name, args, qs)
+        return ("gate", name, args, qs, tuple(mods))
 
     def ref(self):
         name = self.ident()

@@ -210,6 +210,52 @@ def _has_nonunitary(body, gatedefs):
 
 
 # --------------------------------------------------------------------------
+# Gate modifiers, by definition on matrices (operand i = bit i of the local
+# index). A chain [(kind, value)] lists modifiers outermost first; they are
+# applied innermost first. With a derivative dm of the base matrix, returns
+# the derivative of the modified matrix as well.
+#   inv:        M^dag                        d(M^dag) = (dM)^dag
+#   pow(k):     M^k (k < 0: (M^dag)^|k|)     product rule
+#   ctrl(n):    M where the n new leading operands are all 1, identity elsewhere
+#   negctrl(n): the same where they are all 0
+# --------------------------------------------------------------------------
+def _controlled(m, n, on_one, fill):
+    """The matrix of m with n controls as the first operands; `fill` is the
+    value of the uncontrolled diagonal (1 for a matrix, 0 for a derivative)."""
+    d = m.shape[0]
+    big = np.zeros((d << n, d << n), dtype=np.complex128)
+    if fill:
+        np.fill_diagonal(big, fill)
+    c = (1 << n) - 1 if on_one else 0
+    for a in range(d):
+        for b in range(d):
+            big[(a << n) | c, (b << n) | c] = m[a, b]
+    return big
+
+
+def modify(chain, m, dm):
+    for kind, v in reversed(list(chain)):
+        if kind == "inv":
+            m = m.conj().T
+            dm = None if dm is None else dm.conj().T
+        elif kind == "pow":
+            base, dbase = (m, dm) if v >= 0 else (m.conj().T, None if dm is None else dm.conj().T)
+            k = abs(v)
+            pm = np.eye(m.shape[0], dtype=np.complex128)
+            pd = None if dm is None else np.zeros_like(m)
+            for _ in range(k):
+                if pd is not None:
+                    pd = pd @ base + pm @ dbase
+                pm = pm @ base
+            m, dm = pm, pd
+        else:
+            on_one = kind == "ctrl"
+            m = _controlled(m, v, on_one, 1.0)
+            dm = None if dm is None else _controlled(dm, v, on_one, 0.0)
+    return m, dm
+
+
+# --------------------------------------------------------------------------
 # The tree-walking interpreter.
 # --------------------------------------------------------------------------
 class Interpreter:
@@ -404,6 +450,7 @@ class Interpreter:
 
     def exec_gate(self, st, env):
         name, args, qrefs = st[1], st[2], st[3]
+        mods = st[4] if len(st) > 4 else ()
         angles = [self.eval(a, env) for a in args]
         operand_lists = [self.qubits_of(r, env) for r in qrefs]
         width = max(len(o) for o in operand_lists)
@@ -414,7 +461,70 @@ class Interpreter:
             qs = [o[j] if len(o) > 1 else o[0] for o in operand_lists]
             if len(set(qs)) != len(qs):
                 raise OracleError(f"gate {name}: repeated qubit operand")
-            self.apply_named(name, angles, qs, env)
+            if mods:
+                self.apply_modified(mods, name, angles, qs, env)
+            else:
+                self.apply_named(name, angles, qs, env)
+
+    def mod_controls(self, mods, env):
+        """[(kind, n_controls or power)] of a modifier chain, outermost first."""
+        out = []
+        for kind, arg in mods:
+            v = 1 if arg is None else int(round(_val(self.eval(arg, env))))
+            if kind in ("ctrl", "negctrl") and v < 1:
+                raise OracleError(f"{kind} needs at least one control")
+            if kind == "pow" and arg is None:
+                raise OracleError("pow needs an exponent")
+            out.append((kind, v))
+        return out
+
+    def base_unitary(self, name, vals, k):
+        """Matrix of a standard gate, or of a gate definition (its body applied
+        to each basis state of k qubits), with numeric angles."""
+        if G.is_standard(name):
+            m, nq = G.gate_matrix(name, vals)
+            return m, nq
+        if name not in self.prog.gatedefs:
+            raise OracleError(f"unknown gate {name}")
+        _, _, params, qargs, body = self.prog.gatedefs[name]
+        if len(params) != len(vals):
+            raise OracleError(f"gate {name}: wrong number of arguments")
+        nq = len(qargs)
+        sub = Interpreter.__new__(Interpreter)
+        sub.__dict__.update(self.__dict__)
+        sub.tape = None
+        sub.shift = {}
+        sub.gate_count = 0
+        m = np.zeros((1 << nq, 1 << nq), dtype=np.complex128)
+        inner = {p: float(v) for p, v in zip(params, vals)}
+        inner.update({qa: ("qubit", i) for i, qa in enumerate(qargs)})
+        for c in range(1 << nq):
+            sub.eng = TensorEngine(nq)
+            sub.eng.psi = np.zeros(1 << nq, dtype=np.complex128)
+            sub.eng.psi[c] = 1.0
+            sub.exec_body(body, inner)
+            m[:, c] = sub.eng.psi
+        return m, nq
+
+    def apply_modified(self, mods, name, angles, qs, env):
+        chain = self.mod_controls(mods, env)
+        g = self.gate_count
+        self.gate_count += 1
+        vals = [_val(a) for a in angles]
+        for j in range(len(vals)):
+            if (g, j) in self.shift:
+                vals[j] += self.shift[(g, j)]
+        m, k = self.base_unitary(name, vals, None)
+        nctl = sum(v for kind, v in chain if kind in ("ctrl", "negctrl"))
+        if k + nctl != len(qs):
+            raise OracleError(f"modified gate {name} takes {k + nctl} qubits, got {len(qs)}")
+        mm, _ = modify(chain, m, None)
+        if self.tape is not None:
+            derivs = [a.d if isinstance(a, Lin) else {} for a in angles]
+            if any(derivs) and not G.is_standard(name):
+                raise OracleError("gradients through a modified gate definition are not supported")
+            self.tape.append((name, vals, qs, derivs, tuple(chain)))
+        self.eng.apply(mm, qs)
 
     def apply_named(self, name, angles, qs, env):
         if name in self.prog.gatedefs:
@@ -438,7 +548,7 @@ class Interpreter:
             raise OracleError(f"gate {name} takes {nq} qubits, got {len(qs)}")
         if self.tape is not None:
             derivs = [a.d if isinstance(a, Lin) else {} for a in angles]
-            self.tape.append((name, vals, qs, derivs))
+            self.tape.append((name, vals, qs, derivs, ()))
         self.eng.apply(m, qs)
 
     # -- non-unitary events --
@@ -563,11 +673,11 @@ def grad_param_shift(source, theta, coeffs, codes):
     grad = np.zeros(prog.n_params)
     n = prog.n_qubits
     shiftable = {"rx", "ry", "rz", "p", "phase", "u1", "u2", "u3", "u", "U", "cp", "cphase"}
-    for g, (name, vals, qs, derivs) in enumerate(tape):
+    for g, (name, vals, qs, derivs, chain) in enumerate(tape):
         for j, dj in enumerate(derivs):
             if not dj:
                 continue
-            if name not in shiftable:
+            if name not in shiftable or any(kind != "inv" for kind, _ in chain):
                 raise OracleError(f"no two-term shift rule for gate {name}")
             e = []
             for sgn in (+1.0, -1.0):
@@ -596,13 +706,14 @@ def grad_adjoint(source, theta, coeffs, codes):
     psi_e = TensorEngine(n)
     psi_e.psi = psi
     grad = np.zeros(prog.n_params)
-    for name, vals, qs, derivs in reversed(it.tape):
-        m, _ = G.gate_matrix(name, vals)
+    for name, vals, qs, derivs, chain in reversed(it.tape):
+        m, _ = modify(chain, G.gate_matrix(name, vals)[0], None)
         psi_e.apply(m.conj().T, qs)
         for j, dj in enumerate(derivs):
             if not dj:
                 continue
-            dm = G.gate_derivative(name, vals, j)
+            base = G.gate_matrix(name, vals)[0]
+            _, dm = modify(chain, base, G.gate_derivative(name, vals, j))
             tmp = TensorEngine(n)
             tmp.psi = psi_e.psi.copy()
             tmp.apply(dm, qs)
