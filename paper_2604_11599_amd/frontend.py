@@ -98,6 +98,7 @@ class GateCall:
     name: str
     args: list
     operands: List[Operand]
+    mods: list = None    # [(kind, expr or None)], outermost first: inv, pow, ctrl, negctrl
 
 
 @dataclass
@@ -422,8 +423,15 @@ class Parser:
 
     def _gate_call(self):
         name = self._word()
-        if self._is("@"):
-            raise QasmError("gate modifiers (ctrl @, inv @) are not supported")
+        mods = []
+        while name in ("inv", "pow", "ctrl", "negctrl") and (self._is("@") or self._is("(")):
+            arg = None
+            if self._eat("("):
+                arg = self._expr()
+                self._need(")")
+            self._need("@")
+            mods.append((name, arg))
+            name = self._word()
         args = []
         if self._eat("("):
             if not self._eat(")"):
@@ -435,7 +443,7 @@ class Parser:
         while self._eat(","):
             ops.append(self._operand())
         self._need(";")
-        return GateCall(name, args, ops)
+        return GateCall(name, args, ops, mods)
 
     def _operand(self):
         reg = self._word()

@@ -82,6 +82,72 @@ class Affine:
         return f"Affine({self.c}, {self.terms})"
 
 
+def _aff_scale(a, s):
+    return Affine(a.c * s, {k: v * s for k, v in a.terms.items()})
+
+
+def _aff_sum(*parts):
+    """sum of (coefficient, Affine) pairs"""
+    c, terms = 0.0, {}
+    for s, a in parts:
+        c += s * a.c
+        for k, v in a.terms.items():
+            terms[k] = terms.get(k, 0.0) + s * v
+    return Affine(c, terms)
+
+
+# Gate modifiers lower to standard gates. Inverses of the standard gates:
+_SELF_INVERSE = {"id", "x", "y", "z", "h", "cx", "CX", "cnot", "cy", "cz", "ch", "swap"}
+_INVERSE_NAME = {"s": "sdg", "sdg": "s", "t": "tdg", "tdg": "t", "sx": "sxdg", "sxdg": "sx"}
+_NEGATED_ANGLE = {"rx", "ry", "rz", "p", "phase", "u1", "cp", "cphase", "crx", "cry", "crz"}
+# a single control on a one-qubit gate
+_CONTROLLED = {"x": "cx", "y": "cy", "z": "cz", "h": "ch", "rx": "crx", "ry": "cry", "rz": "crz",
+               "p": "cp", "phase": "cp", "u1": "cp"}
+_CONTROLLED_PHASE = {"s": math.pi / 2.0, "sdg": -math.pi / 2.0, "t": math.pi / 4.0, "tdg": -math.pi / 4.0}
+
+
+def _inverse(g):
+    """The inverse of one standard gate (name, angles, qubits)."""
+    name, a, qs = g
+    if name in _SELF_INVERSE:
+        return g
+    if name in _INVERSE_NAME:
+        return (_INVERSE_NAME[name], a, qs)
+    if name in _NEGATED_ANGLE:
+        return (name, [_aff_scale(a[0], -1.0)], qs)
+    if name in ("u", "U", "u3"):  # U(t, p, l)^dag = U(-t, -l, -p)
+        return ("U", [_aff_scale(a[0], -1.0), _aff_scale(a[2], -1.0), _aff_scale(a[1], -1.0)], qs)
+    if name == "u2":
+        return ("U", [Affine(-math.pi / 2.0), _aff_scale(a[1], -1.0), _aff_scale(a[0], -1.0)], qs)
+    raise F.QasmError(f"no inverse for gate {name}")
+
+
+def _controlled(g, c):
+    """Standard gates applying |0><0| (x) I + |1><1| (x) g with control qubit c."""
+    name, a, qs = g
+    if len(qs) != 1:
+        raise F.QasmError(f"ctrl @ {name}: a controlled two-qubit gate is not supported")
+    t = qs[0]
+    if name == "id":
+        return []
+    if name in _CONTROLLED:
+        return [(_CONTROLLED[name], a, [c, t])]
+    if name in _CONTROLLED_PHASE:
+        return [("cp", [Affine(_CONTROLLED_PHASE[name])], [c, t])]
+    if name in ("sx", "sxdg"):  # SX = e^{i pi/4} RX(pi/2): the phase moves to the control
+        sgn = 1.0 if name == "sx" else -1.0
+        return [("p", [Affine(sgn * math.pi / 4.0)], [c]), ("crx", [Affine(sgn * math.pi / 2.0)], [c, t])]
+    if name in ("u", "U", "u3", "u2"):
+        th, ph, la = (a if name != "u2" else [Affine(math.pi / 2.0)] + list(a))
+        return [("p", [_aff_sum((0.5, la), (0.5, ph))], [c]),
+                ("p", [_aff_sum((0.5, la), (-0.5, ph))], [t]),
+                ("cx", [], [c, t]),
+                ("U", [_aff_scale(th, -0.5), Affine(0.0), _aff_sum((-0.5, ph), (-0.5, la))], [t]),
+                ("cx", [], [c, t]),
+                ("U", [_aff_scale(th, 0.5), ph, Affine(0.0)], [t])]
+    raise F.QasmError(f"ctrl @ {name} is not supported")
+
+
 def _aff_add(a, b, sign):
     terms = dict(a.terms)
     for k, v in b.terms.items():
@@ -375,7 +441,64 @@ class _Lowerer:
             qs = [x[j] if len(x) > 1 else x[0] for x in lists]
             if len(set(qs)) != len(qs):
                 raise F.QasmError(f"gate {st.name}: a qubit appears twice")
-            self.apply(st.name, angles, qs, guard)
+            if st.mods:
+                chain = []
+                for kind, arg in st.mods:
+                    v = 1 if arg is None else self.const_int(arg, env)
+                    if kind == "pow" and arg is None:
+                        raise F.QasmError("pow @ needs an exponent")
+                    if kind in ("ctrl", "negctrl") and v != 1:
+                        raise F.QasmError(f"{kind}({v}) @: only one control is supported")
+                    chain.append((kind, v))
+                for name, a, q in self.modified(chain, st.name, angles, qs):
+                    self.apply(name, a, q, guard)
+            else:
+                self.apply(st.name, angles, qs, guard)
+
+    def standard_gates(self, name, angles, qs):
+        """The standard gates (name, angles, qubits) a gate call applies, in order."""
+        if name not in self.gatedefs:
+            if name not in _GATES:
+                raise F.QasmError(f"unknown gate {name}")
+            return [(name, list(angles), list(qs))]
+        d = self.gatedefs[name]
+        if len(d.params) != len(angles) or len(d.qargs) != len(qs):
+            raise F.QasmError(f"gate {name}: wrong number of arguments")
+        env = {p: a for p, a in zip(d.params, angles)}
+        env.update({qa: ("q", q) for qa, q in zip(d.qargs, qs)})
+        out = []
+        for st in d.body:
+            if not isinstance(st, F.GateCall):
+                raise F.QasmError(f"gate {name}: only gate calls may appear in a gate body")
+            a = [self.value(x, env) for x in st.args]
+            q = [self.qubits(o, env)[0] for o in st.operands]
+            if st.mods:
+                chain = [(k, 1 if v is None else self.const_int(v, env)) for k, v in st.mods]
+                out += self.modified(chain, st.name, a, q)
+            else:
+                out += self.standard_gates(st.name, a, q)
+        return out
+
+    def modified(self, chain, name, angles, qs):
+        """Standard gates of a modified gate call; chain lists the modifiers
+        outermost first (controls take the leading operands)."""
+        if not chain:
+            return self.standard_gates(name, angles, qs)
+        kind, v = chain[0]
+        if kind == "inv":
+            return [_inverse(g) for g in reversed(self.modified(chain[1:], name, angles, qs))]
+        if kind == "pow":
+            seq = self.modified(chain[1:], name, angles, qs)
+            if v < 0:
+                seq = [_inverse(g) for g in reversed(seq)]
+            return seq * abs(v)
+        c = qs[0]
+        out = [("x", [], [c])] if kind == "negctrl" else []
+        for g in self.modified(chain[1:], name, angles, qs[1:]):
+            out += _controlled(g, c)
+        if kind == "negctrl":
+            out.append(("x", [], [c]))
+        return out
 
     def apply(self, name, angles, qs, guard):
         if name in self.gatedefs:

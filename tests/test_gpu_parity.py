@@ -255,6 +255,13 @@ def test_trajectory_sharing_runs_passes_once_per_history():
         c.close()
 
 
+def test_gate_modifiers_match_oracle(ctx):
+    """inv @, pow(k) @, ctrl @, negctrl @ programs (lowered to standard gates)
+    against the oracle, which applies the modifiers by definition."""
+    for seed, n in [(0, 6), (1, 11), (2, 13)]:
+        _check_shots(ctx, W.modifier_program(seed, n, 60), 24, seed=seed)
+
+
 # ---------------------------------------------------------------------------
 # Expectation values and gradients
 # ---------------------------------------------------------------------------
@@ -294,6 +301,32 @@ def test_gradient_matrix_core_sweep(ctx):
             eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
             assert abs(e[b] - eo) < 1e-12
             assert np.max(np.abs(g[b] - go)) < 1e-11
+
+
+def test_gradient_through_gate_modifiers(ctx):
+    """Parameters under inv @ and ctrl @ on a 12-qubit program (all-dense passes,
+    matrix-core sweep) against the oracle's adjoint, which differentiates the
+    modified matrices by definition."""
+    n, P = 12, 24
+    lines = ['OPENQASM 3.0;', 'include "stdgates.inc";', f"input array[float[64], {P}] t;", f"qubit[{n}] q;"]
+    for k in range(P):
+        a, b = k % n, (5 * k + 3) % n
+        lines.append(f"h q[{a}];")
+        lines.append([f"inv @ ry(t[{k}]) q[{a}];", f"ctrl @ rz(t[{k}]) q[{a}], q[{b}];",
+                      f"ctrl @ U(t[{k}], 0.3, -0.2) q[{b}], q[{a}];", f"negctrl @ rx(2 * t[{k}]) q[{a}], q[{b}];"][k % 4])
+        lines.append(f"cx q[{a}], q[{(a + 1) % n}];")
+    src = "\n".join(lines) + "\n"
+    from paper_2604_11599_amd import lower
+    from paper_2604_11599_amd.api import plan_inspect
+    st = plan_inspect(lower(src), 0)
+    assert st.n_mfma_sweep_passes == st.n_passes > 0
+    coeffs, codes = W.c4_hamiltonian(seed=21, n=n, terms=16)
+    thetas = W.c4_thetas(seed=22, batch=2, n_params=P)
+    e, g = ctx.load(src).expval_grad(thetas, coeffs, codes)
+    for b in range(2):
+        eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
+        assert abs(e[b] - eo) < 1e-12
+        assert np.max(np.abs(g[b] - go)) < 1e-11
 
 
 def test_expval_closed_form_and_general_gates(ctx):

@@ -216,3 +216,16 @@ def test_context_close_frees_live_programs_first(monkeypatch):
     del progs
     gc.collect()
     assert sorted(calls[:2]) == [("free", 7), ("free", 8)] and calls[2:] == [("destroy", 1)]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_lowering_of_gate_modifiers_matches_oracle(seed):
+    """inv @, pow(k) @, ctrl @, negctrl @ lower to standard gates (controlled U
+    and SX by decomposition); the oracle applies them by definition."""
+    _compare(W.modifier_program(seed, 3 + seed % 3, 30), shots=2)
+
+
+def test_gate_modifier_limits_are_reported():
+    for body in ("ctrl @ cx q[0], q[1], q[2];", "ctrl(2) @ x q[0], q[1], q[2];", "pow @ x q[0];"):
+        with pytest.raises(QasmError):
+            lower('OPENQASM 3.0;\ninclude "stdgates.inc";\nqubit[3] q;\n' + body + "\n")

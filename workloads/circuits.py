@@ -418,3 +418,46 @@ def param_program(seed, n, n_gates, n_params):
             lines.append(f"{('h', 'sx')[kind - 11]} q[{a}];")
     return "\n".join(lines) + "\n"
 
+
+
+def modifier_program(seed, n, n_gates, final_measure=True):
+    """Random circuit of gate calls under gate modifiers: inv @, pow(k) @ (k in
+    -2..3), ctrl @ and negctrl @ (one control) on one-qubit gates, inv @ on
+    two-qubit gates and on a gate definition, mixed with plain gates."""
+    rng = _rng(seed)
+    one = ["x", "y", "z", "h", "s", "sdg", "t", "tdg", "sx", "sxdg", "rx", "ry", "rz", "p", "U", "u2"]
+    two = ["cx", "cz", "cp", "crx", "cry", "swap"]
+    lines = [HEADER, "gate blk(a) u, v { h u; crz(a) u, v; ry(0.5 * a) v; }", f"qubit[{n}] q;"]
+    if final_measure:
+        lines.append(f"bit[{n}] f;")
+
+    def call(name):
+        if name in ("rx", "ry", "rz", "p", "cp", "crx", "cry"):
+            return f"{name}({_ang(rng.random() * TWO_PI)})"
+        if name == "U":
+            a = rng.random(3) * TWO_PI
+            return f"U({_ang(a[0])}, {_ang(a[1])}, {_ang(a[2])})"
+        if name == "u2":
+            a = rng.random(2) * TWO_PI
+            return f"u2({_ang(a[0])}, {_ang(a[1])})"
+        return name
+
+    for _ in range(n_gates):
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        r = rng.random()
+        if r < 0.3:
+            lines.append(f"{call(str(rng.choice(one)))} q[{a}];")
+        elif r < 0.5:
+            mod = ["ctrl", "negctrl"][int(rng.integers(2))]
+            inner = "inv @ " if rng.random() < 0.3 else ""
+            lines.append(f"{mod} @ {inner}{call(str(rng.choice(one)))} q[{a}], q[{b}];")
+        elif r < 0.7:
+            k = int(rng.integers(-2, 4))
+            lines.append(f"pow({k}) @ {call(str(rng.choice(one)))} q[{a}];")
+        elif r < 0.85:
+            lines.append(f"inv @ {call(str(rng.choice(two)))} q[{a}], q[{b}];")
+        else:
+            lines.append(f"inv @ blk({_ang(rng.random() * TWO_PI)}) q[{a}], q[{b}];")
+    if final_measure:
+        lines.append("f = measure q;")
+    return "\n".join(lines) + "\n"
