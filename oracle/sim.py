@@ -358,12 +358,19 @@ class Interpreter:
         return [off + i]
 
     # -- running one shot --
-    def run(self, seed=0, shot=0, forced=None, first_event=0):
+    def run(self, seed=0, shot=0, forced=None, first_event=0, readout_error=0.0, reset_error=0.0):
         """first_event: index in the shot's Philox stream of the first word this
         program draws (0 for a whole program; a program that is one independent
         block of a larger product-state program starts where the draws of the
-        blocks measured before it end)."""
+        blocks measured before it end).
+        readout_error: after a measurement's outcome is drawn (the state keeps
+        it), the next word u flips the recorded bit when u < readout_error.
+        reset_error: after a reset, the next word u flips the qubit when
+        u < reset_error. Either draw happens only when its rate is positive."""
         p = self.prog
+        self.readout_error = float(readout_error)
+        self.reset_error = float(reset_error)
+        self.first_event = int(first_event)
         self.eng = self.engine_cls(p.n_qubits)
         self.cbits = [0] * p.n_clbits
         self.stream = ShotStream(seed, shot)
@@ -574,21 +581,31 @@ class Interpreter:
             forced_value = self.forced[self.n_measures]
         m, u, p0n = self._draw_outcome(q, forced_value)
         self.n_measures += 1
-        self.record.append(m)
         self.events.append(("measure", q, m, u, p0n))
+        r = m
+        if self.readout_error > 0.0 and self.stream.next_uniform() < self.readout_error:
+            r = 1 - m
+        self.record.append(r)
         if c is not None:
-            self.cbits[c] = m
+            self.cbits[c] = r
 
     def reset(self, q):
         m, u, p0n = self._draw_outcome(q, None)
         self.events.append(("reset", q, m, u, p0n))
         if m == 1:
             self.eng.flip(q)
+        if self.reset_error > 0.0 and self.stream.next_uniform() < self.reset_error:
+            self.eng.flip(q)
 
     # -- results --
     @property
     def psi(self):
         return self.eng.psi
+
+    @property
+    def words_drawn(self):
+        """Philox words this shot consumed (one per measure/reset event, plus the error draws)."""
+        return self.stream.event - self.first_event
 
     def creg_words(self):
         words = [0] * max(1, (len(self.cbits) + 63) // 64)
@@ -604,20 +621,22 @@ def _val(x):
 # --------------------------------------------------------------------------
 # Convenience entry points used by tests, the smoke check and the CPU baseline.
 # --------------------------------------------------------------------------
-def run_shot(source, theta=None, seed=0, shot=0, forced=None, engine_cls=TensorEngine, first_event=0):
+def run_shot(source, theta=None, seed=0, shot=0, forced=None, engine_cls=TensorEngine, first_event=0,
+             readout_error=0.0, reset_error=0.0):
     """Run one shot; returns the finished interpreter (psi, cbits, record, ...)."""
     it = Interpreter(source if isinstance(source, Program) else Program(source), theta, engine_cls)
-    return it.run(seed, shot, forced, first_event)
+    return it.run(seed, shot, forced, first_event, readout_error, reset_error)
 
 
-def run_shots(source, n_shots, theta=None, seed=0, shot_offset=0, forced=None):
+def run_shots(source, n_shots, theta=None, seed=0, shot_offset=0, forced=None, readout_error=0.0,
+              reset_error=0.0):
     prog = source if isinstance(source, Program) else Program(source)
     out = []
     for s in range(n_shots):
         f = None if forced is None else forced[s]
-        it = Interpreter(prog, theta).run(seed, shot_offset + s, f)
+        it = Interpreter(prog, theta).run(seed, shot_offset + s, f, 0, readout_error, reset_error)
         out.append({"creg": it.creg_words(), "cbits": list(it.cbits), "record": list(it.record),
-                    "n_events": len(it.events), "record_prob": it.record_prob,
+                    "n_events": it.words_drawn, "record_prob": it.record_prob,
                     "status": it.status, "events": list(it.events)})
     return out
 
