@@ -180,12 +180,18 @@ typedef struct {
   uint32_t forced_len;
   uint32_t flags;        /* QSV_RUN_* */
   double* state_out;     /* NULL, or host [2^n][2] doubles: shot 0's state at program end */
+  double readout_error;  /* in [0, 1): after a measurement's outcome is drawn (the state keeps
+                            it), the shot's next Philox word u flips the recorded bit (record and
+                            classical bit) when u < readout_error; 0: no draw */
+  double reset_error;    /* in [0, 1): after a reset, the next word u leaves the qubit flipped
+                            when u < reset_error; 0: no draw */
 } qsv_run_opts;
 
 typedef struct {
   uint64_t* creg;        /* [n_shots][ceil(n_clbits/64)] classical bits, LSB-first words */
   uint8_t* record;       /* [n_shots][max_events] measure outcomes in execution order, or NULL */
-  uint32_t* n_events;    /* [n_shots] measure + reset events consumed, or NULL */
+  uint32_t* n_events;    /* [n_shots] Philox words consumed (one per measure or reset event, plus
+                            one per error draw), or NULL */
   double* record_prob;   /* [n_shots] product of the outcome probabilities, or NULL */
   int32_t* shot_status;  /* [n_shots] QSV_OK or QSV_ERR_FORCED_ZERO_PROB, or NULL */
 } qsv_shot_results;

@@ -39,7 +39,8 @@ class ProgramInfo(C.Structure):
 
 class RunOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("shot_offset", C.c_uint64), ("forced", C.c_void_p),
-                ("forced_len", C.c_uint32), ("flags", C.c_uint32), ("state_out", C.c_void_p)]
+                ("forced_len", C.c_uint32), ("flags", C.c_uint32), ("state_out", C.c_void_p),
+                ("readout_error", C.c_double), ("reset_error", C.c_double)]
 
 
 class ShotResults(C.Structure):

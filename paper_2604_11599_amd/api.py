@@ -94,7 +94,7 @@ class Context:
         """qsv_run_batch: every shot of every request in one persistent launch.
 
         requests: iterable of dicts with keys prog, shots and optionally theta,
-        seed, shot_offset, forced. Returns one ShotResultArrays per request."""
+        seed, shot_offset, forced, readout_error, reset_error. Returns one ShotResultArrays per request."""
         reqs = list(requests)
         arr = (A.Request * max(1, len(reqs)))()
         keep, results = [], []
@@ -108,7 +108,8 @@ class Context:
             arr[i].theta = None if th is None else th.ctypes.data
             arr[i].n_shots = n
             arr[i].opts = A.RunOpts(int(rq.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF, int(rq.get("shot_offset", 0)),
-                                    _ptr(f), flen, 0, None)
+                                    _ptr(f), flen, 0, None, float(rq.get("readout_error", 0.0)),
+                                    float(rq.get("reset_error", 0.0)))
             arr[i].out = A.ShotResults(*[_ptr(b) for b in bufs])
             results.append(bufs)
         self.check(A.lib().qsv_run_batch(self.handle, arr, len(reqs)))
@@ -192,7 +193,7 @@ class Program:
         return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
-                  share=False):
+                  share=False, readout_error=0.0, reset_error=0.0):
         """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses."""
         lp = self.lowered
         cw = max(1, (lp.n_clbits + 63) // 64)
@@ -216,7 +217,7 @@ class Program:
             flen = f.shape[1]
         st = np.zeros((1 << lp.n_qubits, 2), dtype=np.float64) if state_out else None
         opts = A.RunOpts(seed & 0xFFFFFFFFFFFFFFFF, shot_offset, _ptr(f), flen,
-                         A.QSV_RUN_SHARE_TRAJ if share else 0, _ptr(st))
+                         A.QSV_RUN_SHARE_TRAJ if share else 0, _ptr(st), float(readout_error), float(reset_error))
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
         self.ctx.check(A.lib().qsv_run_shots(self.ctx.handle, self.handle, _ptr(th), n_shots,
                                              C.byref(opts), C.byref(res)))

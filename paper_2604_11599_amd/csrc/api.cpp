@@ -377,6 +377,9 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   if (!opts) opts = &def;
   if (opts->forced_len && !opts->forced) return set_err(ctx, QSV_ERR_ARG, "forced_len without forced");
   if (prog->desc.n_params && !theta) return set_err(ctx, QSV_ERR_ARG, "theta is required");
+  if (!(opts->readout_error >= 0.0 && opts->readout_error < 1.0) ||
+      !(opts->reset_error >= 0.0 && opts->reset_error < 1.0))
+    return set_err(ctx, QSV_ERR_ARG, "error rates must lie in [0, 1)");
   if (n_shots == 0) return QSV_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   const Plan& pl = prog->plan;
@@ -429,6 +432,8 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   rb.forced = d_forced;
   rb.forced_len = opts->forced_len;
   rb.seed = opts->seed;
+  rb.readout_err = opts->readout_error;
+  rb.reset_err = opts->reset_error;
   std::vector<ShotCtl> hctl(batch);
   // trajectory sharing: slot g holds one state (buffer buf_of[g]) and control
   // block for every shot s with slot_of[s] == g, i.e. the same history so far
@@ -619,6 +624,9 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     if (!q.out.creg) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": creg output is required");
     if (q.prog->desc.n_params && !q.theta) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": theta is required");
     if (q.opts.forced_len && !q.opts.forced) return set_err(ctx, QSV_ERR_ARG, "forced_len without forced");
+    if (!(q.opts.readout_error >= 0.0 && q.opts.readout_error < 1.0) ||
+        !(q.opts.reset_error >= 0.0 && q.opts.reset_error < 1.0))
+      return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": error rates must lie in [0, 1)");
     const uint32_t n = q.prog->desc.n_qubits;
     if (q.n_shots == 0) continue;
     // wide states, and streamed states with many shots, run on the tile-pass
@@ -699,6 +707,8 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       R.forced_len = q.opts.forced_len;
       R.seed = q.opts.seed;
       R.shot_offset = q.opts.shot_offset;
+      R.readout_err = q.opts.readout_error;
+      R.reset_err = q.opts.reset_error;
       R.n = p->desc.n_qubits;
       R.n_steps = (uint32_t)p->plan.steps.size();
       R.item_begin = ib;

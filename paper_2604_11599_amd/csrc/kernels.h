@@ -21,6 +21,7 @@ struct RunBuffers {
   uint32_t forced_len;
   uint64_t seed, shot_base;   // Philox key (seed, shot_base + shot)
   uint32_t shots;
+  double readout_err, reset_err;  // error rates of measurements (recorded bit) and resets
   // trajectory sharing (null: one state per shot): a site's histogram of
   // slot g reads state buffer buf_of[g]; shot s finalises from slot slot_of[s]
   const uint32_t* buf_of;

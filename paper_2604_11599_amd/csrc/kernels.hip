@@ -1046,7 +1046,8 @@ __device__ bool eval_pred(const DPred& p, const uint64_t* creg) {
 // composed into the shot's pending collapse and flip frame.
 __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, const SiteArgs& a, const SiteEvent* __restrict__ ev,
                             const DPred* __restrict__ preds, uint64_t* cr, uint8_t* rec, uint32_t max_record,
-                            const uint8_t* frow, uint32_t forced_len, uint64_t seed, uint64_t key1) {
+                            const uint8_t* frow, uint32_t forced_len, uint64_t seed, uint64_t key1,
+                            double readout_err, double reset_err) {
   uint32_t rm = 0, rv = 0;  // restriction on the bins (pre-site logical values)
   uint64_t xf = 0;          // flips applied during this site
   const double kZero = 0x1p-60;
@@ -1086,14 +1087,27 @@ __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, con
       rm |= 1u << k;
       rv |= (o ^ fq) << k;
       if (E.op == SE_MEASURE) {
-        if (cc.n_record < max_record) rec[cc.n_record] = (uint8_t)o;
+        // readout error: the next word flips the recorded bit (the state keeps o)
+        uint32_t r = o;
+        if (readout_err > 0.0) {
+          const uint64_t w2 = philox_word(seed, key1, cc.n_events);
+          cc.n_events++;
+          if ((double)(w2 >> 11) * 0x1p-53 < readout_err) r ^= 1u;
+        }
+        if (cc.n_record < max_record) rec[cc.n_record] = (uint8_t)r;
         cc.n_record++;
         if (E.cbit != 0xFFFFFFFFu) {
           uint64_t bitm = 1ull << (E.cbit & 63);
-          cr[E.cbit >> 6] = o ? (cr[E.cbit >> 6] | bitm) : (cr[E.cbit >> 6] & ~bitm);
+          cr[E.cbit >> 6] = r ? (cr[E.cbit >> 6] | bitm) : (cr[E.cbit >> 6] & ~bitm);
         }
-      } else if (o) {
-        xf ^= 1ull << E.q;  // reset: flip the qubit back to |0>
+      } else {
+        if (o) xf ^= 1ull << E.q;  // reset: flip the qubit back to |0>
+        // reset error: the next word leaves the qubit flipped
+        if (reset_err > 0.0) {
+          const uint64_t w2 = philox_word(seed, key1, cc.n_events);
+          cc.n_events++;
+          if ((double)(w2 >> 11) * 0x1p-53 < reset_err) xf ^= 1ull << E.q;
+        }
       }
     }
   }
@@ -1121,7 +1135,8 @@ __global__ __launch_bounds__(64) void k_site_finalize(
     const DPred* __restrict__ preds, const double* __restrict__ partials, uint32_t pblocks,
     uint64_t* __restrict__ creg,
     uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record, const uint8_t* __restrict__ forced,
-    uint32_t forced_len, uint64_t seed, uint64_t shot_base, const uint32_t* __restrict__ slot_of) {
+    uint32_t forced_len, uint64_t seed, uint64_t shot_base, const uint32_t* __restrict__ slot_of, double readout_err,
+    double reset_err) {
   __shared__ double part[4][kSiteBins];
   const uint32_t shot = blockIdx.x, tid = threadIdx.x;
   ShotCtl* c = ctl + shot;
@@ -1139,7 +1154,7 @@ __global__ __launch_bounds__(64) void k_site_finalize(
   ShotCtl cc = *c;
   site_events(cc, bins, a, ev, preds, creg + (uint64_t)shot * cw, record + (uint64_t)shot * max_record,
               max_record, forced ? forced + (uint64_t)shot * forced_len : nullptr, forced_len, seed,
-              shot_base + shot);
+              shot_base + shot, readout_err, reset_err);
   *c = cc;
 }
 
@@ -1156,7 +1171,7 @@ hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent*
   }
   hipLaunchKernelGGL(k_site_finalize, dim3(rb.shots), dim3(64), 0, st, rb.ctl, a, ev, preds, rb.partials,
                      rb.pblocks, rb.creg, rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len, rb.seed,
-                     rb.shot_base, rb.slot_of);
+                     rb.shot_base, rb.slot_of, rb.readout_err, rb.reset_err);
   return hipGetLastError();
 }
 
@@ -1414,7 +1429,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
           ShotCtl c = cs;
           site_events(c, hb, sa, R.events, R.preds, cr, rec, rec_max,
                       R.forced ? R.forced + (uint64_t)shot * R.forced_len : nullptr, R.forced_len, R.seed,
-                      R.shot_offset + shot);
+                      R.shot_offset + shot, R.readout_err, R.reset_err);
           cs = c;
         }
         __syncthreads();

@@ -171,6 +171,7 @@ struct ReqDev {
   // with state_out set (prefix items) it works in, and leaves its state in,
   // that buffer instead of the workgroup's slot.
   uint32_t step_begin, pad;
+  double readout_err, reset_err;  // error rates of measurements (recorded bit) and resets
   const double* init_state;  // complex128 amplitudes (re, im)
   const ShotCtl* init_ctl;
   double* state_out;         // complex128 amplitudes (re, im)

@@ -41,17 +41,20 @@ def _near_tie(events):
     return any(abs(e[3] - e[4]) < TIE for e in events)
 
 
-def _check_shots(ctx, src, n_shots, seed=11, theta=None, forced_from_oracle=False, state=True):
-    say("case", src.splitlines()[2:4], "shots", n_shots, "seed", seed)
+def _check_shots(ctx, src, n_shots, seed=11, theta=None, forced_from_oracle=False, state=True, noise=(0.0, 0.0),
+                 share=False):
+    say("case", src.splitlines()[2:4], "shots", n_shots, "seed", seed, "noise", noise)
     prog = ctx.load(src)
-    oracle = [sim.run_shot(src, theta, seed=seed, shot=s) for s in range(n_shots)]
+    oracle = [sim.run_shot(src, theta, seed=seed, shot=s, readout_error=noise[0], reset_error=noise[1])
+              for s in range(n_shots)]
     forced = None
     if forced_from_oracle:
         width = max(1, max(len(o.record) for o in oracle))
         forced = np.zeros((n_shots, width), dtype=np.uint8)
         for s, o in enumerate(oracle):
             forced[s, :len(o.record)] = o.record
-    res = prog.run_shots(n_shots, theta=theta, seed=seed, forced=forced, state_out=state)
+    res = prog.run_shots(n_shots, theta=theta, seed=seed, forced=forced, state_out=state, share=share,
+                         readout_error=noise[0], reset_error=noise[1])
     bits = res.bits()
     skipped = 0
     for s, o in enumerate(oracle):
@@ -61,7 +64,7 @@ def _check_shots(ctx, src, n_shots, seed=11, theta=None, forced_from_oracle=Fals
         assert res.shot_status[s] == 0
         assert list(bits[s]) == o.cbits, f"shot {s}"
         assert list(res.record[s, :len(o.record)]) == o.record
-        assert res.n_events[s] == len(o.events)
+        assert res.n_events[s] == o.words_drawn
         assert abs(res.record_prob[s] - o.record_prob) < PROB_TOL
     if state:
         assert np.max(np.abs(res.state - oracle[0].psi)) < AMP_TOL
@@ -260,6 +263,31 @@ def test_gate_modifiers_match_oracle(ctx):
     against the oracle, which applies the modifiers by definition."""
     for seed, n in [(0, 6), (1, 11), (2, 13)]:
         _check_shots(ctx, W.modifier_program(seed, n, 60), 24, seed=seed)
+
+
+def test_readout_and_reset_errors_match_oracle(ctx):
+    """Readout and reset errors drawn from each shot's own Philox stream: shot by
+    shot equal to the oracle on the tile-pass path (with and without trajectory
+    sharing) and in a persistent batch; the noisy conditional reset's flip rate
+    is the closed form 2 e (1 - e)."""
+    noise = (0.07, 0.05)
+    for src, shots in [(W.c1_program(4), 64), (W.random_dynamic_program(31, 13, n_ops=60), 32),
+                       (W.c3_program(6, n=13, layers=3), 32)]:
+        _check_shots(ctx, src, shots, seed=3, noise=noise, state=False)
+        _check_shots(ctx, src, shots, seed=3, noise=noise, state=False, share=True)
+        o = sim.run_shots(src, shots, seed=5, readout_error=noise[0], reset_error=noise[1])
+        r = ctx.run_batch([{"prog": ctx.load(src), "shots": shots, "seed": 5, "readout_error": noise[0],
+                            "reset_error": noise[1]}])[0]
+        for s in range(shots):
+            if _near_tie(sim.run_shot(src, seed=5, shot=s, readout_error=noise[0], reset_error=noise[1]).events):
+                continue
+            assert list(r.record[s, :len(o[s]["record"])]) == o[s]["record"] and r.n_events[s] == o[s]["n_events"]
+    e = 0.1
+    src = W.circuits.HEADER + "qubit[1] q;\nbit c;\nbit f;\nh q[0];\nc = measure q[0];\nif (c == 1) x q[0];\nf = measure q[0];\n"
+    res = ctx.load(src).run_shots(20000, seed=9, readout_error=e)
+    frac = float(np.mean((res.creg[:, 0] >> 1) & 1))
+    p = 2 * e * (1 - e)
+    assert abs(frac - p) < 4 * math.sqrt(p * (1 - p) / 20000)
 
 
 # ---------------------------------------------------------------------------

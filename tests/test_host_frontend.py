@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.Config) == 40
     assert ctypes.sizeof(_abi.ProgramDesc) == 40
-    assert ctypes.sizeof(_abi.RunOpts) == 40
+    assert ctypes.sizeof(_abi.RunOpts) == 56
     assert ctypes.sizeof(_abi.ShotResults) == 40
     assert ctypes.sizeof(_abi.PauliSum) == 24
     assert ctypes.sizeof(_abi.PlanStats) == 315424 + 8 * 65536 + 16
