@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 128 FP64 flops/clock x 2.4 GHz (vector and matrix cores alike)
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of the MI355X
 
 
 def log(*a):
@@ -322,10 +323,36 @@ def main():
                       "share one state (gate passes once per distinct history)"}
     log("shared-trajectory steps done")
 
+    # the same steps with a complex64 state (single-precision amplitudes and
+    # matrix-core products; outcomes agree with complex128 except where a draw
+    # lies within single-precision error of its threshold)
+    prog.run_shots(shots, seed=1000, complex64=True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for s in range(args.steps):
+        prog.run_shots(shots, seed=s, complex64=True)
+    torch.cuda.synchronize()
+    dt_c64 = time.perf_counter() - t2
+    p64 = ctx.profile()
+    l64 = p64["pass_uncond_launches"]
+    t64 = p64["pass_uncond_ms"] / 1e3
+    g64 = p64["pass_uncond_bytes"] / t64 / 1e9 if t64 else 0.0
+    tf32 = p64["pass_uncond_flops"] / t64 / 1e12 if t64 else 0.0
+    c64 = {"value": shots * args.steps / dt_c64, "unit": "shots/s", "ms_per_step": 1e3 * dt_c64 / args.steps,
+           "dtype": "c64",
+           "roofline": {"kernel": "k_tile_pass", "launches": l64, "avg_launch_ms": 1e3 * t64 / l64 if l64 else 0.0,
+                        "hbm": {"achieved": g64, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": g64 / HBM_PEAK_GBS},
+                        "mfma": {"achieved": tf32, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": tf32 / FP32_MFMA_PEAK_TFLOPS}},
+           "note": "same shots with a complex64 state (the precision of the paper's GPU runs)"}
+    log("complex64 steps done")
+
     out = {"metric": "shots/s + achieved HBM GB/s on 16q/28q dynamic circuits; p50/p99 request latency",
            "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof, "shared_trajectories": shared}
+           "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof, "shared_trajectories": shared,
+           "complex64": c64}
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the workload")

@@ -170,7 +170,17 @@ void qsv_program_free(qsv_program* prog);
    stream; a history splits where its shots' outcomes differ. A split copies the
    state only before the next gate pass writes it, so a final measure-all adds
    no copies. Results are bit-identical to running every shot on its own. */
-enum { QSV_RUN_SHARE_TRAJ = 1u };
+/* QSV_RUN_COMPLEX64: the state is held and evolved in complex64 (single
+   precision amplitudes, single-precision matrix-core products), the precision
+   of the GPU runs in the paper's experimental setup (Experiments,
+   Implementation). Probabilities are summed in double precision from the
+   single-precision amplitudes; outcomes, records and feed-forward work as in
+   complex128, so results differ from the complex128 run only where a draw
+   falls within the single-precision error of its threshold. Gate matrices
+   are bound in double precision and rounded once where they are applied.
+   state_out is still complex128 (the complex64 amplitudes widened). Applies
+   to qsv_run_shots only. */
+enum { QSV_RUN_SHARE_TRAJ = 1u, QSV_RUN_COMPLEX64 = 2u };
 
 typedef struct {
   uint64_t seed;         /* Philox key word 0 */

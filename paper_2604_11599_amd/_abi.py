@@ -14,6 +14,7 @@ QSV_OK, QSV_ERR_ARG, QSV_ERR_PARSE, QSV_ERR_UNSUPPORTED = 0, -1, -2, -3
 QSV_ERR_NOMEM, QSV_ERR_DEVICE, QSV_ERR_FORCED_ZERO_PROB, QSV_ERR_LIMIT = -4, -5, -6, -7
 QSV_FLAG_PROFILE, QSV_FLAG_DEVICE_PTRS = 1, 2
 QSV_RUN_SHARE_TRAJ = 1
+QSV_RUN_COMPLEX64 = 2
 STATUS_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_PARSE", -3: "QSV_ERR_UNSUPPORTED",
                 -4: "QSV_ERR_NOMEM", -5: "QSV_ERR_DEVICE", -6: "QSV_ERR_FORCED_ZERO_PROB",
                 -7: "QSV_ERR_LIMIT"}

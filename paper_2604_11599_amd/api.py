@@ -193,8 +193,9 @@ class Program:
         return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
-                  share=False, readout_error=0.0, reset_error=0.0):
-        """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses."""
+                  share=False, readout_error=0.0, reset_error=0.0, complex64=False):
+        """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses.
+        complex64: hold and evolve the state in single precision (QSV_RUN_COMPLEX64)."""
         lp = self.lowered
         cw = max(1, (lp.n_clbits + 63) // 64)
         mr = self.info.max_events
@@ -217,7 +218,8 @@ class Program:
             flen = f.shape[1]
         st = np.zeros((1 << lp.n_qubits, 2), dtype=np.float64) if state_out else None
         opts = A.RunOpts(seed & 0xFFFFFFFFFFFFFFFF, shot_offset, _ptr(f), flen,
-                         A.QSV_RUN_SHARE_TRAJ if share else 0, _ptr(st), float(readout_error), float(reset_error))
+                         (A.QSV_RUN_SHARE_TRAJ if share else 0) | (A.QSV_RUN_COMPLEX64 if complex64 else 0), _ptr(st),
+                         float(readout_error), float(reset_error))
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
         self.ctx.check(A.lib().qsv_run_shots(self.ctx.handle, self.handle, _ptr(th), n_shots,
                                              C.byref(opts), C.byref(res)))

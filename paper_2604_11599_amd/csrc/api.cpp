@@ -387,7 +387,10 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   const uint32_t cw = std::max<uint32_t>(1, (prog->desc.n_clbits + 63) / 64);
   const uint32_t maxrec = std::max<uint32_t>(1, pl.max_record);
   const uint64_t dim = 1ull << n;
-  const size_t state_bytes = dim * sizeof(double2);
+  const bool c64 = (opts->flags & QSV_RUN_COMPLEX64) != 0;
+  const size_t state_bytes = dim * (c64 ? sizeof(float2) : sizeof(double2));
+  // state buffers are allocated in 16-byte units (two complex64 amplitudes)
+  auto state_units = [&](uint64_t bufs) -> size_t { return c64 ? (size_t)((bufs * dim + 1) / 2) : (size_t)(bufs * dim); };
   // shots per batch: what fits in the arena / free memory after the per-shot scratch
   size_t per_shot = state_bytes + sizeof(ShotCtl) + cw * 8 + maxrec + opts->forced_len +
                     (size_t)prog->pblocks * kSiteBins * 8 + 4 * 256;
@@ -416,7 +419,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   // owns its state, grown on demand (doubling) up to one per shot
   const bool share_req = (opts->flags & QSV_RUN_SHARE_TRAJ) != 0;
   uint64_t cap = (share_req && batch > 1) ? std::min<uint64_t>(batch, 8) : batch;
-  HIP_TRY(scr.get(cap * dim, &rb.state));
+  HIP_TRY(scr.get(state_units(cap), &rb.state));
   HIP_TRY(scr.get(batch, &rb.ctl));
   HIP_TRY(scr.get(batch * cw, &rb.creg));
   HIP_TRY(scr.get(batch * maxrec, &rb.record));
@@ -426,6 +429,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   double2* d_out = nullptr;
   if (opts->state_out) HIP_TRY(scr.get(dim, &d_out));
   rb.stride = dim;
+  rb.c64 = c64 ? 1u : 0u;
   rb.cw = cw;
   rb.max_record = maxrec;
   rb.pblocks = prog->pblocks;
@@ -454,7 +458,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     if (need <= cap) return QSV_OK;
     const uint64_t ncap = std::min<uint64_t>(batch, std::max<uint64_t>(2 * cap, need));
     double2* ns = nullptr;
-    HIP_TRY(scr.get(ncap * dim, &ns));
+    HIP_TRY(scr.get(state_units(ncap), &ns));
     HIP_TRY(hipMemcpyAsync(ns, rb.state, cap * state_bytes, hipMemcpyDeviceToDevice, st));
     rb.state = ns;
     cap = ncap;
@@ -488,7 +492,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       rp.shots = n_slot;
       Prof pr(ctx, st);
       if (step.kind == Step::INIT) {
-        HIP_TRY(launch_init_state(rp.state, rp.stride, n, n_slot, st));
+        HIP_TRY(launch_init_state(rp.state, rp.stride, n, n_slot, st, c64));
         pr.done(2);
       } else if (step.kind == Step::PASS) {
         if (share) {
@@ -505,14 +509,15 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
             if (cs != QSV_OK) return cs;
             rp.state = rb.state;
             HIP_TRY(hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice, st));
-            HIP_TRY(launch_buf_copy(rb.state, rb.stride, n, d_pairs, (uint32_t)pairs.size() / 2, st));
+            HIP_TRY(launch_buf_copy(rb.state, rb.stride, n, d_pairs, (uint32_t)pairs.size() / 2, st, c64));
             HIP_TRY(hipMemcpyAsync(d_buf_of, buf_of.data(), n_slot * 4, hipMemcpyHostToDevice, st));
             HIP_TRY(hipStreamSynchronize(st));  // the host tables change again after the uploads
           }
         }
         HIP_TRY(launch_tile_pass(rp, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
         const double amps = (double)dim * n_slot;
-        pr.done(0, pl.pass_uncond[step.index] != 0, pass_bytes_per_amp(pl.passes[step.index]) * amps,
+        pr.done(0, pl.pass_uncond[step.index] != 0,
+                pass_bytes_per_amp(pl.passes[step.index]) * (c64 ? 0.5 : 1.0) * amps,
                 pl.pass_flops_per_amp[step.index] * amps);
       } else if (!share) {
         HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, st));
@@ -584,14 +589,14 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
         pairs.assign({g, buf_of[g]});
         buf_of[g] = g;
         HIP_TRY(hipMemcpyAsync(d_pairs, pairs.data(), 8, hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_buf_copy(rb.state, rb.stride, n, d_pairs, 1, st));
+        HIP_TRY(launch_buf_copy(rb.state, rb.stride, n, d_pairs, 1, st, c64));
       }
       HIP_TRY(launch_materialize(rp, n, g, d_out, st));
-      HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, state_bytes, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, dim * sizeof(double2), hipMemcpyDeviceToHost, st));
     }
     if (!share && s0 == 0 && opts->state_out) {
       HIP_TRY(launch_materialize(rb, n, 0, d_out, st));
-      HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, state_bytes, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, dim * sizeof(double2), hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(hipMemcpyAsync(out->creg + s0 * cw, rb.creg, (size_t)bs * cw * 8, hipMemcpyDeviceToHost, st));
     if (out->record && pl.max_record) {

@@ -25,6 +25,36 @@ __device__ __forceinline__ double2 cmac2(double2 u, double2 a, double2 v, double
   return make_double2(re, im);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// complex64 amplitudes: the same operations in single precision
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, double s) {
+  const float f = (float)s;
+  return make_float2(a.x * f, a.y * f);
+}
+__device__ __forceinline__ float2 cmac2(float2 u, float2 a, float2 v, float2 b) {
+  float re = u.x * a.x - u.y * a.y + v.x * b.x - v.y * b.y;
+  float im = u.x * a.y + u.y * a.x + v.x * b.y + v.y * b.x;
+  return make_float2(re, im);
+}
+
+// Amplitude types of the state: complex128 (double2) or complex64 (float2).
+// Gate matrices are always bound in double precision and rounded to the
+// amplitude type where they are applied.
+template <typename CT> struct CxT;
+template <> struct CxT<double2> {
+  typedef double R;
+  __device__ static double2 make(double re, double im) { return make_double2(re, im); }
+};
+template <> struct CxT<float2> {
+  typedef float R;
+  __device__ static float2 make(double re, double im) { return make_float2((float)re, (float)im); }
+};
+template <typename CT>
+__device__ __forceinline__ CT cmake(double re, double im) {
+  return CxT<CT>::make(re, im);
+}
 
 __device__ __forceinline__ uint32_t ins0(uint32_t x, uint32_t b) {
   return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u));
@@ -34,17 +64,20 @@ __device__ __forceinline__ uint64_t ins0_64(uint64_t x, uint32_t b) {
 }
 
 // 2x2 matrix of a slot, conjugated by X when the frame flips its qubit.
-struct M2 {
-  double2 a, b, c, d;
+template <typename CT>
+struct M2x {
+  CT a, b, c, d;
 };
-__device__ __forceinline__ M2 load_m2(const double* m, uint32_t flip) {
-  M2 r;
-  r.a = make_double2(m[0], m[1]);
-  r.b = make_double2(m[2], m[3]);
-  r.c = make_double2(m[4], m[5]);
-  r.d = make_double2(m[6], m[7]);
+typedef M2x<double2> M2;
+template <typename CT>
+__device__ __forceinline__ M2x<CT> load_m2x(const double* m, uint32_t flip) {
+  M2x<CT> r;
+  r.a = cmake<CT>(m[0], m[1]);
+  r.b = cmake<CT>(m[2], m[3]);
+  r.c = cmake<CT>(m[4], m[5]);
+  r.d = cmake<CT>(m[6], m[7]);
   if (flip) {
-    double2 t = r.a;
+    CT t = r.a;
     r.a = r.d;
     r.d = t;
     t = r.b;
@@ -53,6 +86,7 @@ __device__ __forceinline__ M2 load_m2(const double* m, uint32_t flip) {
   }
   return r;
 }
+__device__ __forceinline__ M2 load_m2(const double* m, uint32_t flip) { return load_m2x<double2>(m, flip); }
 
 __device__ __forceinline__ bool guard_ok(uint64_t flags, uint64_t guard) { return (flags & guard) == guard; }
 
@@ -92,109 +126,110 @@ constexpr int kR = 1 << kRegBits;
 
 __device__ __forceinline__ uint32_t swz(uint32_t l) { return l ^ ((l >> 4) & 15u) ^ ((l >> 8) & 15u); }
 
-template <int J>
-__device__ __forceinline__ void r_dense(double2 (&a)[kR], const M2& u) {
+template <int J, typename CT>
+__device__ __forceinline__ void r_dense(CT (&a)[kR], const M2x<CT>& u) {
 #pragma unroll
   for (int k = 0; k < kR; ++k) {
     if (k & (1 << J)) continue;
     const int k1 = k | (1 << J);
-    const double2 x0 = a[k], x1 = a[k1];
+    const CT x0 = a[k], x1 = a[k1];
     a[k] = cmac2(u.a, x0, u.b, x1);
     a[k1] = cmac2(u.c, x0, u.d, x1);
   }
 }
 
-template <int J>
-__device__ __forceinline__ void r_diag(double2 (&a)[kR], const M2& u) {
+template <int J, typename CT>
+__device__ __forceinline__ void r_diag(CT (&a)[kR], const M2x<CT>& u) {
 #pragma unroll
   for (int k = 0; k < kR; ++k) a[k] = cmul((k & (1 << J)) ? u.d : u.a, a[k]);
 }
 
-template <int J>
-__device__ __forceinline__ void r_x(double2 (&a)[kR]) {
+template <int J, typename CT>
+__device__ __forceinline__ void r_x(CT (&a)[kR]) {
 #pragma unroll
   for (int k = 0; k < kR; ++k) {
     if (k & (1 << J)) continue;
-    const double2 x = a[k];
+    const CT x = a[k];
     a[k] = a[k | (1 << J)];
     a[k | (1 << J)] = x;
   }
 }
 
 // memory value CV of the control bit C selects the pairs along T
-template <int C, int T, int CV>
-__device__ __forceinline__ void r_cx(double2 (&a)[kR]) {
+template <int C, int T, int CV, typename CT>
+__device__ __forceinline__ void r_cx(CT (&a)[kR]) {
 #pragma unroll
   for (int k = 0; k < kR; ++k) {
     if (((k >> C) & 1) != CV || (k & (1 << T))) continue;
-    const double2 x = a[k];
+    const CT x = a[k];
     a[k] = a[k | (1 << T)];
     a[k | (1 << T)] = x;
   }
 }
 
-template <int C, int T, int CV>
-__device__ __forceinline__ void r_ctrl(double2 (&a)[kR], const M2& u) {
+template <int C, int T, int CV, typename CT>
+__device__ __forceinline__ void r_ctrl(CT (&a)[kR], const M2x<CT>& u) {
 #pragma unroll
   for (int k = 0; k < kR; ++k) {
     if (((k >> C) & 1) != CV || (k & (1 << T))) continue;
     const int k1 = k | (1 << T);
-    const double2 x0 = a[k], x1 = a[k1];
+    const CT x0 = a[k], x1 = a[k1];
     a[k] = cmac2(u.a, x0, u.b, x1);
     a[k1] = cmac2(u.c, x0, u.d, x1);
   }
 }
 
-template <int C, int T, int SC, int ST>
-__device__ __forceinline__ void r_cphase(double2 (&a)[kR], double2 ph) {
+template <int C, int T, int SC, int ST, typename CT>
+__device__ __forceinline__ void r_cphase(CT (&a)[kR], CT ph) {
 #pragma unroll
   for (int k = 0; k < kR; ++k)
     if (((k >> C) & 1) == SC && ((k >> T) & 1) == ST) a[k] = cmul(ph, a[k]);
 }
 
 // SWAP in the flip frame: exchange 01<->10, or 00<->11 when one operand is flipped
-template <int A, int B, int ANTI>
-__device__ __forceinline__ void r_swap(double2 (&a)[kR]) {
+template <int A, int B, int ANTI, typename CT>
+__device__ __forceinline__ void r_swap(CT (&a)[kR]) {
 #pragma unroll
   for (int k = 0; k < kR; ++k) {
     if (ANTI) {
       if ((k & (1 << A)) || (k & (1 << B))) continue;
       const int k2 = k | (1 << A) | (1 << B);
-      const double2 x = a[k];
+      const CT x = a[k];
       a[k] = a[k2];
       a[k2] = x;
     } else {
       if (!(k & (1 << A)) || (k & (1 << B))) continue;
       const int k2 = (k ^ (1 << A)) | (1 << B);
-      const double2 x = a[k];
+      const CT x = a[k];
       a[k] = a[k2];
       a[k2] = x;
     }
   }
 }
 
-template <int C, int T>
-__device__ __forceinline__ void r_two(double2 (&a)[kR], uint8_t type, const double* m) {
+template <int C, int T, typename CT>
+__device__ __forceinline__ void r_two(CT (&a)[kR], uint8_t type, const double* m) {
   switch (type) {
     case GT_CX: r_cx<C, T, 1>(a); break;
-    case GT_CTRL1: r_ctrl<C, T, 1>(a, load_m2(m, 0)); break;
-    case GT_CPHASE: r_cphase<C, T, 1, 1>(a, make_double2(m[6], m[7])); break;
+    case GT_CTRL1: r_ctrl<C, T, 1>(a, load_m2x<CT>(m, 0)); break;
+    case GT_CPHASE: r_cphase<C, T, 1, 1>(a, cmake<CT>(m[6], m[7])); break;
     default: r_swap<C, T, 0>(a); break;
   }
 }
 
-template <int J>
-__device__ __forceinline__ void r_one(double2 (&a)[kR], uint8_t type, const double* m) {
+template <int J, typename CT>
+__device__ __forceinline__ void r_one(CT (&a)[kR], uint8_t type, const double* m) {
   if (type == GT_X1) {
     r_x<J>(a);
     return;
   }
-  const M2 u = load_m2(m, 0);
+  const M2x<CT> u = load_m2x<CT>(m, 0);
   if (type == GT_DIAG1) r_diag<J>(a, u);
   else r_dense<J>(a, u);
 }
 
-__device__ __forceinline__ void r_apply(double2 (&a)[kR], uint8_t type, int j0, int j1, const double* m) {
+template <typename CT>
+__device__ __forceinline__ void r_apply(CT (&a)[kR], uint8_t type, int j0, int j1, const double* m) {
   if (type <= GT_X1) {
     switch (j0) {
       case 0: r_one<0>(a, type, m); break;
@@ -232,6 +267,7 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t x, uint32_t mask) {
 }
 
 typedef double qsv_d4 __attribute__((ext_vector_type(4)));
+typedef float qsv_f4 __attribute__((ext_vector_type(4)));
 
 // global index bits of tile w: the bits of w scattered over the non-tile qubits
 __device__ __forceinline__ uint64_t tile_base(uint64_t w, uint64_t free_mask) {

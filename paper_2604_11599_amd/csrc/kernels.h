@@ -21,6 +21,7 @@ struct RunBuffers {
   uint32_t forced_len;
   uint64_t seed, shot_base;   // Philox key (seed, shot_base + shot)
   uint32_t shots;
+  uint32_t c64;            // 1: complex64 amplitudes (state holds float2 values, same stride in amplitudes)
   double readout_err, reset_err;  // error rates of measurements (recorded bit) and resets
   // trajectory sharing (null: one state per shot): a site's histogram of
   // slot g reads state buffer buf_of[g]; shot s finalises from slot slot_of[s]
@@ -42,7 +43,8 @@ hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint
                                 uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st);
 hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* record, uint32_t max_record,
                            uint32_t shots, hipStream_t st);
-hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st);
+hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st,
+                             bool c64 = false);
 hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st);
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
@@ -52,7 +54,7 @@ hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s
 hipError_t launch_ctl_gather(ShotCtl* dst, const ShotCtl* src, const uint32_t* idx, uint32_t count, hipStream_t st);
 // state buffer pairs[2k] <- state buffer pairs[2k + 1] (2^n amplitudes each, k < n_pairs)
 hipError_t launch_buf_copy(double2* state, uint64_t stride, uint32_t n, const uint32_t* pairs, uint32_t n_pairs,
-                           hipStream_t st);
+                           hipStream_t st, bool c64 = false);
 hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, double2* out,
                               hipStream_t st);
 

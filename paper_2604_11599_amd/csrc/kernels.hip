@@ -187,20 +187,26 @@ hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* r
   return hipGetLastError();
 }
 
-__global__ void k_init_state(double2* __restrict__ state, uint64_t stride, uint64_t dim, uint32_t shots) {
+template <typename CT>
+__global__ void k_init_state(CT* __restrict__ state, uint64_t stride, uint64_t dim, uint32_t shots) {
   uint64_t total = dim * shots;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t s = i / dim, j = i % dim;
-    state[s * stride + j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
+    state[s * stride + j] = cmake<CT>(j == 0 ? 1.0 : 0.0, 0.0);
   }
 }
 
-hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st) {
+hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st, bool c64) {
   uint64_t total = (1ull << n) * shots;
   uint64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_init_state, dim3((uint32_t)blocks), dim3(256), 0, st, state, stride, 1ull << n, shots);
+  if (c64)
+    hipLaunchKernelGGL(k_init_state<float2>, dim3((uint32_t)blocks), dim3(256), 0, st,
+                       reinterpret_cast<float2*>(state), stride, 1ull << n, shots);
+  else
+    hipLaunchKernelGGL(k_init_state<double2>, dim3((uint32_t)blocks), dim3(256), 0, st, state, stride, 1ull << n,
+                       shots);
   return hipGetLastError();
 }
 
@@ -208,12 +214,13 @@ hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32
 // Tile pass
 // ---------------------------------------------------------------------------
 // Applies one gate to the LDS tile (tile-local logical indices).
-__device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t t, const DGate& g,
+template <typename CT>
+__device__ __forceinline__ void tile_apply(CT* __restrict__ tile, uint32_t t, const DGate& g,
                                            const double* __restrict__ m) {
   const uint32_t tid = threadIdx.x;
   switch (g.type) {
     case GT_DENSE1: case GT_DIAG1: {
-      const M2 u = load_m2(m, 0);
+      const M2x<CT> u = load_m2x<CT>(m, 0);
       const uint32_t np = 1u << (t - 1), bit = 1u << g.b0;
       if (g.type == GT_DIAG1) {
         for (uint32_t p = tid; p < np; p += kTileThreads) {
@@ -224,7 +231,7 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
       } else {
         for (uint32_t p = tid; p < np; p += kTileThreads) {
           uint32_t i0 = ins0(p, g.b0), i1 = i0 | bit;
-          double2 x0 = tile[i0], x1 = tile[i1];
+          CT x0 = tile[i0], x1 = tile[i1];
           tile[i0] = cmac2(u.a, x0, u.b, x1);
           tile[i1] = cmac2(u.c, x0, u.d, x1);
         }
@@ -235,7 +242,7 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
       const uint32_t np = 1u << (t - 1), bit = 1u << g.b0;
       for (uint32_t p = tid; p < np; p += kTileThreads) {
         uint32_t i0 = ins0(p, g.b0), i1 = i0 | bit;
-        double2 x0 = tile[i0];
+        CT x0 = tile[i0];
         tile[i0] = tile[i1];
         tile[i1] = x0;
       }
@@ -248,20 +255,20 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
       if (g.type == GT_CX) {
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
           uint32_t i = ins0(ins0(p, lo), hi) | B0;
-          double2 x = tile[i];
+          CT x = tile[i];
           tile[i] = tile[i | B1];
           tile[i | B1] = x;
         }
       } else if (g.type == GT_CTRL1) {
-        const M2 u = load_m2(m, 0);
+        const M2x<CT> u = load_m2x<CT>(m, 0);
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
           uint32_t i = ins0(ins0(p, lo), hi) | B0;
-          double2 x0 = tile[i], x1 = tile[i | B1];
+          CT x0 = tile[i], x1 = tile[i | B1];
           tile[i] = cmac2(u.a, x0, u.b, x1);
           tile[i | B1] = cmac2(u.c, x0, u.d, x1);
         }
       } else if (g.type == GT_CPHASE) {
-        const double2 ph = make_double2(m[6], m[7]);
+        const CT ph = cmake<CT>(m[6], m[7]);
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
           uint32_t i = ins0(ins0(p, lo), hi) | B0 | B1;
           tile[i] = cmul(ph, tile[i]);
@@ -269,7 +276,7 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
       } else {  // GT_SWAP
         for (uint32_t p = tid; p < nq; p += kTileThreads) {
           uint32_t i = ins0(ins0(p, lo), hi);
-          double2 x = tile[i | B0];
+          CT x = tile[i | B0];
           tile[i | B0] = tile[i | B1];
           tile[i | B1] = x;
         }
@@ -279,10 +286,12 @@ __device__ __forceinline__ void tile_apply(double2* __restrict__ tile, uint32_t 
   }
 }
 
+template <typename CT>
 __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
-    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
+    CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
     const DGate* __restrict__ gates, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a) {
-  extern __shared__ double2 tile[];
+  extern __shared__ double2 qsv_lds[];
+  CT* const tile = reinterpret_cast<CT*>(qsv_lds);
   const uint32_t shot = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
   ShotCtl* c = ctl + shot;
   if (c->status != 0) return;
@@ -302,15 +311,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
     for (uint32_t q = 0; q < a.n; ++q)
       if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> k++) & 1u) << q;
   }
-  double2* st = state + (uint64_t)shot * stride;
+  CT* st = state + (uint64_t)shot * stride;
   const uint32_t T = 1u << a.t;
   for (uint32_t l = tid; l < T; l += kTileThreads) {
     uint64_t gi = base | local_to_global(l, a);
-    double2 v;
+    CT v;
     if (a.init) {
-      v = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
+      v = cmake<CT>(gi == 0 ? 1.0 : 0.0, 0.0);
     } else if ((gi & M) != V) {
-      v = make_double2(0.0, 0.0);
+      v = cmake<CT>(0.0, 0.0);
     } else {
       v = st[gi ^ F];
       if (pending) v = cscale(v, s);
@@ -342,8 +351,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(
   }
 }
 
-template <bool kDenseOnly>
-__global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
+template <bool kDenseOnly, typename CT>
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl,
                               const DGate* __restrict__ gates, const Phase* __restrict__ phases,
                               const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots);
 
@@ -378,18 +387,20 @@ hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_
   return hipSuccess;
 }
 
+template <typename CT>
 __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
-    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
+    CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
     const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats);
 
-hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
-                            uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
+template <typename CT>
+static hipError_t tile_pass_t(const RunBuffers& rb, CT* state, const DGate* gates, const Phase* phases,
+                              const double* mats, uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
   dim3 grid(a.tiles, rb.shots);
-  size_t lds = (size_t)sizeof(double2) << a.t;
+  size_t lds = (size_t)sizeof(CT) << a.t;
   if (a.phase_count) {
     const uint64_t total = (uint64_t)a.tiles * rb.shots;
     const size_t mat_lds = (size_t)a.phase_count * 256u * sizeof(double2);
-    const size_t max_lds = (sizeof(double2) << kTileMaxBits) + kLdsDensePhases * 256u * sizeof(double2);
+    const size_t max_lds = (sizeof(CT) << kTileMaxBits) + kLdsDensePhases * 256u * sizeof(double2);
     const uint32_t nthr = 1u << (a.t - kRegBits);
     uint32_t g = 0;
     hipError_t e = hipSuccess;
@@ -401,31 +412,38 @@ hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phas
     if (a.all_dense && a.t == (uint32_t)kTileMaxBits) {
       const uint32_t staged = (a.phase_count <= kLdsDensePhases && mat_stride == 0) ? 1u : 0u;
       const size_t l8 = lds + (staged ? mat_lds : 0);
-      e = resident_grid((const void*)k_tile_pass_d8, 2 * nthr, l8, max_lds, &g);
+      e = resident_grid((const void*)k_tile_pass_d8<CT>, 2 * nthr, l8, max_lds, &g);
       if (e != hipSuccess) return e;
       if ((uint64_t)g > total) g = (uint32_t)total;
       if (!g) return hipSuccess;
-      hipLaunchKernelGGL(k_tile_pass_d8, dim3(g), dim3(2 * nthr), l8, st, rb.state, rb.stride, rb.ctl, phases, mats,
+      hipLaunchKernelGGL(k_tile_pass_d8<CT>, dim3(g), dim3(2 * nthr), l8, st, state, rb.stride, rb.ctl, phases, mats,
                          mat_stride, a, rb.shots, staged);
       return hipGetLastError();
     }
     if (dense_only) lds += mat_lds;
-    e = dense_only ? resident_grid((const void*)k_tile_pass_r<true>, nthr, lds, max_lds, &g)
-                   : resident_grid((const void*)k_tile_pass_r<false>, nthr, lds, max_lds, &g);
+    e = dense_only ? resident_grid((const void*)k_tile_pass_r<true, CT>, nthr, lds, max_lds, &g)
+                   : resident_grid((const void*)k_tile_pass_r<false, CT>, nthr, lds, max_lds, &g);
     if (e != hipSuccess) return e;
     if ((uint64_t)g > total) g = (uint32_t)total;
     if (!g) return hipSuccess;
     if (dense_only)
-      hipLaunchKernelGGL(k_tile_pass_r<true>, dim3(g), dim3(nthr), lds, st, rb.state, rb.stride, rb.ctl, gates, phases,
-                         mats, mat_stride, a, rb.shots);
+      k_tile_pass_r<true, CT><<<dim3(g), dim3(nthr), lds, st>>>(state, rb.stride, rb.ctl, gates, phases, mats,
+                                                                 mat_stride, a, rb.shots);
     else
-      hipLaunchKernelGGL(k_tile_pass_r<false>, dim3(g), dim3(nthr), lds, st, rb.state, rb.stride, rb.ctl, gates,
-                         phases, mats, mat_stride, a, rb.shots);
+      k_tile_pass_r<false, CT><<<dim3(g), dim3(nthr), lds, st>>>(state, rb.stride, rb.ctl, gates, phases, mats,
+                                                                  mat_stride, a, rb.shots);
   } else {
-    hipLaunchKernelGGL(k_tile_pass, grid, dim3(kTileThreads), lds, st, rb.state, rb.stride, rb.ctl, gates,
+    hipLaunchKernelGGL(k_tile_pass<CT>, grid, dim3(kTileThreads), lds, st, state, rb.stride, rb.ctl, gates,
                        mats, mat_stride, a);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
+                            uint64_t mat_stride, const PassArgs& a, hipStream_t st) {
+  if (rb.c64)
+    return tile_pass_t(rb, reinterpret_cast<float2*>(rb.state), gates, phases, mats, mat_stride, a, st);
+  return tile_pass_t(rb, rb.state, gates, phases, mats, mat_stride, a, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -510,30 +528,52 @@ __device__ __forceinline__ void load_mfrag(double2 (&mf)[4], bool staged, const 
   }
 }
 
-template <int kBlocks>
-__device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uint32_t T, uint32_t tid,
+// One 16x16x4 product step on the matrix cores in the amplitude precision.
+// kRowsInterleaved: result element v of lane l is row 4 v + l / 16 (the
+// double-precision instruction) rather than row 4 (l / 16) + v (single).
+template <typename CT> struct MfmaT;
+template <> struct MfmaT<double2> {
+  typedef double R;
+  typedef qsv_d4 V4;
+  static constexpr bool kRowsInterleaved = true;
+  __device__ static V4 step(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct MfmaT<float2> {
+  typedef float R;
+  typedef qsv_f4 V4;
+  static constexpr bool kRowsInterleaved = false;
+  __device__ static V4 step(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+template <int kBlocks, typename CT>
+__device__ __forceinline__ void dense_phase_mfma(CT* __restrict__ tile, uint32_t T, uint32_t tid,
                                                  const Phase& ph, const double2 (&mf)[4]) {
+  typedef MfmaT<CT> Mf;
+  typedef typename Mf::R R;
   // this wave's groups: gbase + 16 cb + j, cb < kBlocks
   const uint32_t lane = tid & 63u, q = lane >> 4, j = lane & 15u;
   const uint32_t wbase = __builtin_amdgcn_readfirstlane(tid >> 6) * (16u * kBlocks);
   const uint32_t o0 = 1u << ph.r[0], o1 = 1u << ph.r[1], o2 = 1u << ph.r[2], o3 = 1u << ph.r[3];
   const UBits u = ubits((T - 1u) & ~(o0 | o1 | o2 | o3));
-  double fa[4], fb[4], fs[4];  // fragments of A, B and A + B
+  R fa[4], fb[4], fs[4];  // fragments of A, B and A + B
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
-    fa[kb] = mf[kb].x;
-    fb[kb] = mf[kb].y;
-    fs[kb] = mf[kb].x + mf[kb].y;
+    fa[kb] = (R)mf[kb].x;
+    fb[kb] = (R)mf[kb].y;
+    fs[kb] = (R)(mf[kb].x + mf[kb].y);
   }
   // slot of component q + 4 k of group gbase + 16 cb + j: a per-lane part (group
   // bits 0..3, component bits of q) XOR a wave-uniform part (higher group bits,
   // component bits of k)
   const uint32_t rl = swz(udep<4>(u, j) | ((q & 1u) ? o0 : 0u) | ((q & 2u) ? o1 : 0u));
+  // where results go when the result rows are grouped: element v of lane l is
+  // component 4 q + v (component bits 0..1 from v, bits 2..3 from q)
+  const uint32_t rw = swz(udep<4>(u, j) | ((q & 1u) ? o2 : 0u) | ((q & 2u) ? o3 : 0u));
   // software-pipelined over the blocks: the reads of block b + 1 are issued
   // before the writes of block b, so the LDS round trip of the next block
   // overlaps the tail of the current block's products
   uint32_t slot[2][4];
-  double2 x[2][4];
+  CT x[2][4];
   {
     const uint32_t ug = udep_hi(u, wbase);
 #pragma unroll
@@ -545,12 +585,23 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
 #pragma unroll
   for (uint32_t cb = 0; cb < (uint32_t)kBlocks; ++cb) {
     const uint32_t c = cb & 1u;
-    qsv_d4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
+    typename Mf::V4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
-      p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[kb], x[c][kb].x, p1, 0, 0, 0);
-      p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[kb], x[c][kb].y, p2, 0, 0, 0);
-      p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(fs[kb], x[c][kb].x + x[c][kb].y, p3, 0, 0, 0);
+      p1 = Mf::step(fa[kb], x[c][kb].x, p1);
+      p2 = Mf::step(fb[kb], x[c][kb].y, p2);
+      p3 = Mf::step(fs[kb], x[c][kb].x + x[c][kb].y, p3);
+    }
+    // the block's results go to the slots it read (every read of the block
+    // is complete: its values entered the products above)
+    uint32_t wslot[4];
+    if (Mf::kRowsInterleaved) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) wslot[v] = slot[c][v];
+    } else {
+      const uint32_t ug = udep_hi(u, wbase + 16u * cb);
+#pragma unroll
+      for (uint32_t v = 0; v < 4; ++v) wslot[v] = rw ^ swz(ug | ((v & 1u) ? o0 : 0u) | ((v & 2u) ? o1 : 0u));
     }
     if (cb + 1 < (uint32_t)kBlocks) {
       const uint32_t ug = udep_hi(u, wbase + 16u * (cb + 1));
@@ -561,7 +612,12 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) tile[slot[c][v]] = make_double2(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+    for (int v = 0; v < 4; ++v) {
+      CT o;
+      o.x = p1[v] - p2[v];
+      o.y = p3[v] - p1[v] - p2[v];
+      tile[wslot[v]] = o;
+    }
   }
 }
 
@@ -574,12 +630,12 @@ __device__ __forceinline__ void dense_phase_mfma(double2* __restrict__ tile, uin
 // phases are all dense (unguarded, on tiles of at least 64 threads).
 // lds_mats: the pass's dense matrices staged in LDS (phase p at lds_mats + 256 p),
 // or null to read them from the matrix slots.
-template <bool kDense, bool kGates>
-__device__ __forceinline__ void run_phases(double2* __restrict__ tile, uint32_t T, uint32_t tid, uint32_t nthr, uint64_t flags,
+template <bool kDense, bool kGates, typename CT>
+__device__ __forceinline__ void run_phases(CT* __restrict__ tile, uint32_t T, uint32_t tid, uint32_t nthr, uint64_t flags,
                            const Phase* __restrict__ phases, uint32_t pb, uint32_t pc,
                            const DGate* __restrict__ gates, const double* __restrict__ mb,
                            const double2* __restrict__ lds_mats = nullptr) {
-  double2 r[kR];
+  CT r[kR];
   for (uint32_t p = 0; p < pc; ++p) {
     const Phase ph = load_phase(phases + pb + p);
     if (kGates) {
@@ -727,14 +783,15 @@ __device__ __forceinline__ uint64_t next_pass_item(uint64_t it, uint64_t total, 
 // load layout: logical amplitude i is stored at memory index i ^ F. Every
 // amplitude is read (one straight run of loads); those outside a pending
 // collapse are zeroed when staged.
-__device__ __forceinline__ void fetch16(double2 (&r)[kR], const double2* __restrict__ st, uint64_t gthr, uint64_t h0,
+template <typename CT>
+__device__ __forceinline__ void fetch16(CT (&r)[kR], const CT* __restrict__ st, uint64_t gthr, uint64_t h0,
                                         uint64_t h1, uint64_t h2, uint64_t h3, bool init, uint64_t F) {
   if (init) {
 #pragma unroll
     for (int k = 0; k < kR; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
                           ((k & 8) ? h3 : 0ull);
-      r[k] = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
+      r[k] = cmake<CT>(gi == 0 ? 1.0 : 0.0, 0.0);
     }
   } else {
 #pragma unroll
@@ -748,7 +805,8 @@ __device__ __forceinline__ void fetch16(double2 (&r)[kR], const double2* __restr
 
 // the 16 amplitudes of a thread into LDS (load layout l = tid + k nthr), with
 // the pending collapse's scale applied
-__device__ __forceinline__ void stage16(double2* __restrict__ tile, const double2 (&r)[kR], uint32_t tid,
+template <typename CT>
+__device__ __forceinline__ void stage16(CT* __restrict__ tile, const CT (&r)[kR], uint32_t tid,
                                         uint32_t nthr, uint64_t gthr, uint64_t h0, uint64_t h1, uint64_t h2,
                                         uint64_t h3, uint64_t M, uint64_t V, double s) {
   if (M == 0 && s == 1.0) {
@@ -759,7 +817,7 @@ __device__ __forceinline__ void stage16(double2* __restrict__ tile, const double
     for (int k = 0; k < kR; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
                           ((k & 8) ? h3 : 0ull);
-      tile[swz(tid + (uint32_t)k * nthr)] = ((gi & M) == V) ? cscale(r[k], s) : make_double2(0.0, 0.0);
+      tile[swz(tid + (uint32_t)k * nthr)] = ((gi & M) == V) ? cscale(r[k], s) : cmake<CT>(0.0, 0.0);
     }
   }
 }
@@ -771,12 +829,13 @@ __device__ __forceinline__ void stage16(double2* __restrict__ tile, const double
 // next tile are already in flight (held in registers), so HBM reads overlap
 // the gate arithmetic of the same workgroup. kDenseOnly: the variant for
 // passes whose phases are all dense (matrix cores only, fewer live registers).
-template <bool kDenseOnly>
+template <bool kDenseOnly, typename CT>
 __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
-    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const DGate* __restrict__ gates,
+    CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const DGate* __restrict__ gates,
     const Phase* __restrict__ phases, const double* __restrict__ mats, uint64_t mat_stride, PassArgs a,
     uint32_t shots) {
-  extern __shared__ double2 tile[];
+  extern __shared__ double2 qsv_lds[];
+  CT* const tile = reinterpret_cast<CT*>(qsv_lds);
   const uint32_t tid = threadIdx.x;
   const uint32_t nthr = 1u << (a.t - kRegBits), T = 1u << a.t;
   const uint64_t total = (uint64_t)a.tiles * shots, G = gridDim.x;
@@ -789,7 +848,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
   // the answer for the last shot looked at is kept
   uint32_t last_shot = 0xFFFFFFFFu;
   bool last_active = false;
-  double2 nx[kR];
+  CT nx[kR];
   // the dense-only variant prefetches the next tile and keeps the pass's
   // dense matrices in LDS after the tile (no vector loads but the prefetch
   // while it computes); the gate-list variant (more live registers) loads each
@@ -797,7 +856,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
   constexpr bool kPrefetch = kDenseOnly;
   double2* lds_mats = nullptr;
   if (kDenseOnly) {
-    lds_mats = tile + T;
+    lds_mats = reinterpret_cast<double2*>(tile + T);
     const double* mb0 = mats;  // dense matrices are per call (mat_stride 0 on this path)
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const double2* src = reinterpret_cast<const double2*>(mb0 + (uint64_t)cst(phases + a.phase_begin + p)->dense *
@@ -834,9 +893,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
                                   mats + (uint64_t)shot * mat_stride, lds_mats);
     {
       // back to HBM in the load layout (address bits computed once, above)
-      double2* st = state + (uint64_t)shot * stride;
+      CT* st = state + (uint64_t)shot * stride;
       const uint64_t gthr = base | tb;
-      double2 r[kR];
+      CT r[kR];
 #pragma unroll
       for (int k = 0; k < kR; ++k) r[k] = tile[swz(tid + (uint32_t)k * nthr)];
 #pragma unroll
@@ -881,10 +940,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
 // lds_mats the pass's matrices (shared by every shot: mat_stride 0, at most
 // kLdsDensePhases of them) are staged in LDS once; otherwise each phase reads
 // its matrix from the shot's matrix slots.
+template <typename CT>
 __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
-    double2* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
+    CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
     const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats) {
-  extern __shared__ double2 tile[];
+  extern __shared__ double2 qsv_lds[];
+  CT* const tile = reinterpret_cast<CT*>(qsv_lds);
   constexpr uint32_t kA = 8, kThreads = 2 * kTileThreads;
   const uint32_t tid = threadIdx.x, T = 1u << a.t, lane = tid & 63u;
   const uint64_t total = (uint64_t)a.tiles * shots, G = gridDim.x;
@@ -892,7 +953,7 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
   uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..8]
   for (uint32_t b = 0; b < 9; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
   const uint64_t h0 = 1ull << a.tq[9], h1 = 1ull << a.tq[10], h2 = 1ull << a.tq[11];
-  double2* const lmats = tile + T;
+  double2* const lmats = reinterpret_cast<double2*>(tile + T);
   if (lds_mats)
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const double2* src =
@@ -909,18 +970,18 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
     const double sc = cst(c)->pend_scale;
     const bool pending = M != 0 || sc != 1.0;
     const uint64_t gthr = tile_base(it % a.tiles, free_mask) | tb;
-    double2* st = state + (uint64_t)shot * stride;
-    double2 r[kA];
+    CT* st = state + (uint64_t)shot * stride;
+    CT r[kA];
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
-      r[k] = a.init ? make_double2(gi == 0 ? 1.0 : 0.0, 0.0) : st[gi ^ F];
+      r[k] = a.init ? cmake<CT>(gi == 0 ? 1.0 : 0.0, 0.0) : st[gi ^ F];
     }
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
       tile[swz(tid + (uint32_t)k * kThreads)] =
-          !pending ? r[k] : (((gi & M) == V) ? cscale(r[k], sc) : make_double2(0.0, 0.0));
+          !pending ? r[k] : (((gi & M) == V) ? cscale(r[k], sc) : cmake<CT>(0.0, 0.0));
     }
     __syncthreads();
     const double* ms = mats + (uint64_t)shot * mat_stride;
@@ -965,8 +1026,9 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
 // (unrestricted) index space; every thread keeps its own 16 bins in LDS and
 // the bins are summed in a fixed order, so the result does not depend on how
 // many shots share the launch.
+template <typename CT>
 __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
-    const double2* __restrict__ state, uint64_t stride, const ShotCtl* __restrict__ ctl, SiteArgs a,
+    const CT* __restrict__ state, uint64_t stride, const ShotCtl* __restrict__ ctl, SiteArgs a,
     double* __restrict__ partials, uint32_t pblocks, const uint32_t* __restrict__ buf_of) {
   __shared__ double bins[kSiteBins][kRedThreads];
   __shared__ double red[kRedThreads / kSiteBins][kSiteBins];
@@ -981,7 +1043,7 @@ __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
     const uint64_t nfree = 1ull << (a.n - r);
     const uint64_t per = (nfree + a.blocks - 1) / a.blocks;
     const uint64_t j0 = per * blk, j1 = (j0 + per < nfree) ? j0 + per : nfree;
-    const double2* st = state + (uint64_t)(buf_of ? buf_of[shot] : shot) * stride;
+    const CT* st = state + (uint64_t)(buf_of ? buf_of[shot] : shot) * stride;
     uint32_t qbit[kSiteQubits];
     uint32_t fq = 0;
     for (uint32_t k = 0; k < a.nq; ++k) {
@@ -999,8 +1061,9 @@ __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
         }
         gi |= Vm;
       }
-      double2 v = st[gi];
-      double p = (v.x * v.x + v.y * v.y) * s2;
+      const CT v = st[gi];
+      const double vx = v.x, vy = v.y;
+      double p = (vx * vx + vy * vy) * s2;
       uint32_t bin = 0;
       for (uint32_t k = 0; k < a.nq; ++k) bin |= (uint32_t)((gi >> qbit[k]) & 1ull) << k;
       bin ^= fq;
@@ -1163,9 +1226,15 @@ hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent*
   if (a.nq) {
     // with trajectory sharing the histograms are taken per slot (slot control
     // blocks in site_ctl), the outcomes per shot
-    hipLaunchKernelGGL(k_site_reduce, dim3(a.blocks, rb.slot_of ? rb.site_slots : rb.shots), dim3(kRedThreads), 0,
-                       st, rb.state, rb.stride, rb.slot_of ? rb.site_ctl : rb.ctl, a, rb.partials, rb.pblocks,
-                       rb.buf_of);
+    const dim3 grid(a.blocks, rb.slot_of ? rb.site_slots : rb.shots);
+    const ShotCtl* hc = rb.slot_of ? rb.site_ctl : rb.ctl;
+    if (rb.c64)
+      hipLaunchKernelGGL(k_site_reduce<float2>, grid, dim3(kRedThreads), 0, st,
+                         reinterpret_cast<const float2*>(rb.state), rb.stride, hc, a, rb.partials, rb.pblocks,
+                         rb.buf_of);
+    else
+      hipLaunchKernelGGL(k_site_reduce<double2>, grid, dim3(kRedThreads), 0, st, rb.state, rb.stride, hc, a,
+                         rb.partials, rb.pblocks, rb.buf_of);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1189,7 +1258,8 @@ hipError_t launch_ctl_gather(ShotCtl* dst, const ShotCtl* src, const uint32_t* i
 
 // Copy-on-write of trajectory slots: buffer pairs[2k] takes the amplitudes of
 // buffer pairs[2k + 1]. Sources are never destinations in one launch.
-__global__ void k_buf_copy(double2* __restrict__ state, uint64_t stride, uint64_t dim,
+template <typename CT>
+__global__ void k_buf_copy(CT* __restrict__ state, uint64_t stride, uint64_t dim,
                            const uint32_t* __restrict__ pairs, uint32_t n_pairs) {
   const uint64_t total = dim * n_pairs;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -1200,12 +1270,17 @@ __global__ void k_buf_copy(double2* __restrict__ state, uint64_t stride, uint64_
 }
 
 hipError_t launch_buf_copy(double2* state, uint64_t stride, uint32_t n, const uint32_t* pairs, uint32_t n_pairs,
-                           hipStream_t st) {
+                           hipStream_t st, bool c64) {
   if (!n_pairs) return hipSuccess;
   const uint64_t total = (1ull << n) * n_pairs;
   uint64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_buf_copy, dim3((uint32_t)blocks), dim3(256), 0, st, state, stride, 1ull << n, pairs, n_pairs);
+  if (c64)
+    hipLaunchKernelGGL(k_buf_copy<float2>, dim3((uint32_t)blocks), dim3(256), 0, st, reinterpret_cast<float2*>(state),
+                       stride, 1ull << n, pairs, n_pairs);
+  else
+    hipLaunchKernelGGL(k_buf_copy<double2>, dim3((uint32_t)blocks), dim3(256), 0, st, state, stride, 1ull << n, pairs,
+                       n_pairs);
   return hipGetLastError();
 }
 
@@ -1225,15 +1300,20 @@ hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s
   return hipGetLastError();
 }
 
-// The logical state of one shot: psi[i] = cond(i) ? mem[i ^ frame] * scale : 0.
-__global__ void k_materialize(const double2* __restrict__ state, uint64_t stride, const ShotCtl* ctl,
+// The logical state of one shot: psi[i] = cond(i) ? mem[i ^ frame] * scale : 0,
+// as complex128 whatever the amplitude type.
+template <typename CT>
+__global__ void k_materialize(const CT* __restrict__ state, uint64_t stride, const ShotCtl* ctl,
                               uint32_t shot, uint64_t dim, double2* __restrict__ out) {
   const ShotCtl c = ctl[shot];
-  const double2* st = state + (uint64_t)shot * stride;
+  const CT* st = state + (uint64_t)shot * stride;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
        i += (uint64_t)gridDim.x * blockDim.x) {
     double2 v = make_double2(0.0, 0.0);
-    if ((i & c.pend_mask) == c.pend_val) v = cscale(st[i ^ c.frame], c.pend_scale);
+    if ((i & c.pend_mask) == c.pend_val) {
+      const CT x = st[i ^ c.frame];
+      v = cscale(make_double2(x.x, x.y), c.pend_scale);
+    }
     out[i] = v;
   }
 }
@@ -1242,8 +1322,12 @@ hipError_t launch_materialize(const RunBuffers& rb, uint32_t n, uint32_t shot, d
   uint64_t dim = 1ull << n;
   uint64_t blocks = (dim + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_materialize, dim3((uint32_t)blocks), dim3(256), 0, st, rb.state, rb.stride, rb.ctl,
-                     shot, dim, out);
+  if (rb.c64)
+    hipLaunchKernelGGL(k_materialize<float2>, dim3((uint32_t)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const float2*>(rb.state), rb.stride, rb.ctl, shot, dim, out);
+  else
+    hipLaunchKernelGGL(k_materialize<double2>, dim3((uint32_t)blocks), dim3(256), 0, st, rb.state, rb.stride, rb.ctl,
+                       shot, dim, out);
   return hipGetLastError();
 }
 

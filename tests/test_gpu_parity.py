@@ -37,8 +37,8 @@ def _bits_int(bits):
     return sum(int(b) << i for i, b in enumerate(bits))
 
 
-def _near_tie(events):
-    return any(abs(e[3] - e[4]) < TIE for e in events)
+def _near_tie(events, tie=TIE):
+    return any(abs(e[3] - e[4]) < tie for e in events)
 
 
 def _check_shots(ctx, src, n_shots, seed=11, theta=None, forced_from_oracle=False, state=True, noise=(0.0, 0.0),
@@ -288,6 +288,88 @@ def test_readout_and_reset_errors_match_oracle(ctx):
     frac = float(np.mean((res.creg[:, 0] >> 1) & 1))
     p = 2 * e * (1 - e)
     assert abs(frac - p) < 4 * math.sqrt(p * (1 - p) / 20000)
+
+
+# ---------------------------------------------------------------------------
+# complex64 state (single-precision amplitudes and matrix-core products)
+#
+# Unit roundoff 2^-24 = 6e-8. A dense phase is a 16-term complex product, so it
+# adds at most about 20 roundoffs to the state's 2-norm error (1.2e-6); the
+# programs below have at most ~15 phases and gate lists per shot, so the state
+# error stays below 2e-5 in the 2-norm, the bound the amplitude check uses.
+# Probabilities are sums of squares of those amplitudes (relative error below
+# 4e-5), so outcomes are compared shot by shot except where the oracle's draw
+# lies within 1e-4 of its threshold (the decision is not fixed there at
+# single precision); forced records are compared bit for bit.
+# ---------------------------------------------------------------------------
+C64_AMP = 2e-5
+C64_PROB = 4e-5
+C64_TIE = 1e-4
+
+
+def _check_c64(ctx, src, n_shots, seed=11, forced_from_oracle=False, share=False, state=True):
+    say("c64 case", src.splitlines()[2:4], "shots", n_shots, "seed", seed, "forced", forced_from_oracle, "share", share)
+    prog = ctx.load(src)
+    oracle = [sim.run_shot(src, seed=seed, shot=s) for s in range(n_shots)]
+    forced = None
+    if forced_from_oracle:
+        width = max(1, max(len(o.record) for o in oracle))
+        forced = np.zeros((n_shots, width), dtype=np.uint8)
+        for s, o in enumerate(oracle):
+            forced[s, :len(o.record)] = o.record
+    res = prog.run_shots(n_shots, seed=seed, forced=forced, state_out=state, share=share, complex64=True)
+    bits = res.bits()
+    skipped = 0
+    for s, o in enumerate(oracle):
+        if not forced_from_oracle and _near_tie(o.events, C64_TIE):
+            skipped += 1
+            continue
+        assert res.shot_status[s] == 0
+        assert list(bits[s]) == o.cbits, f"shot {s}"
+        assert list(res.record[s, :len(o.record)]) == o.record
+        assert res.n_events[s] == o.words_drawn
+        assert abs(res.record_prob[s] - o.record_prob) <= C64_PROB * o.record_prob
+    if state and (forced_from_oracle or not _near_tie(oracle[0].events, C64_TIE)):
+        err = float(np.linalg.norm(res.state - oracle[0].psi))
+        say("  c64 state error (2-norm)", err)
+        assert err < C64_AMP
+    assert skipped <= n_shots // 5
+    return res
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 12, 13, 16])
+def test_complex64_random_dynamic_programs(ctx, n):
+    for seed in range(2):
+        src = W.random_dynamic_program(500 * n + seed, n, n_ops=60, final_measure=(seed == 1))
+        _check_c64(ctx, src, 8, seed=seed)
+        _check_c64(ctx, src, 8, seed=seed + 20, forced_from_oracle=True)
+        _check_c64(ctx, src, 8, seed=seed, share=True, state=False)
+
+
+def test_complex64_dense_passes_and_conditional_reset(ctx):
+    """All-dense 12-bit passes (the eight-wave matrix-core pass) on a layered
+    circuit with a mid-circuit measurement, and the conditional reset."""
+    src = W.c2_program(n=14, layers=6, final_measure=False)
+    _check_c64(ctx, src, 8, seed=4)
+    _check_c64(ctx, src, 8, seed=4, forced_from_oracle=True)
+    _check_c64(ctx, src, 16, seed=4, share=True, state=False)
+    b = ctx.load(W.conditional_reset_program("plus")).run_shots(10000, seed=8, complex64=True).bits()
+    assert np.all(b[:, 1] == 0) and 4700 < b[:, 0].sum() < 5300
+
+
+def test_complex64_matches_complex128_at_20_qubits(ctx):
+    """The same shots in both precisions: records equal, trajectory
+    probabilities and final states within the single-precision bound."""
+    src = W.c2_program(n=20, layers=12, final_measure=False)
+    prog = ctx.load(src)
+    r64 = prog.run_shots(4, seed=6, state_out=True, complex64=True)
+    r128 = prog.run_shots(4, seed=6, state_out=True)
+    assert np.array_equal(r64.record, r128.record) and np.array_equal(r64.creg, r128.creg)
+    assert np.all(np.abs(r64.record_prob - r128.record_prob) <= C64_PROB * r128.record_prob)
+    err = float(np.linalg.norm(r64.state - r128.state))
+    say("  c64 vs c128 state error (2-norm), 20 qubits", err)
+    assert err < C64_AMP
+    assert abs(np.linalg.norm(r64.state) - 1.0) < C64_AMP
 
 
 # ---------------------------------------------------------------------------
