@@ -387,8 +387,15 @@ hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_
   return hipSuccess;
 }
 
+// Waves per SIMD the eight-wave dense pass is compiled for: two workgroups per
+// CU with complex128 tiles (64 KiB of LDS each), three with complex64 tiles
+// (32 KiB), so that the HBM, LDS and matrix-core work of different workgroups
+// overlap.
+template <typename CT> struct D8Waves;
+template <> struct D8Waves<double2> { static constexpr int kMin = 4; };
+template <> struct D8Waves<float2> { static constexpr int kMin = 6; };
 template <typename CT>
-__global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
+__global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pass_d8(
     CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
     const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats);
 
@@ -399,8 +406,8 @@ static hipError_t tile_pass_t(const RunBuffers& rb, CT* state, const DGate* gate
   size_t lds = (size_t)sizeof(CT) << a.t;
   if (a.phase_count) {
     const uint64_t total = (uint64_t)a.tiles * rb.shots;
-    const size_t mat_lds = (size_t)a.phase_count * 256u * sizeof(double2);
-    const size_t max_lds = (sizeof(CT) << kTileMaxBits) + kLdsDensePhases * 256u * sizeof(double2);
+    const size_t mat_lds = (size_t)a.phase_count * 256u * sizeof(CT);
+    const size_t max_lds = (sizeof(CT) << kTileMaxBits) + kLdsDensePhases * 256u * sizeof(CT);
     const uint32_t nthr = 1u << (a.t - kRegBits);
     uint32_t g = 0;
     hipError_t e = hipSuccess;
@@ -511,20 +518,26 @@ __device__ __forceinline__ uint32_t udep_hi(const UBits& u, uint32_t g) {
 // the same components. The wave reads a block before it writes it, and the
 // blocks of different waves are disjoint.
 // lane l's matrix-core operand of a phase matrix: Mc[kb * 64 + l], kb = 0..3;
-// from LDS when the pass's matrices are staged there, else from HBM (two
-// loops, so the compiler keeps the LDS reads as LDS reads)
-__device__ __forceinline__ void load_mfrag(double2 (&mf)[4], bool staged, const double2* __restrict__ lds_mats,
+// from LDS when the pass's matrices are staged there (in the amplitude type),
+// else from HBM, rounded to it (two loops, so the compiler keeps the LDS reads
+// as LDS reads)
+template <typename CT>
+__device__ __forceinline__ void load_mfrag(CT (&mf)[4], bool staged, const CT* __restrict__ lds_mats,
                                            const double2* __restrict__ gmat, uint32_t lane) {
-  typedef __attribute__((address_space(3))) const double lds_d;
+  typedef typename CxT<CT>::R R;
+  typedef __attribute__((address_space(3))) const R lds_r;
   typedef __attribute__((address_space(1))) const double glb_d;
   if (staged) {
-    const lds_d* l = (const lds_d*)lds_mats;
+    const lds_r* l = (const lds_r*)lds_mats;
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) mf[kb] = make_double2(l[2 * (kb * 64 + (int)lane)], l[2 * (kb * 64 + (int)lane) + 1]);
+    for (int kb = 0; kb < 4; ++kb) {
+      mf[kb].x = l[2 * (kb * 64 + (int)lane)];
+      mf[kb].y = l[2 * (kb * 64 + (int)lane) + 1];
+    }
   } else {
     const glb_d* g = (const glb_d*)gmat;
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) mf[kb] = make_double2(g[2 * (kb * 64 + (int)lane)], g[2 * (kb * 64 + (int)lane) + 1]);
+    for (int kb = 0; kb < 4; ++kb) mf[kb] = cmake<CT>(g[2 * (kb * 64 + (int)lane)], g[2 * (kb * 64 + (int)lane) + 1]);
   }
 }
 
@@ -547,7 +560,7 @@ template <> struct MfmaT<float2> {
 
 template <int kBlocks, typename CT>
 __device__ __forceinline__ void dense_phase_mfma(CT* __restrict__ tile, uint32_t T, uint32_t tid,
-                                                 const Phase& ph, const double2 (&mf)[4]) {
+                                                 const Phase& ph, const CT (&mf)[4]) {
   typedef MfmaT<CT> Mf;
   typedef typename Mf::R R;
   // this wave's groups: gbase + 16 cb + j, cb < kBlocks
@@ -558,9 +571,9 @@ __device__ __forceinline__ void dense_phase_mfma(CT* __restrict__ tile, uint32_t
   R fa[4], fb[4], fs[4];  // fragments of A, B and A + B
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
-    fa[kb] = (R)mf[kb].x;
-    fb[kb] = (R)mf[kb].y;
-    fs[kb] = (R)(mf[kb].x + mf[kb].y);
+    fa[kb] = mf[kb].x;
+    fb[kb] = mf[kb].y;
+    fs[kb] = mf[kb].x + mf[kb].y;
   }
   // slot of component q + 4 k of group gbase + 16 cb + j: a per-lane part (group
   // bits 0..3, component bits of q) XOR a wave-uniform part (higher group bits,
@@ -634,7 +647,7 @@ template <bool kDense, bool kGates, typename CT>
 __device__ __forceinline__ void run_phases(CT* __restrict__ tile, uint32_t T, uint32_t tid, uint32_t nthr, uint64_t flags,
                            const Phase* __restrict__ phases, uint32_t pb, uint32_t pc,
                            const DGate* __restrict__ gates, const double* __restrict__ mb,
-                           const double2* __restrict__ lds_mats = nullptr) {
+                           const CT* __restrict__ lds_mats = nullptr) {
   CT r[kR];
   for (uint32_t p = 0; p < pc; ++p) {
     const Phase ph = load_phase(phases + pb + p);
@@ -645,7 +658,7 @@ __device__ __forceinline__ void run_phases(CT* __restrict__ tile, uint32_t T, ui
     }
     if (kDense && ph.dense != kNoDense && nthr >= 64u) {
       if (tid < nthr) {
-        double2 mf[4];
+        CT mf[4];
         load_mfrag(mf, lds_mats != nullptr, lds_mats + (size_t)p * 256u,
                    reinterpret_cast<const double2*>(mb + (uint64_t)ph.dense * kMatStride), tid & 63u);
         dense_phase_mfma<4>(tile, T, tid, ph, mf);
@@ -854,14 +867,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
   // while it computes); the gate-list variant (more live registers) loads each
   // tile when it starts on it
   constexpr bool kPrefetch = kDenseOnly;
-  double2* lds_mats = nullptr;
+  CT* lds_mats = nullptr;
   if (kDenseOnly) {
-    lds_mats = reinterpret_cast<double2*>(tile + T);
+    lds_mats = tile + T;
     const double* mb0 = mats;  // dense matrices are per call (mat_stride 0 on this path)
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const double2* src = reinterpret_cast<const double2*>(mb0 + (uint64_t)cst(phases + a.phase_begin + p)->dense *
                                                                       kMatStride);
-      for (uint32_t e = tid; e < 256u; e += nthr) lds_mats[p * 256u + e] = src[e];
+      for (uint32_t e = tid; e < 256u; e += nthr) lds_mats[p * 256u + e] = cmake<CT>(src[e].x, src[e].y);
     }
     __syncthreads();
   }
@@ -941,7 +954,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
 // kLdsDensePhases of them) are staged in LDS once; otherwise each phase reads
 // its matrix from the shot's matrix slots.
 template <typename CT>
-__global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
+__global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pass_d8(
     CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
     const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats) {
   extern __shared__ double2 qsv_lds[];
@@ -953,12 +966,12 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
   uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..8]
   for (uint32_t b = 0; b < 9; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
   const uint64_t h0 = 1ull << a.tq[9], h1 = 1ull << a.tq[10], h2 = 1ull << a.tq[11];
-  double2* const lmats = reinterpret_cast<double2*>(tile + T);
+  CT* const lmats = tile + T;
   if (lds_mats)
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const double2* src =
           reinterpret_cast<const double2*>(mats + (uint64_t)cst(phases + a.phase_begin + p)->dense * kMatStride);
-      for (uint32_t e = tid; e < 256u; e += kThreads) lmats[p * 256u + e] = src[e];
+      for (uint32_t e = tid; e < 256u; e += kThreads) lmats[p * 256u + e] = cmake<CT>(src[e].x, src[e].y);
     }
   uint32_t last_shot = 0xFFFFFFFFu;
   bool last_active = false;
@@ -987,7 +1000,7 @@ __global__ __launch_bounds__(2 * kTileThreads, 4) void k_tile_pass_d8(
     const double* ms = mats + (uint64_t)shot * mat_stride;
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const Phase ph = load_phase(phases + a.phase_begin + p);
-      double2 mf[4];
+      CT mf[4];
       load_mfrag(mf, lds_mats != 0u, lmats + (size_t)p * 256u,
                  reinterpret_cast<const double2*>(ms + (uint64_t)ph.dense * kMatStride), lane);
       dense_phase_mfma<2>(tile, T, tid, ph, mf);
