@@ -17,6 +17,7 @@ builds such an AST as plain tuples for the tree-walking interpreter in
   ('break',)                        ('continue',)
   qref/cref = ('ref', name, index_expr|None)
   cond = ('truth', ref) | ('not', cond) | ('cmp', op, ref, expr)
+       | ('and', cond, cond) | ('or', cond, cond)     (C precedence: ! over && over ||)
   expr = ('num', v) | ('id', name) | ('index', name, expr) | ('neg', e)
        | ('bin', op, a, b) | ('call', fn, [e])
 """
@@ -295,8 +296,23 @@ class _Parser:
         return ("if", cond, then_body, else_body)
 
     def cond(self):
+        terms = [self.cond_conj()]
+        while self.accept("||"):
+            terms.append(self.cond_conj())
+        c = terms[0]
+        for t in terms[1:]:
+            c = ("or", c, t)
+        return c
+
+    def cond_conj(self):
+        c = self.cond_atom()
+        while self.accept("&&"):
+            c = ("and", c, self.cond_atom())
+        return c
+
+    def cond_atom(self):
         if self.accept("!"):
-            return ("not", self.cond())
+            return ("not", self.cond_atom())
         if self.accept("("):
             c = self.cond()
             self.expect(")")

@@ -442,6 +442,10 @@ class Interpreter:
         k = c[0]
         if k == "not":
             return not self.cond(c[1], env)
+        if k == "and":  # both sides read the bits as they are when the if executes
+            return self.cond(c[1], env) and self.cond(c[2], env)
+        if k == "or":
+            return self.cond(c[1], env) or self.cond(c[2], env)
         if k == "truth":
             return self.reg_value(c[1], env) != 0
         if k == "cmp":
