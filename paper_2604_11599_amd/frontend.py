@@ -114,11 +114,12 @@ class Reset:
 
 @dataclass
 class Cond:
-    kind: str                  # "truth" | "cmp" | "not"
+    kind: str                  # "truth" | "cmp" | "not" | "and" | "or"
     operand: Optional[Operand] = None
     op: str = ""
     rhs: object = None
-    inner: Optional["Cond"] = None
+    inner: Optional["Cond"] = None    # "not": the negated condition; "and"/"or": the left side
+    right: Optional["Cond"] = None    # "and"/"or": the right side
 
 
 @dataclass
@@ -463,8 +464,21 @@ class Parser:
         return IfStmt(cond, then_body, else_body)
 
     def _cond(self):
+        """Condition: `||` of `&&` of unary conditions (`&&` binds tighter)."""
+        c = self._cond_and()
+        while self._eat("||"):
+            c = Cond("or", inner=c, right=self._cond_and())
+        return c
+
+    def _cond_and(self):
+        c = self._cond_unary()
+        while self._eat("&&"):
+            c = Cond("and", inner=c, right=self._cond_unary())
+        return c
+
+    def _cond_unary(self):
         if self._eat("!"):
-            return Cond("not", inner=self._cond())
+            return Cond("not", inner=self._cond_unary())
         if self._eat("("):
             c = self._cond()
             self._need(")")

@@ -18,6 +18,10 @@ Control flow becomes flags (64 per shot) and guard masks:
   if (p) A else B   ->  SETF t <- p ; SETF e <- !p ; A guarded by t ; B guarded by e
   for i in [a:b] S  ->  SETF l <- true ; S unrolled for each i, guarded by l
   break / continue  ->  CLRF l / CLRF c (under the enclosing guards)
+  if (p && q) A     ->  SETF t1 <- p ; SETF f1 <- !p ; SETF t2 <- q (guarded by t1) ;
+                        SETF f2 <- !q (guarded by t1) ; A guarded by t1, t2
+  `||` mirrors `&&` (q is tested where p fails); a condition with several ways
+  to hold gets its body once per way, under disjoint guards.
 Custom ``gate`` definitions are inlined.
 """
 import math
@@ -28,6 +32,13 @@ from . import frontend as F
 
 # instruction ops, gate kinds and predicate comparisons of include/qsv.h
 OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF = 1, 2, 3, 4, 5
+
+
+def _has_logic(c):
+    """Whether a condition uses `&&` or `||`."""
+    if c is None:
+        return False
+    return c.kind in ("and", "or") or _has_logic(c.inner)
 (G_ID, G_X, G_Y, G_Z, G_H, G_S, G_SDG, G_T, G_TDG, G_SX, G_SXDG, G_RX, G_RY, G_RZ, G_P, G_U,
  G_CX, G_CY, G_CZ, G_CH, G_SWAP, G_CP, G_CRX, G_CRY, G_CRZ) = range(25)
 CMP_EQ, CMP_NE, CMP_LT, CMP_GT, CMP_LE, CMP_GE, CMP_TRUE = range(7)
@@ -331,6 +342,30 @@ class _Lowerer:
             raise F.QasmError("comparison with a negative value")
         return bits[0], len(bits), v & 0xFFFFFFFFFFFFFFFF, _CMP[c.op]
 
+    def cond_guards(self, c, env, guard, flags):
+        """Guards (lists of masks) under `guard` where c holds and where it fails.
+        The masks of each list are disjoint and together cover exactly those
+        shots; every flag they use is set by a SETF emitted here, in order."""
+        if c.kind == "not":
+            yes, no = self.cond_guards(c.inner, env, guard, flags)
+            return no, yes
+        if c.kind in ("and", "or"):
+            yes_l, no_l = self.cond_guards(c.inner, env, guard, flags)
+            # "and" needs the right side only where the left holds, "or" only where it fails
+            rest = yes_l if c.kind == "and" else no_l
+            yes, no = ([], list(no_l)) if c.kind == "and" else (list(yes_l), [])
+            for g in rest:
+                y, n = self.cond_guards(c.right, env, g, flags)
+                yes += y
+                no += n
+            return yes, no
+        lo, width, value, cmp = self.condition(c, env)
+        ft, ff = self._alloc(), self._alloc()
+        flags += [ft, ff]
+        self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, cmp), flag=ft)
+        self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, _NEGATE[cmp]), flag=ff)
+        return [guard | (1 << ft)], [guard | (1 << ff)]
+
     # -- statements --
     def program(self, stmts):
         body = []
@@ -379,6 +414,19 @@ class _Lowerer:
         elif isinstance(st, F.Reset):
             for q in self.qubits(st.qubits, env):
                 self._emit(OP_RESET, guard, q0=q)
+        elif isinstance(st, F.IfStmt) and _has_logic(st.cond):
+            # `&&` / `||`: the condition becomes disjoint guards (one per way it
+            # can hold, one per way it can fail), each a flag set when the if
+            # executes; a body is emitted once under each of its guards
+            flags = []
+            yes, no = self.cond_guards(st.cond, env, guard, flags)
+            for g in yes:
+                self.block(st.then_body, env, g, loop)
+            if st.else_body:
+                for g in no:
+                    self.block(st.else_body, env, g, loop)
+            for f in reversed(flags):
+                self._release(f)
         elif isinstance(st, F.IfStmt):
             lo, width, value, cmp = self.condition(st.cond, env)
             ft = self._alloc()

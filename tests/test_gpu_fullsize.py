@@ -122,3 +122,40 @@ def test_benchmark_circuit_properties(ctx):
     nomeas = src[:src.rindex("f = measure q;")]
     st = ctx.load(nomeas).run_shots(1, seed=0, state_out=True).state
     assert abs(np.vdot(st, st).real - 1.0) < 1e-10
+
+
+def test_complex64_28q(ctx):
+    """complex64 at full size: the separable 28-qubit state against the oracle's
+    blocks at sampled indices, and the benchmark circuit's 16 shots in the bench
+    launch against the complex128 run of the same shots (records equal,
+    trajectory probabilities within the single-precision bound, sharing
+    bit-identical within complex64). Bounds as in the complex64 parity tests."""
+    full, blocks, offs = W.separable_brickwork(seed=5, n=N, blocks=4, layers=40)
+    psis = [sim.run_shot(b).psi for b in blocks]
+    say("c64 separable 28q: GPU state of one shot")
+    st = ctx.load(full).run_shots(1, state_out=True, complex64=True).state
+    assert abs(np.vdot(st, st).real - 1.0) < 2e-5
+    rng = np.random.default_rng(4)
+    idx = rng.integers(0, 1 << N, size=200000, dtype=np.int64)
+    expect = np.ones(idx.shape, dtype=np.complex128)
+    for psi, src, off in zip(psis, blocks, offs):
+        expect *= psi[(idx >> off) & ((1 << _width(src)) - 1)]
+    err = np.max(np.abs(st[idx] - expect))
+    say("  max amplitude error", err, "of max amplitude", np.max(np.abs(expect)))
+    assert err < 2e-5 * np.max(np.abs(expect))
+    del st
+
+    src = W.c2_program(seed=2, n=N, layers=40)
+    prog = ctx.load(src)
+    say("c64 c2 28q: 16 shots, complex128 then complex64")
+    a = prog.run_shots(16, seed=0)
+    c = prog.run_shots(16, seed=0, complex64=True)
+    assert np.all(c.shot_status == 0)
+    assert np.array_equal(c.creg, a.creg) and np.array_equal(c.record, a.record)
+    assert np.array_equal(c.n_events, a.n_events)
+    assert np.all(np.abs(c.record_prob - a.record_prob) <= 4e-5 * a.record_prob)
+    say("c64 c2 28q: shared trajectories")
+    b = prog.run_shots(16, seed=0, share=True, complex64=True)
+    assert np.array_equal(b.creg, c.creg) and np.array_equal(b.record, c.record)
+    assert np.array_equal(b.record_prob, c.record_prob)
+

@@ -265,6 +265,22 @@ def test_gate_modifiers_match_oracle(ctx):
         _check_shots(ctx, W.modifier_program(seed, n, 60), 24, seed=seed)
 
 
+def test_logical_conditions_match_oracle(ctx):
+    """if conditions with &&, || and ! (disjoint flag guards) on the tile path,
+    with and without trajectory sharing, and in a persistent batch."""
+    for seed, n in [(1, 4), (2, 9), (3, 13), (4, 16)]:
+        src = W.logic_program(seed, n, n_ops=40)
+        _check_shots(ctx, src, 8, seed=seed, state=n <= 13)
+        _check_shots(ctx, src, 8, seed=seed + 10, forced_from_oracle=True, state=False)
+        _check_shots(ctx, src, 8, seed=seed, state=False, share=True)
+        o = sim.run_shots(src, 8, seed=7)
+        r = ctx.run_batch([{"prog": ctx.load(src), "shots": 8, "seed": 7}])[0]
+        for s in range(8):
+            if _near_tie(sim.run_shot(src, seed=7, shot=s).events):
+                continue
+            assert list(r.record[s, :len(o[s]["record"])]) == o[s]["record"]
+
+
 def test_readout_and_reset_errors_match_oracle(ctx):
     """Readout and reset errors drawn from each shot's own Philox stream: shot by
     shot equal to the oracle on the tile-pass path (with and without trajectory

@@ -225,6 +225,23 @@ def test_lowering_of_gate_modifiers_matches_oracle(seed):
     _compare(W.modifier_program(seed, 3 + seed % 3, 30), shots=2)
 
 
+@pytest.mark.parametrize("seed", range(10))
+def test_lowering_of_logical_conditions_matches_oracle(seed):
+    """`&&`, `||` and `!` in if conditions lower to disjoint flag guards (the
+    body once per way the condition holds); the oracle evaluates them directly."""
+    _compare(W.logic_program(seed, 2 + seed % 4, 30), shots=4)
+
+
+def test_logical_condition_guards_are_disjoint():
+    """Every shot runs the then-body at most once: a condition that holds in
+    several ways still flips the target qubit exactly once."""
+    head = 'OPENQASM 3.0;\ninclude "stdgates.inc";\nqubit[4] q;\nbit[3] c;\nbit t;\n'
+    for pre in ("", "x q[0];", "x q[0]; x q[1];", "x q[0]; x q[1]; x q[2];", "x q[2];"):
+        src = (head + pre + "c[0] = measure q[0]; c[1] = measure q[1]; c[2] = measure q[2];"
+               "if (c[0] || c[1] || c[2] || c == 7) x q[3]; t = measure q[3];")
+        _compare(src, shots=1)
+
+
 def test_gate_modifier_limits_are_reported():
     for body in ("ctrl @ cx q[0], q[1], q[2];", "ctrl(2) @ x q[0], q[1], q[2];", "pow @ x q[0];"):
         with pytest.raises(QasmError):

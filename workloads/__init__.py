@@ -13,6 +13,6 @@ from .circuits import (  # noqa: F401
     brickwork_program, separable_brickwork, mirror_program, random_dynamic_program,
     random_clifford_program, qft_program, bv_program, teleport_program,
     conditional_reset_program, if_else_program, multibit_predicate_program, rus_program,
-    hea2_program, param_program, modifier_program,
+    hea2_program, param_program, modifier_program, logic_program,
 )
 from .trace import c5_trace  # noqa: F401

@@ -304,6 +304,53 @@ def random_dynamic_program(seed, n, n_ops=40, n_bits=4, p_dynamic=0.25, final_me
     return "\n".join(lines) + "\n"
 
 
+def _random_logic_cond(rng, n_bits, depth):
+    """A random condition over c[0..n_bits-1] with !, && and || (nested to `depth`)."""
+    if depth == 0 or rng.random() < 0.3:
+        r = rng.random()
+        if r < 0.4:
+            atom = f"c[{int(rng.integers(n_bits))}]"
+        elif r < 0.7:
+            atom = f"c[{int(rng.integers(n_bits))}] == {int(rng.integers(2))}"
+        else:
+            atom = f"c {['==', '!=', '<', '>='][int(rng.integers(4))]} {int(rng.integers(1 << n_bits))}"
+        if rng.random() < 0.25:
+            return f"!({atom})"
+        return f"({atom})" if rng.random() < 0.5 else atom
+    op = "&&" if rng.random() < 0.5 else "||"
+    a = _random_logic_cond(rng, n_bits, depth - 1)
+    b = _random_logic_cond(rng, n_bits, depth - 1)
+    s = f"{a} {op} {b}"
+    return f"!({s})" if rng.random() < 0.2 else f"({s})" if rng.random() < 0.5 else s
+
+
+def logic_program(seed, n, n_ops=30, n_bits=3, final_measure=True):
+    """Random gates, measurements into c[0..n_bits-1] and if / if-else blocks
+    whose conditions combine bit tests and comparisons with !, && and ||."""
+    rng = _rng(seed)
+    lines = [HEADER, f"qubit[{n}] q;", f"bit[{n_bits}] c;"]
+    if final_measure:
+        lines.append(f"bit[{n}] f;")
+    for i in range(n_bits):
+        lines.append(f"h q[{i % n}];")
+        lines.append(f"c[{i}] = measure q[{i % n}];")
+    for _ in range(n_ops):
+        r = rng.random()
+        if r < 0.6:
+            lines.append(_random_gate(rng, n))
+        elif r < 0.75:
+            lines.append(f"c[{int(rng.integers(n_bits))}] = measure q[{int(rng.integers(n))}];")
+        else:
+            body = [_random_gate(rng, n) for _ in range(int(rng.integers(1, 4)))]
+            s = f"if ({_random_logic_cond(rng, n_bits, 2)}) {{ " + " ".join(body) + " }"
+            if rng.random() < 0.5:
+                s += " else { " + " ".join(_random_gate(rng, n) for _ in range(int(rng.integers(1, 3)))) + " }"
+            lines.append(s)
+    if final_measure:
+        lines.append("f = measure q;")
+    return "\n".join(lines) + "\n"
+
+
 def random_clifford_program(seed, n, n_gates):
     """Random H / S / CX circuit (a stabilizer state at the end)."""
     rng = _rng(seed)
