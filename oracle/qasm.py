@@ -12,6 +12,7 @@ builds such an AST as plain tuples for the tree-walking interpreter in
   ('input', name, size|None)        ('const', name, expr)
   ('gatedef', name, params, qargs, body)
   ('gate', name, [expr], [qref], mods)    ('measure', qref, cref|None)
+  ('assign', cref, ('value', expr) | ('cond', cond))   classical assignment
   ('reset', qref)                   ('barrier',)
   ('if', cond, then_body, else_body) ('for', var, start, step, stop, body)
   ('break',)                        ('continue',)
@@ -184,10 +185,18 @@ class _Parser:
                 save = self.i
                 target = self.ref()
                 if self.accept("="):
-                    self.expect("measure")
-                    q = self.ref()
+                    if self.accept("measure"):
+                        q = self.ref()
+                        self.expect(";")
+                        return ("measure", q, target)
+                    # classical assignment: an integer (literal or constant
+                    # expression starting with a number) or a condition
+                    if self.peek()[0] == "num" or self.peek()[1] == "-":
+                        rhs = ("value", self.expr())
+                    else:
+                        rhs = ("cond", self.cond())
                     self.expect(";")
-                    return ("measure", q, target)
+                    return ("assign", target, rhs)
                 self.i = save
             return self.gate_call()
         raise QasmSyntaxError(f"unexpected token {val!r}")

@@ -407,6 +407,8 @@ class Interpreter:
         elif k == "reset":
             for q in self.qubits_of(st[1], env):
                 self.reset(q)
+        elif k == "assign":
+            self.assign(st[1], st[2], env)
         elif k == "barrier":
             pass
         elif k == "if":
@@ -454,6 +456,34 @@ class Interpreter:
             return {"==": lhs == rhs, "!=": lhs != rhs, "<": lhs < rhs, ">": lhs > rhs,
                     "<=": lhs <= rhs, ">=": lhs >= rhs}[c[1]]
         raise OracleError(f"bad condition {c}")
+
+    def assign(self, target, rhs, env):
+        """Classical assignment (OpenQASM 3): a register or bit takes an
+        integer's bits (bit i of the register <- bit i of the value), another
+        register of the same width is copied, or one bit takes the truth value
+        of a condition. The right side is read completely before any bit is
+        written."""
+        bits = self.clbits_of(target, env)
+        value = None
+        if rhs[0] == "value":
+            value = int(round(_val(self.eval(rhs[1], env))))
+        elif rhs[1][0] == "truth" and rhs[1][1][1] not in self.prog.cregs:
+            value = int(round(_val(self.eval(("id", rhs[1][1][1]), env))))  # a constant or loop variable
+        if value is not None:
+            if value < 0:
+                raise OracleError("negative value assigned to classical bits")
+            new = [(value >> i) & 1 for i in range(len(bits))]
+        elif rhs[1][0] == "truth" and len(bits) > 1:
+            src = self.clbits_of(rhs[1][1], env)
+            if len(src) != len(bits):
+                raise OracleError("register copy between registers of different widths")
+            new = [self.cbits[b] for b in src]
+        else:
+            if len(bits) != 1:
+                raise OracleError("a condition is assigned to one bit")
+            new = [int(self.cond(rhs[1], env))]
+        for b, v in zip(bits, new):
+            self.cbits[b] = v
 
     def reg_value(self, ref, env):
         bits = self.clbits_of(ref, env)
