@@ -94,7 +94,9 @@ enum {
   QSV_OP_MEASURE = 2,  /* measure q0 into classical bit `cbit` (cbit = QSV_NONE: discard) */
   QSV_OP_RESET = 3,    /* reset q0 to |0>: a measurement (one draw) followed by X if 1 */
   QSV_OP_SETF = 4,     /* flag <- active && pred */
-  QSV_OP_CLRF = 5      /* if active: flag <- 0 */
+  QSV_OP_CLRF = 5,     /* if active: flag <- 0 */
+  QSV_OP_SETB = 6,     /* if active: classical bit `cbit` <- 1 (classical assignment) */
+  QSV_OP_CLRB = 7      /* if active: classical bit `cbit` <- 0 */
 };
 
 enum {

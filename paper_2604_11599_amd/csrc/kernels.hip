@@ -1138,6 +1138,9 @@ __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, con
     if (!active) continue;
     if (E.op == SE_CLRF) {
       cc.flags &= ~(1ull << E.flag);
+    } else if (E.op == SE_SETB || E.op == SE_CLRB) {  // classical assignment of one bit
+      const uint64_t m = 1ull << (E.cbit & 63u);
+      cr[E.cbit >> 6] = (E.op == SE_SETB) ? (cr[E.cbit >> 6] | m) : (cr[E.cbit >> 6] & ~m);
     } else if (E.op == SE_X) {
       xf ^= 1ull << E.q;
     } else {  // measure or reset

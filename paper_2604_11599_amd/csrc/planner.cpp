@@ -224,6 +224,9 @@ bool validate_program(const qsv_program_desc& d, std::string* err) {
       case QSV_OP_CLRF:
         if (in.flag >= 64) return fail(at + "flag out of range");
         break;
+      case QSV_OP_SETB: case QSV_OP_CLRB:
+        if (in.cbit >= d.n_clbits) return fail(at + "classical bit out of range");
+        break;
       default:
         return fail(at + "unknown op");
     }
@@ -403,6 +406,9 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
       } else if (in.op == QSV_OP_CLRF) {
         e.op = SE_CLRF;
         e.flag = (uint8_t)in.flag;
+      } else if (in.op == QSV_OP_SETB || in.op == QSV_OP_CLRB) {
+        e.op = in.op == QSV_OP_SETB ? SE_SETB : SE_CLRB;
+        e.cbit = in.cbit;
       } else {  // an X gate folded into the site
         e.op = SE_X;
         e.q = in.q0;

@@ -96,7 +96,7 @@ struct PassArgs {
 };
 
 // Sequential events of a measurement site, replayed per shot by one thread.
-enum SiteOp : uint8_t { SE_MEASURE = 1, SE_RESET = 2, SE_SETF = 3, SE_CLRF = 4, SE_X = 5 };
+enum SiteOp : uint8_t { SE_MEASURE = 1, SE_RESET = 2, SE_SETF = 3, SE_CLRF = 4, SE_X = 5, SE_SETB = 6, SE_CLRB = 7 };
 
 struct SiteEvent {  // 24 bytes
   uint8_t op;       // SE_*
@@ -104,7 +104,7 @@ struct SiteEvent {  // 24 bytes
   uint8_t flag;     // SETF/CLRF flag bit
   uint8_t pad;
   uint32_t q;       // global qubit (MEASURE/RESET/X)
-  uint32_t cbit;    // MEASURE target bit or 0xFFFFFFFF
+  uint32_t cbit;    // MEASURE target bit or 0xFFFFFFFF; SETB/CLRB bit
   uint32_t pred;    // SETF predicate index
   uint64_t guard;
 };

@@ -123,6 +123,14 @@ class Cond:
 
 
 @dataclass
+class Assign:
+    """Classical assignment: target <- an integer (value) or a condition (cond)."""
+    target: Operand
+    value: object = None
+    cond: Optional[Cond] = None
+
+
+@dataclass
 class IfStmt:
     cond: Cond
     then_body: list
@@ -366,14 +374,21 @@ class Parser:
             self._take()
             self._need(";")
             return [Continue()]
-        # "c[...] = measure q[...];" or a gate call
+        # "c[...] = measure q[...];", a classical assignment or a gate call
         if self._is("=", 1) or (self._is("[", 1) and self._assignment_ahead()):
             tgt = self._operand()
             self._need("=")
-            self._need("measure")
-            q = self._operand()
+            if self._eat("measure"):
+                q = self._operand()
+                self._need(";")
+                return [Measure(q, tgt)]
+            k, v = self._peek()
+            if k == "n" or v == "-":
+                st = Assign(tgt, value=self._expr())
+            else:
+                st = Assign(tgt, cond=self._cond())
             self._need(";")
-            return [Measure(q, tgt)]
+            return [st]
         return [self._gate_call()]
 
     def _assignment_ahead(self):

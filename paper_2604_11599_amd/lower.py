@@ -22,6 +22,9 @@ Control flow becomes flags (64 per shot) and guard masks:
                         SETF f2 <- !q (guarded by t1) ; A guarded by t1, t2
   `||` mirrors `&&` (q is tested where p fails); a condition with several ways
   to hold gets its body once per way, under disjoint guards.
+  c = v / d = c     ->  SETB / CLRB per bit (v an integer; d = c copies c's bits)
+  c[i] = cond       ->  the guards of cond, then SETB i under each guard where
+                        it holds and CLRB i under each where it fails
 Custom ``gate`` definitions are inlined.
 """
 import math
@@ -31,7 +34,7 @@ import numpy as np
 from . import frontend as F
 
 # instruction ops, gate kinds and predicate comparisons of include/qsv.h
-OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF = 1, 2, 3, 4, 5
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB = 1, 2, 3, 4, 5, 6, 7
 
 
 def _has_logic(c):
@@ -366,6 +369,47 @@ class _Lowerer:
         self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, _NEGATE[cmp]), flag=ff)
         return [guard | (1 << ft)], [guard | (1 << ff)]
 
+    def assign(self, st, env, guard):
+        """Classical assignment: an integer's bits, a register copy, or the
+        truth of a condition into one bit. Every predicate of the right side
+        is evaluated (SETF) before the first bit is written."""
+        bits = self.clbits(st.target, env)
+        value, c = None, st.cond
+        if c is None:
+            value = self.const_int(st.value, env)
+        elif c.kind == "truth" and c.operand.index is None and c.operand.reg not in self.cregs:
+            value = self.const_int(F.Name(c.operand.reg), env)  # a constant or loop variable
+        if value is not None:
+            if value < 0:
+                raise F.QasmError("negative value assigned to classical bits")
+            for i, b in enumerate(bits):
+                self._emit(OP_SETB if (value >> i) & 1 else OP_CLRB, guard, cbit=b)
+            return
+        if c.kind == "truth" and len(bits) > 1:
+            src = self.clbits(c.operand, env)
+            if len(src) != len(bits):
+                raise F.QasmError("register copy between registers of different widths")
+            if src == bits:
+                return
+            # distinct registers do not overlap: each bit is read and written in turn
+            for s, b in zip(src, bits):
+                f = self._alloc()
+                self._emit(OP_SETF, guard, pred=self._pred(s, 1, 0, _CMP["!="]), flag=f)
+                self._emit(OP_CLRB, guard, cbit=b)
+                self._emit(OP_SETB, guard | (1 << f), cbit=b)
+                self._release(f)
+            return
+        if len(bits) != 1:
+            raise F.QasmError("a condition is assigned to one bit")
+        flags = []
+        yes, no = self.cond_guards(c, env, guard, flags)
+        for g in yes:
+            self._emit(OP_SETB, g, cbit=bits[0])
+        for g in no:
+            self._emit(OP_CLRB, g, cbit=bits[0])
+        for f in reversed(flags):
+            self._release(f)
+
     # -- statements --
     def program(self, stmts):
         body = []
@@ -414,6 +458,8 @@ class _Lowerer:
         elif isinstance(st, F.Reset):
             for q in self.qubits(st.qubits, env):
                 self._emit(OP_RESET, guard, q0=q)
+        elif isinstance(st, F.Assign):
+            self.assign(st, env, guard)
         elif isinstance(st, F.IfStmt) and _has_logic(st.cond):
             # `&&` / `||`: the condition becomes disjoint guards (one per way it
             # can hold, one per way it can fail), each a flag set when the if

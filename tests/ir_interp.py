@@ -10,7 +10,7 @@ from oracle import gates as G
 from oracle.philox import ShotStream
 from oracle.sim import TensorEngine
 
-OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF = 1, 2, 3, 4, 5
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB = 1, 2, 3, 4, 5, 6, 7
 KIND_NAMES = ["id", "x", "y", "z", "h", "s", "sdg", "t", "tdg", "sx", "sxdg", "rx", "ry", "rz", "p", "U",
               "cx", "cy", "cz", "ch", "swap", "cp", "crx", "cry", "crz"]
 N_ANGLES = {"rx": 1, "ry": 1, "rz": 1, "p": 1, "U": 3, "cp": 1, "crx": 1, "cry": 1, "crz": 1}
@@ -43,6 +43,8 @@ def run(lp, theta=(), seed=0, shot=0, forced=None):
             continue
         if op == OP_CLRF:
             flags &= ~(1 << int(ins["flag"]))
+        elif op in (OP_SETB, OP_CLRB):
+            bits[int(ins["cbit"])] = 1 if op == OP_SETB else 0
         elif op == OP_GATE:
             name = KIND_NAMES[int(ins["kind"])]
             angles = []

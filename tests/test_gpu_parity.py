@@ -281,6 +281,24 @@ def test_logical_conditions_match_oracle(ctx):
             assert list(r.record[s, :len(o[s]["record"])]) == o[s]["record"]
 
 
+def test_classical_assignment_matches_oracle(ctx):
+    """c[i] = <condition> and c = <integer> (set / clear bit events) on the tile
+    path, with and without trajectory sharing, and in a persistent batch."""
+    for seed, n in [(11, 4), (12, 13)]:
+        src = W.logic_program(seed, n, n_ops=40, assign=True)
+        _check_shots(ctx, src, 8, seed=seed, state=n <= 13)
+        _check_shots(ctx, src, 8, seed=seed + 10, forced_from_oracle=True, state=False)
+        _check_shots(ctx, src, 8, seed=seed, state=False, share=True)
+        o = sim.run_shots(src, 8, seed=7)
+        r = ctx.run_batch([{"prog": ctx.load(src), "shots": 8, "seed": 7}])[0]
+        bits = r.bits()
+        for s in range(8):
+            if _near_tie(sim.run_shot(src, seed=7, shot=s).events):
+                continue
+            assert list(r.record[s, :len(o[s]["record"])]) == o[s]["record"]
+            assert list(bits[s]) == sim.run_shot(src, seed=7, shot=s).cbits
+
+
 def test_readout_and_reset_errors_match_oracle(ctx):
     """Readout and reset errors drawn from each shot's own Philox stream: shot by
     shot equal to the oracle on the tile-pass path (with and without trajectory

@@ -242,6 +242,27 @@ def test_logical_condition_guards_are_disjoint():
         _compare(src, shots=1)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_lowering_of_classical_assignment_matches_oracle(seed):
+    """c[i] = <condition> and c = <integer> lower to set / clear bit events
+    after the condition's predicates; the oracle assigns directly."""
+    _compare(W.logic_program(100 + seed, 2 + seed % 4, 40, assign=True), shots=4)
+
+
+def test_classical_assignment_forms():
+    head = ('OPENQASM 3.0;\ninclude "stdgates.inc";\nconst int k = 6;\nqubit[4] q;\nbit[3] c;\n'
+            'bit[3] d;\nbit t;\n')
+    for pre in ("", "x q[0];", "x q[1]; x q[2];", "x q[0]; x q[1]; x q[2];"):
+        meas = "c[0] = measure q[0]; c[1] = measure q[1]; c[2] = measure q[2];"
+        for body in ("d = c; c = 5;", "c[2] = c[0] && !c[1] || !c[0] && c[1]; if (c[2]) x q[3]; t = measure q[3];",
+                     "c[0] = !c[0] && c[1]; d[1] = c >= 3;", "c = k; d = 0b101; d[0] = c[1];"):
+            _compare(head + pre + meas + body, shots=1)
+    # a condition into a whole register, a negative value, a copy between widths
+    for bad in ("c = d[0] && d[1];", "c = -1;", "c = t;"):
+        with pytest.raises(QasmError):
+            lower(head + bad)
+
+
 def test_gate_modifier_limits_are_reported():
     for body in ("ctrl @ cx q[0], q[1], q[2];", "ctrl(2) @ x q[0], q[1], q[2];", "pow @ x q[0];"):
         with pytest.raises(QasmError):

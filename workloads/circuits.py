@@ -324,9 +324,11 @@ def _random_logic_cond(rng, n_bits, depth):
     return f"!({s})" if rng.random() < 0.2 else f"({s})" if rng.random() < 0.5 else s
 
 
-def logic_program(seed, n, n_ops=30, n_bits=3, final_measure=True):
+def logic_program(seed, n, n_ops=30, n_bits=3, final_measure=True, assign=False):
     """Random gates, measurements into c[0..n_bits-1] and if / if-else blocks
-    whose conditions combine bit tests and comparisons with !, && and ||."""
+    whose conditions combine bit tests and comparisons with !, && and ||.
+    assign: also classical assignments (a condition into one bit, an integer
+    into the register)."""
     rng = _rng(seed)
     lines = [HEADER, f"qubit[{n}] q;", f"bit[{n_bits}] c;"]
     if final_measure:
@@ -340,6 +342,11 @@ def logic_program(seed, n, n_ops=30, n_bits=3, final_measure=True):
             lines.append(_random_gate(rng, n))
         elif r < 0.75:
             lines.append(f"c[{int(rng.integers(n_bits))}] = measure q[{int(rng.integers(n))}];")
+        elif assign and r < 0.85:
+            if rng.random() < 0.8:
+                lines.append(f"c[{int(rng.integers(n_bits))}] = {_random_logic_cond(rng, n_bits, 2)};")
+            else:
+                lines.append(f"c = {int(rng.integers(1 << n_bits))};")
         else:
             body = [_random_gate(rng, n) for _ in range(int(rng.integers(1, 4)))]
             s = f"if ({_random_logic_cond(rng, n_bits, 2)}) {{ " + " ".join(body) + " }"
