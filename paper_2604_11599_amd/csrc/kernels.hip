@@ -391,9 +391,12 @@ hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_
 // CU with complex128 tiles (64 KiB of LDS each), three with complex64 tiles
 // (32 KiB), so that the HBM, LDS and matrix-core work of different workgroups
 // overlap.
+// kPreload: the staged phases' descriptors are read once per workgroup into
+// scalar registers (complex128; the complex64 build, held to 80 VGPRs for its
+// third workgroup, spills more with them and runs slower).
 template <typename CT> struct D8Waves;
-template <> struct D8Waves<double2> { static constexpr int kMin = 4; };
-template <> struct D8Waves<float2> { static constexpr int kMin = 6; };
+template <> struct D8Waves<double2> { static constexpr int kMin = 4; static constexpr bool kPreload = true; };
+template <> struct D8Waves<float2> { static constexpr int kMin = 6; static constexpr bool kPreload = false; };
 template <typename CT>
 __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pass_d8(
     CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, const Phase* __restrict__ phases,
@@ -973,6 +976,16 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
           reinterpret_cast<const double2*>(mats + (uint64_t)cst(phases + a.phase_begin + p)->dense * kMatStride);
       for (uint32_t e = tid; e < 256u; e += kThreads) lmats[p * 256u + e] = cmake<CT>(src[e].x, src[e].y);
     }
+  // the first phases' descriptors, read once (wave-uniform, scalar registers):
+  // every tile runs the same phases, and a descriptor read inside the tile
+  // loop would make each phase wait for it, and for the matrix operand reads
+  // issued with it, before any of its address work
+  Phase pre[kLdsDensePhases];
+  if constexpr (D8Waves<CT>::kPreload) {
+#pragma unroll
+    for (uint32_t p = 0; p < kLdsDensePhases; ++p)
+      pre[p] = load_phase(phases + a.phase_begin + (p < a.phase_count ? p : 0u));
+  }
   uint32_t last_shot = 0xFFFFFFFFu;
   bool last_active = false;
   uint64_t it = next_pass_item(blockIdx.x, total, G, ctl, a, nullptr, last_shot, last_active);
@@ -997,14 +1010,27 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
           !pending ? r[k] : (((gi & M) == V) ? cscale(r[k], sc) : cmake<CT>(0.0, 0.0));
     }
     __syncthreads();
-    const double* ms = mats + (uint64_t)shot * mat_stride;
-    for (uint32_t p = 0; p < a.phase_count; ++p) {
-      const Phase ph = load_phase(phases + a.phase_begin + p);
-      CT mf[4];
-      load_mfrag(mf, lds_mats != 0u, lmats + (size_t)p * 256u,
-                 reinterpret_cast<const double2*>(ms + (uint64_t)ph.dense * kMatStride), lane);
-      dense_phase_mfma<2>(tile, T, tid, ph, mf);
-      __syncthreads();
+    if (D8Waves<CT>::kPreload && lds_mats) {
+      // staged matrices (at most kLdsDensePhases phases): descriptors and
+      // operands from registers and LDS only
+#pragma unroll
+      for (uint32_t p = 0; p < kLdsDensePhases; ++p) {
+        if (p >= a.phase_count) break;
+        CT mf[4];
+        load_mfrag(mf, true, lmats + (size_t)p * 256u, nullptr, lane);
+        dense_phase_mfma<2>(tile, T, tid, pre[p], mf);
+        __syncthreads();
+      }
+    } else {
+      const double* ms = mats + (uint64_t)shot * mat_stride;
+      for (uint32_t p = 0; p < a.phase_count; ++p) {
+        const Phase ph = load_phase(phases + a.phase_begin + p);
+        CT mf[4];
+        load_mfrag(mf, lds_mats != 0u, lmats + (size_t)p * 256u,
+                   reinterpret_cast<const double2*>(ms + (uint64_t)ph.dense * kMatStride), lane);
+        dense_phase_mfma<2>(tile, T, tid, ph, mf);
+        __syncthreads();
+      }
     }
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) r[k] = tile[swz(tid + (uint32_t)k * kThreads)];
