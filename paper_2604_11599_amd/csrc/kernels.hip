@@ -1052,7 +1052,10 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
         }
       }
     }
-    __syncthreads();
+    // no barrier before the next tile: its staging writes go to the slots
+    // swz(tid + k * kThreads) that this thread has just read for the stores
+    // (one wave's LDS accesses complete in order), and the staging barrier
+    // orders them before any other thread's reads
     it = next_pass_item(it + G, total, G, ctl, a, nullptr, last_shot, last_active);
   }
 }
