@@ -281,6 +281,28 @@ def test_logical_conditions_match_oracle(ctx):
             assert list(r.record[s, :len(o[s]["record"])]) == o[s]["record"]
 
 
+def test_run_option_validation_and_complex64_with_noise(ctx):
+    """Error rates outside [0, 1) are rejected before any work; readout and
+    reset errors in complex64 draw the same words as in complex128, so the
+    records agree shot by shot with the noisy oracle outside the tie band."""
+    from paper_2604_11599_amd import QsvError
+    prog = ctx.load(W.c1_program(4))
+    for kw in ({"readout_error": 1.0}, {"reset_error": -0.1}, {"readout_error": float("nan")}):
+        with pytest.raises(QsvError):
+            prog.run_shots(4, seed=1, **kw)
+    src = W.random_dynamic_program(41, 13, n_ops=60)
+    noise = (0.05, 0.08)
+    res = ctx.load(src).run_shots(16, seed=2, complex64=True, readout_error=noise[0], reset_error=noise[1])
+    checked = 0
+    for s in range(16):
+        o = sim.run_shot(src, seed=2, shot=s, readout_error=noise[0], reset_error=noise[1])
+        if _near_tie(o.events, C64_TIE):
+            continue
+        assert list(res.record[s, :len(o.record)]) == o.record and res.n_events[s] == o.words_drawn
+        checked += 1
+    assert checked >= 12
+
+
 def test_classical_assignment_matches_oracle(ctx):
     """c[i] = <condition> and c = <integer> (set / clear bit events) on the tile
     path, with and without trajectory sharing, and in a persistent batch."""
