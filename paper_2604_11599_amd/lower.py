@@ -136,11 +136,75 @@ def _inverse(g):
     raise F.QasmError(f"no inverse for gate {name}")
 
 
+def _two_qubit_parts(g):
+    """A two-qubit standard gate as one-qubit gates and CX, exactly (no global
+    phase): CZ = H CX H, CY = S CX S^dag, CH = RY(pi/4) CX RY(-pi/4) on the
+    target (X RY(pi/2) = H), controlled RY/RZ(t) = R(t/2) CX R(-t/2) CX on the
+    target (X R(a) X = R(-a)), CRX = H CRZ H, CP(l) = P(l/2) on the control
+    and P(l/2) CX P(-l/2) CX on the target, SWAP = three CX."""
+    name, a, (c, t) = g
+    half, neg_half = (_aff_scale(a[0], 0.5), _aff_scale(a[0], -0.5)) if a else (None, None)
+    if name in ("cx", "CX", "cnot"):
+        return [("cx", [], [c, t])]
+    if name == "cz":
+        return [("h", [], [t]), ("cx", [], [c, t]), ("h", [], [t])]
+    if name == "cy":
+        return [("sdg", [], [t]), ("cx", [], [c, t]), ("s", [], [t])]
+    if name == "ch":
+        return [("ry", [Affine(math.pi / 4.0)], [t]), ("cx", [], [c, t]), ("ry", [Affine(-math.pi / 4.0)], [t])]
+    if name == "swap":
+        return [("cx", [], [c, t]), ("cx", [], [t, c]), ("cx", [], [c, t])]
+    if name in ("cry", "crz"):
+        r = name[1:]  # "ry" / "rz"
+        return [(r, [half], [t]), ("cx", [], [c, t]), (r, [neg_half], [t]), ("cx", [], [c, t])]
+    if name == "crx":
+        return ([("h", [], [t])] + _two_qubit_parts(("crz", a, [c, t])) + [("h", [], [t])])
+    if name in ("cp", "cphase"):
+        return [("p", [half], [c]), ("p", [half], [t]), ("cx", [], [c, t]), ("p", [neg_half], [t]),
+                ("cx", [], [c, t])]
+    raise F.QasmError(f"no decomposition for gate {name}")
+
+
+def _toffoli(c1, c2, t):
+    """CCX from one-qubit gates and six CX (the standard exact circuit: H on
+    the target, T / T^dag phases, and a final CX / phase correction on the
+    controls)."""
+    return [("h", [], [t]), ("cx", [], [c2, t]), ("tdg", [], [t]), ("cx", [], [c1, t]), ("t", [], [t]),
+            ("cx", [], [c2, t]), ("tdg", [], [t]), ("cx", [], [c1, t]), ("t", [], [c2]), ("t", [], [t]),
+            ("h", [], [t]), ("cx", [], [c1, c2]), ("t", [], [c1]), ("tdg", [], [c2]), ("cx", [], [c1, c2])]
+
+
+def _controlled_seq(seq, c):
+    """A sequence of standard gates with one more control qubit c: one-qubit
+    gates by their controlled forms, two-qubit gates through their CX
+    decomposition, each controlled CX as a Toffoli."""
+    out = []
+    for g in seq:
+        if len(g[2]) == 1:
+            out += _controlled(g, c)
+            continue
+        for part in _two_qubit_parts(g):
+            out += _toffoli(c, *part[2]) if part[0] == "cx" else _controlled(part, c)
+    return out
+
+
+def _expand_controls(chain):
+    """ctrl(k) @ / negctrl(k) @ as k single controls (they take the leading operands in order)."""
+    out = []
+    for kind, v in chain:
+        if kind in ("ctrl", "negctrl"):
+            if v < 1:
+                raise F.QasmError(f"{kind}({v}) @ needs at least one control")
+            out += [(kind, 1)] * v
+        else:
+            out.append((kind, v))
+    return out
+
+
 def _controlled(g, c):
-    """Standard gates applying |0><0| (x) I + |1><1| (x) g with control qubit c."""
+    """Standard gates applying |0><0| (x) I + |1><1| (x) g with control qubit c,
+    for a one-qubit standard gate g."""
     name, a, qs = g
-    if len(qs) != 1:
-        raise F.QasmError(f"ctrl @ {name}: a controlled two-qubit gate is not supported")
     t = qs[0]
     if name == "id":
         return []
@@ -541,10 +605,8 @@ class _Lowerer:
                     v = 1 if arg is None else self.const_int(arg, env)
                     if kind == "pow" and arg is None:
                         raise F.QasmError("pow @ needs an exponent")
-                    if kind in ("ctrl", "negctrl") and v != 1:
-                        raise F.QasmError(f"{kind}({v}) @: only one control is supported")
                     chain.append((kind, v))
-                for name, a, q in self.modified(chain, st.name, angles, qs):
+                for name, a, q in self.modified(_expand_controls(chain), st.name, angles, qs):
                     self.apply(name, a, q, guard)
             else:
                 self.apply(st.name, angles, qs, guard)
@@ -568,7 +630,7 @@ class _Lowerer:
             q = [self.qubits(o, env)[0] for o in st.operands]
             if st.mods:
                 chain = [(k, 1 if v is None else self.const_int(v, env)) for k, v in st.mods]
-                out += self.modified(chain, st.name, a, q)
+                out += self.modified(_expand_controls(chain), st.name, a, q)
             else:
                 out += self.standard_gates(st.name, a, q)
         return out
@@ -586,10 +648,11 @@ class _Lowerer:
             if v < 0:
                 seq = [_inverse(g) for g in reversed(seq)]
             return seq * abs(v)
+        if len(qs) < 2:
+            raise F.QasmError(f"{kind} @ {name}: the controls leave no operand for the gate")
         c = qs[0]
         out = [("x", [], [c])] if kind == "negctrl" else []
-        for g in self.modified(chain[1:], name, angles, qs[1:]):
-            out += _controlled(g, c)
+        out += _controlled_seq(self.modified(chain[1:], name, angles, qs[1:]), c)
         if kind == "negctrl":
             out.append(("x", [], [c]))
         return out

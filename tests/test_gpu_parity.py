@@ -303,6 +303,19 @@ def test_run_option_validation_and_complex64_with_noise(ctx):
     assert checked >= 12
 
 
+def test_multi_controlled_gates_match_oracle(ctx):
+    """ctrl(k) @ and controls on two-qubit gates (lowered through CX
+    decompositions and Toffolis) on a 13-qubit dynamic program: shots and the
+    final state against the oracle's by-definition matrices."""
+    body = ("ctrl(2) @ x q[0], q[5], q[12]; ctrl @ swap q[3], q[7], q[11]; negctrl @ ctrl @ h q[1], q[2], q[9];"
+            "ctrl(2) @ U(0.4, 1.2, -0.7) q[4], q[8], q[10]; ctrl @ crx(0.9) q[6], q[0], q[3];")
+    head = W.random_dynamic_program(77, 13, n_ops=40, final_measure=True)
+    assert head.endswith("f = measure q;\n")
+    src = head[:-len("f = measure q;\n")] + body.replace(";", ";\n") + "f = measure q;\n"
+    _check_shots(ctx, src, 8, seed=3)
+    _check_shots(ctx, src, 8, seed=4, forced_from_oracle=True, state=False)
+
+
 def test_classical_assignment_matches_oracle(ctx):
     """c[i] = <condition> and c = <integer> (set / clear bit events) on the tile
     path, with and without trajectory sharing, and in a persistent batch."""

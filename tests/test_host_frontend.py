@@ -263,7 +263,30 @@ def test_classical_assignment_forms():
             lower(head + bad)
 
 
+MULTI_CONTROL = [
+    "ctrl @ cx q[0], q[1], q[2];", "ctrl(2) @ x q[0], q[1], q[2];", "ctrl @ ctrl @ U(0.4, 1.2, -0.7) q[0], q[1], q[2];",
+    "negctrl @ ctrl @ h q[3], q[0], q[2];", "ctrl(2) @ rz(th[0]) q[4], q[1], q[0];", "ctrl @ swap q[0], q[1], q[2];",
+    "ctrl(3) @ x q[0], q[1], q[2], q[3];", "ctrl @ cp(0.7) q[2], q[0], q[1];", "ctrl @ crx(th[1]) q[3], q[4], q[0];",
+    "ctrl @ cy q[1], q[2], q[3];", "ctrl @ cz q[4], q[2], q[0];", "ctrl @ ch q[0], q[3], q[1];",
+    "ctrl @ cry(0.9) q[1], q[4], q[2];", "ctrl @ crz(-1.1) q[2], q[0], q[3];", "inv @ ctrl(2) @ sx q[0], q[1], q[2];",
+    "ctrl @ inv @ ctrl @ t q[0], q[1], q[2];", "ctrl @ pow(2) @ ctrl @ sx q[3], q[1], q[2];",
+    "negctrl(2) @ y q[0], q[1], q[4];", "ctrl(2) @ U(th[0], 0.2, th[1]) q[3], q[0], q[1];",
+]
+
+
+@pytest.mark.parametrize("body", MULTI_CONTROL)
+def test_multi_controlled_gates_match_oracle(body):
+    """Several controls and controls on two-qubit gates lower exactly to
+    one-qubit gates and CX (two-qubit gates through their CX decomposition,
+    each controlled CX as a Toffoli); the oracle builds the controlled matrix
+    by definition."""
+    src = ('OPENQASM 3.0;\ninclude "stdgates.inc";\ninput array[float[64], 2] th;\nqubit[5] q;\n'
+           "U(0.3, 1.1, -0.4) q[0]; U(1.3, -0.2, 0.9) q[1]; U(2.1, 0.5, 0.1) q[2]; U(0.7, 2.2, -1.3) q[3];"
+           "U(1.9, -0.8, 0.6) q[4];\n" + body + "\n")
+    _compare(src, theta=np.array([0.37, -1.21]), shots=1)
+
+
 def test_gate_modifier_limits_are_reported():
-    for body in ("ctrl @ cx q[0], q[1], q[2];", "ctrl(2) @ x q[0], q[1], q[2];", "pow @ x q[0];"):
+    for body in ("pow @ x q[0];", "pow(0.5) @ x q[0];", "ctrl(0) @ x q[0];", "ctrl @ x q[0];"):
         with pytest.raises(QasmError):
             lower('OPENQASM 3.0;\ninclude "stdgates.inc";\nqubit[3] q;\n' + body + "\n")
