@@ -37,6 +37,19 @@ def test_library_exports_every_declared_symbol():
     assert set(_abi.SIGNATURES) == declared
 
 
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without libqsv.so the binding raises instead of falling back to anything
+    else (there is no CPU path in the product)."""
+    from paper_2604_11599_amd import _abi
+    with pytest.raises(ImportError):
+        _abi.load_library(str(tmp_path / "libqsv.so"))
+    monkeypatch.setattr(_abi, "_LIB", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "libqsv.so"))
+    monkeypatch.setattr(_abi.load_library, "__defaults__", (str(tmp_path / "libqsv.so"),))
+    with pytest.raises(ImportError):
+        _abi.lib()
+
+
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(_abi.Config) == 40
     assert ctypes.sizeof(_abi.ProgramDesc) == 40
