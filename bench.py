@@ -346,6 +346,7 @@ def main():
                         "mfma": {"achieved": tf32, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": tf32 / FP32_MFMA_PEAK_TFLOPS}},
            "note": "same shots with a complex64 state (the precision of the paper's GPU runs)"}
+    c64["roofline"]["traffic"] = traffic_from_profiles("c2_c64")
     log("complex64 steps done")
 
     out = {"metric": "shots/s + achieved HBM GB/s on 16q/28q dynamic circuits; p50/p99 request latency",

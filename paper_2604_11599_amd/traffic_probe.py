@@ -2,7 +2,8 @@
 
 Runs, in one process: one plain device copy of 4 GiB (qsv_diag_copy, the
 calibration: it reads and writes exactly 4 GiB), then one step of the 28-qubit
-benchmark workload (16 shots) with the same launch configuration as bench.py.
+benchmark workload (16 shots) with the same launch configuration as bench.py;
+with --complex64 the step holds its state in complex64.
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- python3 -m paper_2604_11599_amd.traffic_probe
 """
@@ -34,7 +35,7 @@ def main():
     torch.cuda.empty_cache()
     print("copy done", flush=True)
     prog = ctx.load(W.c2_program(seed=2, n=28, layers=40))
-    prog.run_shots(16, seed=0)
+    prog.run_shots(16, seed=0, complex64="--complex64" in sys.argv[1:])
     print("step done", flush=True)
     ctx.close()
 

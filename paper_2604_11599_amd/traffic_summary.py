@@ -7,7 +7,10 @@ maps the same counter on a plain device copy of known size (4 GiB read, 4 GiB
 written) to its true byte count. Writes profiles/tile_pass_c2_traffic.json (read
 by bench.py while the kernel source hash matches) and a short text summary.
 
-    python -m paper_2604_11599_amd.traffic_summary FETCH_CSV WRITE_CSV PROBE_LOG [COMMAND]
+    python -m paper_2604_11599_amd.traffic_summary [--complex64] FETCH_CSV WRITE_CSV PROBE_LOG [COMMAND]
+
+--complex64: the probe ran with a complex64 state; the results go to
+profiles/tile_pass_c2_c64_traffic.json and tile_pass_c2_28q_c64_traffic.txt.
 
 PROBE_LOG is the output of the probe run; its kernel_hash line names the kernel
 source the counters were taken on.
@@ -109,16 +112,21 @@ def summarize(fetch_csv, write_csv, khash):
 
 
 def main():
-    fetch_csv, write_csv, log = sys.argv[1], sys.argv[2], sys.argv[3]
-    cmd = sys.argv[4] if len(sys.argv) > 4 else ""
+    args = [a for a in sys.argv[1:] if a != "--complex64"]
+    c64 = len(args) != len(sys.argv) - 1
+    fetch_csv, write_csv, log = args[0], args[1], args[2]
+    cmd = args[3] if len(args) > 3 else ""
     d = summarize(fetch_csv, write_csv, probe_hash(log))
     d["command"] = cmd
-    out = os.path.join(ROOT, "profiles", "tile_pass_c2_traffic.json")
+    d["amplitude"] = "complex64" if c64 else "complex128"
+    sfx = "_c64" if c64 else ""
+    out = os.path.join(ROOT, "profiles", f"tile_pass_c2{sfx}_traffic.json")
     with open(out, "w") as f:
         json.dump(d, f, indent=1)
     amps = 16 * 2 ** 28
-    with open(os.path.join(ROOT, "profiles", "tile_pass_c2_28q_traffic.txt"), "w") as f:
-        f.write("HBM traffic of the tile pass, 28 qubits x 16 shots per launch (rocprofv3 --pmc)\n")
+    with open(os.path.join(ROOT, "profiles", f"tile_pass_c2_28q{sfx}_traffic.txt"), "w") as f:
+        f.write(f"HBM traffic of the tile pass, 28 qubits x 16 shots per launch, {d['amplitude']} state "
+                "(rocprofv3 --pmc)\n")
         f.write(f"command: {cmd}\n")
         f.write(f"kernel source hash: {d['kernel_hash']}\n")
         c = d["calibration"]
@@ -129,7 +137,8 @@ def main():
         f.write(f"scaled bytes per launch: fetch {d['fetch_bytes_per_launch']:.4e}, write "
                 f"{d['write_bytes_per_launch']:.4e}, total {d['bytes_per_launch']:.4e} "
                 f"(min {d['per_launch_min']:.4e}, max {d['per_launch_max']:.4e})\n")
-        f.write(f"per amplitude: {d['bytes_per_launch'] / amps:.2f} B (read + write of complex128 is 32 B)\n")
+        f.write(f"per amplitude: {d['bytes_per_launch'] / amps:.2f} B (read + write of {d['amplitude']} is "
+                f"{16 if c64 else 32} B)\n")
     print(json.dumps(d))
 
 
