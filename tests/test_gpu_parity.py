@@ -508,6 +508,33 @@ def test_gradient_through_gate_modifiers(ctx):
         assert np.max(np.abs(g[b] - go)) < 1e-11
 
 
+def test_gradient_through_multi_controlled_gates(ctx):
+    """Parameters under several controls and controls on two-qubit gates (the
+    angle enters the decomposition as +-t/2 in several gates) against the
+    oracle's adjoint of the controlled matrices, on 8 and 12 qubits."""
+    for n, P in ((8, 12), (12, 16)):
+        lines = ['OPENQASM 3.0;', 'include "stdgates.inc";', f"input array[float[64], {P}] t;", f"qubit[{n}] q;"]
+        for k in range(P):
+            a, b, c = k % n, (3 * k + 1) % n, (5 * k + 2) % n
+            if len({a, b, c}) < 3:
+                c = (max(a, b) + 1) % n
+                if c in (a, b):
+                    c = (c + 1) % n
+            lines.append(f"h q[{a}];")
+            lines.append([f"ctrl(2) @ ry(t[{k}]) q[{a}], q[{b}], q[{c}];", f"ctrl @ crz(t[{k}]) q[{c}], q[{a}], q[{b}];",
+                          f"negctrl @ ctrl @ rx(2 * t[{k}]) q[{b}], q[{c}], q[{a}];",
+                          f"ctrl @ cp(t[{k}] + 0.5) q[{a}], q[{c}], q[{b}];"][k % 4])
+            lines.append(f"cx q[{a}], q[{(a + 1) % n}];")
+        src = "\n".join(lines) + "\n"
+        coeffs, codes = W.c4_hamiltonian(seed=31, n=n, terms=10)
+        thetas = W.c4_thetas(seed=32, batch=2, n_params=P)
+        e, g = ctx.load(src).expval_grad(thetas, coeffs, codes)
+        for b in range(2):
+            eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
+            assert abs(e[b] - eo) < 1e-12
+            assert np.max(np.abs(g[b] - go)) < 1e-11
+
+
 def test_expval_closed_form_and_general_gates(ctx):
     prog = ctx.load(W.hea2_program())
     ab = np.array([[0.3, 1.1], [2.0, -0.4]])
