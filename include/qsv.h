@@ -315,8 +315,19 @@ typedef struct {
   double pass_uncond_flops;      /* algorithmic flops of those launches */
   uint64_t site_launches;        /* measurement reduce + finalize launches */
   double site_ms;
-  uint64_t other_launches;       /* init, bind, expval and adjoint kernels */
+  uint64_t other_launches;       /* init, bind, compose, reductions and copies */
   double other_ms;
+  uint64_t ham_launches;         /* lambda = H psi and the energy partials */
+  double ham_ms;
+  double ham_bytes;              /* 16 B per amplitude read (psi), 16 written (lambda, gradients only) */
+  uint64_t sweep_launches;       /* adjoint sweeps over the passes (backward gate passes) */
+  double sweep_ms;
+  double sweep_bytes;            /* 64 B per amplitude: psi and lambda, each read and written */
+  uint64_t persistent_launches;  /* persistent batch launches (qsv_run_batch) */
+  double persistent_ms;
+  double persistent_bytes;       /* 32 B per amplitude of every streamed (13..20-qubit) state per
+                                    pass it runs, 16 per measurement site reduction; states in LDS
+                                    move no HBM bytes */
 } qsv_profile;
 
 /* Copies the counters accumulated since the last reset. QSV_ERR_ARG if ctx was

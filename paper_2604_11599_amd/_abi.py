@@ -74,7 +74,11 @@ class Profile(C.Structure):
                 ("pass_uncond_launches", C.c_uint64), ("pass_uncond_ms", C.c_double),
                 ("pass_uncond_bytes", C.c_double), ("pass_uncond_flops", C.c_double),
                 ("site_launches", C.c_uint64), ("site_ms", C.c_double),
-                ("other_launches", C.c_uint64), ("other_ms", C.c_double)]
+                ("other_launches", C.c_uint64), ("other_ms", C.c_double),
+                ("ham_launches", C.c_uint64), ("ham_ms", C.c_double), ("ham_bytes", C.c_double),
+                ("sweep_launches", C.c_uint64), ("sweep_ms", C.c_double), ("sweep_bytes", C.c_double),
+                ("persistent_launches", C.c_uint64), ("persistent_ms", C.c_double),
+                ("persistent_bytes", C.c_double)]
 
 
 # name -> (restype, argtypes); the ABI surface the tests check for.

@@ -41,7 +41,7 @@ struct qsv_context {
   // profiling (QSV_FLAG_PROFILE): events around every launch, harvested after each sync
   struct Rec {
     hipEvent_t a, b;
-    int kind;  // 0 pass, 1 site, 2 other
+    int kind;  // Kind
     bool uncond;
     double bytes, flops;
   };
@@ -50,6 +50,9 @@ struct qsv_context {
   std::vector<Rec> recs;
   qsv_profile prof{};
   bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0; }
+  // the arena scratch is carved from in the current call, if any
+  uint8_t* call_arena() const { return arena; }
+  size_t call_arena_bytes() const { return arena_bytes; }
 };
 
 struct qsv_program {
@@ -96,6 +99,23 @@ qsv_status set_err(qsv_context* ctx, qsv_status st, const std::string& m) {
   return st;
 }
 
+// HIP keeps the most recent failed call's status per host thread until
+// hipGetLastError reads it, and every kernel launcher reads it right after its
+// launch. So a call whose status is not checked here, or a failed call made
+// by other code on the thread between two library calls, would otherwise be
+// reported as a failure of the next launch. Statuses that are deliberately
+// ignored go through ignore(), which clears that state again, and every entry
+// point clears it after selecting the device (enter()).
+inline void clear_error() { (void)hipGetLastError(); }
+inline void ignore(hipError_t) { clear_error(); }
+
+hipError_t enter_device(int device) {
+  clear_error();
+  const hipError_t e = hipSetDevice(device);
+  clear_error();
+  return e;
+}
+
 // Scratch allocation for one call: from the caller's arena (bump pointer,
 // reset per call) or from grow-only cached hipMalloc slots.
 struct Scratch {
@@ -107,16 +127,16 @@ struct Scratch {
   hipError_t get(size_t bytes, void** out) {
     bytes = (bytes + 255) & ~(size_t)255;
     if (bytes == 0) bytes = 256;
-    if (ctx->arena) {
-      if (ctx->arena_top + bytes > ctx->arena_bytes) return hipErrorOutOfMemory;
-      *out = ctx->arena + ctx->arena_top;
+    if (uint8_t* base = ctx->call_arena()) {
+      if (ctx->arena_top + bytes > ctx->call_arena_bytes()) return hipErrorOutOfMemory;
+      *out = base + ctx->arena_top;
       ctx->arena_top += bytes;
       return hipSuccess;
     }
     if (ctx->slot == ctx->cache.size()) ctx->cache.push_back(DevBuf{});
     DevBuf& b = ctx->cache[ctx->slot++];
     if (b.bytes < bytes) {
-      if (b.p) (void)hipFree(b.p);
+      if (b.p) ignore(hipFree(b.p));
       b.p = nullptr;
       b.bytes = 0;
       hipError_t e = hipMalloc(&b.p, bytes);
@@ -141,6 +161,9 @@ hipError_t upload(const std::vector<T>& v, T** out) {
   return hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// Launch classes of the profile.
+enum Kind { K_PASS = 0, K_SITE = 1, K_OTHER = 2, K_HAM = 3, K_SWEEP = 4, K_PERSISTENT = 5 };
+
 // Brackets one launch with profiling events when the context profiles.
 struct Prof {
   qsv_context* ctx;
@@ -149,12 +172,18 @@ struct Prof {
   Prof(qsv_context* c, hipStream_t s) : ctx(c), st(s) {
     if (!ctx->profiling()) return;
     a = next();
-    (void)hipEventRecord(a, st);
+    if (hipEventRecord(a, st) != hipSuccess) {
+      clear_error();
+      a = nullptr;
+    }
   }
   hipEvent_t next() {
     if (ctx->ev_used == ctx->ev_pool.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (hipEventCreate(&e) != hipSuccess) {
+        clear_error();
+        return nullptr;
+      }
       ctx->ev_pool.push_back(e);
     }
     return ctx->ev_pool[ctx->ev_used++];
@@ -163,7 +192,10 @@ struct Prof {
     if (!ctx->profiling() || !a) return;
     hipEvent_t b = next();
     if (!b) return;
-    (void)hipEventRecord(b, st);
+    if (hipEventRecord(b, st) != hipSuccess) {
+      clear_error();
+      return;
+    }
     ctx->recs.push_back({a, b, kind, uncond, bytes, flops});
   }
 };
@@ -173,7 +205,10 @@ void harvest(qsv_context* ctx) {
   if (!ctx->profiling()) return;
   for (const auto& r : ctx->recs) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      clear_error();
+      continue;
+    }
     qsv_profile& p = ctx->prof;
     if (r.kind == 0) {
       p.pass_launches++;
@@ -184,9 +219,20 @@ void harvest(qsv_context* ctx) {
         p.pass_uncond_bytes += r.bytes;
         p.pass_uncond_flops += r.flops;
       }
-    } else if (r.kind == 1) {
+    } else if (r.kind == K_SITE) {
       p.site_launches++;
       p.site_ms += ms;
+    } else if (r.kind == K_HAM) {
+      p.ham_launches++;
+      p.ham_ms += ms;
+      p.ham_bytes += r.bytes;
+    } else if (r.kind == K_SWEEP) {
+      p.sweep_launches++;
+      p.sweep_ms += ms;
+      p.sweep_bytes += r.bytes;
+    } else if (r.kind == K_PERSISTENT) {
+      p.persistent_launches++;
+      p.persistent_ms += ms;
     } else {
       p.other_launches++;
       p.other_ms += ms;
@@ -202,7 +248,10 @@ double pass_bytes_per_amp(const PassArgs& a) { return a.init ? 16.0 : 32.0; }
 
 size_t free_device_bytes() {
   size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    clear_error();
+    return 0;
+  }
   return fr;
 }
 
@@ -221,13 +270,20 @@ qsv_status qsv_create(const qsv_config* cfg, qsv_context** out) {
   ctx->arena = static_cast<uint8_t*>(cfg->arena);
   ctx->arena_bytes = cfg->arena ? cfg->arena_bytes : 0;
   int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return QSV_ERR_DEVICE;
+  clear_error();
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    clear_error();
+    return QSV_ERR_DEVICE;
+  }
   if (cfg->device < 0 || cfg->device >= count) return QSV_ERR_ARG;
-  if (hipSetDevice(cfg->device) != hipSuccess) return QSV_ERR_DEVICE;
+  if (enter_device(cfg->device) != hipSuccess) return QSV_ERR_DEVICE;
   if (cfg->stream) {
     ctx->stream = static_cast<hipStream_t>(cfg->stream);
   } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) return QSV_ERR_DEVICE;
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      clear_error();
+      return QSV_ERR_DEVICE;
+    }
     ctx->own_stream = true;
   }
   *out = ctx.release();
@@ -236,12 +292,12 @@ qsv_status qsv_create(const qsv_config* cfg, qsv_context** out) {
 
 void qsv_destroy(qsv_context* ctx) {
   if (!ctx) return;
-  (void)hipSetDevice(ctx->device);
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  ignore(enter_device(ctx->device));
+  if (ctx->stream) ignore(hipStreamSynchronize(ctx->stream));
+  for (hipEvent_t e : ctx->ev_pool) ignore(hipEventDestroy(e));
   for (auto& b : ctx->cache)
-    if (b.p) (void)hipFree(b.p);
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (b.p) ignore(hipFree(b.p));
+  if (ctx->own_stream) ignore(hipStreamDestroy(ctx->stream));
   delete ctx;
 }
 
@@ -254,7 +310,7 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
     return set_err(ctx, QSV_ERR_LIMIT, "more than 34 qubits do not fit one GPU's HBM");
   std::string err;
   if (!validate_program(*desc, &err)) return set_err(ctx, QSV_ERR_ARG, err);
-  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, QSV_ERR_DEVICE, "hipSetDevice failed");
+  if (enter_device(ctx->device) != hipSuccess) return set_err(ctx, QSV_ERR_DEVICE, "hipSetDevice failed");
   std::unique_ptr<qsv_program> p(new qsv_program());
   p->ctx = ctx;
   p->instr.assign(desc->instr, desc->instr + desc->n_instr);
@@ -361,10 +417,10 @@ qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) 
 
 void qsv_program_free(qsv_program* p) {
   if (!p) return;
-  (void)hipSetDevice(p->ctx->device);
+  ignore(enter_device(p->ctx->device));
   void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off};
   for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+    if (q) ignore(hipFree(q));
   delete p;
 }
 
@@ -381,7 +437,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       !(opts->reset_error >= 0.0 && opts->reset_error < 1.0))
     return set_err(ctx, QSV_ERR_ARG, "error rates must lie in [0, 1)");
   if (n_shots == 0) return QSV_OK;
-  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(enter_device(ctx->device));
   const Plan& pl = prog->plan;
   const uint32_t n = prog->desc.n_qubits;
   const uint32_t cw = std::max<uint32_t>(1, (prog->desc.n_clbits + 63) / 64);
@@ -394,10 +450,12 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   // shots per batch: what fits in the arena / free memory after the per-shot scratch
   size_t per_shot = state_bytes + sizeof(ShotCtl) + cw * 8 + maxrec + opts->forced_len +
                     (size_t)prog->pblocks * kSiteBins * 8 + 4 * 256;
-  size_t budget = ctx->arena ? ctx->arena_bytes : (free_device_bytes() / 10) * 8;
-  size_t fixed = pl.gate_src.size() * kMatStride * 8 + prog->desc.n_params * 8 + (1u << 20);
+  const bool in_arena = ctx->call_arena() != nullptr;
+  size_t budget = in_arena ? ctx->call_arena_bytes() : (free_device_bytes() / 10) * 8;
+  size_t fixed = pl.gate_src.size() * kMatStride * 8 + prog->desc.n_params * 8 + (1u << 20) +
+                 (opts->state_out ? dim * sizeof(double2) : 0);
   if (budget <= fixed + per_shot) {
-    if (ctx->arena) return set_err(ctx, QSV_ERR_NOMEM, "arena too small for one shot");
+    if (in_arena) return set_err(ctx, QSV_ERR_NOMEM, "arena too small for one shot");
     budget = fixed + per_shot;  // try anyway; hipMalloc reports the failure
   }
   uint64_t batch = std::min<uint64_t>(n_shots, (budget - fixed) / per_shot);
@@ -418,7 +476,9 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   // state buffers: one per shot, or with trajectory sharing one per slot that
   // owns its state, grown on demand (doubling) up to one per shot
   const bool share_req = (opts->flags & QSV_RUN_SHARE_TRAJ) != 0;
-  uint64_t cap = (share_req && batch > 1) ? std::min<uint64_t>(batch, 8) : batch;
+  // (in an arena every shot's buffer is reserved up front: a bump allocator
+  // cannot reuse the buffers a doubling leaves behind)
+  uint64_t cap = (share_req && batch > 1 && !in_arena) ? std::min<uint64_t>(batch, 8) : batch;
   HIP_TRY(scr.get(state_units(cap), &rb.state));
   HIP_TRY(scr.get(batch, &rb.ctl));
   HIP_TRY(scr.get(batch * cw, &rb.creg));
@@ -619,7 +679,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
 
 qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_reqs) {
   if (!ctx || (n_reqs && !reqs)) return set_err(ctx, QSV_ERR_ARG, "null argument");
-  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(enter_device(ctx->device));
   std::vector<uint32_t> pers, big;
   uint32_t max_stream = 0, cw = 1, rec_max = 1;
   uint64_t items = 0;
@@ -655,9 +715,13 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       return reqs[a].prog->desc.n_qubits > reqs[b].prog->desc.n_qubits;
     });
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
-      cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
+      clear_error();
+      cus = 0;
+    }
+    if (cus <= 0) cus = 256;
     const uint32_t wgs = (uint32_t)std::min<uint64_t>(items, (uint64_t)cus * 2);
+    uint64_t pers_bytes[2] = {0, 0};  // streamed-state HBM bytes of the two launches (profile)
     const uint64_t slot_amps = max_stream ? (1ull << max_stream) : 1;
     Scratch scr(ctx);
     size_t mat_total = 0, theta_total = 0, forced_total = 0;
@@ -769,6 +833,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
           pre[k].state_out = reinterpret_cast<double*>(d_pstate + off);
           rd[pre_of[k]].init_state = reinterpret_cast<const double*>(d_pstate + off);
           rd[pre_of[k]].init_ctl = d_pctl + k;
+          rd[pre_of[k]].init_creg = d_pcreg + k * cw;
           off += 1ull << pre[k].n;
           pitem[k] = (uint32_t)k;
         }
@@ -778,7 +843,9 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
         HIP_TRY(launch_persistent(d_pre, d_pitem, (uint32_t)pre.size(), d_queue, d_scratch, slot_amps,
                                   std::min<uint32_t>(wgs, (uint32_t)pre.size()), d_pctl, d_pcreg, cw, d_prec, rec_max,
                                   st));
-        pr.done(2);
+        pr.done(K_PERSISTENT);
+        if (ctx->profiling())
+          HIP_TRY(hipMemcpyAsync(&pers_bytes[0], d_queue + 2, 8, hipMemcpyDeviceToHost, st));
       }
     }
     HIP_TRY(hipMemcpyAsync(d_reqs, rd.data(), rd.size() * sizeof(ReqDev), hipMemcpyHostToDevice, st));
@@ -787,7 +854,9 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       Prof pr(ctx, st);
       HIP_TRY(launch_persistent(d_reqs, d_item_req, (uint32_t)items, d_queue, d_scratch, slot_amps, wgs, d_ctl,
                                 d_creg, cw, d_rec, rec_max, st));
-      pr.done(2);
+      pr.done(K_PERSISTENT);
+      if (ctx->profiling())
+        HIP_TRY(hipMemcpyAsync(&pers_bytes[1], d_queue + 2, 8, hipMemcpyDeviceToHost, st));
     }
     std::vector<ShotCtl> hctl(items);
     std::vector<uint64_t> hcreg(items * cw);
@@ -797,6 +866,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     HIP_TRY(hipMemcpyAsync(hrec.data(), d_rec, items * rec_max, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     harvest(ctx);
+    ctx->prof.persistent_bytes += (double)pers_bytes[0] + (double)pers_bytes[1];
     for (size_t i = 0; i < pers.size(); ++i) {
       const qsv_request& q = reqs[pers[i]];
       const uint32_t qcw = std::max<uint32_t>(1, (q.prog->desc.n_clbits + 63) / 64);
@@ -842,7 +912,7 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   if (h->n_terms && (!h->coeff || !h->pauli)) return set_err(ctx, QSV_ERR_ARG, "null Hamiltonian arrays");
   if (prog->desc.n_params && !theta) return set_err(ctx, QSV_ERR_ARG, "theta is required");
   if (batch == 0) return QSV_OK;
-  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(enter_device(ctx->device));
   const Plan& pl = prog->plan;
   const uint32_t n = prog->desc.n_qubits, P = prog->desc.n_params, T = h->n_terms;
   const uint64_t dim = 1ull << n;
@@ -951,8 +1021,10 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
     }
     // lambda = H psi (kept for the gradient) and the energy Re <psi|lambda> in one sweep
     if (T) {
+      Prof pr(ctx, st);
       HIP_TRY(launch_hamiltonian(rb.state, grad ? d_lam : nullptr, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, blocks,
                                  d_tp, st));
+      pr.done(K_HAM, false, (grad ? 32.0 : 16.0) * (double)dim * bs);
       HIP_TRY(launch_energy_sum(d_tp, blocks, bs, d_energy, st));
     } else {
       HIP_TRY(hipMemsetAsync(d_energy, 0, bs * 8, st));
@@ -971,9 +1043,11 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
         else
           HIP_TRY(launch_backward_pass(rb.state, d_lam, dim, bs, prog->d_gates, prog->d_phases, d_mats, d_dmats, ms,
                                        a, d_gpart, st));
+        pr.done(K_SWEEP, false, 64.0 * (double)dim * bs);
+        Prof pr2(ctx, st);
         HIP_TRY(launch_grad_reduce(d_gpart, parts_of(step.index), a.gate_count, 0, prog->d_gates + a.gate_begin, bs,
                                    std::max<uint32_t>(n_slots, 1), d_dEda, st));
-        pr.done(2);
+        pr2.done(K_OTHER);
       }
       HIP_TRY(launch_grad_chain(d_dEda, std::max<uint32_t>(n_slots, 1), prog->d_csr_off, prog->d_csr_sj,
                                 prog->d_csr_scale, P, bs, d_grad, st));
@@ -1012,7 +1086,7 @@ qsv_status qsv_expval_grad(qsv_context* ctx, const qsv_program* prog, const doub
 
 qsv_status qsv_diag_copy(qsv_context* ctx, void* dst, const void* src, size_t bytes) {
   if (!ctx || !dst || !src || bytes % 16) return set_err(ctx, QSV_ERR_ARG, "bad copy arguments");
-  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(enter_device(ctx->device));
   HIP_TRY(launch_copy(dst, src, bytes, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return QSV_OK;

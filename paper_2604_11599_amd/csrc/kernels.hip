@@ -1417,6 +1417,9 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
     uint64_t* __restrict__ out_creg, uint32_t cw, uint8_t* __restrict__ out_rec, uint32_t rec_max) {
   extern __shared__ double2 tile[];
   __shared__ ShotCtl cs;
+  // algorithmic HBM bytes of the streamed (HBM-slot) states, summed over the
+  // launch for the profile: queue[2..3] as one 64-bit counter
+  unsigned long long* const hbm_bytes = reinterpret_cast<unsigned long long*>(queue + 2);
   __shared__ uint32_t item_s;
   __shared__ double red[4 * kSiteBins];
   __shared__ double bins[kSiteBins];
@@ -1434,7 +1437,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
     const double2* const init_state = reinterpret_cast<const double2*>(R.init_state);
     uint64_t* cr = out_creg + (uint64_t)item * cw;
     uint8_t* rec = out_rec + (uint64_t)item * rec_max;
-    for (uint32_t w = tid; w < cw; w += blockDim.x) cr[w] = 0;
+    for (uint32_t w = tid; w < cw; w += blockDim.x) cr[w] = R.init_creg ? R.init_creg[w] : 0ull;
     for (uint32_t w = tid; w < rec_max; w += blockDim.x) rec[w] = 0;
     if (tid == 0) {
       ShotCtl c;
@@ -1460,6 +1463,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
         for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) tile[swz(l)] = init_state[l];
       } else {
         for (uint64_t j = tid; j < dim; j += blockDim.x) slot[j] = init_state[j];
+        if (tid == 0) atomicAdd(hbm_bytes, 32ull * dim);
       }
     }
     __syncthreads();
@@ -1472,6 +1476,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
           for (uint32_t l = tid; l < (uint32_t)dim; l += blockDim.x) tile[swz(l)] = make_double2(l == 0 ? 1.0 : 0.0, 0.0);
         } else {
           for (uint64_t j = tid; j < dim; j += blockDim.x) slot[j] = make_double2(j == 0 ? 1.0 : 0.0, 0.0);
+          if (tid == 0) atomicAdd(hbm_bytes, 16ull * dim);
         }
         __syncthreads();
       } else if (stp.kind == 1) {  // gate pass
@@ -1519,6 +1524,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             cs.pend_mask = 0;
             cs.pend_val = 0;
             cs.pend_scale = 1.0;
+            atomicAdd(hbm_bytes, 32ull * dim);
           }
           __syncthreads();
         }
@@ -1551,6 +1557,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             for (int b = 0; b < kSiteBins; ++b) acc[b] += (bin == (uint32_t)b) ? p : 0.0;
           }
           wg_bins(acc, red, bins);
+          if (!resident && tid == 0) atomicAdd(hbm_bytes, 16ull * nfree);
         }
         if (tid == 0) {
           double hb[kSiteBins];
@@ -1595,7 +1602,7 @@ hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint3
                              double2* scratch, uint64_t slot_amps, uint32_t workgroups, ShotCtl* out_ctl,
                              uint64_t* out_creg, uint32_t cw, uint8_t* out_rec, uint32_t rec_max, hipStream_t st) {
   if (!n_items) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queue, 1u);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, queue, 4u);  // queue head and byte counter
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = sizeof(double2) << kResidentMaxBits;

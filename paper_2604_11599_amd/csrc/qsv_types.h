@@ -166,14 +166,16 @@ struct ReqDev {
   uint64_t seed, shot_offset;
   uint32_t n, n_steps, forced_len, item_begin;
   // Shot branching in a persistent launch: an item runs steps [step_begin,
-  // n_steps). With init_state set it starts from that state and control block
-  // (the deterministic prefix, computed once per request) instead of |0...0>;
-  // with state_out set (prefix items) it works in, and leaves its state in,
-  // that buffer instead of the workgroup's slot.
+  // n_steps). With init_state set it starts from that state, control block and
+  // classical bits (the deterministic prefix, computed once per request: it
+  // may assign bits before the first measurement) instead of |0...0>; with
+  // state_out set (prefix items) it works in, and leaves its state in, that
+  // buffer instead of the workgroup's slot.
   uint32_t step_begin, pad;
   double readout_err, reset_err;  // error rates of measurements (recorded bit) and resets
   const double* init_state;  // complex128 amplitudes (re, im)
   const ShotCtl* init_ctl;
+  const uint64_t* init_creg;  // [cw] classical bits at the end of the prefix
   double* state_out;         // complex128 amplitudes (re, im)
 };
 

@@ -2,8 +2,10 @@
 
 Mixed widths (resident states up to 12 qubits, HBM-slot states of 13..20
 qubits, a wider request that falls back to qsv_run_shots), uneven trajectory
-lengths, forced records, and the independence of a request's results from the
-rest of its batch.
+lengths, forced records, the shared deterministic prefix of 13..20-qubit
+requests with several shots, the tile-pass route of 13..20-qubit requests with
+at least 64 shots, and the independence of a request's results from the rest
+of its batch.
 """
 import sys
 
@@ -110,3 +112,38 @@ def test_batch_c3_with_mix_sampled(ctx):
     _check(main, res[0], 12, 1)
     for k, (m, r) in enumerate(zip(mix, res[1:])):
         _check(m, r, 3, 50 + k)
+
+
+def test_batch_prefix_keeps_assigned_bits(ctx):
+    """A streamed (13..20-qubit) request with 2..63 shots runs its deterministic
+    prefix once; bits assigned in that prefix, before the first measurement,
+    must reach every shot (one shot takes no prefix: both agree with the
+    oracle)."""
+    src = ("OPENQASM 3.0; qubit[14] q; bit[3] c; c = 2; h q[0]; ry(0.4) q[9]; cx q[0], q[13]; "
+           "c[0] = measure q[0]; if (c == 2) x q[1]; if (c == 3) ry(0.3) q[2]; c[2] = measure q[1];")
+    prog = ctx.load(src)
+    for shots in (8, 1):
+        res = ctx.run_batch([{"prog": prog, "shots": shots, "seed": 12}])[0]
+        _check(src, res, shots, 12)
+        bits = res.bits()
+        assert np.all(bits[:, 1] == 1) and np.all(bits[:, 2] == 1 - bits[:, 0])
+    lo = ctx.load(W.logic_program(5, 14, assign=True))
+    res = ctx.run_batch([{"prog": lo, "shots": 10, "seed": 3}])[0]
+    _check(W.logic_program(5, 14, assign=True), res, 10, 3)
+
+
+def test_batch_many_shot_route_matches_oracle(ctx):
+    """13..20-qubit requests with at least 64 shots leave the persistent launch
+    and run on the tile passes with shared trajectories inside qsv_run_batch:
+    every shot against the oracle, beside persistent requests of the batch."""
+    main = W.c3_program(3, n=16)
+    other = W.random_dynamic_program(321, 14, n_ops=50, final_measure=True)
+    small = W.c1_program(7)
+    reqs = [{"prog": ctx.load(main), "shots": 64, "seed": 5, "shot_offset": 100},
+            {"prog": ctx.load(other), "shots": 96, "seed": 6},
+            {"prog": ctx.load(small), "shots": 16, "seed": 7}]
+    say("batch with two >= 64-shot streamed requests")
+    res = ctx.run_batch(reqs)
+    _check(main, res[0], 64, 5, 100)
+    _check(other, res[1], 96, 6)
+    _check(small, res[2], 16, 7)

@@ -1,7 +1,12 @@
 """GPU checks at the benchmark's full size: 28 qubits (4 GiB per shot), 40
 brickwork layers, 16 shots in one launch as bench.py runs them.
 
-The oracle cannot simulate a 28-qubit shot of 40 layers in test time, so:
+The oracle cannot simulate a 28-qubit shot in test time, so:
+* the benchmark program itself (4 and 40 layers, with the 4-qubit site, the
+  0b1010 block and the if/else) is compared on a forced record with the
+  oracle's results stored by tests/golden/make_c2_28q.py (record, classical
+  bits, record probability, amplitudes at seeded indices, norm and a checksum
+  over every amplitude);
 * a block-separable 28-qubit brickwork (CX gates never cross block
   boundaries, so the state is a product of 7-qubit blocks) is simulated by the
   oracle block by block; sampled amplitudes, and every shot's measure-all record
@@ -12,6 +17,8 @@ The oracle cannot simulate a 28-qubit shot of 40 layers in test time, so:
   re-runs reproduce sampled shots bit for bit, a shot alone equals the same shot
   inside the batch, the trajectory-sharing path is bit-identical, norms stay 1.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -159,3 +166,50 @@ def test_complex64_28q(ctx):
     assert np.array_equal(b.creg, c.creg) and np.array_equal(b.record, c.record)
     assert np.array_equal(b.record_prob, c.record_prob)
 
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _checksum(psi, phi, chunk):
+    """sum_i psi_i conj(w_i), w_i = exp(2 pi i frac(i phi)), in the fixture's chunk order."""
+    acc = 0j
+    for s in range(0, psi.size, chunk):
+        i = np.arange(s, min(psi.size, s + chunk), dtype=np.float64)
+        w = np.exp(2j * np.pi * np.mod(i * phi, 1.0))
+        acc += complex(np.sum(psi[s:s + i.size] * np.conj(w)))
+    return acc
+
+
+@pytest.mark.parametrize("layers", [4, 40])
+def test_c2_28q_forced_record_matches_oracle(ctx, layers):
+    """The benchmark program at 28 qubits (entangled brickwork, the real site,
+    the 0b1010 block and the if/else) on one forced record, against the
+    oracle's stored run: classical bits and record bit-exact, the record's
+    probability within 1e-12, sampled amplitudes within 1e-10, norm and an
+    every-amplitude checksum within 1e-10 and 1e-9."""
+    path = os.path.join(GOLDEN, f"c2_28q_L{layers}_forced.json")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle fixture {os.path.basename(path)} not generated")
+    with open(path) as f:
+        d = json.load(f)
+    g = d["generator"]
+    src = W.c2_program(seed=g["seed"], n=g["n"], layers=g["layers"], final_measure=g["final_measure"])
+    say(f"c2 28q, {layers} layers: forced record {d['shot']['forced']}")
+    forced = np.array([d["shot"]["forced"]], dtype=np.uint8)
+    r = ctx.load(src).run_shots(1, seed=d["shot"]["seed"], shot_offset=d["shot"]["shot"], forced=forced,
+                                state_out=True)
+    assert r.shot_status[0] == 0
+    assert list(r.bits()[0]) == d["cbits"]
+    assert list(r.record[0]) == d["record"]
+    assert abs(r.record_prob[0] - d["record_prob"]) < PROB_TOL
+    st = r.state
+    idx = np.array(d["indices"], dtype=np.int64)
+    expect = np.array(d["amps"], dtype=np.float64).view(np.complex128).reshape(-1)
+    err = float(np.max(np.abs(st[idx] - expect)))
+    say("  max sampled amplitude error", err)
+    assert err < AMP_TOL
+    assert abs(np.vdot(st, st).real - d["norm"]) < AMP_TOL
+    cs = _checksum(st, d["checksum"]["phi"], d["checksum"]["chunk"])
+    say("  checksum error", abs(cs - complex(*d["checksum"]["value"])))
+    assert abs(cs - complex(*d["checksum"]["value"])) < 1e-9

@@ -570,3 +570,50 @@ def test_c4_full_size_energy_and_fd(ctx):
         tm[:, k] -= h
         fd = (prog.expval(tp, coeffs, codes) - prog.expval(tm, coeffs, codes)) / (2 * h)
         assert np.max(np.abs(fd - g[:2, k])) < 1e-7
+
+
+def test_c4_full_size_gradient_matches_oracle_adjoint(ctx):
+    """One full 240-entry gradient of the 20-qubit ansatz (the matrix-core
+    sweep over every pass at the benchmark's size) against the oracle's plain
+    adjoint sequence, and its energy, to 1e-10."""
+    src = W.c4_ansatz(20, 6)
+    coeffs, codes = W.c4_hamiltonian(seed=4, n=20, terms=60)
+    thetas = W.c4_thetas(seed=44, batch=64, n_params=240)
+    e, g = ctx.load(src).expval_grad(thetas, coeffs, codes)
+    for b in (0, 63):
+        say(f"c4 oracle adjoint of vector {b} (240 parameters, 20 qubits)")
+        eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
+        assert abs(e[b] - eo) < 1e-10
+        err = float(np.max(np.abs(g[b] - go)))
+        say("  max gradient error", err)
+        assert err < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# The headline workload's program (28-qubit brickwork with the 4-qubit site,
+# the 0b1010 block and the if/else) at widths and depths the oracle runs in
+# test time, in complex128.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,layers,sampled,records", [(14, 40, 12, range(16)), (20, 12, 3, (0b0101, 0b1010))])
+def test_c2_program_complex128_matches_oracle(ctx, n, layers, sampled, records):
+    """Sampled shots (with the final measure-all) shot by shot; forced records
+    (c[0..3]; at 14 qubits all 16) bit-exact with their probabilities and the
+    state before the measure-all within 1e-10 per amplitude."""
+    full = W.c2_program(seed=2, n=n, layers=layers, final_measure=True)
+    _check_shots(ctx, full, sampled, seed=5, state=False)
+    nomeas = W.c2_program(seed=2, n=n, layers=layers, final_measure=False)
+    prog = ctx.load(nomeas)
+    taken = 0
+    for rec in records:
+        forced = [(rec >> i) & 1 for i in range(4)]
+        o = sim.run_shot(nomeas, seed=9, shot=rec, forced=forced)
+        r = prog.run_shots(1, seed=9, shot_offset=rec, forced=np.array([forced], np.uint8), state_out=True)
+        assert r.shot_status[0] == o.status
+        if o.status:
+            continue
+        taken += 1
+        assert list(r.bits()[0]) == o.cbits
+        assert list(r.record[0]) == o.record
+        assert abs(r.record_prob[0] - o.record_prob) < PROB_TOL
+        assert np.max(np.abs(r.state - o.psi)) < AMP_TOL
+    assert taken >= 2
