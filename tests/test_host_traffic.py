@@ -4,7 +4,7 @@ import csv
 
 import pytest
 
-from paper_2604_11599_amd import traffic_summary as T
+import traffic_summary as T
 
 HEAD = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
 

@@ -5,13 +5,13 @@ calibration: it reads and writes exactly 4 GiB), then one step of the 28-qubit
 benchmark workload (16 shots) with the same launch configuration as bench.py;
 with --complex64 the step holds its state in complex64.
 
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- python3 -m paper_2604_11599_amd.traffic_probe
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- python3 traffic_probe.py
 """
 import ctypes as C
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 COPY_BYTES = 4 << 30
@@ -23,7 +23,7 @@ def main():
     import workloads as W
     from paper_2604_11599_amd import Context
     from paper_2604_11599_amd import _abi as A
-    from paper_2604_11599_amd.traffic_summary import kernel_hash
+    from traffic_summary import kernel_hash
     print(f"kernel_hash={kernel_hash()}", flush=True)
     ctx = Context(0)
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")

@@ -7,7 +7,7 @@ maps the same counter on a plain device copy of known size (4 GiB read, 4 GiB
 written) to its true byte count. Writes profiles/tile_pass_c2_traffic.json (read
 by bench.py while the kernel source hash matches) and a short text summary.
 
-    python -m paper_2604_11599_amd.traffic_summary [--complex64] FETCH_CSV WRITE_CSV PROBE_LOG [COMMAND]
+    python traffic_summary.py [--complex64] FETCH_CSV WRITE_CSV PROBE_LOG [COMMAND]
 
 --complex64: the probe ran with a complex64 state; the results go to
 profiles/tile_pass_c2_c64_traffic.json and tile_pass_c2_28q_c64_traffic.txt.
@@ -21,7 +21,7 @@ import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 4 << 30
 PASS_KERNEL = "k_tile_pass"
 COPY_KERNEL = "k_copy"
