@@ -215,6 +215,30 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
                          uint64_t n_shots, const qsv_run_opts* opts, qsv_shot_results* out);
 
 /* ------------------------------------------------------------------------ */
+/* Shots without device allocation                                           */
+/* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory: code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc. Same
+   arguments, results and errors as qsv_run_shots, and bit-identical results,
+   but every device buffer the call needs besides the caller's own (theta and
+   gate matrices, states, control blocks, classical bits, records, reduction
+   partials, forced outcomes, the state_out staging) is carved from a fixed
+   device array of QSV_NOALLOC_SCRATCH_BYTES per device. The library takes that
+   array's address when a context is created on the device; the array exists
+   from the moment the library is loaded there until the process ends. The
+   call makes no hipMalloc, hipFree or other allocating call, and records no
+   profiling events. Shots run in batches that fit the array (a 20-qubit
+   complex128 shot needs 16 MiB, plus 16 MiB of staging with state_out).
+   QSV_ERR_LIMIT when one shot of the program does not fit. Every call on a
+   device shares that device's array and leaves the last call's contents in it;
+   each call initialises what it reads. Calls that overlap on one device (host
+   threads driving contexts of the same device at once) race on the array and
+   must be serialised by the caller. */
+#define QSV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+qsv_status qsv_run_shots_noalloc(qsv_context* ctx, const qsv_program* prog, const double* theta,
+                                 uint64_t n_shots, const qsv_run_opts* opts, qsv_shot_results* out);
+
+/* ------------------------------------------------------------------------ */
 /* Batches of requests in one persistent launch                              */
 /* ------------------------------------------------------------------------ */
 /* A request: every shot of one loaded program with its own parameters, Philox

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_PARSE", -3: "QSV_ER
                 -4: "QSV_ERR_NOMEM", -5: "QSV_ERR_DEVICE", -6: "QSV_ERR_FORCED_ZERO_PROB",
                 -7: "QSV_ERR_LIMIT"}
 PLAN_MAX_STEPS, PLAN_MAX_GATES = 4096, 65536
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Config(C.Structure):
@@ -91,6 +92,8 @@ SIGNATURES = {
     "qsv_program_free": (None, [C.c_void_p]),
     "qsv_run_shots": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(RunOpts),
                                   C.POINTER(ShotResults)]),
+    "qsv_run_shots_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(RunOpts),
+                                          C.POINTER(ShotResults)]),
     "qsv_run_batch": (C.c_int32, [C.c_void_p, C.POINTER(Request), C.c_uint32]),
     "qsv_expval": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(PauliSum),
                                C.c_void_p]),

@@ -193,9 +193,10 @@ class Program:
         return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
-                  share=False, readout_error=0.0, reset_error=0.0, complex64=False):
+                  share=False, readout_error=0.0, reset_error=0.0, complex64=False, noalloc=False):
         """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses.
-        complex64: hold and evolve the state in single precision (QSV_RUN_COMPLEX64)."""
+        complex64: hold and evolve the state in single precision (QSV_RUN_COMPLEX64).
+        noalloc: call qsv_run_shots_noalloc (device scratch from the library's fixed array)."""
         lp = self.lowered
         cw = max(1, (lp.n_clbits + 63) // 64)
         mr = self.info.max_events
@@ -221,8 +222,8 @@ class Program:
                          (A.QSV_RUN_SHARE_TRAJ if share else 0) | (A.QSV_RUN_COMPLEX64 if complex64 else 0), _ptr(st),
                          float(readout_error), float(reset_error))
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
-        self.ctx.check(A.lib().qsv_run_shots(self.ctx.handle, self.handle, _ptr(th), n_shots,
-                                             C.byref(opts), C.byref(res)))
+        fn = A.lib().qsv_run_shots_noalloc if noalloc else A.lib().qsv_run_shots
+        self.ctx.check(fn(self.ctx.handle, self.handle, _ptr(th), n_shots, C.byref(opts), C.byref(res)))
         state = None if st is None else st.view(np.complex128).reshape(-1)
         return ShotResultArrays(creg, record[:, :mr], nev, prob, status, state, lp.n_clbits)
 

@@ -49,10 +49,13 @@ struct qsv_context {
   size_t ev_used = 0;
   std::vector<Rec> recs;
   qsv_profile prof{};
-  bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0; }
+  // set for the duration of a qsv_run_shots_noalloc call: scratch comes from
+  // the device's fixed array and no events are created or recorded
+  bool noalloc = false;
+  bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0 && !noalloc; }
   // the arena scratch is carved from in the current call, if any
-  uint8_t* call_arena() const { return arena; }
-  size_t call_arena_bytes() const { return arena_bytes; }
+  uint8_t* call_arena() const { return noalloc ? static_cast<uint8_t*>(noalloc_scratch(device)) : arena; }
+  size_t call_arena_bytes() const { return noalloc ? kNoAllocScratchBytes : arena_bytes; }
 };
 
 struct qsv_program {
@@ -133,6 +136,7 @@ struct Scratch {
       ctx->arena_top += bytes;
       return hipSuccess;
     }
+    if (ctx->noalloc) return hipErrorOutOfMemory;  // never allocate on that path
     if (ctx->slot == ctx->cache.size()) ctx->cache.push_back(DevBuf{});
     DevBuf& b = ctx->cache[ctx->slot++];
     if (b.bytes < bytes) {
@@ -277,6 +281,11 @@ qsv_status qsv_create(const qsv_config* cfg, qsv_context** out) {
   }
   if (cfg->device < 0 || cfg->device >= count) return QSV_ERR_ARG;
   if (enter_device(cfg->device) != hipSuccess) return QSV_ERR_DEVICE;
+  // this device's address of the fixed scratch array (no-allocation entry point)
+  if (noalloc_scratch_init(cfg->device) != hipSuccess) {
+    clear_error();
+    return QSV_ERR_DEVICE;
+  }
   if (cfg->stream) {
     ctx->stream = static_cast<hipStream_t>(cfg->stream);
   } else {
@@ -455,6 +464,11 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   size_t fixed = pl.gate_src.size() * kMatStride * 8 + prog->desc.n_params * 8 + (1u << 20) +
                  (opts->state_out ? dim * sizeof(double2) : 0);
   if (budget <= fixed + per_shot) {
+    if (ctx->noalloc)
+      return set_err(ctx, QSV_ERR_LIMIT,
+                     "one shot of this program needs " + std::to_string(fixed + per_shot) +
+                         " bytes of scratch; the no-allocation entry point has " +
+                         std::to_string(kNoAllocScratchBytes));
     if (in_arena) return set_err(ctx, QSV_ERR_NOMEM, "arena too small for one shot");
     budget = fixed + per_shot;  // try anyway; hipMalloc reports the failure
   }
@@ -675,6 +689,17 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     }
   }
   return QSV_OK;
+}
+
+qsv_status qsv_run_shots_noalloc(qsv_context* ctx, const qsv_program* prog, const double* theta,
+                                 uint64_t n_shots, const qsv_run_opts* opts, qsv_shot_results* out) {
+  if (!ctx) return QSV_ERR_ARG;
+  if (!noalloc_scratch(ctx->device))
+    return set_err(ctx, QSV_ERR_DEVICE, "no fixed scratch address for this device");
+  ctx->noalloc = true;
+  const qsv_status st = qsv_run_shots(ctx, prog, theta, n_shots, opts, out);
+  ctx->noalloc = false;
+  return st;
 }
 
 qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_reqs) {

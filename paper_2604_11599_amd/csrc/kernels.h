@@ -92,4 +92,14 @@ hipError_t launch_grad_chain(const double* dEda, uint32_t n_slots, const uint32_
                              const uint32_t* csr_slot, const double* csr_scale, uint32_t n_params,
                              uint32_t batch, double* grad, hipStream_t st);
 
+// Fixed device scratch of qsv_run_shots_noalloc: a file-scope device array of
+// kNoAllocScratchBytes per device. noalloc_scratch_init(device) must run with
+// `device` current (context creation does this); it looks up that device's
+// address of the array once. noalloc_scratch(device) returns it (null before
+// the init succeeded).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
+
 }  // namespace qsv

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -1609,6 +1610,44 @@ hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint3
   hipLaunchKernelGGL(k_persistent, dim3(workgroups), dim3(kTileThreads), lds, st, reqs, item_req, n_items, queue,
                      scratch, slot_amps, out_ctl, out_creg, cw, out_rec, rec_max);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the no-allocation entry point
+// ---------------------------------------------------------------------------
+// Every device the library runs on holds one copy of this array from the
+// moment the code object is loaded there until the process ends. In host code
+// the array's name is not a device address: each device's copy is reached only
+// through the address hipGetSymbolAddress returns with that device current,
+// taken once per device by noalloc_scratch_init (called when a context is
+// created) and handed to the kernels as an ordinary buffer argument.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current first
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace qsv
