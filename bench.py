@@ -72,8 +72,12 @@ def host_info():
 
 
 def _one_thread():
-    os.environ["OMP_NUM_THREADS"] = "1"
+    # every BLAS flavour to one thread before numpy loads its library (the
+    # environment may ask for more), then once more through threadpoolctl
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        os.environ[v] = "1"
     try:
+        import numpy  # noqa: F401
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:
@@ -122,10 +126,20 @@ def _w_adjoint(job):
     return 1, time.perf_counter() - t0
 
 
+def _w_lower(srcs):
+    """Host-side lowering of OpenQASM sources (front end only, no GPU)."""
+    from paper_2604_11599_amd.lower import lower
+    return [lower(s) for s in srcs]
+
+
 def _pool_map(fn, jobs, workers):
     import multiprocessing as mp
+    out = []
     with mp.get_context("spawn").Pool(workers, initializer=_one_thread) as pool:
-        return pool.map(fn, jobs, chunksize=1)
+        for k, r in enumerate(pool.imap(fn, jobs, chunksize=1)):
+            out.append(r)
+            log(f"  cpu worker {k + 1}/{len(jobs)} done: {r[0]} units in {r[1]:.1f} s")
+    return out
 
 
 def _rate(results):
@@ -332,6 +346,14 @@ def bench_shots(args):
     out["roofline"] = roof
     out["passes_per_shot"] = prog.info.n_passes
 
+    if args.workload == "c1":
+        # the same steps as one captured launch sequence replayed per call
+        prog.run_shots(shots, seed=999, graph=True)
+        dt_g = timed(lambda s: prog.run_shots(shots, seed=s, graph=True), args.steps, 0)
+        out["graph"] = {"value": shots * args.steps / dt_g, "unit": "shots/s", "ms_per_step": 1e3 * dt_g / args.steps,
+                        "note": "same shots, QSV_RUN_GRAPH: the call's launches captured once in a HIP graph and "
+                                "replayed (bit-identical results)"}
+        log("graph steps done")
     if args.workload == "c2":
         # the same steps with trajectory sharing (shots with equal measurement histories share one state)
         dt_sp = timed(lambda s: prog.run_shots(shots, seed=s, share=True), args.steps, 0)
@@ -392,6 +414,10 @@ def bench_batching(args):
     dt_plain = timed(lambda s: [r["prog"].run_shots(r["shots"], seed=r["seed"]) for r in reqs], args.steps, 0)
     dt_plain_sh = timed(lambda s: [r["prog"].run_shots(r["shots"], seed=r["seed"], share=True) for r in reqs],
                         args.steps, 0)
+    for r in reqs:
+        r["prog"].run_shots(r["shots"], seed=r["seed"], graph=True)  # capture
+    dt_plain_g = timed(lambda s: [r["prog"].run_shots(r["shots"], seed=r["seed"], graph=True) for r in reqs],
+                       args.steps, 0)
     t_main = timed(lambda s: main_prog.run_shots(4096, seed=1, share=True), args.steps, 0)
     out = base_line(args, shots * args.steps / dt, "shots/s", dt,
                     {"workload": "batching: 4096 shots of a 16-qubit RUS circuit (tile passes, shared "
@@ -413,6 +439,10 @@ def bench_batching(args):
                                        "ms_per_step": 1e3 * dt_plain_sh / args.steps,
                                        "note": "same, with trajectory sharing in every call (the gain of "
                                                "batching alone, sharing on both sides)"}
+    out["plain_per_program_graph"] = {"value": shots * args.steps / dt_plain_g, "unit": "shots/s",
+                                      "ms_per_step": 1e3 * dt_plain_g / args.steps,
+                                      "note": "same requests through qsv_run_shots with QSV_RUN_GRAPH: each program's "
+                                              "launch sequence captured once and replayed, every shot its own state"}
     out["main_request_alone_ms"] = 1e3 * t_main / args.steps
     ctx.close()
     if not args.no_cpu_baseline:
@@ -474,25 +504,41 @@ def bench_serving(args):
     import workloads as W
     from paper_2604_11599_amd import Context
     from paper_2604_11599_amd.serve import replay
+    from concurrent.futures import ThreadPoolExecutor
     ctx = Context(0, profile=True)
+    log("serving: generating the request trace")
     trace = W.c5_trace(seed=5, rate=args.rate, duration=args.window, pool=args.pool or None)
     vqe = ctx.load(W.c4_ansatz(20, 6))
-    loaded, reqs = {}, []
+    # every distinct circuit compiled before the replay: lowered in worker
+    # processes, planned and uploaded by forked contexts on host threads
+    t_c = time.perf_counter()
+    srcs = sorted({r["source"] for r in trace if r["kind"] != "vqe"})
+    workers = host_info()["usable_cpus"]
+    chunks = [srcs[k::workers] for k in range(workers)]
+    log(f"serving: lowering {len(srcs)} distinct circuits over {workers} processes")
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        lowered_chunks = pool.map(_w_lower, chunks)
+    forks = [ctx.fork() for _ in range(min(8, workers))]
+    jobs = [[] for _ in forks]
+    for k, (chunk, lps) in enumerate(zip(chunks, lowered_chunks)):
+        jobs[k % len(forks)] += list(zip(chunk, lps))
+    log(f"serving: planning and uploading on {len(forks)} forked contexts")
+    with ThreadPoolExecutor(len(forks)) as ex:
+        parts = list(ex.map(lambda fj: [(s, fj[0].load(lp)) for s, lp in fj[1]], zip(forks, jobs)))
+    loaded = {s: p for part in parts for s, p in part}
+    compile_s = time.perf_counter() - t_c
+    log(f"serving: {len(loaded)} circuits compiled in {compile_s:.1f} s")
+    reqs = []
     for r in trace:
         r = dict(r)
-        if r["kind"] == "vqe":
-            r["prog"] = vqe
-        else:
-            if r["source"] not in loaded:
-                loaded[r["source"]] = ctx.load(r["source"])
-            r["prog"] = loaded[r["source"]]
+        r["prog"] = vqe if r["kind"] == "vqe" else loaded[r["source"]]
         reqs.append(r)
     offered_shots = sum(r.get("shots", 0) for r in reqs)
     log(f"serving: {len(reqs)} requests over {args.window} s ({offered_shots} shots offered)")
-    ctx.profile_reset()
     out = replay(ctx, reqs, hbm_budget=int(args.hbm_gib * (1 << 30)), shots_per_tick=args.slice,
-                 drain_limit_s=args.drain, log=log)
-    prof = ctx.profile()
+                 drain_limit_s=args.drain, log=log, profile=True)
+    prof = out["profile"]
     lat = np.array(sorted(out["latency"].values())) if out["latency"] else np.zeros(1)
     res = {"metric": METRIC, "value": out["shots_done"] / out["elapsed"], "unit": "shots/s", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": 1e3 * out["elapsed"], "higher_is_better": True,
@@ -506,7 +552,8 @@ def bench_serving(args):
            "offered_req_per_s": len(reqs) / max(out["window"], 1e-9),
            "served_req_per_s": out["completed"] / out["elapsed"],
            "completed": out["completed"], "submitted": out["submitted"], "unfinished": out["unfinished"],
-           "backlog_at_window_end": out["backlog_at_window_end"], "ticks": out["ticks"]}
+           "backlog_at_window_end": out["backlog_at_window_end"], "ticks": out["ticks"],
+           "distinct_circuits": len(loaded), "compile_s_before_replay": compile_s}
     res["roofline"] = hbm_roof("k_tile_pass", prof["pass_uncond_launches"], prof["pass_uncond_ms"],
                                prof["pass_uncond_bytes"], None, None,
                                "32 B per amplitude per tile pass of the wide requests' states")

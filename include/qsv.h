@@ -57,22 +57,44 @@ typedef struct qsv_program qsv_program;
 /* ------------------------------------------------------------------------ */
 /* Context                                                                   */
 /* ------------------------------------------------------------------------ */
-enum { QSV_FLAG_PROFILE = 1u, QSV_FLAG_DEVICE_PTRS = 2u };
+/* QSV_FLAG_PROFILE: time every launch (qsv_profile_read).
+   QSV_FLAG_DEVICE_PTRS: theta, energy and grad of qsv_expval / qsv_expval_grad are
+   device pointers, read and written in the order of the context's stream.
+   QSV_FLAG_NULL_STREAM: with stream = NULL, order all work on the device's null
+   stream (the default stream of a framework that uses it) instead of a stream
+   of the library's own.
+   QSV_FLAG_TUNED_PLANS: qsv_load_program plans with the options the autotuner
+   found fastest for this device architecture and qubit count (complex128),
+   when it has measured them (qsv_autotune, qsv_tune_import); else defaults. */
+enum { QSV_FLAG_PROFILE = 1u, QSV_FLAG_DEVICE_PTRS = 2u, QSV_FLAG_NULL_STREAM = 4u, QSV_FLAG_TUNED_PLANS = 8u };
 
 typedef struct {
   int32_t device;      /* HIP device ordinal */
-  void* stream;        /* hipStream_t to order all work on; NULL = the library's own stream */
+  void* stream;        /* hipStream_t to order all work on; NULL = the library's own non-blocking
+                          stream, or the null stream with QSV_FLAG_NULL_STREAM */
   void* arena;         /* optional device buffer the library sub-allocates from; NULL = hipMalloc */
   size_t arena_bytes;  /* size of `arena` in bytes */
   uint32_t flags;      /* QSV_FLAG_* */
 } qsv_config;
 
-/* Creates a context on cfg->device. *out is owned by the caller; free with qsv_destroy
-   after every program loaded into it has been freed with qsv_program_free. */
+/* Creates a context on cfg->device: the GPU state-vector backend that executes
+   transpiled kernels (Background, CUDA-Q and high-performance simulation; the
+   paper's backends are a GPU and a CPU state-vector simulator, Experiments,
+   Implementation). *out is owned by the caller; free with qsv_destroy after
+   every program loaded into it has been freed with qsv_program_free.
+   Errors: QSV_ERR_ARG (null out, device ordinal out of range), QSV_ERR_DEVICE. */
 qsv_status qsv_create(const qsv_config* cfg, qsv_context** out);
 void qsv_destroy(qsv_context* ctx);
 /* Message of the last failed call on ctx; owned by ctx, valid until the next call. */
 const char* qsv_last_error(const qsv_context* ctx);
+/* A second context on parent's device with a non-blocking stream and scratch
+   of its own, driven from another host thread while the parent or other forks
+   work, so their device work overlaps on the GPU. A context and its forks form
+   one family: each may run (qsv_run_shots, qsv_run_batch, qsv_expval*) the
+   programs any of them loaded; a program stays owned by the context that
+   loaded it (replan and free it there, before that context is destroyed).
+   Destroy forks before the parent. Forks cannot be forked. */
+qsv_status qsv_context_fork(qsv_context* parent, qsv_context** out);
 
 /* ------------------------------------------------------------------------ */
 /* Lowered program (the instruction stream)                                  */
@@ -96,7 +118,9 @@ enum {
   QSV_OP_SETF = 4,     /* flag <- active && pred */
   QSV_OP_CLRF = 5,     /* if active: flag <- 0 */
   QSV_OP_SETB = 6,     /* if active: classical bit `cbit` <- 1 (classical assignment) */
-  QSV_OP_CLRB = 7      /* if active: classical bit `cbit` <- 0 */
+  QSV_OP_CLRB = 7,     /* if active: classical bit `cbit` <- 0 */
+  QSV_OP_CSTORE = 8    /* if active: classical bits [cbit, cbit + flag) <- the low `flag` bits of
+                          the classical expression that starts at code[pred] */
 };
 
 enum {
@@ -126,7 +150,9 @@ typedef struct {
   double offset[3];
 } qsv_instr;
 
-enum { QSV_CMP_EQ = 0, QSV_CMP_NE, QSV_CMP_LT, QSV_CMP_GT, QSV_CMP_LE, QSV_CMP_GE, QSV_CMP_TRUE };
+/* QSV_CMP_EXPR: the predicate holds iff the classical expression that starts
+   at code[value] is nonzero (lo and width unused). */
+enum { QSV_CMP_EQ = 0, QSV_CMP_NE, QSV_CMP_LT, QSV_CMP_GT, QSV_CMP_LE, QSV_CMP_GE, QSV_CMP_TRUE, QSV_CMP_EXPR };
 
 typedef struct {
   uint32_t lo, width;  /* classical bits [lo, lo + width) read as an unsigned integer (width <= 64) */
@@ -134,6 +160,34 @@ typedef struct {
   uint32_t cmp;        /* QSV_CMP_* ; QSV_CMP_TRUE ignores the bits */
   uint32_t reserved;
 } qsv_pred;
+
+/* Classical integer expressions (OpenQASM 3 classical types and operators on
+   registers and variables: the classical registers of the paper's symbol
+   table, Methodology, parsing and semantic analysis) as postfix code run on a
+   stack of at most 16 signed 64-bit values. An expression is a run of ops
+   ending with QSV_C_END, which yields the top of the stack. Every result wraps
+   to 64-bit two's complement; comparisons and logical operators give 0 or 1;
+   division truncates toward zero and x / 0 = x % 0 = 0; a shift by a count
+   outside 0..63 gives 0 (a right shift of a negative value then gives -1);
+   right shifts are arithmetic. */
+enum {
+  QSV_C_END = 0,
+  QSV_C_IMM,      /* push imm */
+  QSV_C_BITS,     /* push classical bits [lo, lo + width) as an integer (two's complement if sgn) */
+  QSV_C_NEG, QSV_C_NOT, QSV_C_LNOT,                       /* unary: -a, ~a, !a */
+  QSV_C_ADD, QSV_C_SUB, QSV_C_MUL, QSV_C_DIV, QSV_C_MOD,  /* binary: a op b, b on top */
+  QSV_C_AND, QSV_C_OR, QSV_C_XOR, QSV_C_SHL, QSV_C_SHR,
+  QSV_C_EQ, QSV_C_NE, QSV_C_LT, QSV_C_GT, QSV_C_LE, QSV_C_GE, QSV_C_LAND, QSV_C_LOR,
+  QSV_C_COUNT
+};
+
+typedef struct {
+  uint8_t op;          /* QSV_C_* */
+  uint8_t sgn;         /* QSV_C_BITS: 1 = signed */
+  uint16_t width;      /* QSV_C_BITS: 1..64 */
+  uint32_t lo;         /* QSV_C_BITS: first classical bit */
+  int64_t imm;         /* QSV_C_IMM */
+} qsv_cop;
 
 typedef struct {
   uint32_t n_qubits;   /* 1 .. 34 */
@@ -144,9 +198,18 @@ typedef struct {
   uint32_t reserved;
   const qsv_instr* instr;
   const qsv_pred* pred;
+  uint32_t n_code;     /* classical expression code (QSV_OP_CSTORE, QSV_CMP_EXPR) */
+  uint32_t reserved2;
+  const qsv_cop* code;
 } qsv_program_desc;
 
-/* Validates and deep-copies desc, plans the GPU passes and uploads them.
+/* Validates and deep-copies desc, plans the GPU passes and uploads them: the
+   compile step of compile-once, run-many (Background, parameter passing and
+   VQE; Methodology, handling runtime parameters: `input` angles stay symbolic
+   and are bound per call from theta). The stream itself is what the paper's
+   AST visitor emits, with gates, measurements, resets and the feed-forward of
+   `if` statements on bits and registers (Methodology, kernel generation via
+   AST visitor; transpiling dynamic control flow).
    Errors: QSV_ERR_ARG (malformed stream: qubit/bit/flag/predicate out of range),
    QSV_ERR_LIMIT (more than 34 qubits). *out is freed with qsv_program_free. */
 qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_program** out);
@@ -182,7 +245,20 @@ void qsv_program_free(qsv_program* prog);
    are bound in double precision and rounded once where they are applied.
    state_out is still complex128 (the complex64 amplitudes widened). Applies
    to qsv_run_shots only. */
-enum { QSV_RUN_SHARE_TRAJ = 1u, QSV_RUN_COMPLEX64 = 2u };
+/* QSV_RUN_GRAPH: the call's launch sequence (parameter binding, phase
+   composition, control-block set-up, every gate pass and measurement site,
+   state materialisation) is captured once in a HIP graph and replayed by later
+   calls of the same program with the same shot count, flags, forced-record
+   length, error rates and state_out request; seed, shot_offset, theta and the
+   forced outcomes may differ between replays (they are copied to the device
+   ahead of the replay). Results are bit-identical to the uncaptured call.
+   Applies when the call's shots fit one batch, without QSV_RUN_SHARE_TRAJ
+   (whose host decisions between launches cannot be captured), on a context
+   with a stream other than the null stream; elsewhere the flag is ignored.
+   One captured sequence is kept per program (a different call replaces it);
+   it refers to the context's scratch buffers and is captured again when those
+   have moved. */
+enum { QSV_RUN_SHARE_TRAJ = 1u, QSV_RUN_COMPLEX64 = 2u, QSV_RUN_GRAPH = 4u };
 
 typedef struct {
   uint64_t seed;         /* Philox key word 0 */
@@ -208,9 +284,17 @@ typedef struct {
   int32_t* shot_status;  /* [n_shots] QSV_OK or QSV_ERR_FORCED_ZERO_PROB, or NULL */
 } qsv_shot_results;
 
-/* Runs n_shots shots of prog with parameters theta[n_params] (host). Outputs are
-   host buffers. A shot whose forced outcome has probability < 2^-60 stops there
-   with shot_status QSV_ERR_FORCED_ZERO_PROB; the call still returns QSV_OK. */
+/* Runs n_shots shots of prog with parameters theta[n_params] (host): per shot,
+   gate application, mid-circuit measurement (outcome drawn from the shot's
+   stream, collapse, renormalisation), reset and classical feed-forward, as in
+   the dynamic circuits the paper validates over repeated shots (Background,
+   dynamic circuit testing; Experiments, dynamic control flow validation: the
+   conditional reset run over 1000 and 10^4 shots). Outputs are host buffers.
+   A shot whose forced outcome has probability < 2^-60 stops there with
+   shot_status QSV_ERR_FORCED_ZERO_PROB; the call still returns QSV_OK.
+   Errors: QSV_ERR_ARG (null program/creg, foreign program, theta missing,
+   forced_len without forced, error rates outside [0, 1)), QSV_ERR_NOMEM,
+   QSV_ERR_DEVICE. */
 qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double* theta,
                          uint64_t n_shots, const qsv_run_opts* opts, qsv_shot_results* out);
 
@@ -249,10 +333,13 @@ qsv_status qsv_run_shots_noalloc(qsv_context* ctx, const qsv_program* prog, cons
    branches) share the GPU. States of up to 12 qubits stay in LDS for the whole
    program; states of 13..20 qubits live in a per-workgroup HBM slot; requests
    with more qubits, and requests of 13..20 qubits with at least 64 shots, run
-   through qsv_run_shots (shots sharing the deterministic prefix) after the
-   launch. The path is chosen from the request alone. Every item is
+   through qsv_run_shots with shared trajectories after the launch. The path
+   is chosen from the request alone. Every item is
    computed the same way whatever else is in the batch, so a request's results
-   do not depend on the batch it is part of. Errors: QSV_ERR_ARG for a null or
+   do not depend on the batch it is part of. The paper runs whole suites of
+   circuits of 2..20 qubits and the dynamic circuits over many shots
+   (Experiments, benchmark suites; dynamic control flow validation); running
+   them as one launch is this library's. Errors: QSV_ERR_ARG for a null or
    foreign program or missing outputs, QSV_ERR_NOMEM when the slots do not fit. */
 typedef struct {
   const qsv_program* prog;
@@ -274,31 +361,58 @@ typedef struct {
   const uint8_t* pauli;  /* [n_terms][n_qubits] 0 = I, 1 = X, 2 = Y, 3 = Z */
 } qsv_pauli_sum;
 
-/* energy[b] = sum_j coeff_j Re <psi(theta_b)| P_j |psi(theta_b)> for b < batch.
-   theta is [batch][n_params]. With QSV_FLAG_DEVICE_PTRS set on the context,
-   theta and energy are device pointers ordered on the context stream. */
+/* energy[b] = sum_j coeff_j Re <psi(theta_b)| P_j |psi(theta_b)> for b < batch:
+   the energy expectation value of the paper's VQE runs, for many parameter
+   vectors of one compiled ansatz (Background, parameter passing and VQE;
+   Methodology, validation framework: energies swept over input parameters;
+   Experiments, hybrid compilation efficiency). theta is [batch][n_params]
+   (row-major); coeff and pauli stay host arrays. With QSV_FLAG_DEVICE_PTRS set
+   on the context, theta and energy are device pointers ordered on the context
+   stream. Errors: QSV_ERR_ARG (null arguments, Pauli code > 3),
+   QSV_ERR_UNSUPPORTED (the program measures, resets or branches). */
 qsv_status qsv_expval(qsv_context* ctx, const qsv_program* prog, const double* theta, uint32_t batch,
                       const qsv_pauli_sum* h, double* energy);
 
-/* As qsv_expval, plus grad[b][k] = dE_b / dtheta_b[k] by the adjoint method. */
+/* As qsv_expval_grad with one Hamiltonian per parameter vector: h is [batch]
+   (h[b] for theta row b), so requests with different Hamiltonians share one
+   sweep over the batch. */
+qsv_status qsv_expval_grad_each(qsv_context* ctx, const qsv_program* prog, const double* theta,
+                                uint32_t batch, const qsv_pauli_sum* h, double* energy, double* grad);
+
+/* As qsv_expval, plus grad[b][k] = dE_b / dtheta_b[k] ([batch][n_params]) by the
+   adjoint method: one backward sweep that undoes the gates on psi and on
+   lambda = H psi and reads each angle's derivative on the way. The paper
+   binds the parameters; the gradient is this library's addition for the
+   optimiser loop around them. With QSV_FLAG_DEVICE_PTRS, grad is a device
+   pointer too. */
 qsv_status qsv_expval_grad(qsv_context* ctx, const qsv_program* prog, const double* theta,
                            uint32_t batch, const qsv_pauli_sum* h, double* energy, double* grad);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of requests                                  */
 /* ------------------------------------------------------------------------ */
-/* A server owns a queue of requests. qsv_server_step runs one scheduling tick:
-   waiting requests are admitted in arrival order while the HBM footprint of
-   the admitted set stays within the budget (footprint of a shots request =
-   its per-tick shot slice x 16 x 2^n bytes, where the slice is shots_per_tick
-   for n <= 16 and shots_per_tick / 2^(n-16) (at least 1) above; of an
-   energy+gradient request 2 x 16 x 2^n bytes); then one slice of every admitted shots request runs in
-   a single persistent launch (qsv_run_batch) and every admitted
-   energy+gradient request is evaluated; requests that finish are retired and
-   their memory is released, so requests that arrive while others run join at
-   the next tick. A shot's results depend only on (program, theta, seed, shot
-   index), never on the other requests. Programs must stay loaded until their
-   requests are fetched. */
+/* Serving is this library's addition (the paper runs one program at a time).
+   A server owns a queue of requests and three worker threads ("lanes"), each
+   driving a context forked from ctx, so their device work overlaps on the GPU:
+   the persistent lane runs shots requests whose states fit the persistent
+   launch (up to 20 qubits with fewer than 64 shots, or up to 12 qubits), one
+   slice of shots of every request it holds per launch (shots_per_tick shots
+   for up to 16 qubits, all shots above), requests handed over meanwhile
+   joining the next launch; the wide lane runs the other shots requests on the
+   tile passes with shared trajectories, one at a time in arrival order; the
+   energy lane runs energy+gradient requests, one sweep per program over every
+   vector it holds (qsv_expval_grad_each). qsv_server_step retires finished
+   requests (their memory returns to the budget) and admits waiting requests
+   in arrival order while the HBM footprint of the admitted set stays within
+   the budget (a shots request is charged 16 x 2^n bytes per state resident at
+   once: its slice in the persistent lane, at most 16 shared histories in the
+   wide lane; an energy request 2 x 16 x 2^n bytes; a request larger than the
+   whole budget is admitted alone); it never waits for device work, so
+   requests that arrive while others run are admitted at the next step. A
+   request's results depend only on (program, theta, seed, shot index) or
+   (program, theta, Hamiltonian), never on the other requests. Programs must
+   stay loaded until their requests are fetched; server calls come from one
+   host thread (the lanes never call back). */
 typedef struct qsv_server qsv_server;
 
 qsv_status qsv_server_create(qsv_context* ctx, size_t hbm_budget, uint32_t shots_per_tick, qsv_server** out);
@@ -309,7 +423,8 @@ qsv_status qsv_submit(qsv_server* srv, const qsv_program* prog, const double* th
 /* Energy + gradient request for one parameter vector (theta and h are copied). */
 qsv_status qsv_submit_expval_grad(qsv_server* srv, const qsv_program* prog, const double* theta,
                                   const qsv_pauli_sum* h, uint64_t* ticket);
-/* One tick; reports how many requests are admitted (running) and waiting. */
+/* Retires finished requests and admits waiting ones (non-blocking); reports how
+   many are admitted and not yet retired (running) and how many wait. */
 qsv_status qsv_server_step(qsv_server* srv, uint32_t* n_running, uint32_t* n_waiting);
 /* done = 1 once the request has finished (its results can be fetched). */
 qsv_status qsv_poll(qsv_server* srv, uint64_t ticket, int32_t* done);
@@ -317,6 +432,58 @@ qsv_status qsv_poll(qsv_server* srv, uint64_t ticket, int32_t* done);
    energy[1] and grad[n_params]) and forgets the request. */
 qsv_status qsv_fetch_shots(qsv_server* srv, uint64_t ticket, qsv_shot_results* out);
 qsv_status qsv_fetch_expval_grad(qsv_server* srv, uint64_t ticket, double* energy, double* grad);
+
+/* ------------------------------------------------------------------------ */
+/* Plan autotuning                                                           */
+/* ------------------------------------------------------------------------ */
+/* The planner's tunable choices (this library's; the paper leaves execution to
+   its backends). tile_bits: qubits of the largest amplitude tile a gate pass
+   holds in LDS (1..12); low_bits: qubits 0..low_bits-1 that every tile holds,
+   so each global access is a contiguous run of 2^low_bits amplitudes;
+   dense_min_cost: a register phase whose gates cost at least this much (a
+   dense one-qubit gate costs 1) is composed into one 16x16 product applied on
+   the matrix cores, cheaper ones apply gate by gate (0: never). */
+typedef struct {
+  uint32_t tile_bits, low_bits;
+  double dense_min_cost;
+} qsv_plan_options;
+
+typedef struct {
+  qsv_plan_options best;   /* the options installed in the program */
+  qsv_plan_options deflt;  /* the default options (the first candidate) */
+  double best_ms;          /* one call of the measured shape with best, wall time */
+  double default_ms;       /* the same with the default options */
+  uint32_t n_candidates;   /* plans measured */
+  uint32_t reserved;
+  char arch[64];           /* device architecture name the result is cached under */
+} qsv_tune_report;
+
+/* Plans prog with every candidate (tile_bits 12/11/10, low_bits 4/5,
+   dense_min_cost 0.5/0/3, the default first), times qsv_run_shots(n_shots,
+   run_flags & (SHARE_TRAJ | COMPLEX64)) on the device for each (one warm-up,
+   best of two), installs the fastest plan in prog and records it in the
+   process-wide cache under (architecture, n_qubits, precision). Every plan
+   computes the same results up to floating-point rounding order. Takes about
+   18 x 3 calls of that shape. Errors as qsv_run_shots. */
+qsv_status qsv_autotune(qsv_context* ctx, qsv_program* prog, const double* theta, uint64_t n_shots,
+                        uint32_t run_flags, qsv_tune_report* out);
+/* The options prog's current plan was built with. */
+qsv_status qsv_program_plan_get(const qsv_program* prog, qsv_plan_options* out);
+/* Re-plans prog with explicit options (QSV_ERR_ARG when out of range). */
+qsv_status qsv_program_replan(qsv_context* ctx, qsv_program* prog, const qsv_plan_options* opts);
+/* Cached options for (ctx's device architecture, n_qubits, run_flags' precision):
+   *found = 1 and *out set, or *found = 0 and *out the defaults. */
+qsv_status qsv_tune_lookup(qsv_context* ctx, uint32_t n_qubits, uint32_t run_flags, qsv_plan_options* out,
+                           int32_t* found);
+/* The cache as text, one entry per line:
+   "<arch> <n_qubits> <c64|c128> <tile_bits> <low_bits> <dense_min_cost> <best_ms> <default_ms>".
+   *len = bytes needed including the terminating NUL; buf may be NULL to query;
+   QSV_ERR_LIMIT when cap is too small. Host only. */
+qsv_status qsv_tune_export(char* buf, size_t cap, size_t* len);
+/* Adds entries in that format (later entries replace equal keys); lines that
+   start with '#' are skipped. QSV_ERR_ARG on a malformed line (nothing is
+   added then). Host only. */
+qsv_status qsv_tune_import(const char* text);
 
 /* ------------------------------------------------------------------------ */
 /* Profiling (contexts created with QSV_FLAG_PROFILE)                        */
@@ -358,6 +525,9 @@ typedef struct {
    created without QSV_FLAG_PROFILE. */
 qsv_status qsv_profile_read(qsv_context* ctx, qsv_profile* out);
 qsv_status qsv_profile_reset(qsv_context* ctx);
+/* Sum of a server's lane profiles (server on a context created with
+   QSV_FLAG_PROFILE; the lanes' contexts inherit the flag). */
+qsv_status qsv_server_profile(qsv_server* srv, qsv_profile* out);
 
 #ifdef __cplusplus
 }

@@ -9,18 +9,22 @@ builds such an AST as plain tuples for the tree-walking interpreter in
 ``oracle.sim``:
 
   ('qubit', name, size|None)        ('bit', name, size|None)
+  ('var', name, width, signed)      classical integer variable (uint/int/bool)
   ('input', name, size|None)        ('const', name, expr)
   ('gatedef', name, params, qargs, body)
   ('gate', name, [expr], [qref], mods)    ('measure', qref, cref|None)
-  ('assign', cref, ('value', expr) | ('cond', cond))   classical assignment
+  ('assign', cref, cexpr)           classical assignment (also variable initialisers)
   ('reset', qref)                   ('barrier',)
-  ('if', cond, then_body, else_body) ('for', var, start, step, stop, body)
+  ('if', cexpr, then_body, else_body) ('for', var, start, step, stop, body)
   ('break',)                        ('continue',)
   qref/cref = ('ref', name, index_expr|None)
-  cond = ('truth', ref) | ('not', cond) | ('cmp', op, ref, expr)
-       | ('and', cond, cond) | ('or', cond, cond)     (C precedence: ! over && over ||)
-  expr = ('num', v) | ('id', name) | ('index', name, expr) | ('neg', e)
-       | ('bin', op, a, b) | ('call', fn, [e])
+  expr  = ('num', v) | ('id', name) | ('index', name, expr) | ('neg', e)
+        | ('bin', op, a, b) | ('call', fn, [e])             (gate angles, constants)
+  cexpr = ('cnum', v) | ('cref', ref) | ('cun', op, e) | ('cbin', op, a, b)
+          classical integer expressions and conditions, C precedence
+          (|| < && < | < ^ < & < == != < relational < shifts < + - < * / % < unary),
+          except that `!` applies to the whole comparison after it
+          (`!c == 1` is `!(c == 1)`)
 """
 import math
 import re
@@ -30,7 +34,7 @@ _TOKEN = re.compile(r"""
   | (?P<num>0b[01_]+|0x[0-9a-fA-F_]+|(?:\d+\.\d*|\.\d+|\d+)(?:[eE][+-]?\d+)?)
   | (?P<str>"[^"]*")
   | (?P<id>[A-Za-z_θπτφλ][A-Za-z0-9_θπτφλ]*)
-  | (?P<op>->|==|!=|<=|>=|&&|\|\||\*\*|[-+*/%()\[\]{};,:=<>!@])
+  | (?P<op>->|<<=|>>=|==|!=|<=|>=|&&|\|\||\*\*|<<|>>|\+=|-=|\*=|/=|%=|&=|\|=|\^=|[-+*/%()\[\]{};,:=<>!@&|^~])
 """, re.S | re.X)
 
 
@@ -128,6 +132,8 @@ class _Parser:
                 return None
             if val in ("qubit", "bit"):
                 return self.declaration()
+            if val in ("uint", "int", "bool"):
+                return self.var_decl()
             if val in ("qreg", "creg"):
                 self.next()
                 name = self.ident()
@@ -180,8 +186,8 @@ class _Parser:
                 return ("continue",)
             if val == "while":
                 raise QasmSyntaxError("while loops are unbounded and not supported")
-            # assignment "c[i] = measure q[j];" or gate call
-            if self.peek(1)[1] in ("=", "["):
+            # assignment "c[i] = measure q[j];", classical assignment, or gate call
+            if self.peek(1)[1] in ("=", "[") or self.peek(1)[1] in _COMPOUND:
                 save = self.i
                 target = self.ref()
                 if self.accept("="):
@@ -189,14 +195,15 @@ class _Parser:
                         q = self.ref()
                         self.expect(";")
                         return ("measure", q, target)
-                    # classical assignment: an integer (literal or constant
-                    # expression starting with a number) or a condition
-                    if self.peek()[0] == "num" or self.peek()[1] == "-":
-                        rhs = ("value", self.expr())
-                    else:
-                        rhs = ("cond", self.cond())
+                    rhs = self.cexpr()
                     self.expect(";")
                     return ("assign", target, rhs)
+                op = self.peek()[1]
+                if op in _COMPOUND:
+                    self.next()
+                    rhs = self.cexpr()
+                    self.expect(";")
+                    return ("assign", target, ("cbin", _COMPOUND[op], ("cref", target), rhs))
                 self.i = save
             return self.gate_call()
         raise QasmSyntaxError(f"unexpected token {val!r}")
@@ -230,6 +237,64 @@ class _Parser:
             return [("bit", name, size), ("measure", q, ("ref", name, None))]
         self.expect(";")
         return (kind, name, size)
+
+    def var_decl(self):
+        """uint[n] x; int[n] x; uint x; int x (32 bits); bool b; each with an
+        optional initialiser."""
+        kind = self.ident()
+        width = 1 if kind == "bool" else 32
+        if kind != "bool" and self.accept("["):
+            width = self.const_int()
+            self.expect("]")
+        if not 1 <= width <= 64:
+            raise QasmSyntaxError("classical variables hold 1..64 bits")
+        name = self.ident()
+        out = [("var", name, width, kind == "int")]
+        if self.accept("="):
+            out.append(("assign", ("ref", name, None), self.cexpr()))
+        self.expect(";")
+        return out
+
+    # -- classical integer expressions and conditions (C precedence) --
+    _CPREC = [("||",), ("&&",), ("|",), ("^",), ("&",), ("==", "!="), ("<", ">", "<=", ">="), ("<<", ">>"),
+              ("+", "-"), ("*", "/", "%")]
+
+    def cexpr(self, level=0):
+        if level == len(self._CPREC):
+            return self.cunary()
+        lhs = self.cexpr(level + 1)
+        while self.peek()[0] == "op" and self.peek()[1] in self._CPREC[level]:
+            op = self.next()[1]
+            lhs = ("cbin", op, lhs, self.cexpr(level + 1))
+        return lhs
+
+    def cunary(self):
+        if self.accept("!"):
+            # `!` takes the whole comparison after it
+            return ("cun", "!", self.cexpr(5))
+        if self.accept("~"):
+            return ("cun", "~", self.cunary())
+        if self.accept("-"):
+            return ("cun", "-", self.cunary())
+        if self.accept("+"):
+            return self.cunary()
+        kind, val = self.peek()
+        if kind == "num":
+            self.next()
+            iv = _parse_int_literal(val)
+            if iv is None:
+                if not re.fullmatch(r"\d+", val):
+                    raise QasmSyntaxError(f"classical expressions are integers, got {val}")
+                iv = int(val)
+            return ("cnum", iv)
+        if self.accept("("):
+            e = self.cexpr()
+            self.expect(")")
+            return e
+        if kind == "id" and val in ("true", "false"):
+            self.next()
+            return ("cnum", 1 if val == "true" else 0)
+        return ("cref", self.ref())
 
     def input_decl(self):
         self.expect("input")
@@ -296,42 +361,13 @@ class _Parser:
     def if_stmt(self):
         self.expect("if")
         self.expect("(")
-        cond = self.cond()
+        cond = self.cexpr()
         self.expect(")")
         then_body = self.block_or_statement()
         else_body = []
         if self.accept("else"):
             else_body = self.block_or_statement()
         return ("if", cond, then_body, else_body)
-
-    def cond(self):
-        terms = [self.cond_conj()]
-        while self.accept("||"):
-            terms.append(self.cond_conj())
-        c = terms[0]
-        for t in terms[1:]:
-            c = ("or", c, t)
-        return c
-
-    def cond_conj(self):
-        c = self.cond_atom()
-        while self.accept("&&"):
-            c = ("and", c, self.cond_atom())
-        return c
-
-    def cond_atom(self):
-        if self.accept("!"):
-            return ("not", self.cond_atom())
-        if self.accept("("):
-            c = self.cond()
-            self.expect(")")
-            return c
-        r = self.ref()
-        op = self.peek()[1]
-        if op in ("==", "!=", "<", ">", "<=", ">="):
-            self.next()
-            return ("cmp", op, r, self.expr())
-        return ("truth", r)
 
     def for_stmt(self):
         self.expect("for")
@@ -406,6 +442,10 @@ class _Parser:
                 return ("index", val, e)
             return ("id", val)
         raise QasmSyntaxError(f"unexpected token {val!r} in expression")
+
+
+_COMPOUND = {"+=": "+", "-=": "-", "*=": "*", "/=": "/", "%=": "%", "&=": "&", "|=": "|", "^=": "^",
+             "<<=": "<<", ">>=": ">>"}
 
 
 def _flatten(body):

@@ -172,6 +172,7 @@ class Program:
     def __init__(self, source):
         self.ast = parse(source) if isinstance(source, str) else source
         self.qregs, self.cregs, self.inputs = {}, {}, {}
+        self.signed = {}  # classical register or variable name -> read as two's complement
         self.consts, self.gatedefs = {}, {}
         self.n_qubits = self.n_clbits = self.n_params = 0
         self.body = []
@@ -184,7 +185,13 @@ class Program:
             elif kind == "bit":
                 size = 1 if st[2] is None else st[2]
                 self.cregs[st[1]] = (self.n_clbits, size, st[2] is None)
+                self.signed[st[1]] = False
                 self.n_clbits += size
+            elif kind == "var":
+                # classical integer variables are bits too, in declaration order
+                self.cregs[st[1]] = (self.n_clbits, st[2], False)
+                self.signed[st[1]] = st[3]
+                self.n_clbits += st[2]
             elif kind == "input":
                 size = 1 if st[2] is None else st[2]
                 self.inputs[st[1]] = (self.n_params, size, st[2] is None)
@@ -441,49 +448,65 @@ class Interpreter:
             raise OracleError(f"unsupported statement {k}")
 
     def cond(self, c, env):
-        k = c[0]
-        if k == "not":
-            return not self.cond(c[1], env)
-        if k == "and":  # both sides read the bits as they are when the if executes
-            return self.cond(c[1], env) and self.cond(c[2], env)
-        if k == "or":
-            return self.cond(c[1], env) or self.cond(c[2], env)
-        if k == "truth":
-            return self.reg_value(c[1], env) != 0
-        if k == "cmp":
-            lhs = self.reg_value(c[2], env)
-            rhs = int(round(_val(self.eval(c[3], env))))
-            return {"==": lhs == rhs, "!=": lhs != rhs, "<": lhs < rhs, ">": lhs > rhs,
-                    "<=": lhs <= rhs, ">=": lhs >= rhs}[c[1]]
-        raise OracleError(f"bad condition {c}")
+        """An if condition: the classical expression read when the if executes, true iff nonzero."""
+        return self.ceval(c, env) != 0
+
+    def ceval(self, e, env):
+        """Classical integer expression in 64-bit two's complement: every
+        intermediate result wraps to a signed 64-bit value; comparisons and
+        logical operators give 0 or 1; division truncates toward zero and
+        x / 0 = x % 0 = 0; a shift by a count outside 0..63 gives 0 (a right
+        shift of a negative value then gives -1); right shifts are arithmetic.
+        A register, a variable or a bit reads its bits as an unsigned integer,
+        or as two's complement for int variables; a constant or loop variable
+        reads its value."""
+        k = e[0]
+        if k == "cnum":
+            return _wrap64(e[1])
+        if k == "cref":
+            ref = e[1]
+            name = ref[1]
+            if name in self.prog.cregs:
+                bits = self.clbits_of(ref, env)
+                v = sum(self.cbits[b] << i for i, b in enumerate(bits))
+                if self.prog.signed.get(name) and ref[2] is None and v >> (len(bits) - 1):
+                    v -= 1 << len(bits)
+                return _wrap64(v)
+            if ref[2] is not None:
+                raise OracleError(f"cannot index {name} in a classical expression")
+            return _wrap64(int(round(_val(self.eval(("id", name), env)))))
+        if k == "cun":
+            a = self.ceval(e[2], env)
+            return {"!": int(a == 0), "~": _wrap64(~a), "-": _wrap64(-a)}[e[1]]
+        op, a, b = e[1], self.ceval(e[2], env), self.ceval(e[3], env)
+        if op in ("+", "-", "*", "&", "|", "^"):
+            return _wrap64({"+": a + b, "-": a - b, "*": a * b, "&": a & b, "|": a | b, "^": a ^ b}[op])
+        if op in ("/", "%"):
+            if b == 0:
+                return 0
+            q = abs(a) // abs(b) * (1 if (a < 0) == (b < 0) else -1)
+            return _wrap64(q if op == "/" else a - q * b)
+        if op == "<<":
+            return _wrap64(a << b) if 0 <= b < 64 else 0
+        if op == ">>":
+            return a >> b if 0 <= b < 64 else (-1 if a < 0 else 0)
+        if op in ("==", "!=", "<", ">", "<=", ">="):
+            return int({"==": a == b, "!=": a != b, "<": a < b, ">": a > b, "<=": a <= b, ">=": a >= b}[op])
+        if op == "&&":
+            return int(a != 0 and b != 0)
+        if op == "||":
+            return int(a != 0 or b != 0)
+        raise OracleError(f"bad classical expression {e}")
 
     def assign(self, target, rhs, env):
-        """Classical assignment (OpenQASM 3): a register or bit takes an
-        integer's bits (bit i of the register <- bit i of the value), another
-        register of the same width is copied, or one bit takes the truth value
-        of a condition. The right side is read completely before any bit is
-        written."""
+        """Classical assignment (OpenQASM 3): the target bit, register or
+        variable takes the low bits of the right side's 64-bit two's-complement
+        value (bit i of the target <- bit i of the value). The right side is
+        read completely before any bit is written."""
         bits = self.clbits_of(target, env)
-        value = None
-        if rhs[0] == "value":
-            value = int(round(_val(self.eval(rhs[1], env))))
-        elif rhs[1][0] == "truth" and rhs[1][1][1] not in self.prog.cregs:
-            value = int(round(_val(self.eval(("id", rhs[1][1][1]), env))))  # a constant or loop variable
-        if value is not None:
-            if value < 0:
-                raise OracleError("negative value assigned to classical bits")
-            new = [(value >> i) & 1 for i in range(len(bits))]
-        elif rhs[1][0] == "truth" and len(bits) > 1:
-            src = self.clbits_of(rhs[1][1], env)
-            if len(src) != len(bits):
-                raise OracleError("register copy between registers of different widths")
-            new = [self.cbits[b] for b in src]
-        else:
-            if len(bits) != 1:
-                raise OracleError("a condition is assigned to one bit")
-            new = [int(self.cond(rhs[1], env))]
-        for b, v in zip(bits, new):
-            self.cbits[b] = v
+        value = self.ceval(rhs, env)
+        for i, b in enumerate(bits):
+            self.cbits[b] = (value >> i) & 1
 
     def reg_value(self, ref, env):
         bits = self.clbits_of(ref, env)
@@ -650,6 +673,12 @@ class Interpreter:
 
 def _val(x):
     return x.v if isinstance(x, Lin) else float(x)
+
+
+def _wrap64(v):
+    """v as a signed 64-bit two's-complement value."""
+    v = int(v) & 0xFFFFFFFFFFFFFFFF
+    return v - (1 << 64) if v >> 63 else v
 
 
 # --------------------------------------------------------------------------

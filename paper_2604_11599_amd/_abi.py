@@ -12,9 +12,10 @@ LIB_PATH = os.path.join(_HERE, "libqsv.so")
 
 QSV_OK, QSV_ERR_ARG, QSV_ERR_PARSE, QSV_ERR_UNSUPPORTED = 0, -1, -2, -3
 QSV_ERR_NOMEM, QSV_ERR_DEVICE, QSV_ERR_FORCED_ZERO_PROB, QSV_ERR_LIMIT = -4, -5, -6, -7
-QSV_FLAG_PROFILE, QSV_FLAG_DEVICE_PTRS = 1, 2
+QSV_FLAG_PROFILE, QSV_FLAG_DEVICE_PTRS, QSV_FLAG_NULL_STREAM, QSV_FLAG_TUNED_PLANS = 1, 2, 4, 8
 QSV_RUN_SHARE_TRAJ = 1
 QSV_RUN_COMPLEX64 = 2
+QSV_RUN_GRAPH = 4
 STATUS_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_PARSE", -3: "QSV_ERR_UNSUPPORTED",
                 -4: "QSV_ERR_NOMEM", -5: "QSV_ERR_DEVICE", -6: "QSV_ERR_FORCED_ZERO_PROB",
                 -7: "QSV_ERR_LIMIT"}
@@ -30,7 +31,8 @@ class Config(C.Structure):
 class ProgramDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_uint32), ("n_clbits", C.c_uint32), ("n_params", C.c_uint32),
                 ("n_instr", C.c_uint32), ("n_pred", C.c_uint32), ("reserved", C.c_uint32),
-                ("instr", C.c_void_p), ("pred", C.c_void_p)]
+                ("instr", C.c_void_p), ("pred", C.c_void_p), ("n_code", C.c_uint32), ("reserved2", C.c_uint32),
+                ("code", C.c_void_p)]
 
 
 class ProgramInfo(C.Structure):
@@ -68,6 +70,15 @@ class PlanStats(C.Structure):
                 ("step_count", C.c_uint32 * PLAN_MAX_STEPS), ("gate_instr", C.c_uint32 * PLAN_MAX_GATES),
                 ("gate_regs", C.c_uint64 * PLAN_MAX_GATES), ("n_phases", C.c_uint32), ("n_dense_phases", C.c_uint32),
                 ("n_mfma_sweep_passes", C.c_uint32)]
+
+
+class PlanOptions(C.Structure):
+    _fields_ = [("tile_bits", C.c_uint32), ("low_bits", C.c_uint32), ("dense_min_cost", C.c_double)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("best", PlanOptions), ("deflt", PlanOptions), ("best_ms", C.c_double), ("default_ms", C.c_double),
+                ("n_candidates", C.c_uint32), ("reserved", C.c_uint32), ("arch", C.c_char * 64)]
 
 
 class Profile(C.Structure):
@@ -113,12 +124,32 @@ SIGNATURES = {
     "qsv_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
     "qsv_diag_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "qsv_profile_reset": (C.c_int32, [C.c_void_p]),
+    "qsv_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
+                                 C.POINTER(TuneReport)]),
+    "qsv_program_plan_get": (C.c_int32, [C.c_void_p, C.POINTER(PlanOptions)]),
+    "qsv_program_replan": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(PlanOptions)]),
+    "qsv_tune_lookup": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(PlanOptions),
+                                    C.POINTER(C.c_int32)]),
+    "qsv_tune_export": (C.c_int32, [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "qsv_tune_import": (C.c_int32, [C.c_char_p]),
+    "qsv_context_fork": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "qsv_expval_grad_each": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
+    "qsv_server_profile": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
 }
 
 
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libqsv.so is not built at {path}; run __graft_entry__.build() first")
+    # One HIP runtime per process: torch ships its own libamdhip64 under the
+    # same soname. Loaded first, it is the runtime libqsv binds to as well;
+    # loaded after libqsv had pulled in the system runtime, torch would bring a
+    # second runtime that finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

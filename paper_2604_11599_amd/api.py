@@ -21,9 +21,11 @@ def _ptr(a):
 def _desc(lp):
     instr = np.ascontiguousarray(lp.instr)
     pred = np.ascontiguousarray(lp.pred)
+    code = np.ascontiguousarray(lp.code)
     d = A.ProgramDesc(lp.n_qubits, lp.n_clbits, lp.n_params, len(instr), len(pred), 0,
-                      instr.ctypes.data if len(instr) else None, pred.ctypes.data if len(pred) else None)
-    return d, (instr, pred)
+                      instr.ctypes.data if len(instr) else None, pred.ctypes.data if len(pred) else None,
+                      len(code), 0, code.ctypes.data if len(code) else None)
+    return d, (instr, pred, code)
 
 
 def plan_inspect(source, tile_bits=0):
@@ -38,14 +40,22 @@ def plan_inspect(source, tile_bits=0):
 
 
 class Context:
-    """qsv_create / qsv_destroy. `stream` may be a torch.cuda.Stream or a raw hipStream_t."""
+    """qsv_create / qsv_destroy. `stream` may be a torch.cuda.Stream or a raw hipStream_t;
+    a stream whose handle is 0 (torch's default stream) is the device's null stream."""
 
-    def __init__(self, device=0, stream=None, arena=None, arena_bytes=0, device_ptrs=False, profile=False):
+    def __init__(self, device=0, stream=None, arena=None, arena_bytes=0, device_ptrs=False, profile=False,
+                 tuned_plans=False):
         raw = None
-        if stream is not None:
-            raw = getattr(stream, "cuda_stream", stream)
         flags = (A.QSV_FLAG_DEVICE_PTRS if device_ptrs else 0) | (A.QSV_FLAG_PROFILE if profile else 0)
-        cfg = A.Config(device, raw, arena, arena_bytes, flags)
+        flags |= A.QSV_FLAG_TUNED_PLANS if tuned_plans else 0
+        if stream is not None:
+            raw = int(getattr(stream, "cuda_stream", stream) or 0)
+            if raw == 0:
+                flags |= A.QSV_FLAG_NULL_STREAM
+        # the stream the library orders its work on (None: its own)
+        self.stream_handle = raw
+        self._forks = []
+        cfg = A.Config(device, raw or None, arena, arena_bytes, flags)
         h = C.c_void_p()
         rc = A.lib().qsv_create(C.byref(cfg), C.byref(h))
         if rc:
@@ -55,13 +65,27 @@ class Context:
         self._programs = weakref.WeakSet()
 
     def close(self):
-        """Frees the context's programs that are still alive, then the context
-        (a program must not outlive its context)."""
+        """Frees the context's forks and programs that are still alive, then the
+        context (a program must not outlive its context)."""
         if self.handle:
+            for f in getattr(self, "_forks", []):
+                f.close()
+            self._forks = []
             for p in list(self._programs):
                 p.free()
             A.lib().qsv_destroy(self.handle)
             self.handle = None
+
+    def fork(self):
+        """qsv_context_fork: a context of the same family with its own stream and
+        scratch (for another host thread); closed with this context."""
+        h = C.c_void_p()
+        self.check(A.lib().qsv_context_fork(self.handle, C.byref(h)))
+        f = Context.__new__(Context)
+        f.handle, f.device_ptrs, f.stream_handle = h, self.device_ptrs, None
+        f._programs, f._forks = weakref.WeakSet(), []
+        self._forks.append(f)
+        return f
 
     def __del__(self):
         try:
@@ -89,6 +113,13 @@ class Context:
     def load(self, source):
         """qsv_load_program on OpenQASM 3 text or a LoweredProgram."""
         return Program(self, source)
+
+    def tune_lookup(self, n_qubits, complex64=False):
+        """qsv_tune_lookup: the cached plan options for n_qubits, or None."""
+        o, f = A.PlanOptions(), C.c_int32()
+        self.check(A.lib().qsv_tune_lookup(self.handle, n_qubits, A.QSV_RUN_COMPLEX64 if complex64 else 0,
+                                           C.byref(o), C.byref(f)))
+        return _opts_dict(o) if f.value else None
 
     def run_batch(self, requests):
         """qsv_run_batch: every shot of every request in one persistent launch.
@@ -118,6 +149,10 @@ class Context:
             mr = rq["prog"].info.max_events
             out.append(ShotResultArrays(creg, record[:, :mr], nev, prob, status, None, rq["prog"].lowered.n_clbits))
         return out
+
+
+def _opts_dict(o):
+    return {"tile_bits": o.tile_bits, "low_bits": o.low_bits, "dense_min_cost": o.dense_min_cost}
 
 
 class ShotResultArrays:
@@ -163,6 +198,35 @@ class Program:
     def n_qubits(self):
         return self.info.n_qubits
 
+    def plan_options(self):
+        """qsv_program_plan_get as a dict."""
+        o = A.PlanOptions()
+        self.ctx.check(A.lib().qsv_program_plan_get(self.handle, C.byref(o)))
+        return _opts_dict(o)
+
+    def replan(self, tile_bits, low_bits, dense_min_cost):
+        """qsv_program_replan with explicit planner options."""
+        o = A.PlanOptions(tile_bits, low_bits, dense_min_cost)
+        self.ctx.check(A.lib().qsv_program_replan(self.ctx.handle, self.handle, C.byref(o)))
+        self._refresh_info()
+
+    def autotune(self, n_shots, theta=None, share=False, complex64=False):
+        """qsv_autotune: measures candidate plans on this call shape, installs the
+        fastest; returns the report as a dict."""
+        th = self._theta(theta if theta is not None else np.zeros(self.info.n_params))
+        r = A.TuneReport()
+        flags = (A.QSV_RUN_SHARE_TRAJ if share else 0) | (A.QSV_RUN_COMPLEX64 if complex64 else 0)
+        self.ctx.check(A.lib().qsv_autotune(self.ctx.handle, self.handle, _ptr(th), int(n_shots), flags,
+                                            C.byref(r)))
+        self._refresh_info()
+        return {"best": _opts_dict(r.best), "default": _opts_dict(r.deflt), "best_ms": r.best_ms,
+                "default_ms": r.default_ms, "n_candidates": r.n_candidates, "arch": r.arch.decode()}
+
+    def _refresh_info(self):
+        info = A.ProgramInfo()
+        A.lib().qsv_program_info_get(self.handle, C.byref(info))
+        self.info = info
+
     def _theta(self, theta, batch=None):
         p = self.info.n_params
         if p == 0:
@@ -193,10 +257,11 @@ class Program:
         return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
-                  share=False, readout_error=0.0, reset_error=0.0, complex64=False, noalloc=False):
+                  share=False, readout_error=0.0, reset_error=0.0, complex64=False, noalloc=False, graph=False):
         """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses.
         complex64: hold and evolve the state in single precision (QSV_RUN_COMPLEX64).
-        noalloc: call qsv_run_shots_noalloc (device scratch from the library's fixed array)."""
+        noalloc: call qsv_run_shots_noalloc (device scratch from the library's fixed array).
+        graph: capture the call's launch sequence in a HIP graph and replay it (QSV_RUN_GRAPH)."""
         lp = self.lowered
         cw = max(1, (lp.n_clbits + 63) // 64)
         mr = self.info.max_events
@@ -219,7 +284,8 @@ class Program:
             flen = f.shape[1]
         st = np.zeros((1 << lp.n_qubits, 2), dtype=np.float64) if state_out else None
         opts = A.RunOpts(seed & 0xFFFFFFFFFFFFFFFF, shot_offset, _ptr(f), flen,
-                         (A.QSV_RUN_SHARE_TRAJ if share else 0) | (A.QSV_RUN_COMPLEX64 if complex64 else 0), _ptr(st),
+                         (A.QSV_RUN_SHARE_TRAJ if share else 0) | (A.QSV_RUN_COMPLEX64 if complex64 else 0)
+                         | (A.QSV_RUN_GRAPH if graph else 0), _ptr(st),
                          float(readout_error), float(reset_error))
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
         fn = A.lib().qsv_run_shots_noalloc if noalloc else A.lib().qsv_run_shots
@@ -252,6 +318,25 @@ class Program:
         g = np.zeros((b, max(1, self.info.n_params)), dtype=np.float64)
         self.ctx.check(A.lib().qsv_expval_grad(self.ctx.handle, self.handle, _ptr(th), b, C.byref(h),
                                                _ptr(e), _ptr(g)))
+        return e, g[:, :self.info.n_params]
+
+    def expval_grad_each(self, thetas, hamiltonians):
+        """qsv_expval_grad_each: thetas [B, P] with one Hamiltonian (coeffs, codes) per row."""
+        th = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
+        b = th.shape[0]
+        th = self._theta(th, b)
+        if len(hamiltonians) != b:
+            raise ValueError("one Hamiltonian per parameter vector")
+        hs = (A.PauliSum * b)()
+        keep = []
+        for k, (coeffs, codes) in enumerate(hamiltonians):
+            h, kp = self._pauli(coeffs, codes)
+            hs[k] = h
+            keep.append(kp)
+        e = np.zeros(b, dtype=np.float64)
+        g = np.zeros((b, max(1, self.info.n_params)), dtype=np.float64)
+        self.ctx.check(A.lib().qsv_expval_grad_each(self.ctx.handle, self.handle, _ptr(th), b, hs, _ptr(e),
+                                                    _ptr(g)))
         return e, g[:, :self.info.n_params]
 
     def expval_grad_device(self, theta_ptr, batch, pauli_sum, energy_ptr, grad_ptr):

@@ -32,20 +32,23 @@ __device__ __forceinline__ double2 ipow(uint32_t k) {
 // Block (blk, b) covers a contiguous slice of vector b: writes lambda there
 // (unless lam is null), terms accumulated in a fixed order per element, and
 // the slice's Re sum conj(psi) lambda to epart[b][blk] (fixed-order tree).
+// Vector b uses terms [toff[b], toff[b + 1]) when toff is set, else all.
 __global__ __launch_bounds__(256) void k_hamiltonian(const double2* __restrict__ psi, double2* __restrict__ lam,
                                                     uint64_t stride, uint32_t n, const uint64_t* __restrict__ xmask,
                                                     const uint64_t* __restrict__ zmask,
                                                     const uint32_t* __restrict__ ny, const double* __restrict__ coeff,
-                                                    uint32_t n_terms, uint32_t blocks, double* __restrict__ epart) {
+                                                    uint32_t n_terms, const uint32_t* __restrict__ toff,
+                                                    uint32_t blocks, double* __restrict__ epart) {
   __shared__ double red[256];
   const uint32_t tid = threadIdx.x, blk = blockIdx.x, b = blockIdx.y;
+  const uint32_t t_begin = toff ? toff[b] : 0u, t_end = toff ? toff[b + 1] : n_terms;
   const uint64_t dim = 1ull << n, per = (dim + blocks - 1) / blocks;
   const uint64_t j0 = per * blk, j1 = (j0 + per < dim) ? j0 + per : dim;
   const double2* st = psi + (uint64_t)b * stride;
   double e = 0.0;
   for (uint64_t i = j0 + tid; i < j1; i += 256) {
     double2 acc = make_double2(0.0, 0.0);
-    for (uint32_t t = 0; t < n_terms; ++t) {
+    for (uint32_t t = t_begin; t < t_end; ++t) {
       const uint64_t src = i ^ xmask[t];
       const double sgn = (__popcll(src & zmask[t]) & 1) ? -1.0 : 1.0;
       acc = cadd(acc, cscale(cmul(ipow(ny[t]), st[src]), coeff[t] * sgn));
@@ -65,9 +68,10 @@ __global__ __launch_bounds__(256) void k_hamiltonian(const double2* __restrict__
 
 hipError_t launch_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
                               const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny, const double* coeff,
-                              uint32_t n_terms, uint32_t blocks, double* epart, hipStream_t st) {
+                              uint32_t n_terms, const uint32_t* toff, uint32_t blocks, double* epart,
+                              hipStream_t st) {
   hipLaunchKernelGGL(k_hamiltonian, dim3(blocks, batch), dim3(256), 0, st, psi, lam, stride, n, xmask, zmask, ny,
-                     coeff, n_terms, blocks, epart);
+                     coeff, n_terms, toff, blocks, epart);
   return hipGetLastError();
 }
 

@@ -4,6 +4,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <unordered_map>
 #include <cstring>
 #include <memory>
@@ -52,7 +57,10 @@ struct qsv_context {
   // set for the duration of a qsv_run_shots_noalloc call: scratch comes from
   // the device's fixed array and no events are created or recorded
   bool noalloc = false;
-  bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0 && !noalloc; }
+  bool capturing = false;  // launches are being recorded into a HIP graph
+  std::string arch;        // the device's architecture name (autotuning cache key)
+  qsv_context* parent = nullptr;  // a forked context runs its parent's programs
+  bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0 && !noalloc && !capturing; }
   // the arena scratch is carved from in the current call, if any
   uint8_t* call_arena() const { return noalloc ? static_cast<uint8_t*>(noalloc_scratch(device)) : arena; }
   size_t call_arena_bytes() const { return noalloc ? kNoAllocScratchBytes : arena_bytes; }
@@ -63,6 +71,7 @@ struct qsv_program {
   qsv_program_desc desc{};
   std::vector<qsv_instr> instr;
   std::vector<qsv_pred> pred;
+  std::vector<qsv_cop> code;
   Plan plan;
   // device copies of the static plan
   DGate* d_gates = nullptr;
@@ -74,6 +83,7 @@ struct qsv_program {
   uint32_t* d_dense = nullptr;  // indices of the dense phases
   SiteEvent* d_events = nullptr;
   DPred* d_preds = nullptr;
+  qsv_cop* d_code = nullptr;
   uint32_t* d_csr_off = nullptr;
   uint32_t* d_csr_sj = nullptr;
   double* d_csr_scale = nullptr;
@@ -84,6 +94,11 @@ struct qsv_program {
   uint32_t* d_ang_off = nullptr;
   uint32_t n_ang_ent = 0;
   std::vector<uint8_t> bw_mfma;  // per pass: swept on the matrix cores
+  PlanOptions opts;              // the options the current plan was built with
+  // the captured launch sequence of the last QSV_RUN_GRAPH call and what it
+  // was captured for (call shape and the scratch pointers it refers to)
+  mutable hipGraphExec_t graph = nullptr;
+  mutable std::vector<uint64_t> graph_key;
 };
 
 namespace {
@@ -100,6 +115,14 @@ namespace {
 qsv_status set_err(qsv_context* ctx, qsv_status st, const std::string& m) {
   if (ctx) ctx->err = m;
   return st;
+}
+
+// Whether ctx may run prog: programs of the same context family (a context,
+// its forks, and the programs any of them loaded).
+bool owns(const qsv_context* ctx, const qsv_program* prog) {
+  const qsv_context* a = ctx->parent ? ctx->parent : ctx;
+  const qsv_context* b = prog->ctx->parent ? prog->ctx->parent : prog->ctx;
+  return a == b;
 }
 
 // HIP keeps the most recent failed call's status per host thread until
@@ -259,75 +282,71 @@ size_t free_device_bytes() {
   return fr;
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// Autotuning cache: the plan options measured fastest, per device
+// architecture, qubit count and precision, shared by the contexts of the
+// process.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  PlanOptions best;
+  double best_ms = 0.0, default_ms = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
 
-extern "C" {
-
-qsv_status qsv_create(const qsv_config* cfg, qsv_context** out) {
-  if (!out) return QSV_ERR_ARG;
-  *out = nullptr;
-  std::unique_ptr<qsv_context> ctx(new qsv_context());
-  qsv_config def{};
-  if (!cfg) cfg = &def;
-  ctx->device = cfg->device;
-  ctx->flags = cfg->flags;
-  ctx->arena = static_cast<uint8_t*>(cfg->arena);
-  ctx->arena_bytes = cfg->arena ? cfg->arena_bytes : 0;
-  int count = 0;
-  clear_error();
-  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
-    clear_error();
-    return QSV_ERR_DEVICE;
-  }
-  if (cfg->device < 0 || cfg->device >= count) return QSV_ERR_ARG;
-  if (enter_device(cfg->device) != hipSuccess) return QSV_ERR_DEVICE;
-  // this device's address of the fixed scratch array (no-allocation entry point)
-  if (noalloc_scratch_init(cfg->device) != hipSuccess) {
-    clear_error();
-    return QSV_ERR_DEVICE;
-  }
-  if (cfg->stream) {
-    ctx->stream = static_cast<hipStream_t>(cfg->stream);
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-      clear_error();
-      return QSV_ERR_DEVICE;
-    }
-    ctx->own_stream = true;
-  }
-  *out = ctx.release();
-  return QSV_OK;
+std::string tune_key(const std::string& arch, uint32_t n, bool c64) {
+  return arch + " " + std::to_string(n) + " " + (c64 ? "c64" : "c128");
 }
 
-void qsv_destroy(qsv_context* ctx) {
-  if (!ctx) return;
-  ignore(enter_device(ctx->device));
-  if (ctx->stream) ignore(hipStreamSynchronize(ctx->stream));
-  for (hipEvent_t e : ctx->ev_pool) ignore(hipEventDestroy(e));
-  for (auto& b : ctx->cache)
-    if (b.p) ignore(hipFree(b.p));
-  if (ctx->own_stream) ignore(hipStreamDestroy(ctx->stream));
-  delete ctx;
+bool tuned_options(const qsv_context* ctx, uint32_t n, bool c64, PlanOptions* o) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(ctx->arch, n, c64));
+  if (it == g_tune.end()) return false;
+  *o = it->second.best;
+  return true;
 }
 
-const char* qsv_last_error(const qsv_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+void to_public(const PlanOptions& o, qsv_plan_options* out) {
+  out->tile_bits = o.tile_bits;
+  out->low_bits = o.low_bits;
+  out->dense_min_cost = o.dense_min_cost;
+}
 
-qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_program** out) {
-  if (!ctx || !desc || !out) return set_err(ctx, QSV_ERR_ARG, "null argument");
-  *out = nullptr;
-  if (desc->n_qubits > (uint32_t)kMaxQubits)
-    return set_err(ctx, QSV_ERR_LIMIT, "more than 34 qubits do not fit one GPU's HBM");
-  std::string err;
-  if (!validate_program(*desc, &err)) return set_err(ctx, QSV_ERR_ARG, err);
-  if (enter_device(ctx->device) != hipSuccess) return set_err(ctx, QSV_ERR_DEVICE, "hipSetDevice failed");
-  std::unique_ptr<qsv_program> p(new qsv_program());
-  p->ctx = ctx;
-  p->instr.assign(desc->instr, desc->instr + desc->n_instr);
-  p->pred.assign(desc->pred, desc->pred + desc->n_pred);
-  p->desc = *desc;
-  p->desc.instr = p->instr.data();
-  p->desc.pred = p->pred.data();
-  p->plan = build_plan(p->desc, PlanOptions());
+// Frees the device copies of a program's plan.
+void free_plan_buffers(qsv_program* p) {
+  if (p->graph) ignore(hipGraphExecDestroy(p->graph));
+  p->graph = nullptr;
+  p->graph_key.clear();
+  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense,
+                  p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off,
+                  p->d_code};
+  for (void* q : ptrs)
+    if (q) ignore(hipFree(q));
+  p->d_gates = nullptr;
+  p->d_phases = nullptr;
+  p->d_steps = nullptr;
+  p->d_passes = nullptr;
+  p->d_sites = nullptr;
+  p->d_src = nullptr;
+  p->d_dense = nullptr;
+  p->d_events = nullptr;
+  p->d_preds = nullptr;
+  p->d_csr_off = nullptr;
+  p->d_csr_sj = nullptr;
+  p->d_csr_scale = nullptr;
+  p->d_ang_ent = nullptr;
+  p->d_ang_off = nullptr;
+  p->d_code = nullptr;
+}
+
+// Plans the program's stream with options o and uploads the plan (replacing a
+// previous one). The device must be current.
+qsv_status install_plan(qsv_context* ctx, qsv_program* p, const PlanOptions& o) {
+  free_plan_buffers(p);
+  const qsv_program_desc* desc = &p->desc;
+  p->opts = o;
+  p->pblocks = 1;
+  p->plan = build_plan(p->desc, o);
   const Plan& pl = p->plan;
   for (const SiteArgs& s : pl.sites) p->pblocks = std::max(p->pblocks, s.blocks);
   std::vector<DPred> dp;
@@ -399,14 +418,120 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
   if (e == hipSuccess) e = upload(pl.dense_phases, &p->d_dense);
   if (e == hipSuccess) e = upload(pl.events, &p->d_events);
   if (e == hipSuccess) e = upload(dp, &p->d_preds);
+  if (e == hipSuccess) e = upload(p->code, &p->d_code);
   if (e == hipSuccess) e = upload(off, &p->d_csr_off);
   if (e == hipSuccess) e = upload(sj, &p->d_csr_sj);
   if (e == hipSuccess) e = upload(sc, &p->d_csr_scale);
   if (e != hipSuccess) {
-    qsv_program_free(p.release());
+    free_plan_buffers(p);
     return set_err(ctx, e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_DEVICE,
                    std::string("program upload: ") + hipGetErrorString(e));
   }
+  return QSV_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_create(const qsv_config* cfg, qsv_context** out) {
+  if (!out) return QSV_ERR_ARG;
+  *out = nullptr;
+  std::unique_ptr<qsv_context> ctx(new qsv_context());
+  qsv_config def{};
+  if (!cfg) cfg = &def;
+  ctx->device = cfg->device;
+  ctx->flags = cfg->flags;
+  ctx->arena = static_cast<uint8_t*>(cfg->arena);
+  ctx->arena_bytes = cfg->arena ? cfg->arena_bytes : 0;
+  int count = 0;
+  clear_error();
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    clear_error();
+    return QSV_ERR_DEVICE;
+  }
+  if (cfg->device < 0 || cfg->device >= count) return QSV_ERR_ARG;
+  if (enter_device(cfg->device) != hipSuccess) return QSV_ERR_DEVICE;
+  // this device's address of the fixed scratch array (no-allocation entry point)
+  if (noalloc_scratch_init(cfg->device) != hipSuccess) {
+    clear_error();
+    return QSV_ERR_DEVICE;
+  }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess) {
+      clear_error();
+      return QSV_ERR_DEVICE;
+    }
+    ctx->arch = prop.gcnArchName;
+    const size_t colon = ctx->arch.find(':');  // feature suffixes (sramecc, xnack) are not part of the key
+    if (colon != std::string::npos) ctx->arch.resize(colon);
+  }
+  if (cfg->stream) {
+    ctx->stream = static_cast<hipStream_t>(cfg->stream);
+  } else if (cfg->flags & QSV_FLAG_NULL_STREAM) {
+    ctx->stream = nullptr;  // the device's null stream
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      clear_error();
+      return QSV_ERR_DEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  *out = ctx.release();
+  return QSV_OK;
+}
+
+qsv_status qsv_context_fork(qsv_context* parent, qsv_context** out) {
+  if (!parent || !out) return QSV_ERR_ARG;
+  *out = nullptr;
+  if (parent->parent) return set_err(parent, QSV_ERR_ARG, "a forked context cannot be forked");
+  qsv_config cfg{};
+  cfg.device = parent->device;
+  cfg.flags = parent->flags & ~(uint32_t)QSV_FLAG_NULL_STREAM;  // always a stream of its own
+  qsv_context* c = nullptr;
+  const qsv_status st = qsv_create(&cfg, &c);
+  if (st != QSV_OK) return set_err(parent, st, "qsv_context_fork: context creation failed");
+  c->parent = parent;
+  *out = c;
+  return QSV_OK;
+}
+
+void qsv_destroy(qsv_context* ctx) {
+  if (!ctx) return;
+  ignore(enter_device(ctx->device));
+  ignore(hipStreamSynchronize(ctx->stream));
+  for (hipEvent_t e : ctx->ev_pool) ignore(hipEventDestroy(e));
+  for (auto& b : ctx->cache)
+    if (b.p) ignore(hipFree(b.p));
+  if (ctx->own_stream) ignore(hipStreamDestroy(ctx->stream));
+  delete ctx;
+}
+
+const char* qsv_last_error(const qsv_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_program** out) {
+  if (!ctx || !desc || !out) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (desc->n_qubits > (uint32_t)kMaxQubits)
+    return set_err(ctx, QSV_ERR_LIMIT, "more than 34 qubits do not fit one GPU's HBM");
+  std::string err;
+  if (!validate_program(*desc, &err)) return set_err(ctx, QSV_ERR_ARG, err);
+  if (enter_device(ctx->device) != hipSuccess) return set_err(ctx, QSV_ERR_DEVICE, "hipSetDevice failed");
+  std::unique_ptr<qsv_program> p(new qsv_program());
+  p->ctx = ctx;
+  p->instr.assign(desc->instr, desc->instr + desc->n_instr);
+  p->pred.assign(desc->pred, desc->pred + desc->n_pred);
+  if (desc->n_code) p->code.assign(desc->code, desc->code + desc->n_code);
+  p->desc = *desc;
+  p->desc.instr = p->instr.data();
+  p->desc.pred = p->pred.data();
+  p->desc.code = p->code.data();
+  PlanOptions o;
+  if (ctx->flags & QSV_FLAG_TUNED_PLANS) tuned_options(ctx, desc->n_qubits, false, &o);
+  const qsv_status st = install_plan(ctx, p.get(), o);
+  if (st != QSV_OK) return st;
   *out = p.release();
   return QSV_OK;
 }
@@ -427,16 +552,14 @@ qsv_status qsv_program_info_get(const qsv_program* prog, qsv_program_info* out) 
 void qsv_program_free(qsv_program* p) {
   if (!p) return;
   ignore(enter_device(p->ctx->device));
-  void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense, p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off};
-  for (void* q : ptrs)
-    if (q) ignore(hipFree(q));
+  free_plan_buffers(p);
   delete p;
 }
 
 qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double* theta, uint64_t n_shots,
                          const qsv_run_opts* opts, qsv_shot_results* out) {
   if (!ctx || !prog || !out) return set_err(ctx, QSV_ERR_ARG, "null argument");
-  if (prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
+  if (!owns(ctx, prog)) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
   if (!out->creg) return set_err(ctx, QSV_ERR_ARG, "creg output is required");
   const qsv_run_opts def{};
   if (!opts) opts = &def;
@@ -483,13 +606,23 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride, &d_mats));
   if (prog->desc.n_params)
     HIP_TRY(hipMemcpyAsync(d_theta, theta, prog->desc.n_params * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, prog->desc.n_params, 1, d_mats, nullptr, st));
-  HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, 1, 0,
-                               d_mats, st));
   RunBuffers rb{};
   // state buffers: one per shot, or with trajectory sharing one per slot that
   // owns its state, grown on demand (doubling) up to one per shot
   const bool share_req = (opts->flags & QSV_RUN_SHARE_TRAJ) != 0;
+  // a captured launch sequence: one batch, no host decisions between launches
+  const bool use_graph = (opts->flags & QSV_RUN_GRAPH) != 0 && !share_req && n_shots <= batch &&
+                         ctx->stream != nullptr && !ctx->noalloc;
+  auto bind = [&]() -> qsv_status {
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, prog->desc.n_params, 1, d_mats, nullptr, st));
+    HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, 1,
+                                 0, d_mats, st));
+    return QSV_OK;
+  };
+  if (!use_graph) {
+    const qsv_status bs = bind();
+    if (bs != QSV_OK) return bs;
+  }
   // (in an arena every shot's buffer is reserved up front: a bump allocator
   // cannot reuse the buffers a doubling leaves behind)
   uint64_t cap = (share_req && batch > 1 && !in_arena) ? std::min<uint64_t>(batch, 8) : batch;
@@ -502,6 +635,9 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   if (opts->forced_len) HIP_TRY(scr.get(batch * opts->forced_len, &d_forced));
   double2* d_out = nullptr;
   if (opts->state_out) HIP_TRY(scr.get(dim, &d_out));
+  uint64_t* d_key = nullptr;
+  HIP_TRY(scr.get(2, &d_key));
+  rb.key = d_key;
   rb.stride = dim;
   rb.c64 = c64 ? 1u : 0u;
   rb.cw = cw;
@@ -538,6 +674,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     cap = ncap;
     return QSV_OK;
   };
+  uint64_t hkey[2];  // (seed, shot_base) of the current batch; stays alive until its sync
   for (uint64_t s0 = 0; s0 < n_shots; s0 += batch) {
     const uint32_t bs = (uint32_t)std::min<uint64_t>(batch, n_shots - s0);
     const bool share = share_req && bs > 1;
@@ -546,6 +683,69 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     if (opts->forced_len)
       HIP_TRY(hipMemcpyAsync(d_forced, opts->forced + s0 * opts->forced_len, (size_t)bs * opts->forced_len,
                              hipMemcpyHostToDevice, st));
+    hkey[0] = opts->seed;
+    hkey[1] = rb.shot_base;
+    HIP_TRY(hipMemcpyAsync(d_key, hkey, sizeof(hkey), hipMemcpyHostToDevice, st));
+    if (use_graph) {
+      // the whole launch sequence of the call, captured once and replayed
+      auto issue = [&]() -> qsv_status {
+        const qsv_status b = bind();
+        if (b != QSV_OK) return b;
+        HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, rb.record, maxrec, bs, st));
+        for (const Step& step : pl.steps) {
+          if (step.kind == Step::INIT)
+            HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st, c64));
+          else if (step.kind == Step::PASS)
+            HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
+          else
+            HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, prog->d_code, st));
+        }
+        if (opts->state_out) HIP_TRY(launch_materialize(rb, n, 0, d_out, st));
+        return QSV_OK;
+      };
+      auto bits = [](double x) {
+        uint64_t u;
+        std::memcpy(&u, &x, 8);
+        return u;
+      };
+      const std::vector<uint64_t> gkey = {
+          n_shots, opts->flags, opts->forced_len, bits(opts->readout_error), bits(opts->reset_error),
+          opts->state_out ? 1ull : 0ull, (uint64_t)(uintptr_t)d_theta, (uint64_t)(uintptr_t)d_mats,
+          (uint64_t)(uintptr_t)rb.state, (uint64_t)(uintptr_t)rb.ctl, (uint64_t)(uintptr_t)rb.creg,
+          (uint64_t)(uintptr_t)rb.record, (uint64_t)(uintptr_t)rb.partials, (uint64_t)(uintptr_t)d_forced,
+          (uint64_t)(uintptr_t)d_out, (uint64_t)(uintptr_t)d_key, (uint64_t)(uintptr_t)st};
+      if (!prog->graph || prog->graph_key != gkey) {
+        if (prog->graph) ignore(hipGraphExecDestroy(prog->graph));
+        prog->graph = nullptr;
+        prog->graph_key.clear();
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        ctx->capturing = true;
+        const qsv_status is = issue();
+        ctx->capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(st, &g);
+        if (is != QSV_OK || ee != hipSuccess) {
+          if (g) ignore(hipGraphDestroy(g));
+          clear_error();
+          return is != QSV_OK ? is : set_err(ctx, QSV_ERR_DEVICE, std::string("hipStreamEndCapture: ") +
+                                                                    hipGetErrorString(ee));
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        ignore(hipGraphDestroy(g));
+        if (ie != hipSuccess)
+          return set_err(ctx, QSV_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        prog->graph = ex;
+        prog->graph_key = gkey;
+      }
+      {
+        Prof pr(ctx, st);
+        HIP_TRY(hipGraphLaunch(prog->graph, st));
+        pr.done(K_OTHER);
+      }
+      if (opts->state_out)
+        HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, dim * sizeof(double2), hipMemcpyDeviceToHost, st));
+    } else {
     HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, rb.record, maxrec, bs, st));
     // the view the passes run on: one state per slot with the slot's control block
     RunBuffers rp = rb;
@@ -594,7 +794,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
                 pass_bytes_per_amp(pl.passes[step.index]) * (c64 ? 0.5 : 1.0) * amps,
                 pl.pass_flops_per_amp[step.index] * amps);
       } else if (!share) {
-        HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, st));
+        HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, prog->d_code, st));
         pr.done(1);
       } else {
         const SiteArgs& sa = pl.sites[step.index];
@@ -606,7 +806,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
         rs.buf_of = d_buf_of;
         rs.site_ctl = d_slot_ctl;
         rs.site_slots = n_slot;
-        HIP_TRY(launch_site(rs, sa, prog->d_events, prog->d_preds, st));
+        HIP_TRY(launch_site(rs, sa, prog->d_events, prog->d_preds, prog->d_code, st));
         pr.done(1);
         if (sa.nq) {
           // split the slots by the new histories
@@ -672,6 +872,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       HIP_TRY(launch_materialize(rb, n, 0, d_out, st));
       HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, dim * sizeof(double2), hipMemcpyDeviceToHost, st));
     }
+    }  // eager launches
     HIP_TRY(hipMemcpyAsync(out->creg + s0 * cw, rb.creg, (size_t)bs * cw * 8, hipMemcpyDeviceToHost, st));
     if (out->record && pl.max_record) {
       if (maxrec == pl.max_record) {
@@ -710,7 +911,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
   uint64_t items = 0;
   for (uint32_t r = 0; r < n_reqs; ++r) {
     const qsv_request& q = reqs[r];
-    if (!q.prog || q.prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": bad program");
+    if (!q.prog || !owns(ctx, q.prog)) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": bad program");
     if (!q.out.creg) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": creg output is required");
     if (q.prog->desc.n_params && !q.theta) return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": theta is required");
     if (q.opts.forced_len && !q.opts.forced) return set_err(ctx, QSV_ERR_ARG, "forced_len without forced");
@@ -792,6 +993,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       R.sites = p->d_sites;
       R.events = p->d_events;
       R.preds = p->d_preds;
+      R.code = p->d_code;
       R.mats = d_mats + mo;
       if (q.opts.forced_len) {
         HIP_TRY(hipMemcpyAsync(d_forced + fo, q.opts.forced, q.n_shots * q.opts.forced_len, hipMemcpyHostToDevice, st));
@@ -928,39 +1130,50 @@ struct HamDev {
   double* c = nullptr;
 };
 
+// h: one Hamiltonian shared by every vector (per_vector false) or h[b] for
+// vector b (per_vector true).
 qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* theta, uint32_t batch,
-                       const qsv_pauli_sum* h, double* energy, double* grad) {
+                       const qsv_pauli_sum* h, double* energy, double* grad, bool per_vector = false) {
   if (!ctx || !prog || !h || !energy) return set_err(ctx, QSV_ERR_ARG, "null argument");
-  if (prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
+  if (!owns(ctx, prog)) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
   if (!prog->plan.unitary)
     return set_err(ctx, QSV_ERR_UNSUPPORTED, "expectation values need a program without measurement or control flow");
-  if (h->n_terms && (!h->coeff || !h->pauli)) return set_err(ctx, QSV_ERR_ARG, "null Hamiltonian arrays");
+  const uint32_t n_ham = per_vector ? batch : 1;
+  for (uint32_t k = 0; k < n_ham; ++k)
+    if (h[k].n_terms && (!h[k].coeff || !h[k].pauli)) return set_err(ctx, QSV_ERR_ARG, "null Hamiltonian arrays");
   if (prog->desc.n_params && !theta) return set_err(ctx, QSV_ERR_ARG, "theta is required");
   if (batch == 0) return QSV_OK;
   HIP_TRY(enter_device(ctx->device));
   const Plan& pl = prog->plan;
-  const uint32_t n = prog->desc.n_qubits, P = prog->desc.n_params, T = h->n_terms;
+  const uint32_t n = prog->desc.n_qubits, P = prog->desc.n_params;
   const uint64_t dim = 1ull << n;
   const uint32_t n_slots = (uint32_t)pl.gate_src.size();
   const bool dev = (ctx->flags & QSV_FLAG_DEVICE_PTRS) != 0;
   hipStream_t st = ctx->stream;
-  // Pauli strings as (x mask, z mask, #Y)
-  std::vector<uint64_t> xm(T), zm(T);
-  std::vector<uint32_t> ny(T);
-  for (uint32_t t = 0; t < T; ++t) {
-    uint64_t x = 0, z = 0;
-    uint32_t y = 0;
-    for (uint32_t q = 0; q < n; ++q) {
-      uint8_t c = h->pauli[(size_t)t * n + q];
-      if (c > 3) return set_err(ctx, QSV_ERR_ARG, "Pauli code must be 0..3");
-      if (c == 1 || c == 2) x |= 1ull << q;
-      if (c == 3 || c == 2) z |= 1ull << q;
-      if (c == 2) ++y;
+  // Pauli strings as (x mask, z mask, #Y), every Hamiltonian's terms in a row;
+  // vector b uses terms [toff[b], toff[b + 1]) (per-vector Hamiltonians only)
+  std::vector<uint64_t> xm, zm;
+  std::vector<uint32_t> ny, toff(1, 0);
+  std::vector<double> cf;
+  for (uint32_t k = 0; k < n_ham; ++k) {
+    for (uint32_t t = 0; t < h[k].n_terms; ++t) {
+      uint64_t x = 0, z = 0;
+      uint32_t y = 0;
+      for (uint32_t q = 0; q < n; ++q) {
+        uint8_t c = h[k].pauli[(size_t)t * n + q];
+        if (c > 3) return set_err(ctx, QSV_ERR_ARG, "Pauli code must be 0..3");
+        if (c == 1 || c == 2) x |= 1ull << q;
+        if (c == 3 || c == 2) z |= 1ull << q;
+        if (c == 2) ++y;
+      }
+      xm.push_back(x);
+      zm.push_back(z);
+      ny.push_back(y & 3u);
+      cf.push_back(h[k].coeff[t]);
     }
-    xm[t] = x;
-    zm[t] = z;
-    ny[t] = y & 3u;
+    toff.push_back((uint32_t)xm.size());
   }
+  const uint32_t T = (uint32_t)xm.size();
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, dim / 4096));
   // vectors per chunk: states (x2 with a gradient) must fit
   size_t per = dim * 16 * (grad ? 2 : 1) + (size_t)n_slots * kMatStride * 8 * (grad ? 4 : 1) +
@@ -991,12 +1204,15 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.z));
   HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.ny));
   HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.c));
+  uint32_t* d_toff = nullptr;
+  if (per_vector) HIP_TRY(scr.get(batch + 1, &d_toff));
   if (T) {
     HIP_TRY(hipMemcpyAsync(hd.x, xm.data(), T * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(hd.z, zm.data(), T * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(hd.ny, ny.data(), T * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(hd.c, h->coeff, T * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(hd.c, cf.data(), T * 8, hipMemcpyHostToDevice, st));
   }
+  if (per_vector) HIP_TRY(hipMemcpyAsync(d_toff, toff.data(), (batch + 1) * 4, hipMemcpyHostToDevice, st));
   double *d_theta, *d_mats, *d_dmats = nullptr, *d_tp, *d_energy, *d_dEda = nullptr, *d_gpart = nullptr,
                             *d_grad = nullptr;
   RunBuffers rb{};
@@ -1047,8 +1263,8 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
     // lambda = H psi (kept for the gradient) and the energy Re <psi|lambda> in one sweep
     if (T) {
       Prof pr(ctx, st);
-      HIP_TRY(launch_hamiltonian(rb.state, grad ? d_lam : nullptr, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T, blocks,
-                                 d_tp, st));
+      HIP_TRY(launch_hamiltonian(rb.state, grad ? d_lam : nullptr, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T,
+                                 per_vector ? d_toff + b0 : nullptr, blocks, d_tp, st));
       pr.done(K_HAM, false, (grad ? 32.0 : 16.0) * (double)dim * bs);
       HIP_TRY(launch_energy_sum(d_tp, blocks, bs, d_energy, st));
     } else {
@@ -1107,6 +1323,12 @@ qsv_status qsv_expval_grad(qsv_context* ctx, const qsv_program* prog, const doub
                            const qsv_pauli_sum* h, double* energy, double* grad) {
   if (!grad) return set_err(ctx, QSV_ERR_ARG, "grad is required");
   return expval_impl(ctx, prog, theta, batch, h, energy, grad);
+}
+
+qsv_status qsv_expval_grad_each(qsv_context* ctx, const qsv_program* prog, const double* theta, uint32_t batch,
+                                const qsv_pauli_sum* h, double* energy, double* grad) {
+  if (!grad) return set_err(ctx, QSV_ERR_ARG, "grad is required");
+  return expval_impl(ctx, prog, theta, batch, h, energy, grad, true);
 }
 
 qsv_status qsv_diag_copy(qsv_context* ctx, void* dst, const void* src, size_t bytes) {
@@ -1185,6 +1407,152 @@ qsv_status qsv_plan_inspect(const qsv_program_desc* desc, uint32_t tile_bits, qs
       out->gate_regs[g] = regs;
     }
   }
+  return QSV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plan autotuning
+// ---------------------------------------------------------------------------
+qsv_status qsv_program_plan_get(const qsv_program* prog, qsv_plan_options* out) {
+  if (!prog || !out) return QSV_ERR_ARG;
+  to_public(prog->opts, out);
+  return QSV_OK;
+}
+
+qsv_status qsv_program_replan(qsv_context* ctx, qsv_program* prog, const qsv_plan_options* o) {
+  if (!ctx || !prog || !o) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  if (prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
+  if (o->tile_bits < 1 || o->tile_bits > (uint32_t)kTileMaxBits || o->low_bits < 1 || o->low_bits > o->tile_bits ||
+      !(o->dense_min_cost >= 0.0))
+    return set_err(ctx, QSV_ERR_ARG, "plan options out of range");
+  HIP_TRY(enter_device(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));  // no launch of the old plan is still running
+  PlanOptions po;
+  po.tile_bits = o->tile_bits;
+  po.low_bits = o->low_bits;
+  po.dense_min_cost = o->dense_min_cost;
+  return install_plan(ctx, prog, po);
+}
+
+qsv_status qsv_autotune(qsv_context* ctx, qsv_program* prog, const double* theta, uint64_t n_shots,
+                        uint32_t run_flags, qsv_tune_report* out) {
+  if (!ctx || !prog || !out) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  if (prog->ctx != ctx) return set_err(ctx, QSV_ERR_ARG, "program belongs to another context");
+  if (prog->desc.n_params && !theta) return set_err(ctx, QSV_ERR_ARG, "theta is required");
+  if (n_shots == 0) return set_err(ctx, QSV_ERR_ARG, "n_shots must be positive");
+  HIP_TRY(enter_device(ctx->device));
+  const uint32_t n = prog->desc.n_qubits;
+  const bool c64 = (run_flags & QSV_RUN_COMPLEX64) != 0;
+  // candidates: the default plan first, then tile widths, the always-held low
+  // qubits and the dense-phase threshold
+  std::vector<PlanOptions> cand;
+  auto add = [&](uint32_t t, uint32_t low, double dense) {
+    PlanOptions o;
+    o.tile_bits = std::min<uint32_t>(t, std::max<uint32_t>(1, n));
+    o.low_bits = std::min<uint32_t>(low, o.tile_bits);
+    o.dense_min_cost = dense;
+    for (const PlanOptions& c : cand)
+      if (c.tile_bits == o.tile_bits && c.low_bits == o.low_bits && c.dense_min_cost == o.dense_min_cost) return;
+    cand.push_back(o);
+  };
+  const PlanOptions def;
+  add(def.tile_bits, def.low_bits, def.dense_min_cost);
+  for (uint32_t t : {12u, 11u, 10u})
+    for (uint32_t low : {4u, 5u})
+      for (double dense : {QSV_DENSE_MIN_COST, 0.0, 3.0}) add(t, low, dense);
+  const uint32_t cw = std::max<uint32_t>(1, (prog->desc.n_clbits + 63) / 64);
+  std::vector<uint64_t> creg((size_t)n_shots * cw);
+  qsv_shot_results res{};
+  res.creg = creg.data();
+  qsv_run_opts ro{};
+  ro.seed = 0x5eed;
+  ro.flags = run_flags & (QSV_RUN_SHARE_TRAJ | QSV_RUN_COMPLEX64);
+  std::vector<double> ms(cand.size(), 0.0);
+  for (size_t k = 0; k < cand.size(); ++k) {
+    qsv_status st = install_plan(ctx, prog, cand[k]);
+    if (st != QSV_OK) return st;
+    st = qsv_run_shots(ctx, prog, theta, n_shots, &ro, &res);  // first run: warm-up
+    if (st != QSV_OK) return st;
+    double best = 1e300;
+    for (int r = 0; r < 2; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = qsv_run_shots(ctx, prog, theta, n_shots, &ro, &res);
+      if (st != QSV_OK) return st;
+      best = std::min(best, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    ms[k] = best;
+  }
+  const size_t b = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+  const qsv_status st = install_plan(ctx, prog, cand[b]);
+  if (st != QSV_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    TuneEntry& e = g_tune[tune_key(ctx->arch, n, c64)];
+    e.best = cand[b];
+    e.best_ms = ms[b];
+    e.default_ms = ms[0];
+  }
+  std::memset(out, 0, sizeof(*out));
+  to_public(cand[b], &out->best);
+  to_public(cand[0], &out->deflt);
+  out->best_ms = ms[b];
+  out->default_ms = ms[0];
+  out->n_candidates = (uint32_t)cand.size();
+  std::snprintf(out->arch, sizeof(out->arch), "%s", ctx->arch.c_str());
+  return QSV_OK;
+}
+
+qsv_status qsv_tune_lookup(qsv_context* ctx, uint32_t n_qubits, uint32_t run_flags, qsv_plan_options* out,
+                           int32_t* found) {
+  if (!ctx || !out || !found) return set_err(ctx, QSV_ERR_ARG, "null argument");
+  PlanOptions o;
+  *found = tuned_options(ctx, n_qubits, (run_flags & QSV_RUN_COMPLEX64) != 0, &o) ? 1 : 0;
+  to_public(o, out);
+  return QSV_OK;
+}
+
+qsv_status qsv_tune_export(char* buf, size_t cap, size_t* len) {
+  if (!len) return QSV_ERR_ARG;
+  std::ostringstream os;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune) {
+      char line[256];
+      std::snprintf(line, sizeof(line), "%s %u %u %.17g %.6g %.6g\n", kv.first.c_str(), kv.second.best.tile_bits,
+                    kv.second.best.low_bits, kv.second.best.dense_min_cost, kv.second.best_ms, kv.second.default_ms);
+      os << line;
+    }
+  }
+  const std::string s = os.str();
+  *len = s.size() + 1;
+  if (!buf) return QSV_OK;
+  if (cap < s.size() + 1) return QSV_ERR_LIMIT;
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return QSV_OK;
+}
+
+qsv_status qsv_tune_import(const char* text) {
+  if (!text) return QSV_ERR_ARG;
+  std::istringstream is(text);
+  std::string line;
+  std::map<std::string, TuneEntry> add;
+  while (std::getline(is, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream ls(line);
+    std::string arch, prec;
+    uint32_t n = 0;
+    TuneEntry e;
+    if (!(ls >> arch >> n >> prec >> e.best.tile_bits >> e.best.low_bits >> e.best.dense_min_cost >> e.best_ms >>
+          e.default_ms))
+      return QSV_ERR_ARG;
+    if ((prec != "c64" && prec != "c128") || n < 1 || n > (uint32_t)kMaxQubits || e.best.tile_bits < 1 ||
+        e.best.tile_bits > (uint32_t)kTileMaxBits || e.best.low_bits < 1 || e.best.low_bits > e.best.tile_bits ||
+        !(e.best.dense_min_cost >= 0.0))
+      return QSV_ERR_ARG;
+    add[tune_key(arch, n, prec == "c64")] = e;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : add) g_tune[kv.first] = kv.second;
   return QSV_OK;
 }
 

@@ -29,6 +29,10 @@ struct RunBuffers {
   const uint32_t* slot_of;
   const ShotCtl* site_ctl;  // slot control blocks the histograms follow
   uint32_t site_slots;      // slots the site reduces over
+  // device copy of (seed, shot_base), read by the site finaliser instead of
+  // the two fields above when set (a captured launch sequence keeps its
+  // kernel arguments; the key of each call is written here before it runs)
+  const uint64_t* key;
 };
 
 // Workgroups of `kernel` (threads per workgroup, bytes of dynamic LDS) that the
@@ -48,7 +52,7 @@ hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32
 hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phase* phases, const double* mats,
                             uint64_t mat_stride, const PassArgs& a, hipStream_t st);
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev,
-                       const DPred* preds, hipStream_t st);
+                       const DPred* preds, const qsv_cop* code, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
 // dst[i] = src[idx[i]] for i < count (control blocks of trajectory slots and shots)
 hipError_t launch_ctl_gather(ShotCtl* dst, const ShotCtl* src, const uint32_t* idx, uint32_t count, hipStream_t st);
@@ -68,7 +72,8 @@ hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint3
 // (epart[batch][blocks]); launch_energy_sum reduces them to energy[batch].
 hipError_t launch_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
                               const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny, const double* coeff,
-                              uint32_t n_terms, uint32_t blocks, double* epart, hipStream_t st);
+                              uint32_t n_terms, const uint32_t* toff, uint32_t blocks, double* epart,
+                              hipStream_t st);
 hipError_t launch_energy_sum(const double* epart, uint32_t blocks, uint32_t batch, double* energy, hipStream_t st);
 hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uint32_t batch,
                                 const DGate* gates, const Phase* phases, const double* mats, const double* dmats,

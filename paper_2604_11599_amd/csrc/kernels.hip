@@ -367,6 +367,8 @@ hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_
   };
   static Entry cache[64];
   static int used = 0;
+  static std::mutex mu;  // forked contexts launch from several host threads
+  std::lock_guard<std::mutex> lk(mu);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1128,8 +1130,65 @@ __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
   }
 }
 
-__device__ bool eval_pred(const DPred& p, const uint64_t* creg) {
+// A classical expression (postfix code from code[pc] to its QSV_C_END) on one
+// shot's classical bits, in 64-bit two's complement (include/qsv.h).
+__device__ int64_t cexec(const qsv_cop* __restrict__ code, uint64_t pc, const uint64_t* creg) {
+  int64_t s[kCStack];
+  int sp = 0;
+  for (;; ++pc) {
+    const qsv_cop c = code[pc];
+    if (c.op == QSV_C_END) return s[sp - 1];
+    if (c.op == QSV_C_IMM) {
+      s[sp++] = c.imm;
+      continue;
+    }
+    if (c.op == QSV_C_BITS) {
+      uint64_t v = 0;
+      for (uint32_t i = 0; i < c.width; ++i) {
+        const uint32_t bit = c.lo + i;
+        v |= ((creg[bit >> 6] >> (bit & 63)) & 1ull) << i;
+      }
+      if (c.sgn && c.width < 64 && ((v >> (c.width - 1)) & 1ull)) v |= ~0ull << c.width;
+      s[sp++] = (int64_t)v;
+      continue;
+    }
+    if (c.op == QSV_C_NEG || c.op == QSV_C_NOT || c.op == QSV_C_LNOT) {
+      const uint64_t a = (uint64_t)s[sp - 1];
+      s[sp - 1] = c.op == QSV_C_NEG ? (int64_t)(0ull - a) : c.op == QSV_C_NOT ? (int64_t)~a : (int64_t)(a == 0);
+      continue;
+    }
+    const int64_t b = s[--sp], a = s[sp - 1];
+    const uint64_t ua = (uint64_t)a, ub = (uint64_t)b;
+    int64_t r;
+    switch (c.op) {
+      case QSV_C_ADD: r = (int64_t)(ua + ub); break;
+      case QSV_C_SUB: r = (int64_t)(ua - ub); break;
+      case QSV_C_MUL: r = (int64_t)(ua * ub); break;
+      case QSV_C_DIV:  // truncation toward zero; INT64_MIN / -1 wraps to INT64_MIN
+        r = b == 0 ? 0 : (b == -1 ? (int64_t)(0ull - ua) : a / b);
+        break;
+      case QSV_C_MOD: r = (b == 0 || b == -1) ? 0 : a % b; break;
+      case QSV_C_AND: r = a & b; break;
+      case QSV_C_OR: r = a | b; break;
+      case QSV_C_XOR: r = a ^ b; break;
+      case QSV_C_SHL: r = (b < 0 || b >= 64) ? 0 : (int64_t)(ua << b); break;
+      case QSV_C_SHR: r = (b < 0 || b >= 64) ? (a < 0 ? -1 : 0) : (a >> b); break;
+      case QSV_C_EQ: r = a == b; break;
+      case QSV_C_NE: r = a != b; break;
+      case QSV_C_LT: r = a < b; break;
+      case QSV_C_GT: r = a > b; break;
+      case QSV_C_LE: r = a <= b; break;
+      case QSV_C_GE: r = a >= b; break;
+      case QSV_C_LAND: r = (a != 0) && (b != 0); break;
+      default: r = (a != 0) || (b != 0); break;
+    }
+    s[sp - 1] = r;
+  }
+}
+
+__device__ bool eval_pred(const DPred& p, const uint64_t* creg, const qsv_cop* code) {
   if (p.cmp == QSV_CMP_TRUE) return true;
+  if (p.cmp == QSV_CMP_EXPR) return cexec(code, p.value, creg) != 0;
   uint64_t v = 0;
   for (uint32_t i = 0; i < p.width; ++i) {
     uint32_t bit = p.lo + i;
@@ -1151,7 +1210,8 @@ __device__ bool eval_pred(const DPred& p, const uint64_t* creg) {
 // record, trajectory probability; then the site's collapse and flips are
 // composed into the shot's pending collapse and flip frame.
 __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, const SiteArgs& a, const SiteEvent* __restrict__ ev,
-                            const DPred* __restrict__ preds, uint64_t* cr, uint8_t* rec, uint32_t max_record,
+                            const DPred* __restrict__ preds, const qsv_cop* __restrict__ code, uint64_t* cr,
+                            uint8_t* rec, uint32_t max_record,
                             const uint8_t* frow, uint32_t forced_len, uint64_t seed, uint64_t key1,
                             double readout_err, double reset_err) {
   uint32_t rm = 0, rv = 0;  // restriction on the bins (pre-site logical values)
@@ -1161,7 +1221,7 @@ __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, con
     const SiteEvent E = ev[a.ev_begin + e];
     const bool active = guard_ok(cc.flags, E.guard);
     if (E.op == SE_SETF) {
-      bool v = active && eval_pred(preds[E.pred], cr);
+      bool v = active && eval_pred(preds[E.pred], cr, code);
       cc.flags = (cc.flags & ~(1ull << E.flag)) | ((uint64_t)v << E.flag);
       continue;
     }
@@ -1171,6 +1231,13 @@ __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, con
     } else if (E.op == SE_SETB || E.op == SE_CLRB) {  // classical assignment of one bit
       const uint64_t m = 1ull << (E.cbit & 63u);
       cr[E.cbit >> 6] = (E.op == SE_SETB) ? (cr[E.cbit >> 6] | m) : (cr[E.cbit >> 6] & ~m);
+    } else if (E.op == SE_CSTORE) {  // classical assignment of a computed value
+      const uint64_t v = (uint64_t)cexec(code, E.pred, cr);
+      for (uint32_t i = 0; i < E.flag; ++i) {
+        const uint32_t bit = E.cbit + i;
+        const uint64_t m = 1ull << (bit & 63u);
+        cr[bit >> 6] = ((v >> i) & 1ull) ? (cr[bit >> 6] | m) : (cr[bit >> 6] & ~m);
+      }
     } else if (E.op == SE_X) {
       xf ^= 1ull << E.q;
     } else {  // measure or reset
@@ -1241,11 +1308,12 @@ __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, con
 
 __global__ __launch_bounds__(64) void k_site_finalize(
     ShotCtl* __restrict__ ctl, SiteArgs a, const SiteEvent* __restrict__ ev,
-    const DPred* __restrict__ preds, const double* __restrict__ partials, uint32_t pblocks,
+    const DPred* __restrict__ preds, const qsv_cop* __restrict__ code, const double* __restrict__ partials,
+    uint32_t pblocks,
     uint64_t* __restrict__ creg,
     uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record, const uint8_t* __restrict__ forced,
     uint32_t forced_len, uint64_t seed, uint64_t shot_base, const uint32_t* __restrict__ slot_of, double readout_err,
-    double reset_err) {
+    double reset_err, const uint64_t* __restrict__ key) {
   __shared__ double part[4][kSiteBins];
   const uint32_t shot = blockIdx.x, tid = threadIdx.x;
   ShotCtl* c = ctl + shot;
@@ -1261,14 +1329,18 @@ __global__ __launch_bounds__(64) void k_site_finalize(
   double bins[kSiteBins];
   for (int b = 0; b < kSiteBins; ++b) bins[b] = a.nq ? ((part[0][b] + part[1][b]) + part[2][b]) + part[3][b] : 0.0;
   ShotCtl cc = *c;
-  site_events(cc, bins, a, ev, preds, creg + (uint64_t)shot * cw, record + (uint64_t)shot * max_record,
+  if (key) {
+    seed = key[0];
+    shot_base = key[1];
+  }
+  site_events(cc, bins, a, ev, preds, code, creg + (uint64_t)shot * cw, record + (uint64_t)shot * max_record,
               max_record, forced ? forced + (uint64_t)shot * forced_len : nullptr, forced_len, seed,
               shot_base + shot, readout_err, reset_err);
   *c = cc;
 }
 
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev, const DPred* preds,
-                       hipStream_t st) {
+                       const qsv_cop* code, hipStream_t st) {
   if (a.nq) {
     // with trajectory sharing the histograms are taken per slot (slot control
     // blocks in site_ctl), the outcomes per shot
@@ -1284,9 +1356,9 @@ hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_site_finalize, dim3(rb.shots), dim3(64), 0, st, rb.ctl, a, ev, preds, rb.partials,
+  hipLaunchKernelGGL(k_site_finalize, dim3(rb.shots), dim3(64), 0, st, rb.ctl, a, ev, preds, code, rb.partials,
                      rb.pblocks, rb.creg, rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len, rb.seed,
-                     rb.shot_base, rb.slot_of, rb.readout_err, rb.reset_err);
+                     rb.shot_base, rb.slot_of, rb.readout_err, rb.reset_err, rb.key);
   return hipGetLastError();
 }
 
@@ -1564,7 +1636,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
           double hb[kSiteBins];
           for (int b = 0; b < kSiteBins; ++b) hb[b] = sa.nq ? bins[b] : 0.0;
           ShotCtl c = cs;
-          site_events(c, hb, sa, R.events, R.preds, cr, rec, rec_max,
+          site_events(c, hb, sa, R.events, R.preds, R.code, cr, rec, rec_max,
                       R.forced ? R.forced + (uint64_t)shot * R.forced_len : nullptr, R.forced_len, R.seed,
                       R.shot_offset + shot, R.readout_err, R.reset_err);
           cs = c;

@@ -187,10 +187,39 @@ bool validate_program(const qsv_program_desc& d, std::string* err) {
   if (d.n_instr && !d.instr) return fail("instr is NULL");
   if (d.n_pred && !d.pred) return fail("pred is NULL");
   if (d.n_clbits > (1u << 20)) return fail("too many classical bits");
+  if (d.n_code && !d.code) return fail("code is NULL");
+  // classical expressions: every one that a predicate or store names must end
+  // within the code, read bits in range and leave exactly one value on a
+  // stack of at most kCStack values
+  auto expr_ok = [&](uint64_t begin, std::string* why) {
+    if (begin >= d.n_code) return (*why = "expression start out of range", false);
+    int depth = 0;
+    for (uint64_t pc = begin; pc < d.n_code; ++pc) {
+      const qsv_cop& c = d.code[pc];
+      int pops = 0, pushes = 1;
+      if (c.op == QSV_C_END) return depth == 1 ? true : (*why = "expression leaves a bad stack", false);
+      if (c.op >= QSV_C_COUNT) return (*why = "unknown expression op", false);
+      if (c.op == QSV_C_BITS) {
+        if (c.width < 1 || c.width > 64 || (uint64_t)c.lo + c.width > d.n_clbits)
+          return (*why = "expression bits out of range", false);
+      } else if (c.op == QSV_C_NEG || c.op == QSV_C_NOT || c.op == QSV_C_LNOT) {
+        pops = 1;
+      } else if (c.op != QSV_C_IMM) {
+        pops = 2;
+      }
+      if (depth < pops) return (*why = "expression stack underflow", false);
+      depth += pushes - pops;
+      if (depth > kCStack) return (*why = "expression stack deeper than 16", false);
+    }
+    return (*why = "expression does not end", false);
+  };
+  std::string why;
   for (uint32_t i = 0; i < d.n_pred; ++i) {
     const qsv_pred& p = d.pred[i];
-    if (p.cmp > QSV_CMP_TRUE) return fail("predicate " + std::to_string(i) + ": bad comparison");
-    if (p.cmp != QSV_CMP_TRUE) {
+    if (p.cmp > QSV_CMP_EXPR) return fail("predicate " + std::to_string(i) + ": bad comparison");
+    if (p.cmp == QSV_CMP_EXPR) {
+      if (!expr_ok(p.value, &why)) return fail("predicate " + std::to_string(i) + ": " + why);
+    } else if (p.cmp != QSV_CMP_TRUE) {
       if (p.width < 1 || p.width > 64) return fail("predicate " + std::to_string(i) + ": width must be 1..64");
       if ((uint64_t)p.lo + p.width > d.n_clbits)
         return fail("predicate " + std::to_string(i) + ": bits out of range");
@@ -226,6 +255,11 @@ bool validate_program(const qsv_program_desc& d, std::string* err) {
         break;
       case QSV_OP_SETB: case QSV_OP_CLRB:
         if (in.cbit >= d.n_clbits) return fail(at + "classical bit out of range");
+        break;
+      case QSV_OP_CSTORE:
+        if (in.flag < 1 || in.flag > 64 || (uint64_t)in.cbit + in.flag > d.n_clbits)
+          return fail(at + "stored bits out of range");
+        if (!expr_ok(in.pred, &why)) return fail(at + why);
         break;
       default:
         return fail(at + "unknown op");
@@ -409,6 +443,11 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
       } else if (in.op == QSV_OP_SETB || in.op == QSV_OP_CLRB) {
         e.op = in.op == QSV_OP_SETB ? SE_SETB : SE_CLRB;
         e.cbit = in.cbit;
+      } else if (in.op == QSV_OP_CSTORE) {
+        e.op = SE_CSTORE;
+        e.cbit = in.cbit;
+        e.flag = (uint8_t)in.flag;
+        e.pred = in.pred;
       } else {  // an X gate folded into the site
         e.op = SE_X;
         e.q = in.q0;

@@ -4,6 +4,8 @@
 #pragma once
 #include <stdint.h>
 
+#include "qsv.h"
+
 namespace qsv {
 
 constexpr int kMaxQubits = 34;      // 2^34 complex128 = 256 GiB, the HBM ceiling of one MI355X
@@ -96,7 +98,11 @@ struct PassArgs {
 };
 
 // Sequential events of a measurement site, replayed per shot by one thread.
-enum SiteOp : uint8_t { SE_MEASURE = 1, SE_RESET = 2, SE_SETF = 3, SE_CLRF = 4, SE_X = 5, SE_SETB = 6, SE_CLRB = 7 };
+enum SiteOp : uint8_t {
+  SE_MEASURE = 1, SE_RESET = 2, SE_SETF = 3, SE_CLRF = 4, SE_X = 5, SE_SETB = 6, SE_CLRB = 7,
+  SE_CSTORE = 8  // classical bits [cbit, cbit + flag) <- expression at code[pred]
+};
+constexpr int kCStack = 16;  // stack depth of classical expressions
 
 struct SiteEvent {  // 24 bytes
   uint8_t op;       // SE_*
@@ -161,6 +167,7 @@ struct ReqDev {
   const SiteArgs* sites;
   const SiteEvent* events;
   const DPred* preds;
+  const qsv_cop* code;    // classical expression code
   const double* mats;
   const uint8_t* forced;  // [shots][forced_len] or null
   uint64_t seed, shot_offset;

@@ -112,27 +112,41 @@ class Reset:
     qubits: Operand
 
 
+# Classical integer expressions (conditions included): C precedence, 64-bit
+# two's-complement values; `!` takes the whole comparison after it.
 @dataclass
-class Cond:
-    kind: str                  # "truth" | "cmp" | "not" | "and" | "or"
-    operand: Optional[Operand] = None
-    op: str = ""
-    rhs: object = None
-    inner: Optional["Cond"] = None    # "not": the negated condition; "and"/"or": the left side
-    right: Optional["Cond"] = None    # "and"/"or": the right side
+class CNum:
+    value: int
+
+
+@dataclass
+class CRef:
+    operand: Operand           # a register, variable, bit, constant or loop variable
+
+
+@dataclass
+class CUn:
+    op: str                    # "!" | "~" | "-"
+    arg: object
+
+
+@dataclass
+class CBin:
+    op: str                    # || && | ^ & == != < > <= >= << >> + - * / %
+    lhs: object
+    rhs: object
 
 
 @dataclass
 class Assign:
-    """Classical assignment: target <- an integer (value) or a condition (cond)."""
+    """Classical assignment: target <- the low bits of a classical expression."""
     target: Operand
-    value: object = None
-    cond: Optional[Cond] = None
+    expr: object
 
 
 @dataclass
 class IfStmt:
-    cond: Cond
+    cond: object               # a classical expression, true iff nonzero
     then_body: list
     else_body: list = field(default_factory=list)
 
@@ -159,8 +173,10 @@ class Continue:
 # ---------------------------------------------------------------------------
 # scanner
 # ---------------------------------------------------------------------------
-_PUNCT2 = ("->", "==", "!=", "<=", ">=", "**", "&&", "||")
-_PUNCT1 = set("()[]{};,:=<>!+-*/%@")
+_PUNCT3 = ("<<=", ">>=")
+_PUNCT2 = ("->", "==", "!=", "<=", ">=", "**", "&&", "||", "<<", ">>", "+=", "-=", "*=", "/=", "%=", "&=", "|=",
+           "^=")
+_PUNCT1 = set("()[]{};,:=<>!+-*/%@&|^~")
 
 
 def scan(text):
@@ -216,6 +232,9 @@ def scan(text):
                 j += 1
             out.append(("w", text[i:j]))
             i = j
+        elif text[i:i + 3] in _PUNCT3:
+            out.append(("p", text[i:i + 3]))
+            i += 3
         elif text[i:i + 2] in _PUNCT2:
             out.append(("p", text[i:i + 2]))
             i += 2
@@ -232,6 +251,11 @@ def scan(text):
 # parser
 # ---------------------------------------------------------------------------
 _CMP_OPS = ("==", "!=", "<", ">", "<=", ">=")
+# classical expression operators, loosest first
+_CLASSICAL_LEVELS = [("||",), ("&&",), ("|",), ("^",), ("&",), ("==", "!="), ("<", ">", "<=", ">="), ("<<", ">>"),
+                     ("+", "-"), ("*", "/", "%")]
+_COMPOUND = {"+=": "+", "-=": "-", "*=": "*", "/=": "/", "%=": "%", "&=": "&", "|=": "|", "^=": "^",
+             "<<=": "<<", ">>=": ">>"}
 _BINARY_PRECEDENCE = [("+", "-"), ("*", "/", "%"), ("**",)]
 _FUNCTIONS = ("sin", "cos", "tan", "exp", "ln", "sqrt", "arcsin", "arccos", "arctan")
 
@@ -319,6 +343,22 @@ class Parser:
                 return [Declare(v, name, size), Measure(src, Operand(name))]
             self._need(";")
             return [Declare(v, name, size)]
+        if v in ("uint", "int", "bool"):
+            # classical integer variable: uint[n] / int[n] (32 bits without a
+            # width), bool (1 bit), optionally initialised
+            self._take()
+            width = 1 if v == "bool" else 32
+            if v != "bool" and self._eat("["):
+                width = self._int_const()
+                self._need("]")
+            if not 1 <= width <= 64:
+                raise QasmError("classical variables hold 1..64 bits")
+            name = self._word()
+            out = [Declare(v, name, width)]
+            if self._eat("="):
+                out.append(Assign(Operand(name), self._cexpr()))
+            self._need(";")
+            return out
         if v in ("qreg", "creg"):
             self._take()
             name = self._word()
@@ -375,18 +415,21 @@ class Parser:
             self._need(";")
             return [Continue()]
         # "c[...] = measure q[...];", a classical assignment or a gate call
-        if self._is("=", 1) or (self._is("[", 1) and self._assignment_ahead()):
+        nxt = self._peek(1)
+        if (nxt[0] == "p" and (nxt[1] == "=" or nxt[1] in _COMPOUND)) or (self._is("[", 1) and self._assignment_ahead()):
             tgt = self._operand()
-            self._need("=")
+            k, v = self._take()
+            if v in _COMPOUND:
+                st = Assign(tgt, CBin(_COMPOUND[v], CRef(tgt), self._cexpr()))
+                self._need(";")
+                return [st]
+            if v != "=":
+                raise QasmError(f"expected = after {tgt.reg}")
             if self._eat("measure"):
                 q = self._operand()
                 self._need(";")
                 return [Measure(q, tgt)]
-            k, v = self._peek()
-            if k == "n" or v == "-":
-                st = Assign(tgt, value=self._expr())
-            else:
-                st = Assign(tgt, cond=self._cond())
+            st = Assign(tgt, self._cexpr())
             self._need(";")
             return [st]
         return [self._gate_call()]
@@ -401,7 +444,7 @@ class Parser:
                 depth -= 1
                 if depth == 0:
                     nk, nv = self.tok[j + 1]
-                    return nk == "p" and nv == "="
+                    return nk == "p" and (nv == "=" or nv in _COMPOUND)
             j += 1
         return False
 
@@ -472,38 +515,45 @@ class Parser:
     def _if(self):
         self._need("if")
         self._need("(")
-        cond = self._cond()
+        cond = self._cexpr()
         self._need(")")
         then_body = self._block()
         else_body = self._block() if self._eat("else") else []
         return IfStmt(cond, then_body, else_body)
 
-    def _cond(self):
-        """Condition: `||` of `&&` of unary conditions (`&&` binds tighter)."""
-        c = self._cond_and()
-        while self._eat("||"):
-            c = Cond("or", inner=c, right=self._cond_and())
-        return c
+    def _cexpr(self, level=0):
+        """Classical expression by precedence level (loosest first)."""
+        if level == len(_CLASSICAL_LEVELS):
+            return self._cunary()
+        lhs = self._cexpr(level + 1)
+        while self._peek()[0] == "p" and self._peek()[1] in _CLASSICAL_LEVELS[level]:
+            op = self._take()[1]
+            lhs = CBin(op, lhs, self._cexpr(level + 1))
+        return lhs
 
-    def _cond_and(self):
-        c = self._cond_unary()
-        while self._eat("&&"):
-            c = Cond("and", inner=c, right=self._cond_unary())
-        return c
-
-    def _cond_unary(self):
+    def _cunary(self):
         if self._eat("!"):
-            return Cond("not", inner=self._cond_unary())
+            return CUn("!", self._cexpr(_CLASSICAL_LEVELS.index(("==", "!="))))
+        if self._eat("~"):
+            return CUn("~", self._cunary())
+        if self._eat("-"):
+            return CUn("-", self._cunary())
+        if self._eat("+"):
+            return self._cunary()
         if self._eat("("):
-            c = self._cond()
+            e = self._cexpr()
             self._need(")")
-            return c
-        opd = self._operand()
+            return e
         k, v = self._peek()
-        if k == "p" and v in _CMP_OPS:
+        if k == "n":
             self._take()
-            return Cond("cmp", operand=opd, op=v, rhs=self._expr())
-        return Cond("truth", operand=opd)
+            if isinstance(v, float):
+                raise QasmError(f"classical expressions are integers, got {v}")
+            return CNum(v)
+        if k == "w" and v in ("true", "false"):
+            self._take()
+            return CNum(1 if v == "true" else 0)
+        return CRef(self._operand())
 
     def _for(self):
         self._need("for")

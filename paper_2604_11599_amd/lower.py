@@ -11,8 +11,9 @@ Symbol handling (Methodology, parsing and semantic analysis):
   * ``input`` parameters become slots of one flat theta vector (declaration
     order, arrays contiguous); a gate angle must be affine in at most one slot:
     angle = scale * theta[slot] + offset;
-  * classical bits of all ``bit`` registers form one flat array in declaration
-    order; a register's value is sum_i c[i] 2^i.
+  * classical bits of all ``bit`` registers and classical variables (``uint[n]``,
+    ``int[n]``, ``bool``) form one flat array in declaration order; a register's
+    value is sum_i c[i] 2^i (two's complement for ``int`` variables).
 
 Control flow becomes flags (64 per shot) and guard masks:
   if (p) A else B   ->  SETF t <- p ; SETF e <- !p ; A guarded by t ; B guarded by e
@@ -25,6 +26,11 @@ Control flow becomes flags (64 per shot) and guard masks:
   c = v / d = c     ->  SETB / CLRB per bit (v an integer; d = c copies c's bits)
   c[i] = cond       ->  the guards of cond, then SETB i under each guard where
                         it holds and CLRB i under each where it fails
+  x = <expression>  ->  CSTORE: the device evaluates the expression's postfix
+                        code on the shot's classical bits (64-bit two's
+                        complement) and stores its low bits
+  if (<expression>) ->  a predicate on the expression's code where the
+                        condition is not a register compared with a constant
 Custom ``gate`` definitions are inlined.
 """
 import math
@@ -34,14 +40,46 @@ import numpy as np
 from . import frontend as F
 
 # instruction ops, gate kinds and predicate comparisons of include/qsv.h
-OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB = 1, 2, 3, 4, 5, 6, 7
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB, OP_CSTORE = 1, 2, 3, 4, 5, 6, 7, 8
+# classical expression ops of include/qsv.h (QSV_C_*)
+(C_END, C_IMM, C_BITS, C_NEG, C_NOT, C_LNOT, C_ADD, C_SUB, C_MUL, C_DIV, C_MOD, C_AND, C_OR, C_XOR, C_SHL, C_SHR,
+ C_EQ, C_NE, C_LT, C_GT, C_LE, C_GE, C_LAND, C_LOR) = range(24)
+_C_UNARY = {"-": C_NEG, "~": C_NOT, "!": C_LNOT}
+_C_BINARY = {"+": C_ADD, "-": C_SUB, "*": C_MUL, "/": C_DIV, "%": C_MOD, "&": C_AND, "|": C_OR, "^": C_XOR,
+             "<<": C_SHL, ">>": C_SHR, "==": C_EQ, "!=": C_NE, "<": C_LT, ">": C_GT, "<=": C_LE, ">=": C_GE,
+             "&&": C_LAND, "||": C_LOR}
+C_STACK = 16
+_BOOLEAN_OPS = ("==", "!=", "<", ">", "<=", ">=", "&&", "||")
 
 
-def _has_logic(c):
-    """Whether a condition uses `&&` or `||`."""
-    if c is None:
-        return False
-    return c.kind in ("and", "or") or _has_logic(c.inner)
+def _i64(v):
+    """v as a signed 64-bit two's-complement value."""
+    v = int(v) & 0xFFFFFFFFFFFFFFFF
+    return v - (1 << 64) if v >= 1 << 63 else v
+
+
+def _fold_unary(op, a):
+    return {"-": _i64(-a), "~": _i64(~a), "!": int(a == 0)}[op]
+
+
+def _fold_binary(op, a, b):
+    """The device's 64-bit classical arithmetic on two constants."""
+    if op in ("/", "%"):
+        if b == 0:
+            return 0
+        q = abs(a) // abs(b)
+        if (a < 0) != (b < 0):
+            q = -q
+        return _i64(q if op == "/" else a - q * b)
+    if op == "<<":
+        return _i64(a << b) if 0 <= b < 64 else 0
+    if op == ">>":
+        return a >> b if 0 <= b < 64 else (-1 if a < 0 else 0)
+    table = {"+": lambda: a + b, "-": lambda: a - b, "*": lambda: a * b, "&": lambda: a & b,
+             "|": lambda: a | b, "^": lambda: a ^ b, "==": lambda: a == b, "!=": lambda: a != b,
+             "<": lambda: a < b, ">": lambda: a > b, "<=": lambda: a <= b, ">=": lambda: a >= b,
+             "&&": lambda: a != 0 and b != 0, "||": lambda: a != 0 or b != 0}
+    return _i64(int(table[op]()))
 (G_ID, G_X, G_Y, G_Z, G_H, G_S, G_SDG, G_T, G_TDG, G_SX, G_SXDG, G_RX, G_RY, G_RZ, G_P, G_U,
  G_CX, G_CY, G_CZ, G_CH, G_SWAP, G_CP, G_CRX, G_CRY, G_CRZ) = range(25)
 CMP_EQ, CMP_NE, CMP_LT, CMP_GT, CMP_LE, CMP_GE, CMP_TRUE = range(7)
@@ -59,6 +97,10 @@ INSTR_DTYPE = np.dtype({
 PRED_DTYPE = np.dtype({"names": ["lo", "width", "value", "cmp", "reserved"],
                        "formats": [np.uint32, np.uint32, np.uint64, np.uint32, np.uint32],
                        "offsets": [0, 4, 8, 16, 20], "itemsize": 24})
+CMP_EXPR = 7
+COP_DTYPE = np.dtype({"names": ["op", "sgn", "width", "lo", "imm"],
+                      "formats": [np.uint8, np.uint8, np.uint16, np.uint32, np.int64],
+                      "offsets": [0, 1, 2, 4, 8], "itemsize": 16})
 
 # name -> (kind, qubits, angles); u2 is U with theta fixed to pi/2
 _GATES = {
@@ -236,9 +278,10 @@ def _aff_add(a, b, sign):
 class LoweredProgram:
     """The flat instruction stream plus the symbol layout it was lowered with."""
 
-    def __init__(self, n_qubits, n_clbits, n_params, instr, pred, qregs, cregs, inputs):
+    def __init__(self, n_qubits, n_clbits, n_params, instr, pred, qregs, cregs, inputs, code=None):
         self.n_qubits, self.n_clbits, self.n_params = n_qubits, n_clbits, n_params
         self.instr, self.pred = instr, pred
+        self.code = np.zeros(0, COP_DTYPE) if code is None else code
         self.qregs, self.cregs, self.inputs = qregs, cregs, inputs
 
     @property
@@ -259,7 +302,9 @@ class _Lowerer:
     def __init__(self):
         self.rows = []
         self.preds, self.pred_ids = [], {}
+        self.code = []              # classical expression code (postfix), expressions end with C_END
         self.qregs, self.cregs, self.inputs = {}, {}, {}
+        self.csigned = {}           # classical register or variable -> read as two's complement
         self.consts, self.gatedefs = {}, {}
         self.nq = self.nc = self.npar = 0
         self.free = list(range(63, -1, -1))
@@ -392,87 +437,157 @@ class _Lowerer:
             raise F.QasmError(f"bit index {i} out of range for {opd.reg}")
         return [off + i]
 
-    # -- conditions --
-    def condition(self, c, env):
-        if c.kind == "not":
-            lo, width, value, cmp = self.condition(c.inner, env)
-            return lo, width, value, _NEGATE[cmp]
-        bits = self.clbits(c.operand, env)
+    # -- classical expressions --
+    def cfold(self, e, env):
+        """The value of a classical expression that reads no classical bits
+        (numbers, constants, loop variables), else None."""
+        if isinstance(e, F.CNum):
+            return _i64(e.value)
+        if isinstance(e, F.CRef):
+            o = e.operand
+            if o.reg in self.cregs:
+                return None
+            if o.index is not None:
+                raise F.QasmError(f"{o.reg} cannot be indexed in a classical expression")
+            return _i64(self.const_int(F.Name(o.reg), env))
+        if isinstance(e, F.CUn):
+            a = self.cfold(e.arg, env)
+            return None if a is None else _fold_unary(e.op, a)
+        a, b = self.cfold(e.lhs, env), self.cfold(e.rhs, env)
+        return None if a is None or b is None else _fold_binary(e.op, a, b)
+
+    def cread(self, opd, env):
+        """(first bit, width, signed) of a register, variable or bit read in an expression."""
+        bits = self.clbits(opd, env)
         if len(bits) > 64:
-            raise F.QasmError("conditions read at most 64 bits")
+            raise F.QasmError("classical values hold at most 64 bits")
         if any(b != bits[0] + i for i, b in enumerate(bits)):
-            raise F.QasmError("condition bits must be contiguous")
-        if c.kind == "truth":
-            return bits[0], len(bits), 0, CMP_NE
-        v = self.const_int(c.rhs, env)
-        if v < 0:
-            raise F.QasmError("comparison with a negative value")
-        return bits[0], len(bits), v & 0xFFFFFFFFFFFFFFFF, _CMP[c.op]
+            raise F.QasmError("classical bits must be contiguous")
+        return bits[0], len(bits), opd.index is None and self.csigned.get(opd.reg, False)
+
+    def ccode(self, e, env):
+        """Appends e's postfix code; returns where it starts."""
+        start = len(self.code)
+        depth = self._cgen(e, env, 0)
+        if depth > C_STACK:
+            raise F.QasmError(f"classical expression needs a stack deeper than {C_STACK}")
+        self.code.append((C_END, 0, 0, 0, 0))
+        return start
+
+    def _cgen(self, e, env, depth):
+        """Emits e; returns the deepest stack it uses (depth values below it)."""
+        v = self.cfold(e, env)
+        if v is not None:
+            self.code.append((C_IMM, 0, 0, 0, v))
+            return depth + 1
+        if isinstance(e, F.CRef):
+            lo, width, signed = self.cread(e.operand, env)
+            self.code.append((C_BITS, int(signed), width, lo, 0))
+            return depth + 1
+        if isinstance(e, F.CUn):
+            d = self._cgen(e.arg, env, depth)
+            self.code.append((_C_UNARY[e.op], 0, 0, 0, 0))
+            return d
+        d1 = self._cgen(e.lhs, env, depth)
+        d2 = self._cgen(e.rhs, env, depth + 1)
+        self.code.append((_C_BINARY[e.op], 0, 0, 0, 0))
+        return max(d1, d2)
+
+    # -- conditions --
+    def leaf(self, e, env):
+        """(lo, width, value, cmp) when the device can test e as a plain
+        predicate: an unsigned register, variable or bit of at most 63 bits,
+        alone (nonzero) or compared with a constant in 0..2^63-1; else None."""
+        if isinstance(e, F.CRef) and e.operand.reg in self.cregs:
+            lo, width, signed = self.cread(e.operand, env)
+            return (lo, width, 0, CMP_NE) if width <= 63 else None
+        if isinstance(e, F.CBin) and e.op in _CMP and isinstance(e.lhs, F.CRef) and e.lhs.operand.reg in self.cregs:
+            lo, width, signed = self.cread(e.lhs.operand, env)
+            v = self.cfold(e.rhs, env)
+            if signed or width > 63 or v is None or v < 0:
+                return None
+            return lo, width, v, _CMP[e.op]
+        return None
+
+    def simple(self, e, env):
+        """e as one predicate (a leaf under any number of `!`), or None."""
+        if isinstance(e, F.CUn) and e.op == "!":
+            r = self.simple(e.arg, env)
+            return None if r is None else (r[0], r[1], r[2], _NEGATE[r[3]])
+        return self.leaf(e, env)
 
     def cond_guards(self, c, env, guard, flags):
         """Guards (lists of masks) under `guard` where c holds and where it fails.
         The masks of each list are disjoint and together cover exactly those
         shots; every flag they use is set by a SETF emitted here, in order."""
-        if c.kind == "not":
-            yes, no = self.cond_guards(c.inner, env, guard, flags)
+        if isinstance(c, F.CUn) and c.op == "!":
+            yes, no = self.cond_guards(c.arg, env, guard, flags)
             return no, yes
-        if c.kind in ("and", "or"):
-            yes_l, no_l = self.cond_guards(c.inner, env, guard, flags)
+        if isinstance(c, F.CBin) and c.op in ("&&", "||"):
+            yes_l, no_l = self.cond_guards(c.lhs, env, guard, flags)
             # "and" needs the right side only where the left holds, "or" only where it fails
-            rest = yes_l if c.kind == "and" else no_l
-            yes, no = ([], list(no_l)) if c.kind == "and" else (list(yes_l), [])
+            rest = yes_l if c.op == "&&" else no_l
+            yes, no = ([], list(no_l)) if c.op == "&&" else (list(yes_l), [])
             for g in rest:
-                y, n = self.cond_guards(c.right, env, g, flags)
+                y, n = self.cond_guards(c.rhs, env, g, flags)
                 yes += y
                 no += n
             return yes, no
-        lo, width, value, cmp = self.condition(c, env)
+        lf = self.leaf(c, env)
+        if lf is not None:
+            p_yes = self._pred(*lf)
+            p_no = self._pred(lf[0], lf[1], lf[2], _NEGATE[lf[3]])
+        else:
+            # computed on the device: predicates on the expression and on its negation
+            p_yes = self._pred(0, 0, self.ccode(c, env), CMP_EXPR)
+            p_no = self._pred(0, 0, self.ccode(F.CUn("!", c), env), CMP_EXPR)
         ft, ff = self._alloc(), self._alloc()
         flags += [ft, ff]
-        self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, cmp), flag=ft)
-        self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, _NEGATE[cmp]), flag=ff)
+        self._emit(OP_SETF, guard, pred=p_yes, flag=ft)
+        self._emit(OP_SETF, guard, pred=p_no, flag=ff)
         return [guard | (1 << ft)], [guard | (1 << ff)]
 
     def assign(self, st, env, guard):
-        """Classical assignment: an integer's bits, a register copy, or the
-        truth of a condition into one bit. Every predicate of the right side
-        is evaluated (SETF) before the first bit is written."""
+        """Classical assignment: the target takes the low bits of the right
+        side's 64-bit two's-complement value. Constants become set/clear-bit
+        instructions, a register copy of equal width a per-bit copy, one bit
+        from a condition the condition's guards; anything else is evaluated on
+        the device (CSTORE). Every read of the right side happens before the
+        first bit is written."""
         bits = self.clbits(st.target, env)
-        value, c = None, st.cond
-        if c is None:
-            value = self.const_int(st.value, env)
-        elif c.kind == "truth" and c.operand.index is None and c.operand.reg not in self.cregs:
-            value = self.const_int(F.Name(c.operand.reg), env)  # a constant or loop variable
-        if value is not None:
-            if value < 0:
-                raise F.QasmError("negative value assigned to classical bits")
+        e = st.expr
+        v = self.cfold(e, env)
+        if v is not None:
             for i, b in enumerate(bits):
-                self._emit(OP_SETB if (value >> i) & 1 else OP_CLRB, guard, cbit=b)
+                self._emit(OP_SETB if (v >> i) & 1 else OP_CLRB, guard, cbit=b)
             return
-        if c.kind == "truth" and len(bits) > 1:
-            src = self.clbits(c.operand, env)
-            if len(src) != len(bits):
-                raise F.QasmError("register copy between registers of different widths")
+        if isinstance(e, F.CRef) and e.operand.reg in self.cregs:
+            src = self.clbits(e.operand, env)
             if src == bits:
                 return
-            # distinct registers do not overlap: each bit is read and written in turn
-            for s, b in zip(src, bits):
-                f = self._alloc()
-                self._emit(OP_SETF, guard, pred=self._pred(s, 1, 0, _CMP["!="]), flag=f)
-                self._emit(OP_CLRB, guard, cbit=b)
-                self._emit(OP_SETB, guard | (1 << f), cbit=b)
+            if len(src) == len(bits) and not set(src) & set(bits):
+                # distinct registers do not overlap: each bit is read and written in turn
+                for s_, b in zip(src, bits):
+                    f = self._alloc()
+                    self._emit(OP_SETF, guard, pred=self._pred(s_, 1, 0, _CMP["!="]), flag=f)
+                    self._emit(OP_CLRB, guard, cbit=b)
+                    self._emit(OP_SETB, guard | (1 << f), cbit=b)
+                    self._release(f)
+                return
+        boolean = (isinstance(e, F.CBin) and e.op in _BOOLEAN_OPS) or (isinstance(e, F.CUn) and e.op == "!")
+        if len(bits) == 1 and (boolean or isinstance(e, F.CRef)):
+            flags = []
+            yes, no = self.cond_guards(e, env, guard, flags)
+            for g in yes:
+                self._emit(OP_SETB, g, cbit=bits[0])
+            for g in no:
+                self._emit(OP_CLRB, g, cbit=bits[0])
+            for f in reversed(flags):
                 self._release(f)
             return
-        if len(bits) != 1:
-            raise F.QasmError("a condition is assigned to one bit")
-        flags = []
-        yes, no = self.cond_guards(c, env, guard, flags)
-        for g in yes:
-            self._emit(OP_SETB, g, cbit=bits[0])
-        for g in no:
-            self._emit(OP_CLRB, g, cbit=bits[0])
-        for f in reversed(flags):
-            self._release(f)
+        if any(b != bits[0] + i for i, b in enumerate(bits)) or len(bits) > 64:
+            raise F.QasmError("an assigned value needs at most 64 contiguous bits")
+        self._emit(OP_CSTORE, guard, cbit=bits[0], pred=self.ccode(e, env), flag=len(bits))
 
     # -- statements --
     def program(self, stmts):
@@ -487,7 +602,9 @@ class _Lowerer:
                     table[st.name] = (self.nq, size)
                     self.nq += size
                 else:
+                    # bit registers and classical variables share the flat array
                     table[st.name] = (self.nc, size)
+                    self.csigned[st.name] = st.kind == "int"
                     self.nc += size
             elif isinstance(st, F.InputDecl):
                 size = 1 if st.size is None else st.size
@@ -524,9 +641,9 @@ class _Lowerer:
                 self._emit(OP_RESET, guard, q0=q)
         elif isinstance(st, F.Assign):
             self.assign(st, env, guard)
-        elif isinstance(st, F.IfStmt) and _has_logic(st.cond):
-            # `&&` / `||`: the condition becomes disjoint guards (one per way it
-            # can hold, one per way it can fail), each a flag set when the if
+        elif isinstance(st, F.IfStmt) and self.simple(st.cond, env) is None:
+            # `&&` / `||` or a computed condition: disjoint guards (one per way
+            # it can hold, one per way it can fail), each a flag set when the if
             # executes; a body is emitted once under each of its guards
             flags = []
             yes, no = self.cond_guards(st.cond, env, guard, flags)
@@ -538,7 +655,7 @@ class _Lowerer:
             for f in reversed(flags):
                 self._release(f)
         elif isinstance(st, F.IfStmt):
-            lo, width, value, cmp = self.condition(st.cond, env)
+            lo, width, value, cmp = self.simple(st.cond, env)
             ft = self._alloc()
             self._emit(OP_SETF, guard, pred=self._pred(lo, width, value, cmp), flag=ft)
             fe = None
@@ -683,8 +800,9 @@ class _Lowerer:
     def result(self):
         instr = np.array(self.rows, dtype=INSTR_DTYPE) if self.rows else np.zeros(0, INSTR_DTYPE)
         pred = np.array(self.preds, dtype=PRED_DTYPE) if self.preds else np.zeros(0, PRED_DTYPE)
+        code = np.array(self.code, dtype=COP_DTYPE) if self.code else np.zeros(0, COP_DTYPE)
         return LoweredProgram(self.nq, self.nc, self.npar, instr, pred, dict(self.qregs),
-                              dict(self.cregs), dict(self.inputs))
+                              dict(self.cregs), dict(self.inputs), code)
 
 
 def _contains(body, cls):

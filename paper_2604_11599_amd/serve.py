@@ -1,9 +1,11 @@
 """Serving driver: replays a request trace against libqsv's serving engine.
 
-The engine (qsv_server_*: admission by HBM footprint, one persistent launch
-per tick over a slice of every admitted shots request, energy+gradient
-requests evaluated per tick) is native; this module only submits requests at
-their arrival times, drives the ticks and records latencies.
+The engine (qsv_server_*: admission by HBM footprint, three native worker
+lanes whose device work overlaps: persistent launches over slices of the
+admitted shots requests, wide requests on the tile passes, energy+gradient
+requests batched per program) is native; this module only submits requests at
+their arrival times, calls the non-blocking admission step and records
+latencies.
 """
 import ctypes as C
 import time
@@ -53,6 +55,12 @@ class Server:
         self._keep[t.value] = ("vqe", prog, 0)
         return t.value
 
+    def profile(self):
+        """qsv_server_profile: the lanes' summed profile as a dict."""
+        p = A.Profile()
+        self.ctx.check(A.lib().qsv_server_profile(self.handle, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in A.Profile._fields_}
+
     def step(self):
         r, w = C.c_uint32(), C.c_uint32()
         self.ctx.check(A.lib().qsv_server_step(self.handle, C.byref(r), C.byref(w)))
@@ -78,9 +86,10 @@ class Server:
                                 prog.lowered.n_clbits)
 
 
-def replay(ctx, requests, hbm_budget, shots_per_tick=256, drain_limit_s=60.0, log=None):
+def replay(ctx, requests, hbm_budget, shots_per_tick=256, drain_limit_s=60.0, log=None, profile=False):
     """Replays requests (dicts with arrival, kind, prog, shots/theta/coeffs/codes, seed)
-    in real time. Returns per-request latencies and aggregate counters."""
+    in real time. Returns per-request latencies and aggregate counters (and the
+    lanes' profile with profile=True)."""
     srv = Server(ctx, hbm_budget, shots_per_tick)
     reqs = sorted(requests, key=lambda r: r["arrival"])
     t0 = time.perf_counter()
@@ -102,25 +111,30 @@ def replay(ctx, requests, hbm_budget, shots_per_tick=256, drain_limit_s=60.0, lo
         running, waiting = srv.step()
         ticks += 1
         now = time.perf_counter() - t0
+        progressed = False
         for t in list(tickets):
             if srv.done(t):
                 r = tickets.pop(t)
                 results[r["id"]] = srv.fetch(t)
                 lat[r["id"]] = now - r["arrival"]
                 shots_done += r.get("shots", 0)
+                progressed = True
         if backlog_at_window is None and now >= window:
             backlog_at_window = len(tickets) + (len(reqs) - nxt)
         if nxt == len(reqs) and not tickets:
             break
         if now > window + drain_limit_s:
             break
-        if running == 0 and waiting == 0 and nxt < len(reqs):
-            time.sleep(max(0.0, min(0.002, reqs[nxt]["arrival"] - now)))
-        if log and ticks % 50 == 0:
+        if not progressed:
+            # nothing finished: wait a little for the lanes or the next arrival
+            nxt_t = reqs[nxt]["arrival"] - now if nxt < len(reqs) else 0.002
+            time.sleep(max(0.0, min(0.0005, nxt_t)))
+        if log and ticks % 2000 == 0:
             log(f"t={now:.1f}s submitted {nxt}/{len(reqs)} done {len(lat)} running {running} waiting {waiting}")
     elapsed = time.perf_counter() - t0
+    prof = srv.profile() if profile else None
     srv.close()
     return {"latency": lat, "results": results, "elapsed": elapsed, "window": window, "ticks": ticks,
             "shots_done": shots_done, "completed": len(lat), "submitted": nxt,
             "backlog_at_window_end": backlog_at_window if backlog_at_window is not None else 0,
-            "unfinished": len(tickets) + (len(reqs) - nxt)}
+            "unfinished": len(tickets) + (len(reqs) - nxt), "profile": prof}

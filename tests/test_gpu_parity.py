@@ -617,3 +617,51 @@ def test_c2_program_complex128_matches_oracle(ctx, n, layers, sampled, records):
         assert abs(r.record_prob[0] - o.record_prob) < PROB_TOL
         assert np.max(np.abs(r.state - o.psi)) < AMP_TOL
     assert taken >= 2
+
+
+# ---------------------------------------------------------------------------
+# Classical integer expressions and variables on the device (expression code
+# evaluated by the event interpreter: CSTORE and expression predicates)
+# ---------------------------------------------------------------------------
+CLASSICAL_BODIES = [
+    "d = c + 1; t = c > d; int[8] x = c * 3 - d; uint[5] u = (c << 2) | d; x >>= 1; u ^= x; "
+    "if (u > x) rx(0.7) q[5]; t = measure q[5];",
+    "if (c == d) x q[3]; if (c < d && (c & 1) == 0) h q[3]; if (!(c + d > 4) || c ^ d) x q[3]; t = measure q[3];",
+    "uint[4] n = 0; for uint i in [0:2] { h q[i + 6]; d[i] = measure q[i + 6]; if (d[i]) n += 1; } "
+    "if (n >= 2) x q[3]; t = measure q[3]; c = n;",
+    "int[6] y = -5; y = y / 2 + c % 3; int[16] z = (y << 3) >> 1; uint[3] w = z; if (y < 0) x q[4]; "
+    "t = measure q[4];",
+]
+
+
+def _classical_src(body, n=14, seed=0):
+    rng = np.random.default_rng(seed)
+    lines = [W.circuits.HEADER, f"qubit[{n}] q;", "bit[3] c;", "bit[3] d;", "bit t;"]
+    for q in range(n):
+        t = [float(x) for x in rng.uniform(0, 6.283, 3)]
+        lines.append(f"U({t[0]!r}, {t[1]!r}, {t[2]!r}) q[{q}];")
+    for q in range(0, n - 1, 2):
+        lines.append(f"cx q[{q}], q[{q + 1}];")
+    lines += ["c[0] = measure q[0];", "c[1] = measure q[1];", "c[2] = measure q[2];", "d = c;", body]
+    for q in range(n):
+        lines.append(f"ry({0.3 + 0.1 * q!r}) q[{q}];")
+    return "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("k", range(len(CLASSICAL_BODIES)))
+def test_classical_expressions_match_oracle(ctx, k):
+    src = _classical_src(CLASSICAL_BODIES[k], seed=k)
+    _check_shots(ctx, src, 10, seed=30 + k)
+    _check_shots(ctx, src, 10, seed=40 + k, share=True, state=False)
+    _check_shots(ctx, src, 6, seed=50 + k, forced_from_oracle=True)
+    # the persistent interpreter (12 qubits in LDS, 13 in an HBM slot)
+    for n in (12, 13):
+        s2 = _classical_src(CLASSICAL_BODIES[k], n=n, seed=k)
+        res = ctx.run_batch([{"prog": ctx.load(s2), "shots": 12, "seed": 7}])[0]
+        bits = res.bits()
+        for s in range(12):
+            o = sim.run_shot(s2, seed=7, shot=s)
+            if _near_tie(o.events):
+                continue
+            assert list(bits[s]) == o.cbits
+            assert abs(res.record_prob[s] - o.record_prob) < PROB_TOL

@@ -80,3 +80,51 @@ def test_tight_budget_admits_one_at_a_time(ctx):
     for r in reqs:
         a, b = loose["results"][r["id"]], tight["results"][r["id"]]
         assert np.array_equal(a.creg, b.creg) and np.array_equal(a.record_prob, b.record_prob)
+
+
+def test_expval_grad_each_equals_separate_calls_and_oracle(ctx):
+    """One sweep over vectors with their own Hamiltonians (what the serving
+    engine's energy lane batches) equals one call per vector bit for bit, and
+    the oracle's adjoint."""
+    src = W.c4_ansatz(8, 2)
+    prog = ctx.load(src)
+    hams = [W.c4_hamiltonian(seed=50 + k, n=8, terms=6 + k) for k in range(5)]
+    th = W.c4_thetas(seed=3, batch=5, n_params=32)
+    e, g = prog.expval_grad_each(th, hams)
+    for k in range(5):
+        e1, g1 = prog.expval_grad(th[k:k + 1], *hams[k])
+        assert e[k] == e1[0] and np.array_equal(g[k], g1[0])
+        eo, go = sim.grad_adjoint(src, th[k], *hams[k])
+        assert abs(e[k] - eo) < 1e-12 and np.max(np.abs(g[k] - go)) < 1e-11
+
+
+def test_lanes_overlap_and_late_arrivals_join(ctx):
+    """Requests submitted while the lanes work (wide, persistent and energy at
+    once) are admitted at the next step and finish with the results they have
+    alone."""
+    from paper_2604_11599_amd.serve import Server
+    wide = ctx.load(W.c1_program(seed=5, n=21, layers=6, sites=(2, 4)))
+    small = ctx.load(W.c1_program(seed=6, n=9, layers=5, sites=(1, 3)))
+    vqe = ctx.load(W.c4_ansatz(8, 2))
+    coeffs, codes = W.c4_hamiltonian(seed=9, n=8, terms=8)
+    th = W.c4_thetas(seed=4, batch=1, n_params=32)[0]
+    srv = Server(ctx, 1 << 34, shots_per_tick=16)
+    try:
+        t_w = srv.submit(wide, 12, seed=1)
+        srv.step()
+        t_s = srv.submit(small, 70, seed=2)      # arrives while the wide lane works
+        t_v = srv.submit_expval_grad(vqe, th, coeffs, codes)
+        done = {}
+        while len(done) < 3:
+            srv.step()
+            for t in (t_w, t_s, t_v):
+                if t not in done and srv.done(t):
+                    done[t] = srv.fetch(t)
+        a = wide.run_shots(12, seed=1, share=True)
+        assert np.array_equal(done[t_w].creg, a.creg) and np.array_equal(done[t_w].record_prob, a.record_prob)
+        b = ctx.run_batch([{"prog": small, "shots": 70, "seed": 2}])[0]
+        assert np.array_equal(done[t_s].creg, b.creg) and np.array_equal(done[t_s].record_prob, b.record_prob)
+        e, g = vqe.expval_grad(th[None, :], coeffs, codes)
+        assert done[t_v][0] == e[0] and np.array_equal(done[t_v][1], g[0])
+    finally:
+        srv.close()

@@ -50,15 +50,44 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         _abi.lib()
 
 
-def test_struct_layouts_match_header():
-    assert ctypes.sizeof(_abi.Config) == 40
-    assert ctypes.sizeof(_abi.ProgramDesc) == 40
-    assert ctypes.sizeof(_abi.RunOpts) == 56
-    assert ctypes.sizeof(_abi.ShotResults) == 40
-    assert ctypes.sizeof(_abi.PauliSum) == 24
-    assert ctypes.sizeof(_abi.PlanStats) == 315424 + 8 * 65536 + 16
-    from paper_2604_11599_amd.lower import INSTR_DTYPE, PRED_DTYPE
-    assert INSTR_DTYPE.itemsize == 96 and PRED_DTYPE.itemsize == 24
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures and numpy record types against the C
+    compiler's own sizeof/offsetof of include/qsv.h."""
+    import shutil
+    import subprocess
+    from paper_2604_11599_amd.lower import COP_DTYPE, INSTR_DTYPE, PRED_DTYPE
+    checks = {"qsv_config": _abi.Config, "qsv_program_desc": _abi.ProgramDesc, "qsv_run_opts": _abi.RunOpts,
+              "qsv_shot_results": _abi.ShotResults, "qsv_pauli_sum": _abi.PauliSum, "qsv_request": _abi.Request,
+              "qsv_profile": _abi.Profile, "qsv_plan_options": _abi.PlanOptions, "qsv_tune_report": _abi.TuneReport,
+              "qsv_program_info": _abi.ProgramInfo, "qsv_plan_stats": _abi.PlanStats}
+    dtypes = {"qsv_instr": INSTR_DTYPE, "qsv_pred": PRED_DTYPE, "qsv_cop": COP_DTYPE}
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qsv.h"', '#include "qsv_plan.h"',
+             'int main(void) {']
+    for name, st in checks.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    for name, dt in dtypes.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in dt.names:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    (tmp_path / "probe.c").write_text("\n".join(lines) + "\n")
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(tmp_path / "probe.c"), "-o",
+                    str(tmp_path / "probe")], check=True)
+    out = dict(line.split() for line in subprocess.run([str(tmp_path / "probe")], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for name, st in checks.items():
+        assert ctypes.sizeof(st) == int(out[name]), name
+        for f, _ in st._fields_:
+            assert getattr(st, f).offset == int(out[f"{name}.{f}"]), (name, f)
+    for name, dt in dtypes.items():
+        assert dt.itemsize == int(out[name]), name
+        for f in dt.names:
+            assert dt.fields[f][1] == int(out[f"{name}.{f}"]), (name, f)
 
 
 # ---------------------------------------------------------------------------
@@ -270,10 +299,41 @@ def test_classical_assignment_forms():
         for body in ("d = c; c = 5;", "c[2] = c[0] && !c[1] || !c[0] && c[1]; if (c[2]) x q[3]; t = measure q[3];",
                      "c[0] = !c[0] && c[1]; d[1] = c >= 3;", "c = k; d = 0b101; d[0] = c[1];"):
             _compare(head + pre + meas + body, shots=1)
-    # a condition into a whole register, a negative value, a copy between widths
-    for bad in ("c = d[0] && d[1];", "c = -1;", "c = t;"):
+        # integer semantics: a condition into a whole register, a negative value,
+        # a copy between widths
+        for body in ("c = d[0] && d[1];", "c = -1;", "c = t;", "d = c + 3;"):
+            _compare(head + pre + meas + body, shots=1)
+    # not integers, or not classical
+    for bad in ("c = 1.5;", "c = q;", "c = c + q[0];"):
         with pytest.raises(QasmError):
             lower(head + bad)
+
+
+CLASSICAL_PROGRAMS = [
+    # register arithmetic and bitwise operators, stored on the device
+    "d = c + 1; t = c > d; int[8] x = c * 3 - d; uint[5] u = (c << 2) | d; x >>= 1; u ^= x;",
+    # register-versus-register comparisons and expressions in conditions
+    "if (c == d) x q[3]; if (c < d && (c & 1) == 0) h q[3]; if (!(c + d > 4) || c ^ d) x q[3]; t = measure q[3];",
+    # a counter over a bounded loop with feed-forward on the count
+    "uint[4] n = 0; for uint i in [0:2] { h q[i]; c[i] = measure q[i]; if (c[i]) n += 1; } "
+    "if (n >= 2) x q[3]; t = measure q[3]; d = n;",
+    # signed variables, division and modulo, shifts past the width
+    "int[6] y = -5; y = y / 2 + c % 3; int[16] z = (y << 3) >> 1; uint[3] w = z; if (y < 0) x q[3]; t = measure q[3];",
+    # compound assignments on bits and variables; constants fold
+    "bool b = c[0]; b |= c[1]; c[2] ^= b; int[8] m = k * 4 + 1; m -= c; if (m % 2 == 1) x q[3]; t = measure q[3];",
+]
+
+
+@pytest.mark.parametrize("body", CLASSICAL_PROGRAMS)
+def test_lowering_of_classical_expressions_matches_oracle(body):
+    """Integer variables, register arithmetic, register-versus-register
+    comparisons and computed conditions: the lowered stream (expression code
+    stored by CSTORE, EXPR predicates) equals the oracle's tree walk."""
+    head = ('OPENQASM 3.0;\ninclude "stdgates.inc";\nconst int k = 6;\nqubit[4] q;\nbit[3] c;\n'
+            'bit[3] d;\nbit t;\n')
+    for pre in ("", "x q[0];", "x q[1]; x q[2];", "x q[0]; x q[2];", "h q[0]; h q[1]; h q[2];"):
+        meas = "c[0] = measure q[0]; c[1] = measure q[1]; c[2] = measure q[2]; d = c;"
+        _compare(head + pre + meas + body, shots=3)
 
 
 MULTI_CONTROL = [

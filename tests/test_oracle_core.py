@@ -114,7 +114,7 @@ def test_parser_constructs():
     kinds = [st[0] for st in ast]
     assert kinds == ["input", "qubit", "bit", "const", "gatedef", "gate", "measure", "measure",
                      "if", "for", "barrier"]
-    assert ast[8][1] == ("cmp", "==", ("ref", "c", None), ("num", 3))
+    assert ast[8][1] == ("cbin", "==", ("cref", ("ref", "c", None)), ("cnum", 3))
     with pytest.raises(QasmSyntaxError):
         parse("qubit[2] q; while (c == 0) { x q[0]; }")
 
