@@ -143,7 +143,8 @@ typedef struct {
   uint32_t pred;       /* SETF: index into the predicate table */
   uint32_t flag;       /* SETF/CLRF: flag bit 0..63 */
   uint64_t guard;      /* guard mask over the flag bits */
-  /* gate angle k = scale[k] * theta[param[k]] + offset[k]; param[k] = QSV_NONE -> offset[k] */
+  /* gate angle k = scale[k] * theta[param[k]] + offset[k]; param[k] = QSV_NONE -> offset[k];
+     param[k] >= n_params names derived parameter param[k] - n_params */
   uint32_t param[3];
   uint32_t reserved2;
   double scale[3];
@@ -190,6 +191,12 @@ typedef struct {
 } qsv_cop;
 
 typedef struct {
+  uint32_t out;        /* derived parameter index (< n_derived) */
+  uint32_t in;         /* input parameter index (< n_params) */
+  double coef;
+} qsv_lin;
+
+typedef struct {
   uint32_t n_qubits;   /* 1 .. 34 */
   uint32_t n_clbits;
   uint32_t n_params;   /* length of the theta vector */
@@ -201,6 +208,12 @@ typedef struct {
   uint32_t n_code;     /* classical expression code (QSV_OP_CSTORE, QSV_CMP_EXPR) */
   uint32_t reserved2;
   const qsv_cop* code;
+  /* Derived parameters, for gate angles that combine several inputs: derived
+     parameter k (k < n_derived) is sum of coef * theta[in] over the entries
+     with out == k; a gate angle's param index n_params + k reads it. */
+  uint32_t n_lin;
+  uint32_t n_derived;
+  const qsv_lin* lin;
 } qsv_program_desc;
 
 /* Validates and deep-copies desc, plans the GPU passes and uploads them: the

@@ -32,7 +32,7 @@ class ProgramDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_uint32), ("n_clbits", C.c_uint32), ("n_params", C.c_uint32),
                 ("n_instr", C.c_uint32), ("n_pred", C.c_uint32), ("reserved", C.c_uint32),
                 ("instr", C.c_void_p), ("pred", C.c_void_p), ("n_code", C.c_uint32), ("reserved2", C.c_uint32),
-                ("code", C.c_void_p)]
+                ("code", C.c_void_p), ("n_lin", C.c_uint32), ("n_derived", C.c_uint32), ("lin", C.c_void_p)]
 
 
 class ProgramInfo(C.Structure):

@@ -22,10 +22,12 @@ def _desc(lp):
     instr = np.ascontiguousarray(lp.instr)
     pred = np.ascontiguousarray(lp.pred)
     code = np.ascontiguousarray(lp.code)
+    lin = np.ascontiguousarray(lp.lin)
     d = A.ProgramDesc(lp.n_qubits, lp.n_clbits, lp.n_params, len(instr), len(pred), 0,
                       instr.ctypes.data if len(instr) else None, pred.ctypes.data if len(pred) else None,
-                      len(code), 0, code.ctypes.data if len(code) else None)
-    return d, (instr, pred, code)
+                      len(code), 0, code.ctypes.data if len(code) else None,
+                      len(lin), lp.n_derived, lin.ctypes.data if len(lin) else None)
+    return d, (instr, pred, code, lin)
 
 
 def plan_inspect(source, tile_bits=0):

@@ -72,6 +72,7 @@ struct qsv_program {
   std::vector<qsv_instr> instr;
   std::vector<qsv_pred> pred;
   std::vector<qsv_cop> code;
+  std::vector<qsv_lin> lin;
   Plan plan;
   // device copies of the static plan
   DGate* d_gates = nullptr;
@@ -84,6 +85,10 @@ struct qsv_program {
   SiteEvent* d_events = nullptr;
   DPred* d_preds = nullptr;
   qsv_cop* d_code = nullptr;
+  // derived parameters by index: entries [lin_off[k], lin_off[k + 1]) of (in, coef)
+  uint32_t* d_lin_off = nullptr;
+  uint32_t* d_lin_in = nullptr;
+  double* d_lin_coef = nullptr;
   uint32_t* d_csr_off = nullptr;
   uint32_t* d_csr_sj = nullptr;
   double* d_csr_scale = nullptr;
@@ -312,6 +317,21 @@ void to_public(const PlanOptions& o, qsv_plan_options* out) {
   out->dense_min_cost = o.dense_min_cost;
 }
 
+// The theta rows gate matrices are bound from: theta itself, or theta
+// extended by the program's derived parameters into ext ([batch][P + D]).
+hipError_t bind_theta(const qsv_program* prog, const double* theta, uint32_t batch, double* ext, hipStream_t st,
+                      const double** rows, uint32_t* stride) {
+  const uint32_t P = prog->desc.n_params, D = prog->desc.n_derived;
+  if (!D) {
+    *rows = theta;
+    *stride = P;
+    return hipSuccess;
+  }
+  *rows = ext;
+  *stride = P + D;
+  return launch_derive_params(theta, P, D, prog->d_lin_off, prog->d_lin_in, prog->d_lin_coef, batch, ext, st);
+}
+
 // Frees the device copies of a program's plan.
 void free_plan_buffers(qsv_program* p) {
   if (p->graph) ignore(hipGraphExecDestroy(p->graph));
@@ -319,7 +339,7 @@ void free_plan_buffers(qsv_program* p) {
   p->graph_key.clear();
   void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense,
                   p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off,
-                  p->d_code};
+                  p->d_code, p->d_lin_off, p->d_lin_in, p->d_lin_coef};
   for (void* q : ptrs)
     if (q) ignore(hipFree(q));
   p->d_gates = nullptr;
@@ -337,6 +357,9 @@ void free_plan_buffers(qsv_program* p) {
   p->d_ang_ent = nullptr;
   p->d_ang_off = nullptr;
   p->d_code = nullptr;
+  p->d_lin_off = nullptr;
+  p->d_lin_in = nullptr;
+  p->d_lin_coef = nullptr;
 }
 
 // Plans the program's stream with options o and uploads the plan (replacing a
@@ -361,12 +384,22 @@ qsv_status install_plan(qsv_context* ctx, qsv_program* p, const PlanOptions& o) 
   // parameter -> (slot*3 + angle, scale) lists for the gradient chain rule
   std::vector<uint32_t> off(desc->n_params + 1, 0), sj;
   std::vector<double> sc;
+  // (an angle on a derived parameter contributes to each of its inputs)
+  std::vector<std::vector<std::pair<uint32_t, double>>> derived(desc->n_derived);
+  for (const qsv_lin& l : p->lin) derived[l.out].push_back({l.in, l.coef});
   {
     std::vector<std::vector<std::pair<uint32_t, double>>> lists(desc->n_params);
     for (uint32_t s = 0; s < pl.gate_src.size(); ++s)
-      for (int j = 0; j < 3; ++j)
-        if (pl.gate_src[s].param[j] != QSV_NONE)
-          lists[pl.gate_src[s].param[j]].push_back({s * 3 + j, pl.gate_src[s].scale[j]});
+      for (int j = 0; j < 3; ++j) {
+        const uint32_t par = pl.gate_src[s].param[j];
+        if (par == QSV_NONE) continue;
+        if (par < desc->n_params) {
+          lists[par].push_back({s * 3 + j, pl.gate_src[s].scale[j]});
+        } else {
+          for (const auto& t : derived[par - desc->n_params])
+            lists[t.first].push_back({s * 3 + j, pl.gate_src[s].scale[j] * t.second});
+        }
+      }
     for (uint32_t k = 0; k < desc->n_params; ++k) {
       off[k + 1] = off[k] + (uint32_t)lists[k].size();
       for (auto& e : lists[k]) {
@@ -419,6 +452,20 @@ qsv_status install_plan(qsv_context* ctx, qsv_program* p, const PlanOptions& o) 
   if (e == hipSuccess) e = upload(pl.events, &p->d_events);
   if (e == hipSuccess) e = upload(dp, &p->d_preds);
   if (e == hipSuccess) e = upload(p->code, &p->d_code);
+  if (desc->n_derived) {
+    std::vector<uint32_t> loff(desc->n_derived + 1, 0), lin_in;
+    std::vector<double> lin_coef;
+    for (uint32_t k = 0; k < desc->n_derived; ++k) {
+      for (const auto& t : derived[k]) {
+        lin_in.push_back(t.first);
+        lin_coef.push_back(t.second);
+      }
+      loff[k + 1] = (uint32_t)lin_in.size();
+    }
+    if (e == hipSuccess) e = upload(loff, &p->d_lin_off);
+    if (e == hipSuccess) e = upload(lin_in, &p->d_lin_in);
+    if (e == hipSuccess) e = upload(lin_coef, &p->d_lin_coef);
+  }
   if (e == hipSuccess) e = upload(off, &p->d_csr_off);
   if (e == hipSuccess) e = upload(sj, &p->d_csr_sj);
   if (e == hipSuccess) e = upload(sc, &p->d_csr_scale);
@@ -524,10 +571,12 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
   p->instr.assign(desc->instr, desc->instr + desc->n_instr);
   p->pred.assign(desc->pred, desc->pred + desc->n_pred);
   if (desc->n_code) p->code.assign(desc->code, desc->code + desc->n_code);
+  if (desc->n_lin) p->lin.assign(desc->lin, desc->lin + desc->n_lin);
   p->desc = *desc;
   p->desc.instr = p->instr.data();
   p->desc.pred = p->pred.data();
   p->desc.code = p->code.data();
+  p->desc.lin = p->lin.data();
   PlanOptions o;
   if (ctx->flags & QSV_FLAG_TUNED_PLANS) tuned_options(ctx, desc->n_qubits, false, &o);
   const qsv_status st = install_plan(ctx, p.get(), o);
@@ -604,6 +653,8 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   const uint32_t n_slots = (uint32_t)pl.gate_src.size();
   HIP_TRY(scr.get(std::max<uint32_t>(1, prog->desc.n_params), &d_theta));
   HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride, &d_mats));
+  double* d_ext = nullptr;
+  if (prog->desc.n_derived) HIP_TRY(scr.get(prog->desc.n_params + prog->desc.n_derived, &d_ext));
   if (prog->desc.n_params)
     HIP_TRY(hipMemcpyAsync(d_theta, theta, prog->desc.n_params * 8, hipMemcpyHostToDevice, st));
   RunBuffers rb{};
@@ -614,7 +665,10 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   const bool use_graph = (opts->flags & QSV_RUN_GRAPH) != 0 && !share_req && n_shots <= batch &&
                          ctx->stream != nullptr && !ctx->noalloc;
   auto bind = [&]() -> qsv_status {
-    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, prog->desc.n_params, 1, d_mats, nullptr, st));
+    const double* rows = nullptr;
+    uint32_t stride = 0;
+    HIP_TRY(bind_theta(prog, d_theta, 1, d_ext, st, &rows, &stride));
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, stride, 1, d_mats, nullptr, st));
     HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, 1,
                                  0, d_mats, st));
     return QSV_OK;
@@ -983,7 +1037,12 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       const qsv_program* p = q.prog;
       const uint32_t P = p->desc.n_params, slots = (uint32_t)p->plan.gate_src.size();
       if (P) HIP_TRY(hipMemcpyAsync(d_theta + to, q.theta, P * 8, hipMemcpyHostToDevice, st));
-      HIP_TRY(launch_bind_matrices(p->d_src, slots, d_theta + to, P, 1, d_mats + mo, nullptr, st));
+      double* ext = nullptr;
+      if (p->desc.n_derived) HIP_TRY(scr.get(P + p->desc.n_derived, &ext));
+      const double* rows = nullptr;
+      uint32_t stride = 0;
+      HIP_TRY(bind_theta(p, d_theta + to, 1, ext, st, &rows, &stride));
+      HIP_TRY(launch_bind_matrices(p->d_src, slots, rows, stride, 1, d_mats + mo, nullptr, st));
       ReqDev& R = rd[i];
       std::memset(&R, 0, sizeof(R));
       R.steps = p->d_steps;
@@ -1218,6 +1277,8 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   RunBuffers rb{};
   double2* d_lam = nullptr;
   HIP_TRY(scr.get(chunk * std::max<uint32_t>(P, 1), &d_theta));
+  double* d_ext = nullptr;
+  if (prog->desc.n_derived) HIP_TRY(scr.get(chunk * (P + prog->desc.n_derived), &d_ext));
   HIP_TRY(scr.get(chunk * std::max<uint32_t>(n_slots, 1) * kMatStride, &d_mats));
   HIP_TRY(scr.get(chunk * blocks, &d_tp));
   HIP_TRY(scr.get(chunk, &d_energy));
@@ -1242,7 +1303,10 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
     if (P)
       HIP_TRY(hipMemcpyAsync(d_theta, theta + b0 * P, (size_t)bs * P * 8,
                              dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, d_theta, P, bs, d_mats, d_dmats, st));
+    const double* rows = nullptr;
+    uint32_t stride = 0;
+    HIP_TRY(bind_theta(prog, d_theta, bs, d_ext, st, &rows, &stride));
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, stride, bs, d_mats, d_dmats, st));
     HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, bs,
                                  ms, d_mats, st));
     if (grad && n_ent)

@@ -40,6 +40,9 @@ struct RunBuffers {
 // LDS limit to max_lds. Cached per device, kernel, size and LDS.
 hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_t max_lds, uint32_t* out);
 
+// theta [batch][P] -> [batch][P + D] with the derived parameters appended
+hipError_t launch_derive_params(const double* theta, uint32_t P, uint32_t D, const uint32_t* off, const uint32_t* in,
+                                const double* coef, uint32_t batch, double* out, hipStream_t st);
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);

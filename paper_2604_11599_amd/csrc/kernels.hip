@@ -65,6 +65,35 @@ __device__ __forceinline__ double2 cexpi(double t) {
   return make_double2(c, s);
 }
 
+// theta extended by the derived parameters: out[b] = theta[b] (P values)
+// followed by D values, derived k = sum of coef[e] * theta[b][in[e]] over
+// e in [off[k], off[k + 1]) in that order.
+__global__ void k_derive_params(const double* __restrict__ theta, uint32_t P, uint32_t D,
+                                const uint32_t* __restrict__ off, const uint32_t* __restrict__ in,
+                                const double* __restrict__ coef, uint32_t batch, double* __restrict__ out) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t W = P + D;
+  if (idx >= (uint64_t)batch * W) return;
+  const uint32_t b = (uint32_t)(idx / W), j = (uint32_t)(idx % W);
+  const double* t = theta + (uint64_t)b * P;
+  double v = 0.0;
+  if (j < P) {
+    v = t[j];
+  } else {
+    for (uint32_t e = off[j - P]; e < off[j - P + 1]; ++e) v += coef[e] * t[in[e]];
+  }
+  out[idx] = v;
+}
+
+hipError_t launch_derive_params(const double* theta, uint32_t P, uint32_t D, const uint32_t* off, const uint32_t* in,
+                                const double* coef, uint32_t batch, double* out, hipStream_t st) {
+  const uint64_t total = (uint64_t)batch * (P + D);
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_derive_params, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, theta, P, D, off, in,
+                     coef, batch, out);
+  return hipGetLastError();
+}
+
 __global__ void k_bind_matrices(const GateSrc* __restrict__ src, uint32_t n_slots,
                                 const double* __restrict__ theta, uint32_t n_params, uint32_t batch,
                                 double* __restrict__ mats, double* __restrict__ dmats) {

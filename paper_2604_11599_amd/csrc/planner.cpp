@@ -188,6 +188,11 @@ bool validate_program(const qsv_program_desc& d, std::string* err) {
   if (d.n_pred && !d.pred) return fail("pred is NULL");
   if (d.n_clbits > (1u << 20)) return fail("too many classical bits");
   if (d.n_code && !d.code) return fail("code is NULL");
+  if (d.n_lin && !d.lin) return fail("lin is NULL");
+  if (d.n_derived > (1u << 20)) return fail("too many derived parameters");
+  for (uint32_t i = 0; i < d.n_lin; ++i)
+    if (d.lin[i].out >= d.n_derived || d.lin[i].in >= d.n_params)
+      return fail("derived parameter entry " + std::to_string(i) + " out of range");
   // classical expressions: every one that a predicate or store names must end
   // within the code, read bits in range and leave exactly one value on a
   // stack of at most kCStack values
@@ -235,7 +240,7 @@ bool validate_program(const qsv_program_desc& d, std::string* err) {
         if (two_qubit(in.kind) && (in.q1 >= d.n_qubits || in.q1 == in.q0))
           return fail(at + "second qubit out of range or repeated");
         for (int k = 0; k < angle_count(in.kind); ++k)
-          if (in.param[k] != QSV_NONE && in.param[k] >= d.n_params)
+          if (in.param[k] != QSV_NONE && in.param[k] >= d.n_params + d.n_derived)
             return fail(at + "parameter index out of range");
         break;
       }

@@ -9,8 +9,10 @@ program is lowered and loaded once and run with many parameter vectors.
 Symbol handling (Methodology, parsing and semantic analysis):
   * compile-time constants and loop variables are folded to numbers;
   * ``input`` parameters become slots of one flat theta vector (declaration
-    order, arrays contiguous); a gate angle must be affine in at most one slot:
-    angle = scale * theta[slot] + offset;
+    order, arrays contiguous); a gate angle is affine in them:
+    angle = scale * theta[slot] + offset, where an angle that combines several
+    inputs reads a derived parameter (a linear combination of inputs the
+    device forms from theta before binding);
   * classical bits of all ``bit`` registers and classical variables (``uint[n]``,
     ``int[n]``, ``bool``) form one flat array in declaration order; a register's
     value is sum_i c[i] 2^i (two's complement for ``int`` variables).
@@ -98,6 +100,8 @@ PRED_DTYPE = np.dtype({"names": ["lo", "width", "value", "cmp", "reserved"],
                        "formats": [np.uint32, np.uint32, np.uint64, np.uint32, np.uint32],
                        "offsets": [0, 4, 8, 16, 20], "itemsize": 24})
 CMP_EXPR = 7
+LIN_DTYPE = np.dtype({"names": ["out", "in", "coef"], "formats": [np.uint32, np.uint32, np.float64],
+                      "offsets": [0, 4, 8], "itemsize": 16})
 COP_DTYPE = np.dtype({"names": ["op", "sgn", "width", "lo", "imm"],
                       "formats": [np.uint8, np.uint8, np.uint16, np.uint32, np.int64],
                       "offsets": [0, 1, 2, 4, 8], "itemsize": 16})
@@ -278,10 +282,13 @@ def _aff_add(a, b, sign):
 class LoweredProgram:
     """The flat instruction stream plus the symbol layout it was lowered with."""
 
-    def __init__(self, n_qubits, n_clbits, n_params, instr, pred, qregs, cregs, inputs, code=None):
+    def __init__(self, n_qubits, n_clbits, n_params, instr, pred, qregs, cregs, inputs, code=None, lin=None,
+                 n_derived=0):
         self.n_qubits, self.n_clbits, self.n_params = n_qubits, n_clbits, n_params
         self.instr, self.pred = instr, pred
         self.code = np.zeros(0, COP_DTYPE) if code is None else code
+        self.lin = np.zeros(0, LIN_DTYPE) if lin is None else lin
+        self.n_derived = n_derived
         self.qregs, self.cregs, self.inputs = qregs, cregs, inputs
 
     @property
@@ -303,6 +310,7 @@ class _Lowerer:
         self.rows = []
         self.preds, self.pred_ids = [], {}
         self.code = []              # classical expression code (postfix), expressions end with C_END
+        self.derived, self.derived_ids = [], {}  # derived parameters: sorted ((slot, coef), ...)
         self.qregs, self.cregs, self.inputs = {}, {}, {}
         self.csigned = {}           # classical register or variable -> read as two's complement
         self.consts, self.gatedefs = {}, {}
@@ -325,11 +333,16 @@ class _Lowerer:
             raise F.QasmError("program unrolls to too many instructions")
         param, scale, offset = [NONE32] * 3, [0.0] * 3, [0.0] * 3
         for k, a in enumerate(angles):
-            if len(a.terms) > 1:
-                raise F.QasmError("a gate angle may depend on at most one input parameter")
             offset[k] = float(a.c)
-            for slot, coef in a.terms.items():
-                param[k], scale[k] = slot, float(coef)
+            terms = {s_: float(c) for s_, c in a.terms.items() if c != 0.0}
+            if len(terms) > 1:
+                key = tuple(sorted(terms.items()))
+                if key not in self.derived_ids:
+                    self.derived_ids[key] = len(self.derived)
+                    self.derived.append(key)
+                param[k], scale[k] = self.npar + self.derived_ids[key], 1.0
+            for slot, coef in terms.items() if len(terms) == 1 else ():
+                param[k], scale[k] = slot, coef
         self.rows.append((op, kind, 0, q0, q1, cbit, pred, flag, guard, tuple(param), 0,
                           tuple(scale), tuple(offset)))
 
@@ -801,8 +814,10 @@ class _Lowerer:
         instr = np.array(self.rows, dtype=INSTR_DTYPE) if self.rows else np.zeros(0, INSTR_DTYPE)
         pred = np.array(self.preds, dtype=PRED_DTYPE) if self.preds else np.zeros(0, PRED_DTYPE)
         code = np.array(self.code, dtype=COP_DTYPE) if self.code else np.zeros(0, COP_DTYPE)
+        lin = [(k, slot, coef) for k, terms in enumerate(self.derived) for slot, coef in terms]
+        lin = np.array(lin, dtype=LIN_DTYPE) if lin else np.zeros(0, LIN_DTYPE)
         return LoweredProgram(self.nq, self.nc, self.npar, instr, pred, dict(self.qregs),
-                              dict(self.cregs), dict(self.inputs), code)
+                              dict(self.cregs), dict(self.inputs), code, lin, len(self.derived))
 
 
 def _contains(body, cls):

@@ -109,8 +109,14 @@ def run(lp, theta=(), seed=0, shot=0, forced=None):
             angles = []
             for k in range(N_ANGLES.get(name, 0)):
                 a = float(ins["offset"][k])
-                if int(ins["param"][k]) != 0xFFFFFFFF:
-                    a += float(ins["scale"][k]) * float(theta[int(ins["param"][k])])
+                par = int(ins["param"][k])
+                if par != 0xFFFFFFFF:
+                    if par >= lp.n_params:  # a derived parameter: a combination of inputs
+                        v = sum(float(e["coef"]) * float(theta[int(e["in"])]) for e in lp.lin
+                                if int(e["out"]) == par - lp.n_params)
+                    else:
+                        v = float(theta[par])
+                    a += float(ins["scale"][k]) * v
                 angles.append(a)
             m, nq = G.gate_matrix(name, angles)
             qs = [int(ins["q0"])] + ([int(ins["q1"])] if nq == 2 else [])

@@ -665,3 +665,48 @@ def test_classical_expressions_match_oracle(ctx, k):
                 continue
             assert list(bits[s]) == o.cbits
             assert abs(res.record_prob[s] - o.record_prob) < PROB_TOL
+
+
+# ---------------------------------------------------------------------------
+# Gate angles that combine several inputs (derived parameters formed on the
+# device before binding; gradients reach every input through the chain rule)
+# ---------------------------------------------------------------------------
+def _multi_input_program(n, measure):
+    lines = [W.circuits.HEADER, "input array[float[64], 4] t;", "input float[64] s;", f"qubit[{n}] q;"]
+    if measure:
+        lines.append(f"bit[{n}] c;")
+    for layer in range(3):
+        for q in range(n):
+            lines.append([f"rx(t[0] + t[1] * {q + 1}) q[{q}];", f"ry(2 * t[2] - t[{q % 4}] + 0.3) q[{q}];",
+                          f"U(t[3] - s, t[1] + t[2], s / 2 + t[{(q + layer) % 4}]) q[{q}];"][(q + layer) % 3])
+        for q in range(layer % 2, n - 1, 2):
+            lines.append(f"crz(t[0] + s) q[{q}], q[{q + 1}];" if q % 4 == 0 else f"cx q[{q}], q[{q + 1}];")
+    if measure:
+        lines.append("c = measure q;")
+    return "\n".join(lines) + "\n"
+
+
+def test_angles_combining_inputs_shots_and_gradients(ctx):
+    th = np.array([0.4, -1.1, 2.3, 0.7, -0.35])
+    dyn = _multi_input_program(13, True)
+    _check_shots(ctx, dyn, 6, seed=3, theta=th, state=False)
+    res = ctx.run_batch([{"prog": ctx.load(dyn), "shots": 6, "seed": 3, "theta": th}])[0]
+    for s in range(6):
+        o = sim.run_shot(dyn, th, seed=3, shot=s)
+        if not _near_tie(o.events):
+            assert list(res.bits()[s]) == o.cbits
+    src = _multi_input_program(12, False)
+    coeffs, codes = W.c4_hamiltonian(seed=12, n=12, terms=14)
+    thetas = np.stack([th, th[::-1] * 0.7, th + 1.0])
+    prog = ctx.load(src)
+    e, g = prog.expval_grad(thetas, coeffs, codes)
+    for b in range(3):
+        eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
+        assert abs(e[b] - eo) < 1e-12 and np.max(np.abs(g[b] - go)) < 1e-11
+    h = 1e-5
+    for k in range(5):
+        tp, tm = thetas[:1].copy(), thetas[:1].copy()
+        tp[0, k] += h
+        tm[0, k] -= h
+        fd = (prog.expval(tp, coeffs, codes)[0] - prog.expval(tm, coeffs, codes)[0]) / (2 * h)
+        assert abs(fd - g[0, k]) < 1e-7

@@ -55,12 +55,12 @@ def test_struct_layouts_match_header(tmp_path):
     compiler's own sizeof/offsetof of include/qsv.h."""
     import shutil
     import subprocess
-    from paper_2604_11599_amd.lower import COP_DTYPE, INSTR_DTYPE, PRED_DTYPE
+    from paper_2604_11599_amd.lower import COP_DTYPE, INSTR_DTYPE, LIN_DTYPE, PRED_DTYPE
     checks = {"qsv_config": _abi.Config, "qsv_program_desc": _abi.ProgramDesc, "qsv_run_opts": _abi.RunOpts,
               "qsv_shot_results": _abi.ShotResults, "qsv_pauli_sum": _abi.PauliSum, "qsv_request": _abi.Request,
               "qsv_profile": _abi.Profile, "qsv_plan_options": _abi.PlanOptions, "qsv_tune_report": _abi.TuneReport,
               "qsv_program_info": _abi.ProgramInfo, "qsv_plan_stats": _abi.PlanStats}
-    dtypes = {"qsv_instr": INSTR_DTYPE, "qsv_pred": PRED_DTYPE, "qsv_cop": COP_DTYPE}
+    dtypes = {"qsv_instr": INSTR_DTYPE, "qsv_pred": PRED_DTYPE, "qsv_cop": COP_DTYPE, "qsv_lin": LIN_DTYPE}
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
@@ -140,7 +140,6 @@ def test_lowering_errors():
     for bad in ["qubit[2] q; while (true) { x q[0]; }",
                 "qubit[2] q; foo q[0];",
                 "qubit[2] q; input float[64] a; input float[64] b; rx(a * b) q[0];",
-                "qubit[2] q; input float[64] a; input float[64] b; rx(a + b) q[0];",
                 "qubit[2] q; break;",
                 "qubit[2] q; cx q[0], q[0];",
                 "qubit[35] q;",
@@ -148,6 +147,20 @@ def test_lowering_errors():
                 "bit[2] c;"]:
         with pytest.raises(QasmError):
             lower(bad)
+
+
+def test_angles_combining_several_inputs_match_oracle():
+    """An angle affine in several inputs reads a derived parameter (one per
+    distinct combination, formed on the device before binding)."""
+    src = ('OPENQASM 3.0;\ninclude "stdgates.inc";\ninput array[float[64], 3] t;\ninput float[64] s;\n'
+           'qubit[3] q;\nbit[3] c;\n'
+           'rx(t[0] + t[1]) q[0]; ry(2 * t[2] - t[0] + 0.3) q[1]; U(t[0] - s, t[1] + t[2], s / 2 + t[0]) q[2];\n'
+           'cx q[0], q[1]; crz(t[0] + t[1]) q[1], q[2]; rz(t[1]) q[0]; cp(3 * s + t[2]) q[2], q[0];\n'
+           'c = measure q;\n')
+    lp = lower(src)
+    assert lp.n_derived == 6 and lp.n_params == 4
+    for theta in ([0.4, -1.1, 2.3, 0.7], [1.9, 0.2, -0.6, -2.5]):
+        _compare(src, np.array(theta), shots=3)
 
 
 def test_flag_layout_of_if_else():
