@@ -252,6 +252,20 @@ def traffic_from_profiles(name):
     return d.get("bytes_per_launch")
 
 
+def c4_traffic():
+    """HBM bytes per launch of the energy + gradient kernels from committed
+    counter runs taken on the current kernel source, by kernel name."""
+    path = os.path.join(ROOT, "profiles", "c4_20q_traffic.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        d = json.load(f)
+    from traffic_summary import kernel_hash
+    if d.get("kernel_hash") != kernel_hash():
+        return {}
+    return {k: v["bytes_per_launch"] for k, v in d.get("kernels", {}).items()}
+
+
 def hbm_roof(kernel, launches, ms, nbytes, ceiling=None, traffic=None, bytes_note=""):
     t = ms / 1e3
     gbs = nbytes / t / 1e9 if t else 0.0
@@ -477,11 +491,12 @@ def bench_vqe(args):
     out = base_line(args, 64 * args.steps / dt, "parameter vectors/s (energy + 240-entry gradient)", dt,
                     {"workload": "20-qubit HEA, 6 layers RY/RZ + CX ladder, 240 parameters, 60-term "
                                  "2-local Pauli Hamiltonian, batch of 64 parameter vectors per call"})
+    tr = c4_traffic()
     out["roofline"] = hbm_roof("k_backward_mfma", prof["sweep_launches"], prof["sweep_ms"], prof["sweep_bytes"],
-                               None, None, "64 B per amplitude per swept pass (psi and lambda, each read and "
-                                           "written, complex128)")
+                               None, tr.get("k_backward_mfma"), "64 B per amplitude per swept pass (psi and "
+                                                                "lambda, each read and written, complex128)")
     out["roofline"]["hamiltonian"] = hbm_roof("k_hamiltonian", prof["ham_launches"], prof["ham_ms"],
-                                              prof["ham_bytes"], None, None,
+                                              prof["ham_bytes"], None, tr.get("k_hamiltonian"),
                                               "16 B per amplitude read (psi) + 16 B written (lambda)")
     out["roofline"]["forward_tile_pass"] = hbm_roof("k_tile_pass_d8", prof["pass_uncond_launches"],
                                                     prof["pass_uncond_ms"], prof["pass_uncond_bytes"], None, None,

@@ -29,49 +29,135 @@ __device__ __forceinline__ double2 ipow(uint32_t k) {
   }
 }
 
-// Block (blk, b) covers a contiguous slice of vector b: writes lambda there
-// (unless lam is null), terms accumulated in a fixed order per element, and
-// the slice's Re sum conj(psi) lambda to epart[b][blk] (fixed-order tree).
-// Vector b uses terms [toff[b], toff[b + 1]) when toff is set, else all.
-__global__ __launch_bounds__(256) void k_hamiltonian(const double2* __restrict__ psi, double2* __restrict__ lam,
-                                                    uint64_t stride, uint32_t n, const uint64_t* __restrict__ xmask,
-                                                    const uint64_t* __restrict__ zmask,
-                                                    const uint32_t* __restrict__ ny, const double* __restrict__ coeff,
-                                                    uint32_t n_terms, const uint32_t* __restrict__ toff,
-                                                    uint32_t blocks, double* __restrict__ epart) {
-  __shared__ double red[256];
-  const uint32_t tid = threadIdx.x, blk = blockIdx.x, b = blockIdx.y;
-  const uint32_t t_begin = toff ? toff[b] : 0u, t_end = toff ? toff[b + 1] : n_terms;
-  const uint64_t dim = 1ull << n, per = (dim + blocks - 1) / blocks;
-  const uint64_t j0 = per * blk, j1 = (j0 + per < dim) ? j0 + per : dim;
-  const double2* st = psi + (uint64_t)b * stride;
-  double e = 0.0;
-  for (uint64_t i = j0 + tid; i < j1; i += 256) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (uint32_t t = t_begin; t < t_end; ++t) {
-      const uint64_t src = i ^ xmask[t];
-      const double sgn = (__popcll(src & zmask[t]) & 1) ? -1.0 : 1.0;
-      acc = cadd(acc, cscale(cmul(ipow(ny[t]), st[src]), coeff[t] * sgn));
-    }
-    if (lam) lam[(uint64_t)b * stride + i] = acc;
-    const double2 p = st[i];
-    e += p.x * acc.x + p.y * acc.y;
+// lambda = H psi over amplitude tiles. A workgroup stages the 2^t amplitudes
+// of one tile of vector b in LDS (the tile holds qubits 0..3, so every
+// global access is a run of 16 amplitudes, and the qubits that put the most
+// distinct X masks of its Hamiltonian inside the tile), then sums the
+// Hamiltonian's groups of terms with equal X mask x for each of them:
+//   lambda[i] += psi[i ^ x] * sum_t r_t (-1)^popcount(i & z_t) (i or 1)
+// reading psi[i ^ x] from LDS when x lies within the tile, else from memory
+// (a run of the partner tile), groups in ascending x; within a group the
+// terms with a real phase first, then those with an imaginary one, each part
+// one real sum f and two multiply-adds per amplitude. Thread tid holds local indices l_j = tid | (j << 9): the
+// sign's parity over the bits outside the tile is the same for the whole
+// workgroup, over local bits 9..11 the same for every thread, so only
+// popcount(tid & zl) is per thread. The energy partial of the tile,
+// Re sum conj(psi) lambda, goes to epart[b][tile] (fixed-order tree).
+constexpr uint32_t kHamThreads = 512;
+constexpr uint32_t kHamPerThread = (1u << kTileMaxBits) / kHamThreads;  // 8
+
+__global__ __launch_bounds__(kHamThreads, 4) void k_hamiltonian(
+    const double2* __restrict__ psi, double2* __restrict__ lam, uint64_t stride, uint32_t n,
+    const HamTile* __restrict__ tiles_of, uint32_t per_vector, const HamGroup* __restrict__ groups,
+    const uint32_t* __restrict__ goff, const HamTerm* __restrict__ terms, uint32_t n_tiles,
+    double* __restrict__ epart) {
+  extern __shared__ double2 tl[];
+  __shared__ uint64_t lut[128];
+  __shared__ double red[kHamThreads];
+  const uint32_t tid = threadIdx.x, tile = blockIdx.x, b = blockIdx.y, h = per_vector ? b : 0u;
+  const HamTile* TQ = tiles_of + h;
+  const uint32_t t = TQ->t, T = 1u << t;
+  // local index -> global bits: low six local bits through lut[0..63], the rest through lut[64..127]
+  if (tid < 128) {
+    const uint32_t k = tid & 63u, hi = tid >> 6;
+    uint64_t m = 0;
+    for (uint32_t j = 0; j < 6; ++j)
+      if (hi * 6 + j < t && ((k >> j) & 1u)) m |= 1ull << TQ->tq[hi * 6 + j];
+    lut[tid] = m;
   }
+  uint64_t tmask = 0;
+  for (uint32_t j = 0; j < t; ++j) tmask |= 1ull << TQ->tq[j];
+  uint64_t base = 0;  // the tile index scattered over the qubits outside the tile, ascending
+  {
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < n; ++q)
+      if (!((tmask >> q) & 1ull)) base |= (uint64_t)((tile >> k++) & 1u) << q;
+  }
+  __syncthreads();
+  const double2* st = psi + (uint64_t)b * stride;
+  for (uint32_t l = tid; l < T; l += kHamThreads) tl[l] = st[base | lut[l & 63u] | lut[64 + (l >> 6)]];
+  __syncthreads();
+  // this thread's amplitudes: j < cnt (cnt = 0 when the tile is smaller than tid)
+  const uint32_t cnt = T >= kHamThreads ? T / kHamThreads : (tid < T ? 1u : 0u);
+  uint64_t gi[kHamPerThread];
+#pragma unroll
+  for (uint32_t j = 0; j < kHamPerThread; ++j) gi[j] = base | lut[tid & 63u] | lut[64 + (((tid >> 6) | (j << 3)) & 63u)];
+  double2 acc[kHamPerThread];
+#pragma unroll
+  for (uint32_t j = 0; j < kHamPerThread; ++j) acc[j] = make_double2(0.0, 0.0);
+  // f[j] = sum over terms [k0, k1) of r (-1)^popcount(i_j & z): the sign's
+  // parity over the workgroup's bits outside the tile and over local bits
+  // 9..11 (j) is uniform, only tid & zl is per thread
+  auto add_term = [&](uint32_t k, bool first, double* f) {
+    const HamTerm M = terms[k];
+    const double sl = (__popc(tid & M.zl) & 1) ? -1.0 : 1.0;
+    const uint32_t pw = (uint32_t)__popcll(base & M.zo);
+#pragma unroll
+    for (uint32_t j = 0; j < kHamPerThread; ++j) {
+      const double c = ((pw + (uint32_t)__popc((j << 9) & M.zl)) & 1u) ? -M.r : M.r;
+      f[j] = first ? sl * c : fma(sl, c, f[j]);
+    }
+  };
+  auto sum_terms = [&](uint32_t k0, uint32_t k1, double* f) {  // k0 < k1
+    add_term(k0, true, f);
+    for (uint32_t k = k0 + 1; k < k1; ++k) add_term(k, false, f);
+  };
+  const uint32_t g0 = goff[h], g1 = goff[h + 1];
+  if (cnt) {
+    for (uint32_t g = g0; g < g1; ++g) {
+      const HamGroup G = groups[g];
+      double2 v[kHamPerThread];
+      if (G.local) {
+#pragma unroll
+        for (uint32_t j = 0; j < kHamPerThread; ++j) v[j] = tl[((tid | (j << 9)) ^ G.xl) & (T - 1u)];
+      } else {
+#pragma unroll
+        for (uint32_t j = 0; j < kHamPerThread; ++j) v[j] = j < cnt ? st[gi[j] ^ G.x] : make_double2(0.0, 0.0);
+      }
+      double f[kHamPerThread];
+      if (G.t0 < G.ti) {  // terms with a real phase: lambda += f psi
+        sum_terms(G.t0, G.ti, f);
+#pragma unroll
+        for (uint32_t j = 0; j < kHamPerThread; ++j) {
+          acc[j].x = fma(f[j], v[j].x, acc[j].x);
+          acc[j].y = fma(f[j], v[j].y, acc[j].y);
+        }
+      }
+      if (G.ti < G.t1) {  // terms with an imaginary phase: lambda += i f psi
+        sum_terms(G.ti, G.t1, f);
+#pragma unroll
+        for (uint32_t j = 0; j < kHamPerThread; ++j) {
+          acc[j].x = fma(-f[j], v[j].y, acc[j].x);
+          acc[j].y = fma(f[j], v[j].x, acc[j].y);
+        }
+      }
+    }
+  }
+  double e = 0.0;
+#pragma unroll
+  for (uint32_t j = 0; j < kHamPerThread; ++j)
+    if (j < cnt) {
+      if (lam) lam[(uint64_t)b * stride + gi[j]] = acc[j];
+      const double2 p = tl[tid | (j << 9)];
+      e += p.x * acc[j].x + p.y * acc[j].y;
+    }
   red[tid] = e;
   __syncthreads();
-  for (uint32_t s = 128; s > 0; s >>= 1) {
+  for (uint32_t s = kHamThreads / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) epart[(uint64_t)b * blocks + blk] = red[0];
+  if (tid == 0) epart[(uint64_t)b * n_tiles + tile] = red[0];
 }
 
 hipError_t launch_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
-                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny, const double* coeff,
-                              uint32_t n_terms, const uint32_t* toff, uint32_t blocks, double* epart,
+                              const HamTile* tiles_of, uint32_t per_vector, const HamGroup* groups,
+                              const uint32_t* goff, const HamTerm* terms, uint32_t t, double* epart,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_hamiltonian, dim3(blocks, batch), dim3(256), 0, st, psi, lam, stride, n, xmask, zmask, ny,
-                     coeff, n_terms, toff, blocks, epart);
+  if (t > kTileMaxBits || t > n) return hipErrorInvalidValue;
+  const uint32_t n_tiles = 1u << (n - t);
+  hipLaunchKernelGGL(k_hamiltonian, dim3(n_tiles, batch), dim3(kHamThreads), sizeof(double2) << t, st, psi, lam,
+                     stride, n, tiles_of, per_vector, groups, goff, terms, n_tiles, epart);
   return hipGetLastError();
 }
 

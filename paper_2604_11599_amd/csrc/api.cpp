@@ -1182,12 +1182,59 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
 
 namespace {
 
-struct HamDev {
-  uint64_t* x = nullptr;
-  uint64_t* z = nullptr;
-  uint32_t* ny = nullptr;
-  double* c = nullptr;
-};
+// The Hamiltonian sweep's tile for one Hamiltonian with X masks gx: all
+// qubits when the state fits a tile, else qubits 0..3 (16-amplitude runs) and
+// the t - 4 others that put the most distinct X masks inside the tile (every
+// choice tried while there are at most 200000, else greedily).
+HamTile ham_tile(uint32_t n, const std::vector<uint64_t>& gx) {
+  HamTile T{};
+  const uint32_t t = std::min<uint32_t>(kTileMaxBits, n);
+  T.t = t;
+  uint64_t mask = (t == 64) ? ~0ull : ((1ull << t) - 1ull);
+  if (n > t) {
+    const uint32_t low = 4, free = n - low, k = t - low;
+    auto local = [&](uint64_t m) {
+      uint32_t c = 0;
+      for (uint64_t x : gx) c += (x & ~m) == 0;
+      return c;
+    };
+    double combos = 1.0;
+    for (uint32_t i = 0; i < k; ++i) combos = combos * (free - i) / (i + 1);
+    const uint64_t lowm = (1ull << low) - 1ull;
+    if (combos <= 200000.0) {
+      uint32_t best = 0;
+      uint64_t bm = 0;
+      for (uint64_t s = (1ull << k) - 1ull; s < (1ull << free);) {  // subsets of size k in increasing order
+        const uint32_t c = local(lowm | (s << low));
+        if (c > best || bm == 0) {
+          best = c;
+          bm = s;
+        }
+        const uint64_t u = s & (0ull - s), v = s + u;
+        s = v + (((v ^ s) / u) >> 2);
+      }
+      mask = lowm | (bm << low);
+    } else {
+      mask = lowm;
+      for (uint32_t i = 0; i < k; ++i) {
+        uint32_t best = 0, bq = n;
+        for (uint32_t q = low; q < n; ++q)
+          if (!((mask >> q) & 1ull)) {
+            const uint32_t c = local(mask | (1ull << q));
+            if (bq == n || c > best) {
+              best = c;
+              bq = q;
+            }
+          }
+        mask |= 1ull << bq;
+      }
+    }
+  }
+  uint32_t j = 0;
+  for (uint32_t q = 0; q < n && j < t; ++q)
+    if ((mask >> q) & 1ull) T.tq[j++] = (uint8_t)q;
+  return T;
+}
 
 // h: one Hamiltonian shared by every vector (per_vector false) or h[b] for
 // vector b (per_vector true).
@@ -1233,7 +1280,8 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
     toff.push_back((uint32_t)xm.size());
   }
   const uint32_t T = (uint32_t)xm.size();
-  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, dim / 4096));
+  // energy partials: one per amplitude tile of the Hamiltonian sweep
+  const uint32_t blocks = 1u << (n - std::min<uint32_t>(kTileMaxBits, n));
   // vectors per chunk: states (x2 with a gradient) must fit
   size_t per = dim * 16 * (grad ? 2 : 1) + (size_t)n_slots * kMatStride * 8 * (grad ? 4 : 1) +
                (size_t)blocks * 8 + P * 16 + 4096;
@@ -1258,20 +1306,68 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
   uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(batch, (budget > 65536 ? budget - 65536 : 0) / per));
   chunk = std::min<uint64_t>(chunk, 65535);
   Scratch scr(ctx);
-  HamDev hd;
-  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.x));
-  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.z));
-  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.ny));
-  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &hd.c));
-  uint32_t* d_toff = nullptr;
-  if (per_vector) HIP_TRY(scr.get(batch + 1, &d_toff));
-  if (T) {
-    HIP_TRY(hipMemcpyAsync(hd.x, xm.data(), T * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(hd.z, zm.data(), T * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(hd.ny, ny.data(), T * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(hd.c, cf.data(), T * 8, hipMemcpyHostToDevice, st));
+  // per Hamiltonian: its tile, and its terms grouped by X mask (groups in
+  // ascending mask, terms in their order within a group)
+  std::vector<HamTile> htiles(n_ham);
+  std::vector<HamGroup> hgroups;
+  std::vector<uint32_t> goff(1, 0);
+  std::vector<HamTerm> gterms;
+  for (uint32_t k = 0; k < n_ham; ++k) {
+    std::vector<uint32_t> order;
+    for (uint32_t t = toff[k]; t < toff[k + 1]; ++t) order.push_back(t);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return xm[a] < xm[b]; });
+    std::vector<uint64_t> gx;
+    for (uint32_t t : order)
+      if (gx.empty() || gx.back() != xm[t]) gx.push_back(xm[t]);
+    htiles[k] = ham_tile(n, gx);
+    const HamTile& TQ = htiles[k];
+    uint64_t tmask = 0;
+    for (uint32_t j = 0; j < TQ.t; ++j) tmask |= 1ull << TQ.tq[j];
+    for (size_t i = 0; i < order.size();) {
+      HamGroup G{};
+      G.x = xm[order[i]];
+      G.local = (G.x & ~tmask) == 0 ? 1u : 0u;
+      for (uint32_t j = 0; j < TQ.t; ++j)
+        if ((G.x >> TQ.tq[j]) & 1ull) G.xl |= 1u << j;
+      G.t0 = (uint32_t)gterms.size();
+      size_t i1 = i;
+      while (i1 < order.size() && xm[order[i1]] == G.x) ++i1;
+      // real phases (#Y even) first, then imaginary, each in term order
+      std::stable_sort(order.begin() + i, order.begin() + i1,
+                       [&](uint32_t a, uint32_t b) { return (ny[a] & 1u) < (ny[b] & 1u); });
+      G.ti = G.t0;
+      for (size_t i2 = i; i2 < i1; ++i2) G.ti += (ny[order[i2]] & 1u) ? 0u : 1u;
+      for (; i < i1; ++i) {
+        const uint32_t k = order[i];
+        HamTerm M{};
+        M.zo = zm[k] & ~tmask;
+        for (uint32_t j = 0; j < TQ.t; ++j)
+          if ((zm[k] >> TQ.tq[j]) & 1ull) M.zl |= 1u << j;
+        // i^ny = (+-1) or (+-i); (-1)^popcount((i ^ x) & z) = (-1)^popcount(x & z) (-1)^popcount(i & z)
+        M.imag = ny[k] & 1u;
+        const bool neg = ((ny[k] >> 1) & 1u) ^ (uint32_t)(__builtin_popcountll(G.x & zm[k]) & 1);
+        M.r = neg ? -cf[k] : cf[k];
+        gterms.push_back(M);
+      }
+      G.t1 = (uint32_t)gterms.size();
+      hgroups.push_back(G);
+    }
+    goff.push_back((uint32_t)hgroups.size());
   }
-  if (per_vector) HIP_TRY(hipMemcpyAsync(d_toff, toff.data(), (batch + 1) * 4, hipMemcpyHostToDevice, st));
+  const uint32_t ht = htiles[0].t;  // the same for every Hamiltonian (min(12, n))
+  HamTile* d_htiles = nullptr;
+  HamGroup* d_hgroups = nullptr;
+  uint32_t* d_goff = nullptr;
+  HamTerm* d_gterms = nullptr;
+  HIP_TRY(scr.get(n_ham, &d_htiles));
+  HIP_TRY(scr.get(std::max<size_t>(1, hgroups.size()), &d_hgroups));
+  HIP_TRY(scr.get(n_ham + 1, &d_goff));
+  HIP_TRY(scr.get(std::max<uint32_t>(T, 1), &d_gterms));
+  HIP_TRY(hipMemcpyAsync(d_htiles, htiles.data(), n_ham * sizeof(HamTile), hipMemcpyHostToDevice, st));
+  if (!hgroups.empty())
+    HIP_TRY(hipMemcpyAsync(d_hgroups, hgroups.data(), hgroups.size() * sizeof(HamGroup), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, st));
+  if (T) HIP_TRY(hipMemcpyAsync(d_gterms, gterms.data(), T * sizeof(HamTerm), hipMemcpyHostToDevice, st));
   double *d_theta, *d_mats, *d_dmats = nullptr, *d_tp, *d_energy, *d_dEda = nullptr, *d_gpart = nullptr,
                             *d_grad = nullptr;
   RunBuffers rb{};
@@ -1327,8 +1423,9 @@ qsv_status expval_impl(qsv_context* ctx, const qsv_program* prog, const double* 
     // lambda = H psi (kept for the gradient) and the energy Re <psi|lambda> in one sweep
     if (T) {
       Prof pr(ctx, st);
-      HIP_TRY(launch_hamiltonian(rb.state, grad ? d_lam : nullptr, dim, n, bs, hd.x, hd.z, hd.ny, hd.c, T,
-                                 per_vector ? d_toff + b0 : nullptr, blocks, d_tp, st));
+      HIP_TRY(launch_hamiltonian(rb.state, grad ? d_lam : nullptr, dim, n, bs, d_htiles + (per_vector ? b0 : 0),
+                                 per_vector ? 1u : 0u, d_hgroups, d_goff + (per_vector ? b0 : 0), d_gterms, ht,
+                                 d_tp, st));
       pr.done(K_HAM, false, (grad ? 32.0 : 16.0) * (double)dim * bs);
       HIP_TRY(launch_energy_sum(d_tp, blocks, bs, d_energy, st));
     } else {

@@ -73,9 +73,12 @@ hipError_t launch_persistent(const ReqDev* reqs, const uint32_t* item_req, uint3
 // Expectation values and adjoint gradients over a batch of parameter vectors.
 // lambda = H psi (lam may be null) and per-slice partials of Re <psi|H psi>
 // (epart[batch][blocks]); launch_energy_sum reduces them to energy[batch].
+// Tiles of 2^t amplitudes (t <= 12; 2^(n - t) per vector); tiles_of[h] and
+// groups [goff[h], goff[h + 1]) belong to Hamiltonian h = per_vector ? b : 0;
+// epart is [batch][2^(n - t)].
 hipError_t launch_hamiltonian(const double2* psi, double2* lam, uint64_t stride, uint32_t n, uint32_t batch,
-                              const uint64_t* xmask, const uint64_t* zmask, const uint32_t* ny, const double* coeff,
-                              uint32_t n_terms, const uint32_t* toff, uint32_t blocks, double* epart,
+                              const HamTile* tiles_of, uint32_t per_vector, const HamGroup* groups,
+                              const uint32_t* goff, const HamTerm* terms, uint32_t t, double* epart,
                               hipStream_t st);
 hipError_t launch_energy_sum(const double* epart, uint32_t blocks, uint32_t batch, double* energy, hipStream_t st);
 hipError_t launch_backward_pass(double2* psi, double2* lam, uint64_t stride, uint32_t batch,

@@ -147,6 +147,35 @@ struct ShotCtl {
   uint32_t wg_done;      // workgroups of the current pass finished for this shot
 };
 
+// Tiles of the Hamiltonian sweep: tile-local bit j <-> qubit tq[j] (ascending).
+struct HamTile {
+  uint8_t tq[kTileMaxBits];
+  uint32_t t;
+};
+
+// The terms of one Hamiltonian with one X mask (the qubits its Pauli string
+// flips), grouped so that each amplitude reads its partner once per group.
+struct HamGroup {   // 32 bytes
+  uint64_t x;       // X/Y support over the global qubits
+  uint32_t xl;      // the same over the tile-local bits (when local)
+  uint32_t local;   // 1: x lies within the tile
+  uint32_t t0, t1;  // terms [t0, t1): those with a real phase in [t0, ti), imaginary in [ti, t1)
+  uint32_t ti;
+  uint32_t pad;
+};
+
+// One term of a group, with its phase folded in: the term adds
+//   r * (-1)^popcount(i & z) * (imag ? i : 1) * psi[i ^ x]
+// to lambda[i], where r = c * (+-1) carries i^ny and (-1)^popcount(x & z), and
+// the parity of i & z splits into the tile-local bits (zl, over local index
+// bits) and the bits outside the tile (zo, over global qubits).
+struct HamTerm {    // 24 bytes
+  uint64_t zo;
+  uint32_t zl;
+  uint32_t imag;
+  double r;
+};
+
 // Device copy of a plan step (Step in planner.h).
 struct DStep {
   uint32_t kind, index;   // 0 init, 1 pass, 2 site

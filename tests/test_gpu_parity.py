@@ -552,6 +552,40 @@ def test_expval_closed_form_and_general_gates(ctx):
         assert abs(e[b] - eo) < 1e-12 and np.max(np.abs(g[b] - go)) < 1e-11
 
 
+def test_hamiltonian_tiles_local_and_remote_groups(ctx):
+    """The H psi sweep on states larger than one amplitude tile: terms whose X
+    masks lie inside the tile (partners read from LDS) and outside it (partners
+    read from memory), several terms per X mask, Y counts of 0..3, an identity
+    term and a term with X on every qubit, at 13 and 16 qubits, against the
+    oracle's energy and adjoint gradient; per-vector Hamiltonians equal one call
+    per vector bit for bit."""
+    for n in (13, 16):
+        src = W.c4_ansatz(n, 2)
+        rng = np.random.default_rng(600 + n)
+        base = rng.integers(0, 4, size=(24, n)).astype(np.uint8)
+        same_x = base[:8].copy()                     # same X masks as the first 8, other Z parts
+        flip = (same_x == 3) | (same_x == 0)
+        same_x[flip] = 3 - same_x[flip]
+        ys = np.zeros((4, n), dtype=np.uint8)
+        for k in range(4):
+            ys[k, rng.choice(n, size=k + 1, replace=False)] = 2
+        codes = np.concatenate([base, same_x, ys, np.zeros((1, n), np.uint8), np.ones((1, n), np.uint8)])
+        coeffs = rng.standard_normal(len(codes))
+        thetas = W.c4_thetas(seed=700 + n, batch=2, n_params=4 * n)
+        prog = ctx.load(src)
+        say("hamiltonian tiles case", n, "qubits", len(codes), "terms")
+        e, g = prog.expval_grad(thetas, coeffs, codes)
+        for b in range(2):
+            eo, go = sim.grad_adjoint(src, thetas[b], coeffs, codes)
+            assert abs(e[b] - eo) < 1e-12
+            assert np.max(np.abs(g[b] - go)) < 1e-11
+        hams = [(coeffs, codes), W.c4_hamiltonian(seed=n, n=n, terms=20)]
+        ee, ge = prog.expval_grad_each(thetas, hams)
+        for b in range(2):
+            e1, g1 = prog.expval_grad(thetas[b:b + 1], *hams[b])
+            assert ee[b] == e1[0] and np.array_equal(ge[b], g1[0])
+
+
 def test_c4_full_size_energy_and_fd(ctx):
     src = W.c4_ansatz(20, 6)
     coeffs, codes = W.c4_hamiltonian(seed=4, n=20, terms=60)

@@ -3,7 +3,8 @@
 Runs, in one process: one plain device copy of 4 GiB (qsv_diag_copy, the
 calibration: it reads and writes exactly 4 GiB), then one step of the 28-qubit
 benchmark workload (16 shots) with the same launch configuration as bench.py;
-with --complex64 the step holds its state in complex64.
+with --complex64 the step holds its state in complex64; with --workload c4 the
+step is one energy + gradient call of the 20-qubit ansatz over 64 vectors.
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- python3 traffic_probe.py
 """
@@ -34,8 +35,13 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     print("copy done", flush=True)
-    prog = ctx.load(W.c2_program(seed=2, n=28, layers=40))
-    prog.run_shots(16, seed=0, complex64="--complex64" in sys.argv[1:])
+    if "c4" in sys.argv[1:]:
+        prog = ctx.load(W.c4_ansatz(20, 6))
+        coeffs, codes = W.c4_hamiltonian(seed=4, n=20, terms=60)
+        prog.expval_grad(W.c4_thetas(seed=44, batch=64, n_params=240), coeffs, codes)
+    else:
+        prog = ctx.load(W.c2_program(seed=2, n=28, layers=40))
+        prog.run_shots(16, seed=0, complex64="--complex64" in sys.argv[1:])
     print("step done", flush=True)
     ctx.close()
 

@@ -28,10 +28,13 @@ COPY_KERNEL = "k_copy"
 
 
 def kernel_hash():
+    """Hash of every device source (kernels, launchers, shared device types)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_common.h", "qsv_types.h"):
-        with open(os.path.join(ROOT, "paper_2604_11599_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2604_11599_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -111,7 +114,70 @@ def summarize(fetch_csv, write_csv, khash):
     }
 
 
+# the energy + gradient workload: 20 qubits, 64 parameter vectors per call
+C4_AMPS = 64 * 2 ** 20
+C4_KERNELS = {"k_hamiltonian": 32.0, "k_backward_mfma": 64.0}  # algorithmic B per amplitude per launch
+
+
+def summarize_kernels(fetch_csv, write_csv, khash, kernels, amps):
+    """Scaled HBM bytes per launch of each named kernel (all its launches)."""
+    fe = read_counter(fetch_csv, "FETCH_SIZE")
+    wr = read_counter(write_csv, "WRITE_SIZE")
+    cf = [v for _, k, v in fe if k == COPY_KERNEL]
+    cw = [v for _, k, v in wr if k == COPY_KERNEL]
+    if len(cf) != 1 or len(cw) != 1:
+        raise SystemExit("expected exactly one calibration copy per run")
+    f_fac = COPY_BYTES / (cf[0] * 1024.0)
+    w_fac = COPY_BYTES / (cw[0] * 1024.0)
+    out = {"kernel_hash": khash, "amplitudes_per_launch": amps, "kernels": {},
+           "calibration": {"copy_bytes_each_way": COPY_BYTES, "copy_fetch_kib": cf[0], "copy_write_kib": cw[0],
+                           "fetch_factor": f_fac, "write_factor": w_fac}}
+    for name, alg in kernels.items():
+        pf = [v for _, k, v in fe if k == name]
+        pw = [v for _, k, v in wr if k == name]
+        if not pf or len(pf) != len(pw):
+            raise SystemExit(f"{name}: dispatch counts differ between the two runs")
+        fetch = sum(pf) * 1024.0 * f_fac / len(pf)
+        write = sum(pw) * 1024.0 * w_fac / len(pw)
+        out["kernels"][name] = {"launches": len(pf), "bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
+                                "write_bytes_per_launch": write, "bytes_per_amplitude": (fetch + write) / amps,
+                                "algorithmic_bytes_per_amplitude": alg}
+    return out
+
+
+def main_c4(args):
+    fetch_csv, write_csv, log = args[0], args[1], args[2]
+    cmd = args[3] if len(args) > 3 else ""
+    d = summarize_kernels(fetch_csv, write_csv, probe_hash(log), C4_KERNELS, C4_AMPS)
+    d["command"] = cmd
+    d["workload"] = "20-qubit ansatz, 64 parameter vectors, one energy + gradient call"
+    with open(os.path.join(ROOT, "profiles", "c4_20q_traffic.json"), "w") as f:
+        json.dump(d, f, indent=1)
+    with open(os.path.join(ROOT, "profiles", "c4_20q_traffic.txt"), "w") as f:
+        f.write("HBM traffic of the energy + gradient kernels, 20 qubits x 64 vectors per launch (rocprofv3 --pmc)\n")
+        f.write(f"command: {cmd}\n")
+        f.write(f"kernel source hash: {d['kernel_hash']}\n")
+        c = d["calibration"]
+        f.write(f"calibration copy (4 GiB each way): FETCH_SIZE {c['copy_fetch_kib']:.0f} KiB "
+                f"(factor {c['fetch_factor']:.4f}), WRITE_SIZE {c['copy_write_kib']:.0f} KiB "
+                f"(factor {c['write_factor']:.4f})\n")
+        for name, k in d["kernels"].items():
+            f.write(f"{name}: {k['launches']} launches, fetch {k['fetch_bytes_per_launch']:.4e} B, write "
+                    f"{k['write_bytes_per_launch']:.4e} B per launch = {k['bytes_per_amplitude']:.2f} B per amplitude "
+                    f"(algorithmic {k['algorithmic_bytes_per_amplitude']:.0f})\n")
+    print(json.dumps(d))
+
+
 def main():
+    if "--workload" in sys.argv:
+        i = sys.argv.index("--workload")
+        wl = sys.argv[i + 1]
+        rest = sys.argv[1:i] + sys.argv[i + 2:]
+        if wl == "c4":
+            return main_c4(rest)
+        if wl != "c2":
+            raise SystemExit(f"unknown workload {wl}")
+        sys.argv = [sys.argv[0]] + rest
     args = [a for a in sys.argv[1:] if a != "--complex64"]
     c64 = len(args) != len(sys.argv) - 1
     fetch_csv, write_csv, log = args[0], args[1], args[2]
