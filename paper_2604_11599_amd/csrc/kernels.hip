@@ -450,8 +450,8 @@ static hipError_t tile_pass_t(const RunBuffers& rb, CT* state, const DGate* gate
     // so it runs where every shot of the launch shares them
     const bool dense_only = a.all_dense && a.t >= kDenseMinTileBits && a.phase_count <= kLdsDensePhases &&
                             mat_stride == 0;
-    // all-dense passes on full tiles: eight waves per tile
-    if (a.all_dense && a.t == (uint32_t)kTileMaxBits) {
+    // all-dense passes: eight amplitudes per thread, 2^(t - 9) waves per tile
+    if (a.all_dense && a.t >= kDenseMinTileBits) {
       const uint32_t staged = (a.phase_count <= kLdsDensePhases && mat_stride == 0) ? 1u : 0u;
       const size_t l8 = lds + (staged ? mat_lds : 0);
       e = resident_grid((const void*)k_tile_pass_d8<CT>, 2 * nthr, l8, max_lds, &g);
@@ -979,12 +979,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass_r(
   }
 }
 
-// Tile pass for passes made only of dense phases, on full tiles (2^12
-// amplitudes), with eight waves per tile: each thread stages and stores 8
-// amplitudes (load layout l = tid + k * 512), each wave applies the phases to
-// 2 blocks of 16 amplitude groups on the matrix cores, and at most 128
-// registers per thread let two workgroups (16 waves) share a CU, so that the
-// waits of one wave (LDS, barriers, HBM) are covered by the others. With
+// Tile pass for passes made only of dense phases, on tiles of 2^t amplitudes
+// (10 <= t <= 12), with 2^(t - 9) waves per tile: each thread stages and
+// stores 8 amplitudes (load layout l = tid + k * 2^(t - 3)), each wave applies
+// the phases to 2 blocks of 16 amplitude groups on the matrix cores, and at
+// most 128 registers per thread let several workgroups share a CU (two of
+// 2^12, three of 2^11, five of 2^10 amplitudes with their staged matrices),
+// so that the waits of one workgroup (LDS, barriers, HBM) are covered by the
+// others' matrix-core work. With
 // lds_mats the pass's matrices (shared by every shot: mat_stride 0, at most
 // kLdsDensePhases of them) are staged in LDS once; otherwise each phase reads
 // its matrix from the shot's matrix slots.
@@ -994,19 +996,19 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
     const double* __restrict__ mats, uint64_t mat_stride, PassArgs a, uint32_t shots, uint32_t lds_mats) {
   extern __shared__ double2 qsv_lds[];
   CT* const tile = reinterpret_cast<CT*>(qsv_lds);
-  constexpr uint32_t kA = 8, kThreads = 2 * kTileThreads;
-  const uint32_t tid = threadIdx.x, T = 1u << a.t, lane = tid & 63u;
+  constexpr uint32_t kA = 8;
+  const uint32_t tid = threadIdx.x, T = 1u << a.t, lane = tid & 63u, nth = T / kA;  // nth = blockDim.x
   const uint64_t total = (uint64_t)a.tiles * shots, G = gridDim.x;
   const uint64_t free_mask = ~a.tile_mask & ((a.n >= 64) ? ~0ull : ((1ull << a.n) - 1ull));
-  uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..8]
-  for (uint32_t b = 0; b < 9; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
-  const uint64_t h0 = 1ull << a.tq[9], h1 = 1ull << a.tq[10], h2 = 1ull << a.tq[11];
+  uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..t-4]
+  for (uint32_t b = 0; b + 3 < a.t; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
+  const uint64_t h0 = 1ull << a.tq[a.t - 3], h1 = 1ull << a.tq[a.t - 2], h2 = 1ull << a.tq[a.t - 1];
   CT* const lmats = tile + T;
   if (lds_mats)
     for (uint32_t p = 0; p < a.phase_count; ++p) {
       const double2* src =
           reinterpret_cast<const double2*>(mats + (uint64_t)cst(phases + a.phase_begin + p)->dense * kMatStride);
-      for (uint32_t e = tid; e < 256u; e += kThreads) lmats[p * 256u + e] = cmake<CT>(src[e].x, src[e].y);
+      for (uint32_t e = tid; e < 256u; e += nth) lmats[p * 256u + e] = cmake<CT>(src[e].x, src[e].y);
     }
   // the first phases' descriptors, read once (wave-uniform, scalar registers):
   // every tile runs the same phases, and a descriptor read inside the tile
@@ -1038,7 +1040,7 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
-      tile[swz(tid + (uint32_t)k * kThreads)] =
+      tile[swz(tid + (uint32_t)k * nth)] =
           !pending ? r[k] : (((gi & M) == V) ? cscale(r[k], sc) : cmake<CT>(0.0, 0.0));
     }
     __syncthreads();
@@ -1065,7 +1067,7 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
       }
     }
 #pragma unroll
-    for (int k = 0; k < (int)kA; ++k) r[k] = tile[swz(tid + (uint32_t)k * kThreads)];
+    for (int k = 0; k < (int)kA; ++k) r[k] = tile[swz(tid + (uint32_t)k * nth)];
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
@@ -1085,7 +1087,7 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
       }
     }
     // no barrier before the next tile: its staging writes go to the slots
-    // swz(tid + k * kThreads) that this thread has just read for the stores
+    // swz(tid + k * nth) that this thread has just read for the stores
     // (one wave's LDS accesses complete in order), and the staging barrier
     // orders them before any other thread's reads
     it = next_pass_item(it + G, total, G, ctl, a, nullptr, last_shot, last_active);
