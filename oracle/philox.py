@@ -14,7 +14,8 @@ event, per shot):
     word(seed, shot, e) = philox4x64_10(ctr=(e//4 + 1, 0, 0, 0), key=(seed, shot))[e % 4]
 i.e. the e-th output of ``numpy.random.Philox(key=[seed, shot]).random_raw()``,
 which advances its counter before producing its first block. The uniform
-variate is u = (word >> 11) * 2**-53, in [0, 1).
+variate is u = (word >> 11) * 2**-53, in [0, 1). Depolarizing noise draws use
+their own counters (noise_word), independent of the event stream.
 """
 
 MASK64 = (1 << 64) - 1
@@ -48,6 +49,13 @@ def event_word(seed, shot, event):
     """The 64-bit word a shot consumes at its ``event``-th measure/reset."""
     block = philox4x64((event // 4 + 1, 0, 0, 0), (seed, shot))
     return block[event % 4]
+
+
+def noise_word(seed, shot, sid, loop_code, operand):
+    """The word of one depolarizing draw: counter (sid, loop_code, operand, 1),
+    output word 0. The fourth counter word is 1 here and 0 in every event
+    counter, so noise draws never coincide with measurement/reset draws."""
+    return philox4x64((sid, loop_code, operand, 1), (seed, shot))[0]
 
 
 def word_to_uniform(word):

@@ -12,7 +12,9 @@ builds such an AST as plain tuples for the tree-walking interpreter in
   ('var', name, width, signed)      classical integer variable (uint/int/bool)
   ('input', name, size|None)        ('const', name, expr)
   ('gatedef', name, params, qargs, body)
-  ('gate', name, [expr], [qref], mods)    ('measure', qref, cref|None)
+  ('gate', name, [expr], [qref], mods, sid)    ('measure', qref, cref|None)
+        sid: index of the gate statement among those outside gate definitions,
+        in source order (None inside a definition); names its noise draws
   ('assign', cref, cexpr)           classical assignment (also variable initialisers)
   ('reset', qref)                   ('barrier',)
   ('if', cexpr, then_body, else_body) ('for', var, start, step, stop, body)
@@ -70,6 +72,8 @@ class _Parser:
     def __init__(self, text):
         self.toks = tokenize(text)
         self.i = 0
+        self.gate_sid = 0   # gate statements seen outside gate definitions
+        self.in_def = 0
 
     # -- token helpers --
     def peek(self, k=0):
@@ -319,10 +323,12 @@ class _Parser:
             qargs.append(self.ident())
         self.expect("{")
         body = []
+        self.in_def += 1
         while not self.accept("}"):
             st = self.statement()
             if st is not None:
                 body.append(st)
+        self.in_def -= 1
         return ("gatedef", name, params, qargs, body)
 
     def gate_call(self):
@@ -348,7 +354,11 @@ class _Parser:
         while self.accept(","):
             qs.append(self.ref())
         self.expect(";")
-        return ("gate", name, args, qs, tuple(mods))
+        sid = None
+        if not self.in_def:
+            sid = self.gate_sid
+            self.gate_sid += 1
+        return ("gate", name, args, qs, tuple(mods), sid)
 
     def ref(self):
         name = self.ident()

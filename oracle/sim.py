@@ -35,7 +35,7 @@ import math
 import numpy as np
 
 from . import gates as G
-from .philox import ShotStream
+from .philox import ShotStream, noise_word, word_to_uniform
 from .qasm import CONSTANTS, parse
 
 # A forced outcome whose probability (relative to the current norm) is below
@@ -365,7 +365,8 @@ class Interpreter:
         return [off + i]
 
     # -- running one shot --
-    def run(self, seed=0, shot=0, forced=None, first_event=0, readout_error=0.0, reset_error=0.0):
+    def run(self, seed=0, shot=0, forced=None, first_event=0, readout_error=0.0, reset_error=0.0,
+            depolarizing=0.0):
         """first_event: index in the shot's Philox stream of the first word this
         program draws (0 for a whole program; a program that is one independent
         block of a larger product-state program starts where the draws of the
@@ -373,10 +374,18 @@ class Interpreter:
         readout_error: after a measurement's outcome is drawn (the state keeps
         it), the next word u flips the recorded bit when u < readout_error.
         reset_error: after a reset, the next word u flips the qubit when
-        u < reset_error. Either draw happens only when its rate is positive."""
+        u < reset_error. Either draw happens only when its rate is positive.
+        depolarizing: after every application of a gate statement, each of its
+        qubits independently takes X, Y or Z with probability p/3 each (the
+        single-qubit depolarizing channel as a quantum trajectory); the draws
+        come from their own counters (noise_word), not from the event stream."""
         p = self.prog
         self.readout_error = float(readout_error)
         self.reset_error = float(reset_error)
+        self.depolarizing = float(depolarizing)
+        self.seed, self.shot = int(seed), int(shot)
+        self.loop_ords = []      # iteration ordinal of each enclosing for loop, outermost first
+        self.noise_events = []   # (sid, loop code, application, operand, qubit, pauli)
         self.first_event = int(first_event)
         self.eng = self.engine_cls(p.n_qubits)
         self.cbits = [0] * p.n_clbits
@@ -430,16 +439,21 @@ class Interpreter:
             if step == 0:
                 raise OracleError("for loop with zero step")
             i = a
-            while (i <= b) if step > 0 else (i >= b):
-                inner = dict(env)
-                inner[st[1]] = Lin(i) if self.with_derivs else float(i)
-                try:
-                    self.exec_body(st[5], inner)
-                except _Break:
-                    break
-                except _Continue:
-                    pass
-                i += step
+            self.loop_ords.append(0)
+            try:
+                while (i <= b) if step > 0 else (i >= b):
+                    inner = dict(env)
+                    inner[st[1]] = Lin(i) if self.with_derivs else float(i)
+                    try:
+                        self.exec_body(st[5], inner)
+                    except _Break:
+                        break
+                    except _Continue:
+                        pass
+                    i += step
+                    self.loop_ords[-1] += 1
+            finally:
+                self.loop_ords.pop()
         elif k == "break":
             raise _Break()
         elif k == "continue":
@@ -529,6 +543,31 @@ class Interpreter:
                 self.apply_modified(mods, name, angles, qs, env)
             else:
                 self.apply_named(name, angles, qs, env)
+            sid = st[5] if len(st) > 5 else None
+            if sid is not None and getattr(self, "depolarizing", 0.0) > 0.0:
+                self.depolarize(sid, j, qs)
+
+    def loop_code(self):
+        """sum_d ordinal_d * 2**(16 d) over the enclosing for loops (outermost d = 0)."""
+        if len(self.loop_ords) > 4 or any(o >= 1 << 16 for o in self.loop_ords):
+            raise OracleError("noise draws support at most 4 nested loops of at most 65536 iterations")
+        return sum(o << (16 * d) for d, o in enumerate(self.loop_ords))
+
+    def depolarize(self, sid, j, qs):
+        """One draw per qubit of application j of gate statement sid: the word
+        noise_word(seed, shot, (sid, loop code, 64 j + k)) for operand k; with
+        u = (word >> 11) 2**-53 the qubit takes X if u < p/3, Y if u < 2p/3, Z if
+        u < p, nothing otherwise."""
+        if len(qs) > 64:
+            raise OracleError("noise draws support at most 64 operands")
+        code, p = self.loop_code(), self.depolarizing
+        for k, q in enumerate(qs):
+            u = word_to_uniform(noise_word(self.seed, self.shot, sid, code, 64 * j + k))
+            if u >= p:
+                continue
+            pauli = "x" if u < p / 3.0 else ("y" if u < 2.0 * p / 3.0 else "z")
+            self.noise_events.append((sid, code, j, k, q, pauli))
+            self.eng.apply(G.gate_matrix(pauli, [])[0], [q])
 
     def mod_controls(self, mods, env):
         """[(kind, n_controls or power)] of a modifier chain, outermost first."""
@@ -685,19 +724,19 @@ def _wrap64(v):
 # Convenience entry points used by tests, the smoke check and the CPU baseline.
 # --------------------------------------------------------------------------
 def run_shot(source, theta=None, seed=0, shot=0, forced=None, engine_cls=TensorEngine, first_event=0,
-             readout_error=0.0, reset_error=0.0):
+             readout_error=0.0, reset_error=0.0, depolarizing=0.0):
     """Run one shot; returns the finished interpreter (psi, cbits, record, ...)."""
     it = Interpreter(source if isinstance(source, Program) else Program(source), theta, engine_cls)
-    return it.run(seed, shot, forced, first_event, readout_error, reset_error)
+    return it.run(seed, shot, forced, first_event, readout_error, reset_error, depolarizing)
 
 
 def run_shots(source, n_shots, theta=None, seed=0, shot_offset=0, forced=None, readout_error=0.0,
-              reset_error=0.0):
+              reset_error=0.0, depolarizing=0.0):
     prog = source if isinstance(source, Program) else Program(source)
     out = []
     for s in range(n_shots):
         f = None if forced is None else forced[s]
-        it = Interpreter(prog, theta).run(seed, shot_offset + s, f, 0, readout_error, reset_error)
+        it = Interpreter(prog, theta).run(seed, shot_offset + s, f, 0, readout_error, reset_error, depolarizing)
         out.append({"creg": it.creg_words(), "cbits": list(it.cbits), "record": list(it.record),
                     "n_events": it.words_drawn, "record_prob": it.record_prob,
                     "status": it.status, "events": list(it.events)})

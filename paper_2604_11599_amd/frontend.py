@@ -99,6 +99,7 @@ class GateCall:
     args: list
     operands: List[Operand]
     mods: list = None    # [(kind, expr or None)], outermost first: inv, pow, ctrl, negctrl
+    sid: Optional[int] = None  # index among the gate statements outside gate definitions, in source order
 
 
 @dataclass
@@ -264,6 +265,8 @@ class Parser:
     def __init__(self, text):
         self.tok = scan(text)
         self.pos = 0
+        self.n_calls = 0     # gate statements seen outside gate definitions
+        self.in_def = False
 
     def _peek(self, ahead=0):
         return self.tok[min(self.pos + ahead, len(self.tok) - 1)]
@@ -476,8 +479,10 @@ class Parser:
             qargs.append(self._word())
         self._need("{")
         body = []
+        self.in_def = True
         while not self._eat("}"):
             body.extend(self._statement())
+        self.in_def = False
         return GateDef(name, params, qargs, body)
 
     def _gate_call(self):
@@ -502,7 +507,11 @@ class Parser:
         while self._eat(","):
             ops.append(self._operand())
         self._need(";")
-        return GateCall(name, args, ops, mods)
+        sid = None
+        if not self.in_def:
+            sid = self.n_calls
+            self.n_calls += 1
+        return GateCall(name, args, ops, mods, sid)
 
     def _operand(self):
         reg = self._word()

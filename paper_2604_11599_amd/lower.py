@@ -42,7 +42,7 @@ import numpy as np
 from . import frontend as F
 
 # instruction ops, gate kinds and predicate comparisons of include/qsv.h
-OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB, OP_CSTORE = 1, 2, 3, 4, 5, 6, 7, 8
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB, OP_CSTORE, OP_NOISE = 1, 2, 3, 4, 5, 6, 7, 8, 9
 # classical expression ops of include/qsv.h (QSV_C_*)
 (C_END, C_IMM, C_BITS, C_NEG, C_NOT, C_LNOT, C_ADD, C_SUB, C_MUL, C_DIV, C_MOD, C_AND, C_OR, C_XOR, C_SHL, C_SHR,
  C_EQ, C_NE, C_LT, C_GT, C_LE, C_GE, C_LAND, C_LOR) = range(24)
@@ -102,6 +102,8 @@ PRED_DTYPE = np.dtype({"names": ["lo", "width", "value", "cmp", "reserved"],
 CMP_EXPR = 7
 LIN_DTYPE = np.dtype({"names": ["out", "in", "coef"], "formats": [np.uint32, np.uint32, np.float64],
                       "offsets": [0, 4, 8], "itemsize": 16})
+# qsv_noise: the first three Philox counter words of one depolarizing draw
+NOISE_DTYPE = np.dtype({"names": ["ctr"], "formats": [(np.uint64, 3)], "offsets": [0], "itemsize": 24})
 COP_DTYPE = np.dtype({"names": ["op", "sgn", "width", "lo", "imm"],
                       "formats": [np.uint8, np.uint8, np.uint16, np.uint32, np.int64],
                       "offsets": [0, 1, 2, 4, 8], "itemsize": 16})
@@ -283,12 +285,13 @@ class LoweredProgram:
     """The flat instruction stream plus the symbol layout it was lowered with."""
 
     def __init__(self, n_qubits, n_clbits, n_params, instr, pred, qregs, cregs, inputs, code=None, lin=None,
-                 n_derived=0):
+                 n_derived=0, noise=None):
         self.n_qubits, self.n_clbits, self.n_params = n_qubits, n_clbits, n_params
         self.instr, self.pred = instr, pred
         self.code = np.zeros(0, COP_DTYPE) if code is None else code
         self.lin = np.zeros(0, LIN_DTYPE) if lin is None else lin
         self.n_derived = n_derived
+        self.noise = np.zeros(0, NOISE_DTYPE) if noise is None else noise
         self.qregs, self.cregs, self.inputs = qregs, cregs, inputs
 
     @property
@@ -306,7 +309,10 @@ class _LoopCtx:
 
 
 class _Lowerer:
-    def __init__(self):
+    def __init__(self, noise=False):
+        self.with_noise = noise     # emit a depolarizing slot per operand after each gate application
+        self.noise = []             # (sid, loop code, 64 j + k) of each slot
+        self.loop_ords = []         # iteration ordinal of each enclosing for loop, outermost first
         self.rows = []
         self.preds, self.pred_ids = [], {}
         self.code = []              # classical expression code (postfix), expressions end with C_END
@@ -707,14 +713,17 @@ class _Lowerer:
         if fb is not None:
             self._emit(OP_SETF, guard, pred=self._pred(0, 0, 0, CMP_TRUE), flag=fb)
             g |= 1 << fb
-        for v in values:
+        self.loop_ords.append(0)
+        for ordinal, v in enumerate(values):
             inner = dict(env)
             inner[st.var] = v
             gi = g
             if fc is not None:
                 self._emit(OP_SETF, g, pred=self._pred(0, 0, 0, CMP_TRUE), flag=fc)
                 gi |= 1 << fc
+            self.loop_ords[-1] = ordinal
             self.block(st.body, inner, gi, _LoopCtx(fb, fc))
+        self.loop_ords.pop()
         for f in (fc, fb):
             if f is not None:
                 self._release(f)
@@ -740,6 +749,20 @@ class _Lowerer:
                     self.apply(name, a, q, guard)
             else:
                 self.apply(st.name, angles, qs, guard)
+            if self.with_noise and st.sid is not None:
+                self.noise_slots(st.sid, j, qs, guard)
+
+    def noise_slots(self, sid, j, qs, guard):
+        """After application j of gate statement sid: one depolarizing slot per
+        operand k, whose draw has counter (sid, loop code, 64 j + k, 1); the
+        loop code is sum_d ordinal_d * 2**(16 d) over the enclosing loops."""
+        if len(self.loop_ords) > 4 or any(o >= 1 << 16 for o in self.loop_ords) or len(qs) > 64:
+            raise F.QasmError("noise slots support at most 4 nested loops of at most 65536 iterations "
+                              "and 64 operands")
+        code = sum(o << (16 * d) for d, o in enumerate(self.loop_ords))
+        for k, q in enumerate(qs):
+            self.noise.append((sid, code, 64 * j + k))
+            self._emit(OP_NOISE, guard, q0=q, pred=len(self.noise) - 1)
 
     def standard_gates(self, name, angles, qs):
         """The standard gates (name, angles, qubits) a gate call applies, in order."""
@@ -816,8 +839,11 @@ class _Lowerer:
         code = np.array(self.code, dtype=COP_DTYPE) if self.code else np.zeros(0, COP_DTYPE)
         lin = [(k, slot, coef) for k, terms in enumerate(self.derived) for slot, coef in terms]
         lin = np.array(lin, dtype=LIN_DTYPE) if lin else np.zeros(0, LIN_DTYPE)
+        noise = np.zeros(len(self.noise), NOISE_DTYPE)
+        if self.noise:
+            noise["ctr"] = np.array(self.noise, dtype=np.uint64)
         return LoweredProgram(self.nq, self.nc, self.npar, instr, pred, dict(self.qregs),
-                              dict(self.cregs), dict(self.inputs), code, lin, len(self.derived))
+                              dict(self.cregs), dict(self.inputs), code, lin, len(self.derived), noise)
 
 
 def _contains(body, cls):
@@ -829,9 +855,12 @@ def _contains(body, cls):
     return False
 
 
-def lower(source):
-    """OpenQASM 3 text (or a parsed statement list) -> LoweredProgram."""
+def lower(source, noise=False):
+    """OpenQASM 3 text (or a parsed statement list) -> LoweredProgram. With
+    noise, every application of a gate statement is followed by one
+    depolarizing slot (QSV_OP_NOISE) per qubit it acts on; the slots act only
+    in calls with a positive depolarizing rate."""
     stmts = F.parse(source) if isinstance(source, str) else source
-    lw = _Lowerer()
+    lw = _Lowerer(noise)
     lw.program(stmts)
     return lw.result()

@@ -7,10 +7,10 @@ oracle's direct walk of the syntax tree on the CPU.
 import math
 
 from oracle import gates as G
-from oracle.philox import ShotStream
+from oracle.philox import ShotStream, noise_word, word_to_uniform
 from oracle.sim import TensorEngine
 
-OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB, OP_CSTORE = 1, 2, 3, 4, 5, 6, 7, 8
+OP_GATE, OP_MEASURE, OP_RESET, OP_SETF, OP_CLRF, OP_SETB, OP_CLRB, OP_CSTORE, OP_NOISE = 1, 2, 3, 4, 5, 6, 7, 8, 9
 CMP_TRUE, CMP_EXPR = 6, 7
 M64 = (1 << 64) - 1
 
@@ -78,7 +78,7 @@ def eval_pred(p, bits, code=None):
     return [v == value, v != value, v < value, v > value, v <= value, v >= value][cmp]
 
 
-def run(lp, theta=(), seed=0, shot=0, forced=None):
+def run(lp, theta=(), seed=0, shot=0, forced=None, depolarizing=0.0):
     eng = TensorEngine(lp.n_qubits)
     bits = [0] * lp.n_clbits
     flags = 0
@@ -100,6 +100,13 @@ def run(lp, theta=(), seed=0, shot=0, forced=None):
             flags &= ~(1 << int(ins["flag"]))
         elif op in (OP_SETB, OP_CLRB):
             bits[int(ins["cbit"])] = 1 if op == OP_SETB else 0
+        elif op == OP_NOISE:
+            if depolarizing > 0.0:
+                c = [int(x) for x in lp.noise[int(ins["pred"])]["ctr"]]
+                u = word_to_uniform(noise_word(seed, shot, *c))
+                if u < depolarizing:
+                    name = "x" if u < depolarizing / 3 else ("y" if u < 2 * depolarizing / 3 else "z")
+                    eng.apply(G.gate_matrix(name, [])[0], [int(ins["q0"])])
         elif op == OP_CSTORE:
             v = run_code(code, int(ins["pred"]), bits)
             for i in range(int(ins["flag"])):

@@ -376,3 +376,51 @@ def test_gate_modifier_limits_are_reported():
     for body in ("pow @ x q[0];", "pow(0.5) @ x q[0];", "ctrl(0) @ x q[0];", "ctrl @ x q[0];"):
         with pytest.raises(QasmError):
             lower('OPENQASM 3.0;\ninclude "stdgates.inc";\nqubit[3] q;\n' + body + "\n")
+
+
+# ---------------------------------------------------------------------------
+# Depolarizing slots: lowering with noise == the oracle with noise, shot by shot
+# ---------------------------------------------------------------------------
+def _compare_noisy(src, p=0.2, shots=4, seed=13):
+    lp = lower(src, noise=True)
+    assert not lp.is_unitary and len(lp.noise) == int(np.sum(lp.instr["op"] == 9))
+    hit = 0
+    for shot in range(shots):
+        o = sim.run_shot(src, seed=seed, shot=shot, depolarizing=p)
+        psi, bits, record = ir_interp.run(lp, (), seed=seed, shot=shot, depolarizing=p)
+        assert bits == o.cbits and record == o.record
+        assert np.max(np.abs(psi - o.psi)) < 1e-13
+        hit += len(o.noise_events)
+    return hit
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_noise_slots_match_oracle_random_dynamic(seed):
+    assert _compare_noisy(W.random_dynamic_program(seed, 2 + seed % 5, n_ops=40, final_measure=True)) > 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_noise_slots_match_oracle_modifiers_and_logic(seed):
+    """Modified gates (one draw per operand, controls included, after the whole
+    decomposition) and bodies emitted once per guard of a logical condition
+    (each copy carries the same draws)."""
+    _compare_noisy(W.modifier_program(seed, 3 + seed % 3, 30), shots=2)
+    _compare_noisy(W.logic_program(seed, 2 + seed % 4, 30), shots=3)
+
+
+def test_noise_slots_loops_custom_gates_and_broadcast():
+    """Draws named by statement, loop ordinals (nested, with break and
+    continue), application index of a broadcast and operand; a custom gate
+    call draws once per operand after its body."""
+    src = ('OPENQASM 3.0;\ninclude "stdgates.inc";\ngate g(a) x, y { rx(a) x; cx x, y; ry(a) y; }\n'
+           'qubit[3] q;\nbit[3] c;\nbit f;\n'
+           'for int i in [0:3] { h q[0]; f = measure q[0]; if (f == 1) continue; '
+           'for int j in [1:2] { g(0.3) q[j], q[0]; h q[2]; c[2] = measure q[2]; if (c[2] == 1) break; } }\n'
+           'x q;\nc = measure q;\n')
+    assert _compare_noisy(src, p=0.3, shots=6) > 0
+    # without a positive rate the slots change nothing
+    lp = lower(src, noise=True)
+    for shot in range(3):
+        o = sim.run_shot(src, seed=2, shot=shot)
+        psi, bits, record = ir_interp.run(lp, (), seed=2, shot=shot)
+        assert bits == o.cbits and np.max(np.abs(psi - o.psi)) < 1e-13
