@@ -119,8 +119,11 @@ enum {
   QSV_OP_CLRF = 5,     /* if active: flag <- 0 */
   QSV_OP_SETB = 6,     /* if active: classical bit `cbit` <- 1 (classical assignment) */
   QSV_OP_CLRB = 7,     /* if active: classical bit `cbit` <- 0 */
-  QSV_OP_CSTORE = 8    /* if active: classical bits [cbit, cbit + flag) <- the low `flag` bits of
+  QSV_OP_CSTORE = 8,   /* if active: classical bits [cbit, cbit + flag) <- the low `flag` bits of
                           the classical expression that starts at code[pred] */
+  QSV_OP_NOISE = 9     /* if active and the call's depolarizing rate p > 0: qubit q0 takes X, Y or
+                          Z with probability p/3 each, decided by the Philox word with counter
+                          (noise[pred].ctr[0..2], 1) (see qsv_run_opts.depolarizing) */
 };
 
 enum {
@@ -196,6 +199,15 @@ typedef struct {
   double coef;
 } qsv_lin;
 
+/* The first three Philox counter words of one depolarizing draw (QSV_OP_NOISE).
+   The lowering sets them to (gate statement index, loop code, 64 j + k): the
+   statement among those outside gate definitions in source order, sum over
+   the enclosing for loops of iteration ordinal << (16 * depth), application j
+   of the statement (register broadcast) and operand k. */
+typedef struct {
+  uint64_t ctr[3];
+} qsv_noise;
+
 typedef struct {
   uint32_t n_qubits;   /* 1 .. 34 */
   uint32_t n_clbits;
@@ -214,6 +226,10 @@ typedef struct {
   uint32_t n_lin;
   uint32_t n_derived;
   const qsv_lin* lin;
+  /* counters of the depolarizing slots (QSV_OP_NOISE pred indexes them) */
+  uint32_t n_noise;
+  uint32_t reserved3;
+  const qsv_noise* noise;
 } qsv_program_desc;
 
 /* Validates and deep-copies desc, plans the GPU passes and uploads them: the
@@ -286,6 +302,14 @@ typedef struct {
                             classical bit) when u < readout_error; 0: no draw */
   double reset_error;    /* in [0, 1): after a reset, the next word u leaves the qubit flipped
                             when u < reset_error; 0: no draw */
+  double depolarizing;   /* in [0, 1]: the rate p of the program's depolarizing slots
+                            (QSV_OP_NOISE; the paper's future-work depolarization, as quantum
+                            trajectories): an active slot draws the word w of its own counter
+                            (key (seed, shot)), u = (w >> 11) 2^-53, and applies X if u < p/3,
+                            Y if u < 2p/3, Z if u < p. The draws never touch the measurement
+                            stream. p > 0 needs a program with slots; each shot then binds its
+                            own gate matrices, and QSV_RUN_SHARE_TRAJ has no effect.
+                            qsv_run_shots only (qsv_run_batch rejects programs with slots). */
 } qsv_run_opts;
 
 typedef struct {

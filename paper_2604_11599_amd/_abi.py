@@ -32,7 +32,8 @@ class ProgramDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_uint32), ("n_clbits", C.c_uint32), ("n_params", C.c_uint32),
                 ("n_instr", C.c_uint32), ("n_pred", C.c_uint32), ("reserved", C.c_uint32),
                 ("instr", C.c_void_p), ("pred", C.c_void_p), ("n_code", C.c_uint32), ("reserved2", C.c_uint32),
-                ("code", C.c_void_p), ("n_lin", C.c_uint32), ("n_derived", C.c_uint32), ("lin", C.c_void_p)]
+                ("code", C.c_void_p), ("n_lin", C.c_uint32), ("n_derived", C.c_uint32), ("lin", C.c_void_p),
+                ("n_noise", C.c_uint32), ("reserved3", C.c_uint32), ("noise", C.c_void_p)]
 
 
 class ProgramInfo(C.Structure):
@@ -44,7 +45,7 @@ class ProgramInfo(C.Structure):
 class RunOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("shot_offset", C.c_uint64), ("forced", C.c_void_p),
                 ("forced_len", C.c_uint32), ("flags", C.c_uint32), ("state_out", C.c_void_p),
-                ("readout_error", C.c_double), ("reset_error", C.c_double)]
+                ("readout_error", C.c_double), ("reset_error", C.c_double), ("depolarizing", C.c_double)]
 
 
 class ShotResults(C.Structure):

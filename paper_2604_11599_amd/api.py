@@ -23,11 +23,13 @@ def _desc(lp):
     pred = np.ascontiguousarray(lp.pred)
     code = np.ascontiguousarray(lp.code)
     lin = np.ascontiguousarray(lp.lin)
+    noise = np.ascontiguousarray(lp.noise)
     d = A.ProgramDesc(lp.n_qubits, lp.n_clbits, lp.n_params, len(instr), len(pred), 0,
                       instr.ctypes.data if len(instr) else None, pred.ctypes.data if len(pred) else None,
                       len(code), 0, code.ctypes.data if len(code) else None,
-                      len(lin), lp.n_derived, lin.ctypes.data if len(lin) else None)
-    return d, (instr, pred, code, lin)
+                      len(lin), lp.n_derived, lin.ctypes.data if len(lin) else None,
+                      len(noise), 0, noise.ctypes.data if len(noise) else None)
+    return d, (instr, pred, code, lin, noise)
 
 
 def plan_inspect(source, tile_bits=0):
@@ -112,9 +114,10 @@ class Context:
     def profile_reset(self):
         self.check(A.lib().qsv_profile_reset(self.handle))
 
-    def load(self, source):
-        """qsv_load_program on OpenQASM 3 text or a LoweredProgram."""
-        return Program(self, source)
+    def load(self, source, noise=False):
+        """qsv_load_program on OpenQASM 3 text or a LoweredProgram. noise: lower
+        the text with depolarizing slots (run_shots(depolarizing=p) sets their rate)."""
+        return Program(self, lower(source, noise=True) if noise and isinstance(source, str) else source)
 
     def tune_lookup(self, n_qubits, complex64=False):
         """qsv_tune_lookup: the cached plan options for n_qubits, or None."""
@@ -259,9 +262,11 @@ class Program:
         return f, f.shape[1]
 
     def run_shots(self, n_shots, theta=None, seed=0, shot_offset=0, forced=None, state_out=False,
-                  share=False, readout_error=0.0, reset_error=0.0, complex64=False, noalloc=False, graph=False):
+                  share=False, readout_error=0.0, reset_error=0.0, complex64=False, noalloc=False, graph=False,
+                  depolarizing=0.0):
         """qsv_run_shots: returns host arrays of classical bits, records, probabilities, statuses.
         complex64: hold and evolve the state in single precision (QSV_RUN_COMPLEX64).
+        depolarizing: rate of the program's noise slots (a program loaded with noise=True).
         noalloc: call qsv_run_shots_noalloc (device scratch from the library's fixed array).
         graph: capture the call's launch sequence in a HIP graph and replay it (QSV_RUN_GRAPH)."""
         lp = self.lowered
@@ -288,7 +293,7 @@ class Program:
         opts = A.RunOpts(seed & 0xFFFFFFFFFFFFFFFF, shot_offset, _ptr(f), flen,
                          (A.QSV_RUN_SHARE_TRAJ if share else 0) | (A.QSV_RUN_COMPLEX64 if complex64 else 0)
                          | (A.QSV_RUN_GRAPH if graph else 0), _ptr(st),
-                         float(readout_error), float(reset_error))
+                         float(readout_error), float(reset_error), float(depolarizing))
         res = A.ShotResults(_ptr(creg), _ptr(record) if mr else None, _ptr(nev), _ptr(prob), _ptr(status))
         fn = A.lib().qsv_run_shots_noalloc if noalloc else A.lib().qsv_run_shots
         self.ctx.check(fn(self.ctx.handle, self.handle, _ptr(th), n_shots, C.byref(opts), C.byref(res)))

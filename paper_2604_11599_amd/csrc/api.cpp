@@ -73,6 +73,7 @@ struct qsv_program {
   std::vector<qsv_pred> pred;
   std::vector<qsv_cop> code;
   std::vector<qsv_lin> lin;
+  std::vector<qsv_noise> noise;
   Plan plan;
   // device copies of the static plan
   DGate* d_gates = nullptr;
@@ -89,6 +90,10 @@ struct qsv_program {
   uint32_t* d_lin_off = nullptr;
   uint32_t* d_lin_in = nullptr;
   double* d_lin_coef = nullptr;
+  // depolarizing slots: counters, and the plan's (matrix slot, counter) lists
+  qsv_noise* d_noise = nullptr;
+  uint32_t* d_noise_slot = nullptr;
+  uint32_t* d_noise_ctr = nullptr;
   uint32_t* d_csr_off = nullptr;
   uint32_t* d_csr_sj = nullptr;
   double* d_csr_scale = nullptr;
@@ -339,7 +344,8 @@ void free_plan_buffers(qsv_program* p) {
   p->graph_key.clear();
   void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense,
                   p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off,
-                  p->d_code, p->d_lin_off, p->d_lin_in, p->d_lin_coef};
+                  p->d_code, p->d_lin_off, p->d_lin_in, p->d_lin_coef, p->d_noise, p->d_noise_slot,
+                  p->d_noise_ctr};
   for (void* q : ptrs)
     if (q) ignore(hipFree(q));
   p->d_gates = nullptr;
@@ -360,6 +366,9 @@ void free_plan_buffers(qsv_program* p) {
   p->d_lin_off = nullptr;
   p->d_lin_in = nullptr;
   p->d_lin_coef = nullptr;
+  p->d_noise = nullptr;
+  p->d_noise_slot = nullptr;
+  p->d_noise_ctr = nullptr;
 }
 
 // Plans the program's stream with options o and uploads the plan (replacing a
@@ -452,6 +461,9 @@ qsv_status install_plan(qsv_context* ctx, qsv_program* p, const PlanOptions& o) 
   if (e == hipSuccess) e = upload(pl.events, &p->d_events);
   if (e == hipSuccess) e = upload(dp, &p->d_preds);
   if (e == hipSuccess) e = upload(p->code, &p->d_code);
+  if (e == hipSuccess) e = upload(p->noise, &p->d_noise);
+  if (e == hipSuccess) e = upload(pl.noise_slot, &p->d_noise_slot);
+  if (e == hipSuccess) e = upload(pl.noise_ctr, &p->d_noise_ctr);
   if (desc->n_derived) {
     std::vector<uint32_t> loff(desc->n_derived + 1, 0), lin_in;
     std::vector<double> lin_coef;
@@ -572,11 +584,13 @@ qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_
   p->pred.assign(desc->pred, desc->pred + desc->n_pred);
   if (desc->n_code) p->code.assign(desc->code, desc->code + desc->n_code);
   if (desc->n_lin) p->lin.assign(desc->lin, desc->lin + desc->n_lin);
+  if (desc->n_noise) p->noise.assign(desc->noise, desc->noise + desc->n_noise);
   p->desc = *desc;
   p->desc.instr = p->instr.data();
   p->desc.pred = p->pred.data();
   p->desc.code = p->code.data();
   p->desc.lin = p->lin.data();
+  p->desc.noise = p->noise.data();
   PlanOptions o;
   if (ctx->flags & QSV_FLAG_TUNED_PLANS) tuned_options(ctx, desc->n_qubits, false, &o);
   const qsv_status st = install_plan(ctx, p.get(), o);
@@ -617,9 +631,15 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   if (!(opts->readout_error >= 0.0 && opts->readout_error < 1.0) ||
       !(opts->reset_error >= 0.0 && opts->reset_error < 1.0))
     return set_err(ctx, QSV_ERR_ARG, "error rates must lie in [0, 1)");
+  if (!(opts->depolarizing >= 0.0 && opts->depolarizing <= 1.0))
+    return set_err(ctx, QSV_ERR_ARG, "the depolarizing rate must lie in [0, 1]");
+  if (opts->depolarizing > 0.0 && prog->plan.noise_slot.empty())
+    return set_err(ctx, QSV_ERR_ARG, "a depolarizing rate needs a program with noise slots (QSV_OP_NOISE)");
   if (n_shots == 0) return QSV_OK;
   HIP_TRY(enter_device(ctx->device));
   const Plan& pl = prog->plan;
+  // noisy calls: every shot binds its own matrices (its Paulis in the slots)
+  const bool noisy = opts->depolarizing > 0.0;
   const uint32_t n = prog->desc.n_qubits;
   const uint32_t cw = std::max<uint32_t>(1, (prog->desc.n_clbits + 63) / 64);
   const uint32_t maxrec = std::max<uint32_t>(1, pl.max_record);
@@ -630,7 +650,8 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   auto state_units = [&](uint64_t bufs) -> size_t { return c64 ? (size_t)((bufs * dim + 1) / 2) : (size_t)(bufs * dim); };
   // shots per batch: what fits in the arena / free memory after the per-shot scratch
   size_t per_shot = state_bytes + sizeof(ShotCtl) + cw * 8 + maxrec + opts->forced_len +
-                    (size_t)prog->pblocks * kSiteBins * 8 + 4 * 256;
+                    (size_t)prog->pblocks * kSiteBins * 8 + 4 * 256 +
+                    (noisy ? pl.gate_src.size() * kMatStride * 8 : 0);
   const bool in_arena = ctx->call_arena() != nullptr;
   size_t budget = in_arena ? ctx->call_arena_bytes() : (free_device_bytes() / 10) * 8;
   size_t fixed = pl.gate_src.size() * kMatStride * 8 + prog->desc.n_params * 8 + (1u << 20) +
@@ -652,7 +673,9 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   double* d_mats = nullptr;
   const uint32_t n_slots = (uint32_t)pl.gate_src.size();
   HIP_TRY(scr.get(std::max<uint32_t>(1, prog->desc.n_params), &d_theta));
-  HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride, &d_mats));
+  // matrices: one set for the call, or one per shot of a batch when noisy
+  const uint64_t ms = noisy ? (uint64_t)std::max<uint32_t>(1, n_slots) * kMatStride : 0;
+  HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride * (noisy ? batch : 1), &d_mats));
   double* d_ext = nullptr;
   if (prog->desc.n_derived) HIP_TRY(scr.get(prog->desc.n_params + prog->desc.n_derived, &d_ext));
   if (prog->desc.n_params)
@@ -660,21 +683,27 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   RunBuffers rb{};
   // state buffers: one per shot, or with trajectory sharing one per slot that
   // owns its state, grown on demand (doubling) up to one per shot
-  const bool share_req = (opts->flags & QSV_RUN_SHARE_TRAJ) != 0;
+  const bool share_req = (opts->flags & QSV_RUN_SHARE_TRAJ) != 0 && !noisy;
   // a captured launch sequence: one batch, no host decisions between launches
   const bool use_graph = (opts->flags & QSV_RUN_GRAPH) != 0 && !share_req && n_shots <= batch &&
                          ctx->stream != nullptr && !ctx->noalloc;
-  auto bind = [&]() -> qsv_status {
+  // binds the call's matrices (noisy: the shots of the batch, each with its
+  // Paulis drawn under the batch's key, already in d_key)
+  auto bind = [&](uint32_t bs) -> qsv_status {
     const double* rows = nullptr;
     uint32_t stride = 0;
+    const uint32_t sets = noisy ? bs : 1u;
     HIP_TRY(bind_theta(prog, d_theta, 1, d_ext, st, &rows, &stride));
-    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, stride, 1, d_mats, nullptr, st));
-    HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates, 1,
-                                 0, d_mats, st));
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, noisy ? 0u : stride, sets, d_mats, nullptr, st));
+    if (noisy)
+      HIP_TRY(launch_noise_matrices(prog->d_noise_slot, prog->d_noise_ctr, (uint32_t)pl.noise_slot.size(),
+                                    prog->d_noise, rb.key, opts->depolarizing, bs, ms, d_mats, st));
+    HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates,
+                                 sets, ms, d_mats, st));
     return QSV_OK;
   };
-  if (!use_graph) {
-    const qsv_status bs = bind();
+  if (!use_graph && !noisy) {
+    const qsv_status bs = bind(1);
     if (bs != QSV_OK) return bs;
   }
   // (in an arena every shot's buffer is reserved up front: a bump allocator
@@ -743,14 +772,14 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     if (use_graph) {
       // the whole launch sequence of the call, captured once and replayed
       auto issue = [&]() -> qsv_status {
-        const qsv_status b = bind();
+        const qsv_status b = bind(bs);
         if (b != QSV_OK) return b;
         HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, rb.record, maxrec, bs, st));
         for (const Step& step : pl.steps) {
           if (step.kind == Step::INIT)
             HIP_TRY(launch_init_state(rb.state, rb.stride, n, bs, st, c64));
           else if (step.kind == Step::PASS)
-            HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
+            HIP_TRY(launch_tile_pass(rb, prog->d_gates, prog->d_phases, d_mats, ms, pl.passes[step.index], st));
           else
             HIP_TRY(launch_site(rb, pl.sites[step.index], prog->d_events, prog->d_preds, prog->d_code, st));
         }
@@ -764,6 +793,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       };
       const std::vector<uint64_t> gkey = {
           n_shots, opts->flags, opts->forced_len, bits(opts->readout_error), bits(opts->reset_error),
+          bits(opts->depolarizing),
           opts->state_out ? 1ull : 0ull, (uint64_t)(uintptr_t)d_theta, (uint64_t)(uintptr_t)d_mats,
           (uint64_t)(uintptr_t)rb.state, (uint64_t)(uintptr_t)rb.ctl, (uint64_t)(uintptr_t)rb.creg,
           (uint64_t)(uintptr_t)rb.record, (uint64_t)(uintptr_t)rb.partials, (uint64_t)(uintptr_t)d_forced,
@@ -800,6 +830,10 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
       if (opts->state_out)
         HIP_TRY(hipMemcpyAsync(opts->state_out, d_out, dim * sizeof(double2), hipMemcpyDeviceToHost, st));
     } else {
+    if (noisy) {
+      const qsv_status b = bind(bs);
+      if (b != QSV_OK) return b;
+    }
     HIP_TRY(launch_init_ctl(rb.ctl, rb.creg, cw, rb.record, maxrec, bs, st));
     // the view the passes run on: one state per slot with the slot's control block
     RunBuffers rp = rb;
@@ -842,7 +876,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
             HIP_TRY(hipStreamSynchronize(st));  // the host tables change again after the uploads
           }
         }
-        HIP_TRY(launch_tile_pass(rp, prog->d_gates, prog->d_phases, d_mats, 0, pl.passes[step.index], st));
+        HIP_TRY(launch_tile_pass(rp, prog->d_gates, prog->d_phases, d_mats, ms, pl.passes[step.index], st));
         const double amps = (double)dim * n_slot;
         pr.done(0, pl.pass_uncond[step.index] != 0,
                 pass_bytes_per_amp(pl.passes[step.index]) * (c64 ? 0.5 : 1.0) * amps,
@@ -972,6 +1006,9 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     if (!(q.opts.readout_error >= 0.0 && q.opts.readout_error < 1.0) ||
         !(q.opts.reset_error >= 0.0 && q.opts.reset_error < 1.0))
       return set_err(ctx, QSV_ERR_ARG, "request " + std::to_string(r) + ": error rates must lie in [0, 1)");
+    if (!q.prog->plan.noise_slot.empty() || q.opts.depolarizing != 0.0)
+      return set_err(ctx, QSV_ERR_UNSUPPORTED, "request " + std::to_string(r) +
+                                                   ": programs with noise slots run through qsv_run_shots");
     const uint32_t n = q.prog->desc.n_qubits;
     if (q.n_shots == 0) continue;
     // wide states, and streamed states with many shots, run on the tile-pass

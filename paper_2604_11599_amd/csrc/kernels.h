@@ -43,6 +43,11 @@ hipError_t resident_grid(const void* kernel, uint32_t threads, size_t lds, size_
 // theta [batch][P] -> [batch][P + D] with the derived parameters appended
 hipError_t launch_derive_params(const double* theta, uint32_t P, uint32_t D, const uint32_t* off, const uint32_t* in,
                                 const double* coef, uint32_t batch, double* out, hipStream_t st);
+// Per-shot Paulis of the depolarizing slots (rate p; key = (seed, first shot)
+// in device memory, shot s uses key word 1 + s) into the shots' matrices.
+hipError_t launch_noise_matrices(const uint32_t* slot, const uint32_t* ctr, uint32_t n, const qsv_noise* noise,
+                                 const uint64_t* key, double p, uint32_t shots, uint64_t mat_stride, double* mats,
+                                 hipStream_t st);
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);

@@ -27,10 +27,10 @@
 
 namespace qsv {
 
-// Philox4x64-10 (Salmon et al., SC'11): multipliers and Weyl increments of Philox4x64.
-__device__ __forceinline__ uint64_t philox_word(uint64_t seed, uint64_t shot, uint64_t event) {
-  uint64_t c0 = event / 4 + 1, c1 = 0, c2 = 0, c3 = 0;
-  uint64_t k0 = seed, k1 = shot;
+// Philox4x64-10 (Salmon et al., SC'11): multipliers and Weyl increments of
+// Philox4x64. One block for key (k0, k1) and counter (c0, c1, c2, c3), in place.
+__device__ __forceinline__ void philox_block(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3, uint64_t k0,
+                                             uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
@@ -45,6 +45,12 @@ __device__ __forceinline__ uint64_t philox_word(uint64_t seed, uint64_t shot, ui
     k0 += W0;
     k1 += W1;
   }
+}
+
+// The shot's word of measure/reset event `event`: counter (event / 4 + 1, 0, 0, 0), word event % 4.
+__device__ __forceinline__ uint64_t philox_word(uint64_t seed, uint64_t shot, uint64_t event) {
+  uint64_t c0 = event / 4 + 1, c1 = 0, c2 = 0, c3 = 0;
+  philox_block(c0, c1, c2, c3, seed, shot);
   switch (event & 3) {
     case 0: return c0;
     case 1: return c1;
@@ -182,6 +188,39 @@ hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const doub
   uint32_t blocks = (uint32_t)((total + 255) / 256);
   hipLaunchKernelGGL(k_bind_matrices, dim3(blocks), dim3(256), 0, st, src, n_slots, theta, n_params,
                      batch, mats, dmats);
+  return hipGetLastError();
+}
+
+// Depolarizing slots of a call with rate p (one thread per shot and slot): the
+// word of counter (noise[ctr[e]].ctr[0..2], 1) under key (key[0], key[1] + s),
+// as u = (w >> 11) 2^-53, puts X (u < p/3), Y (u < 2p/3), Z (u < p) or the
+// identity into matrix slot slot[e] of shot s. The fourth counter word is 0 in
+// every measure/reset event's counter, so the two kinds of draws never meet.
+__global__ void k_noise_matrices(const uint32_t* __restrict__ slot, const uint32_t* __restrict__ ctr, uint32_t n,
+                                 const qsv_noise* __restrict__ noise, const uint64_t* __restrict__ key, double p,
+                                 uint32_t shots, uint64_t mat_stride, double* __restrict__ mats) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n * shots) return;
+  const uint32_t s = (uint32_t)(idx / n), e = (uint32_t)(idx % n);
+  const qsv_noise c = noise[ctr[e]];
+  uint64_t c0 = c.ctr[0], c1 = c.ctr[1], c2 = c.ctr[2], c3 = 1;
+  philox_block(c0, c1, c2, c3, key[0], key[1] + s);
+  const double u = (double)(c0 >> 11) * 0x1p-53;
+  const double2 Z0 = make_double2(0, 0), O1 = make_double2(1, 0);
+  double* m = mats + (uint64_t)s * mat_stride + (uint64_t)slot[e] * kMatStride;
+  if (u >= p) set2(m, O1, Z0, Z0, O1);
+  else if (u < p / 3.0) set2(m, Z0, O1, O1, Z0);
+  else if (u < 2.0 * p / 3.0) set2(m, Z0, make_double2(0, -1), make_double2(0, 1), Z0);
+  else set2(m, O1, Z0, Z0, make_double2(-1, 0));
+}
+
+hipError_t launch_noise_matrices(const uint32_t* slot, const uint32_t* ctr, uint32_t n, const qsv_noise* noise,
+                                 const uint64_t* key, double p, uint32_t shots, uint64_t mat_stride, double* mats,
+                                 hipStream_t st) {
+  const uint64_t total = (uint64_t)n * shots;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_noise_matrices, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, slot, ctr, n, noise,
+                     key, p, shots, mat_stride, mats);
   return hipGetLastError();
 }
 

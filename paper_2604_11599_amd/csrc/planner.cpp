@@ -266,6 +266,11 @@ bool validate_program(const qsv_program_desc& d, std::string* err) {
           return fail(at + "stored bits out of range");
         if (!expr_ok(in.pred, &why)) return fail(at + why);
         break;
+      case QSV_OP_NOISE:
+        if (in.q0 >= d.n_qubits) return fail(at + "qubit out of range");
+        if (in.kind != QSV_G_ID) return fail(at + "a noise slot carries gate kind 0");
+        if (in.pred >= d.n_noise || !d.noise) return fail(at + "noise counter out of range");
+        break;
       default:
         return fail(at + "unknown op");
     }
@@ -292,11 +297,11 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
     const qsv_instr& in = d.instr[i];
     GateSrc s;
     std::memset(&s, 0, sizeof(s));
-    s.kind = in.kind;
+    s.kind = in.op == QSV_OP_NOISE ? kNoiseSlotKind : in.kind;
     for (int k = 0; k < 3; ++k) {
-      s.param[k] = in.param[k];
-      s.scale[k] = in.scale[k];
-      s.offset[k] = in.offset[k];
+      s.param[k] = in.op == QSV_OP_NOISE ? QSV_NONE : in.param[k];
+      s.scale[k] = in.op == QSV_OP_NOISE ? 0.0 : in.scale[k];
+      s.offset[k] = in.op == QSV_OP_NOISE ? 0.0 : in.offset[k];
     }
     plan.gate_src.push_back(s);
     plan.slot_instr.push_back(i);
@@ -307,7 +312,7 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
     std::vector<GateRef> rem;
     for (uint32_t i : run) {
       const qsv_instr& in = d.instr[i];
-      if (in.kind == QSV_G_ID) continue;
+      if (in.op == QSV_OP_GATE && in.kind == QSV_G_ID) continue;
       uint64_t m = 1ull << in.q0;
       if (two_qubit(in.kind)) m |= 1ull << in.q1;
       rem.push_back({i, m});
@@ -372,7 +377,8 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
         const qsv_instr& in = d.instr[rem[i].instr];
         DGate g;
         std::memset(&g, 0, sizeof(g));
-        g.type = gate_type(in.kind);
+        // a depolarizing slot is a one-qubit gate whose matrix each shot binds
+        g.type = in.op == QSV_OP_NOISE ? GT_DENSE1 : gate_type(in.kind);
         g.b0 = (uint8_t)pos[in.q0];
         g.b1 = two_qubit(in.kind) ? (uint8_t)pos[in.q1] : 0;
         g.guard = in.guard;
@@ -467,7 +473,7 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
   bool in_site = false;
   for (uint32_t i = 0; i < d.n_instr; ++i) {
     const qsv_instr& in = d.instr[i];
-    bool event = in.op != QSV_OP_GATE;
+    bool event = in.op != QSV_OP_GATE && in.op != QSV_OP_NOISE;
     bool foldable_x = in.op == QSV_OP_GATE && in.kind == QSV_G_X && in_site;
     if (event || foldable_x) {
       if (!in_site && !run.empty()) {
@@ -498,6 +504,10 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
       src[i] = plan.gate_src[plan.gates[i].mat];
       instr[i] = plan.slot_instr[plan.gates[i].mat];
       plan.gates[i].mat = (uint32_t)i;
+      if (d.instr[instr[i]].op == QSV_OP_NOISE) {
+        plan.noise_slot.push_back((uint32_t)i);
+        plan.noise_ctr.push_back(d.instr[instr[i]].pred);
+      }
     }
     plan.gate_src.swap(src);
     plan.slot_instr.swap(instr);

@@ -29,6 +29,10 @@ struct Plan {
   std::vector<GateSrc> gate_src;  // one matrix slot per planned gate
   std::vector<uint32_t> slot_instr;  // instruction index of each matrix slot
   std::vector<uint32_t> dense_phases;  // phases applied as one composed 16x16 matrix
+  // depolarizing slots: (matrix slot, index into the program's noise counters);
+  // a slot's matrix is the identity unless a call with a positive rate binds
+  // its shot's Pauli there
+  std::vector<uint32_t> noise_slot, noise_ctr;
   uint32_t max_record = 0;        // measure instructions in the stream
   uint32_t max_events = 0;        // measure + reset instructions
   bool unitary = true;

@@ -43,6 +43,10 @@ struct DGate {      // 32 bytes (one scalar 8-dword load)
 };
 
 // Source of a gate matrix: rebuilt on the device from theta at every call.
+// GateSrc kind of a depolarizing slot (QSV_OP_NOISE): bound as the identity,
+// its Pauli written per shot by the noise kernel.
+constexpr uint32_t kNoiseSlotKind = QSV_G_COUNT;
+
 struct GateSrc {    // 64 bytes
   uint32_t kind;    // QSV_G_*
   uint32_t param[3];

@@ -55,12 +55,13 @@ def test_struct_layouts_match_header(tmp_path):
     compiler's own sizeof/offsetof of include/qsv.h."""
     import shutil
     import subprocess
-    from paper_2604_11599_amd.lower import COP_DTYPE, INSTR_DTYPE, LIN_DTYPE, PRED_DTYPE
+    from paper_2604_11599_amd.lower import COP_DTYPE, INSTR_DTYPE, LIN_DTYPE, NOISE_DTYPE, PRED_DTYPE
     checks = {"qsv_config": _abi.Config, "qsv_program_desc": _abi.ProgramDesc, "qsv_run_opts": _abi.RunOpts,
               "qsv_shot_results": _abi.ShotResults, "qsv_pauli_sum": _abi.PauliSum, "qsv_request": _abi.Request,
               "qsv_profile": _abi.Profile, "qsv_plan_options": _abi.PlanOptions, "qsv_tune_report": _abi.TuneReport,
               "qsv_program_info": _abi.ProgramInfo, "qsv_plan_stats": _abi.PlanStats}
-    dtypes = {"qsv_instr": INSTR_DTYPE, "qsv_pred": PRED_DTYPE, "qsv_cop": COP_DTYPE, "qsv_lin": LIN_DTYPE}
+    dtypes = {"qsv_instr": INSTR_DTYPE, "qsv_pred": PRED_DTYPE, "qsv_cop": COP_DTYPE, "qsv_lin": LIN_DTYPE,
+              "qsv_noise": NOISE_DTYPE}
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
