@@ -260,8 +260,8 @@ def c4_traffic():
         return {}
     with open(path) as f:
         d = json.load(f)
-    from traffic_summary import kernel_hash
-    if d.get("kernel_hash") != kernel_hash():
+    from traffic_summary import ADJOINT_SOURCES, kernel_hash
+    if d.get("kernel_hash") != kernel_hash(ADJOINT_SOURCES):
         return {}
     return {k: v["bytes_per_launch"] for k, v in d.get("kernels", {}).items()}
 
@@ -368,6 +368,17 @@ def bench_shots(args):
                         "note": "same shots, QSV_RUN_GRAPH: the call's launches captured once in a HIP graph and "
                                 "replayed (bit-identical results)"}
         log("graph steps done")
+        # the same shots under depolarizing noise (rate 1e-3 per qubit after every gate)
+        noisy = ctx.load(src, noise=True)
+        noisy.run_shots(shots, seed=998, depolarizing=1e-3)
+        dt_n = timed(lambda s: noisy.run_shots(shots, seed=s, depolarizing=1e-3), args.steps, 0)
+        out["depolarizing"] = {"value": shots * args.steps / dt_n, "unit": "shots/s",
+                               "ms_per_step": 1e3 * dt_n / args.steps, "rate": 1e-3,
+                               "passes_per_shot": noisy.info.n_passes,
+                               "note": "same program loaded with depolarizing slots: after every gate each of "
+                                       "its qubits takes X, Y or Z with probability 1e-3/3; each shot binds and "
+                                       "composes its own matrices"}
+        log("depolarizing steps done")
     if args.workload == "c2":
         # the same steps with trajectory sharing (shots with equal measurement histories share one state)
         dt_sp = timed(lambda s: prog.run_shots(shots, seed=s, share=True), args.steps, 0)

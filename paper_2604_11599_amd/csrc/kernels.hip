@@ -1069,13 +1069,16 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
     const double sc = cst(c)->pend_scale;
     const bool pending = M != 0 || sc != 1.0;
     const uint64_t gthr = tile_base(it % a.tiles, free_mask) | tb;
-    CT* st = state + (uint64_t)shot * stride;
+    // amplitude k of this thread is at physical index (gthr | h_k) ^ F = lb + off(k):
+    // flipping tile bit h moves by +h, or by -h where the frame holds that bit
+    // (gthr never does), so the offsets are wave-uniform and only lb is per lane
+    const int64_t d0 = (F & h0) ? -(int64_t)h0 : (int64_t)h0, d1 = (F & h1) ? -(int64_t)h1 : (int64_t)h1,
+                  d2 = (F & h2) ? -(int64_t)h2 : (int64_t)h2;
+    auto off = [&](int k) { return ((k & 1) ? d0 : 0) + ((k & 2) ? d1 : 0) + ((k & 4) ? d2 : 0); };
+    CT* sp = state + (uint64_t)shot * stride + (gthr ^ F);
     CT r[kA];
 #pragma unroll
-    for (int k = 0; k < (int)kA; ++k) {
-      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
-      r[k] = a.init ? cmake<CT>(gi == 0 ? 1.0 : 0.0, 0.0) : st[gi ^ F];
-    }
+    for (int k = 0; k < (int)kA; ++k) r[k] = a.init ? cmake<CT>(k == 0 && gthr == 0 ? 1.0 : 0.0, 0.0) : sp[off(k)];
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) {
       const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
@@ -1108,10 +1111,7 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
 #pragma unroll
     for (int k = 0; k < (int)kA; ++k) r[k] = tile[swz(tid + (uint32_t)k * nth)];
 #pragma unroll
-    for (int k = 0; k < (int)kA; ++k) {
-      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull);
-      st[gi ^ F] = r[k];
-    }
+    for (int k = 0; k < (int)kA; ++k) sp[off(k)] = r[k];
     if (pending) {
       __syncthreads();
       if (tid == 0) {

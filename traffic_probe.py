@@ -24,8 +24,9 @@ def main():
     import workloads as W
     from paper_2604_11599_amd import Context
     from paper_2604_11599_amd import _abi as A
-    from traffic_summary import kernel_hash
+    from traffic_summary import ADJOINT_SOURCES, kernel_hash
     print(f"kernel_hash={kernel_hash()}", flush=True)
+    print(f"kernel_hash_adjoint={kernel_hash(ADJOINT_SOURCES)}", flush=True)
     ctx = Context(0)
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)

@@ -27,14 +27,17 @@ PASS_KERNEL = "k_tile_pass"
 COPY_KERNEL = "k_copy"
 
 
-def kernel_hash():
-    """Hash of every device source (kernels, launchers, shared device types)."""
+# device sources of the tile pass and of the energy + gradient kernels
+PASS_SOURCES = ("kernels.hip", "device_common.h", "qsv_types.h")
+ADJOINT_SOURCES = ("adjoint.hip", "device_common.h", "qsv_types.h")
+
+
+def kernel_hash(sources=PASS_SOURCES):
+    """Hash of the device sources the counted kernels are built from."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2604_11599_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sources:
+        with open(os.path.join(ROOT, "paper_2604_11599_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -55,12 +58,12 @@ def read_counter(path, counter):
     return rows
 
 
-def probe_hash(log):
+def probe_hash(log, tag="kernel_hash"):
     with open(log) as f:
         for line in f:
-            if line.startswith("kernel_hash="):
+            if line.startswith(tag + "="):
                 return line.strip().split("=", 1)[1]
-    raise SystemExit("no kernel_hash line in the probe log")
+    raise SystemExit(f"no {tag} line in the probe log")
 
 
 def uncond_mask():
@@ -148,7 +151,7 @@ def summarize_kernels(fetch_csv, write_csv, khash, kernels, amps):
 def main_c4(args):
     fetch_csv, write_csv, log = args[0], args[1], args[2]
     cmd = args[3] if len(args) > 3 else ""
-    d = summarize_kernels(fetch_csv, write_csv, probe_hash(log), C4_KERNELS, C4_AMPS)
+    d = summarize_kernels(fetch_csv, write_csv, probe_hash(log, "kernel_hash_adjoint"), C4_KERNELS, C4_AMPS)
     d["command"] = cmd
     d["workload"] = "20-qubit ansatz, 64 parameter vectors, one energy + gradient call"
     with open(os.path.join(ROOT, "profiles", "c4_20q_traffic.json"), "w") as f:
