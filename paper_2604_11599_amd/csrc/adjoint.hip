@@ -67,11 +67,16 @@ __global__ __launch_bounds__(kHamThreads, 4) void k_hamiltonian(
   }
   uint64_t tmask = 0;
   for (uint32_t j = 0; j < t; ++j) tmask |= 1ull << TQ->tq[j];
-  uint64_t base = 0;  // the tile index scattered over the qubits outside the tile, ascending
+  uint64_t base = 0;  // the tile index scattered over the qubits outside the tile
   {
-    uint32_t k = 0;
+    uint64_t xm = 0;
+    for (uint32_t j = 0; j < TQ->nx; ++j) {
+      base |= (uint64_t)((tile >> j) & 1u) << TQ->xq[j];
+      xm |= 1ull << TQ->xq[j];
+    }
+    uint32_t k = TQ->nx;
     for (uint32_t q = 0; q < n; ++q)
-      if (!((tmask >> q) & 1ull)) base |= (uint64_t)((tile >> k++) & 1u) << q;
+      if (!(((tmask | xm) >> q) & 1ull)) base |= (uint64_t)((tile >> k++) & 1u) << q;
   }
   __syncthreads();
   const double2* st = psi + (uint64_t)b * stride;

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cstdio>
 #include <map>
@@ -1270,6 +1271,37 @@ HamTile ham_tile(uint32_t n, const std::vector<uint64_t>& gx) {
   uint32_t j = 0;
   for (uint32_t q = 0; q < n && j < t; ++q)
     if ((mask >> q) & 1ull) T.tq[j++] = (uint8_t)q;
+  // the tile-index bits that pick the XCD: the outside qubits in the fewest
+  // remote X masks (every choice of kXcdBits of them; ties to the lowest)
+  std::vector<uint32_t> out;
+  for (uint32_t q = 0; q < n; ++q)
+    if (!((mask >> q) & 1ull)) out.push_back(q);
+  T.nx = (uint8_t)std::min<size_t>(kXcdBits, out.size());
+  auto cost = [&](uint64_t sel) {
+    uint32_t c = 0;
+    for (uint64_t x : gx) c += (x & sel) != 0;
+    return c;
+  };
+  std::vector<uint32_t> best(T.nx), cur(T.nx);
+  uint32_t best_c = UINT32_MAX;
+  std::function<void(uint32_t, uint32_t)> pick = [&](uint32_t from, uint32_t k) {
+    if (k == T.nx) {
+      uint64_t sel = 0;
+      for (uint32_t q : cur) sel |= 1ull << q;
+      const uint32_t c = cost(sel);
+      if (c < best_c) {
+        best_c = c;
+        best = cur;
+      }
+      return;
+    }
+    for (uint32_t i = from; i < out.size(); ++i) {
+      cur[k] = out[i];
+      pick(i + 1, k + 1);
+    }
+  };
+  pick(0, 0);
+  for (uint32_t k = 0; k < T.nx; ++k) T.xq[k] = (uint8_t)best[k];
   return T;
 }
 

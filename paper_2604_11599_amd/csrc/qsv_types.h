@@ -152,8 +152,16 @@ struct ShotCtl {
 };
 
 // Tiles of the Hamiltonian sweep: tile-local bit j <-> qubit tq[j] (ascending).
+// Bits 0..nx-1 of the tile index select outside qubits xq[0..nx-1], the rest
+// the other outside qubits in ascending order. Workgroups go to the XCDs
+// round-robin, so those bits pick the XCD (and its L2) of a tile: chosen among
+// the qubits the fewest X masks flip, they keep most partner tiles on the XCD
+// that reads them.
+constexpr uint32_t kXcdBits = 3;  // 8 XCDs
 struct HamTile {
   uint8_t tq[kTileMaxBits];
+  uint8_t xq[kXcdBits];
+  uint8_t nx;
   uint32_t t;
 };
 
