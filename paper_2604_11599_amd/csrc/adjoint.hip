@@ -782,6 +782,14 @@ __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
       }
       qsv_d4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
       adjoint_phase_mfma(tp, tl, T, lane, wave, ph, wf, c1, c2, c3);
+      // this wave's first S, requested before the partials are summed (its
+      // load then overlaps the barriers below)
+      double2 s0[4];
+      if (my_n) {
+        const double2* S = sb + (uint64_t)(e0 + wave) * 256u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s0[v] = S[v * 64 + (int)lane];
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         cbuf[wave * 256u + (uint32_t)v * 64u + lane] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
@@ -816,7 +824,7 @@ __global__ __launch_bounds__(kBwWaves * 64) void k_backward_mfma(
             const double2* S = sb + (uint64_t)(e0 + wave + (k0 + uu) * nwaves) * 256u;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const double2 sv = S[v * 64 + (int)lane];
+              const double2 sv = (k0 + uu == 0) ? s0[v] : S[v * 64 + (int)lane];
               part[uu] += sv.x * cr[v] - sv.y * ci[v];
             }
           }
