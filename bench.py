@@ -341,7 +341,7 @@ def bench_shots(args):
     prof = ctx.profile()
     out = base_line(args, shots * args.steps / dt, "shots/s", dt, cfg)
     launches = prof["pass_uncond_launches"]
-    roof = hbm_roof("k_tile_pass_d8" if args.workload == "c2" else "k_tile_pass", launches,
+    roof = hbm_roof("k_tile_pass_d8" if args.workload == "c2" else "k_tile_pass_d8, k_tile_pass_r", launches,
                     prof["pass_uncond_ms"], prof["pass_uncond_bytes"], ceiling,
                     traffic_from_profiles(args.workload),
                     "32 B per amplitude per tile pass (read + write of a complex128), 16 B for the pass "
