@@ -425,3 +425,24 @@ def test_noise_slots_loops_custom_gates_and_broadcast():
         o = sim.run_shot(src, seed=2, shot=shot)
         psi, bits, record = ir_interp.run(lp, (), seed=2, shot=shot)
         assert bits == o.cbits and np.max(np.abs(psi - o.psi)) < 1e-13
+
+
+def test_noise_slot_validation_on_the_host():
+    """The planner takes noise slots as one-qubit dense gates (one matrix slot
+    each) and rejects slots whose counter index or gate kind is out of range."""
+    from paper_2604_11599_amd import QsvError
+    from paper_2604_11599_amd.api import plan_inspect
+    src = 'OPENQASM 3.0;\ninclude "stdgates.inc";\nqubit[3] q;\nbit[3] c;\nh q[0];\ncx q[0], q[1];\nc = measure q;\n'
+    plain, noisy = plan_inspect(lower(src)), plan_inspect(lower(src, noise=True))
+    assert noisy.n_gates == plain.n_gates + 3 and not noisy.is_unitary
+    lp = lower(src, noise=True)
+    bad = lower(src, noise=True)
+    k = int(np.flatnonzero(bad.instr["op"] == 9)[0])
+    bad.instr["pred"][k] = len(bad.noise)
+    with pytest.raises(QsvError):
+        plan_inspect(bad)
+    bad = lower(src, noise=True)
+    bad.instr["kind"][k] = 4
+    with pytest.raises(QsvError):
+        plan_inspect(bad)
+    assert plan_inspect(lp).n_gates == noisy.n_gates
