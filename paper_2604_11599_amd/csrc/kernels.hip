@@ -780,47 +780,11 @@ __device__ __forceinline__ void run_phases(CT* __restrict__ tile, uint32_t T, ui
   }
 }
 
-// Tile-local index l = tid + k * 2^(t-4) (k = 0..15) of thread tid: its global
-// index is base | (tid's bits over tq[0..t-5]) | (k's bits over tq[t-4..t-1]).
-// Logical amplitude i is stored at memory index i ^ F (the shot's flip frame),
-// so a workgroup reads and writes one memory tile while gates see logical
-// indices. All 16 loads are issued before the first use.
-__device__ __forceinline__ void load_tile16(double2* __restrict__ tile, const double2* __restrict__ st,
-                                            const PassArgs& a, uint64_t base, uint32_t tid, uint64_t M, uint64_t V,
-                                            uint64_t F, double s, bool pending) {
-  const uint32_t nthr = 1u << (a.t - kRegBits);
-  uint64_t gthr = base;
-  for (uint32_t b = 0; b + kRegBits < a.t; ++b) gthr |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
-  const uint64_t h0 = 1ull << a.tq[a.t - 4], h1 = 1ull << a.tq[a.t - 3], h2 = 1ull << a.tq[a.t - 2],
-                 h3 = 1ull << a.tq[a.t - 1];
-  double2 r[kR];
-  if (a.init) {
-#pragma unroll
-    for (int k = 0; k < kR; ++k) {
-      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
-                          ((k & 8) ? h3 : 0ull);
-      r[k] = make_double2(gi == 0 ? 1.0 : 0.0, 0.0);
-    }
-  } else if (M == 0) {
-#pragma unroll
-    for (int k = 0; k < kR; ++k) {
-      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
-                          ((k & 8) ? h3 : 0ull);
-      r[k] = st[gi ^ F];
-    }
-  } else {
-    // a collapse is owed: amplitudes outside the kept outcome are zero and not read
-#pragma unroll
-    for (int k = 0; k < kR; ++k) {
-      const uint64_t gi = gthr | ((k & 1) ? h0 : 0ull) | ((k & 2) ? h1 : 0ull) | ((k & 4) ? h2 : 0ull) |
-                          ((k & 8) ? h3 : 0ull);
-      r[k] = ((gi & M) == V) ? st[gi ^ F] : make_double2(0.0, 0.0);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kR; ++k) tile[swz(tid + (uint32_t)k * nthr)] = pending ? cscale(r[k], s) : r[k];
-}
-
+// Tile-local index l = tid + k * 2^(t-4) (k = 0..15) of thread tid < 2^(t-4):
+// its global index is base | (tid's bits over tq[0..t-5]) | (k's bits over
+// tq[t-4..t-1]). Logical amplitude i is stored at memory index i ^ F (the
+// shot's flip frame), so a workgroup reads and writes one memory tile while
+// gates see logical indices.
 __device__ __forceinline__ void store_tile16(const double2* __restrict__ tile, double2* __restrict__ st,
                                              const PassArgs& a, uint64_t base, uint32_t tid, uint64_t F) {
   const uint32_t nthr = 1u << (a.t - kRegBits);
@@ -1645,22 +1609,28 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             }
           }
         } else {
-          // stream the HBM slot tile by tile; the pending collapse and frame apply on load
+          // stream the HBM slot tile by tile; the pending collapse and frame
+          // apply on staging. The 16 loads per thread of the next tile are
+          // issued before the current tile's phases run (tiles of one pass
+          // are disjoint), so they overlap its gate arithmetic.
           const uint64_t M = cs.pend_mask, V = cs.pend_val, F = cs.frame;
           const double sc = cs.pend_scale;
-          const bool pending = M != 0 || sc != 1.0;
           const uint32_t T = 1u << a.t, nthr = T >> kRegBits;
+          uint64_t tb = 0;  // this thread's bits over tile qubits tq[0..t-5]
+          for (uint32_t b = 0; b + kRegBits < a.t; ++b) tb |= (uint64_t)((tid >> b) & 1u) << a.tq[b];
+          const uint64_t h0 = 1ull << a.tq[a.t - 4], h1 = 1ull << a.tq[a.t - 3], h2 = 1ull << a.tq[a.t - 2],
+                         h3 = 1ull << a.tq[a.t - 1];
+          const uint64_t free_mask = ~a.tile_mask & ((n >= 64) ? ~0ull : ((1ull << n) - 1ull));
+          double2 nx[kR];
+          if (tid < nthr) fetch16(nx, slot, tile_base(0, free_mask) | tb, h0, h1, h2, h3, a.init != 0, F);
           for (uint32_t w = 0; w < a.tiles; ++w) {
-            uint64_t base = 0;
-            {
-              uint32_t kk = 0;
-              for (uint32_t q = 0; q < n; ++q)
-                if (!((a.tile_mask >> q) & 1ull)) base |= (uint64_t)((w >> kk++) & 1u) << q;
-            }
-            load_tile16(tile, slot, a, base, tid, M, V, F, sc, pending);
+            const uint64_t gthr = tile_base(w, free_mask) | tb;
+            if (tid < nthr) stage16(tile, nx, tid, nthr, gthr, h0, h1, h2, h3, M, V, sc);
             __syncthreads();
+            if (w + 1 < a.tiles && tid < nthr)
+              fetch16(nx, slot, tile_base(w + 1, free_mask) | tb, h0, h1, h2, h3, a.init != 0, F);
             run_phases<false, true>(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
-            store_tile16(tile, slot, a, base, tid, F);
+            if (tid < nthr) store_tile16(tile, slot, a, tile_base(w, free_mask), tid, F);
             __syncthreads();
           }
           if (tid == 0) {

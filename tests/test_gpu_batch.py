@@ -147,3 +147,17 @@ def test_batch_many_shot_route_matches_oracle(ctx):
     _check(main, res[0], 64, 5, 100)
     _check(other, res[1], 96, 6)
     _check(small, res[2], 16, 7)
+
+
+def test_batch_streamed_states_on_narrower_tiles(ctx):
+    """Streamed (13..20-qubit) requests in the persistent launch whose plans
+    use 11- and 10-bit tiles (fewer threads per tile than the workgroup has):
+    every shot against the oracle, and equal to the default 12-bit plan."""
+    src = W.random_dynamic_program(401, 15, n_ops=60, final_measure=True)
+    base = ctx.run_batch([{"prog": ctx.load(src), "shots": 6, "seed": 9}])[0]
+    _check(src, base, 6, 9)
+    for tb in (11, 10):
+        prog = ctx.load(src)
+        prog.replan(tb, 4, 0.5)
+        res = ctx.run_batch([{"prog": prog, "shots": 6, "seed": 9}])[0]
+        _check(src, res, 6, 9)
