@@ -1068,6 +1068,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     HIP_TRY(scr.get(items * rec_max, &d_rec));
     std::vector<ReqDev> rd(pers.size());
     std::vector<uint32_t> item_req(items);
+    std::vector<ComposeUnit> units;  // the dense phases of every request, composed in one launch
     size_t mo = 0, to = 0, fo = 0;
     uint32_t ib = 0;
     for (size_t i = 0; i < pers.size(); ++i) {
@@ -1081,6 +1082,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       uint32_t stride = 0;
       HIP_TRY(bind_theta(p, d_theta + to, 1, ext, st, &rows, &stride));
       HIP_TRY(launch_bind_matrices(p->d_src, slots, rows, stride, 1, d_mats + mo, nullptr, st));
+      for (uint32_t ph : p->plan.dense_phases) units.push_back({p->d_phases, p->d_gates, d_mats + mo, ph, 0u});
       ReqDev& R = rd[i];
       std::memset(&R, 0, sizeof(R));
       R.steps = p->d_steps;
@@ -1109,6 +1111,13 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       ib += (uint32_t)q.n_shots;
       mo += std::max<size_t>(1, slots) * kMatStride;
       to += std::max<uint32_t>(1, P);
+    }
+    // the composed 16x16 matrices of every request's dense phases, in one launch
+    if (!units.empty()) {
+      ComposeUnit* d_units = nullptr;
+      HIP_TRY(scr.get(units.size(), &d_units));
+      HIP_TRY(hipMemcpyAsync(d_units, units.data(), units.size() * sizeof(ComposeUnit), hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_compose_units(d_units, (uint32_t)units.size(), st));
     }
     // Shot branching for streamed states: the deterministic prefix (every step
     // before the first measurement) of a request with several shots runs once,

@@ -48,6 +48,16 @@ hipError_t launch_derive_params(const double* theta, uint32_t P, uint32_t D, con
 hipError_t launch_noise_matrices(const uint32_t* slot, const uint32_t* ctr, uint32_t n, const qsv_noise* noise,
                                  const uint64_t* key, double p, uint32_t shots, uint64_t mat_stride, double* mats,
                                  hipStream_t st);
+// One dense phase of one program to compose: phase `phase` of `phases`, its
+// gates in `gates`, its matrix slots (gate matrices bound) at `mats`.
+struct ComposeUnit {
+  const Phase* phases;
+  const DGate* gates;
+  double* mats;
+  uint32_t phase;
+  uint32_t pad;
+};
+hipError_t launch_compose_units(const ComposeUnit* units, uint32_t n_units, hipStream_t st);
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);

@@ -540,16 +540,8 @@ hipError_t launch_tile_pass(const RunBuffers& rb, const DGate* gates, const Phas
 // phase's gate list applied, in order, to the basis vector e_c (one thread per
 // batch element, phase and column), stored in matrix-core operand order.
 
-__global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t* __restrict__ dense,
-                                uint32_t n_dense, const DGate* __restrict__ gates, uint32_t batch,
-                                uint64_t mat_stride, double* __restrict__ mats) {
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)n_dense * kR * batch) return;
-  const uint32_t c = (uint32_t)(idx % kR);
-  const uint64_t rest = idx / kR;
-  const uint32_t d = (uint32_t)(rest % n_dense), b = (uint32_t)(rest / n_dense);
-  const Phase ph = phases[dense[d]];
-  double* mb = mats + (uint64_t)b * mat_stride;
+__device__ __forceinline__ void compose_column(const Phase& ph, const DGate* __restrict__ gates, double* mb,
+                                               uint32_t c) {
   double2 a[kR];
 #pragma unroll
   for (int k = 0; k < kR; ++k) a[k] = make_double2(k == (int)c ? 1.0 : 0.0, 0.0);
@@ -560,6 +552,33 @@ __global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t
   double2* A = reinterpret_cast<double2*>(mb + (uint64_t)ph.dense * kMatStride);
 #pragma unroll
   for (uint32_t r = 0; r < (uint32_t)kR; ++r) A[dense_pos(r, c)] = a[r];
+}
+
+__global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t* __restrict__ dense,
+                                uint32_t n_dense, const DGate* __restrict__ gates, uint32_t batch,
+                                uint64_t mat_stride, double* __restrict__ mats) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n_dense * kR * batch) return;
+  const uint32_t c = (uint32_t)(idx % kR);
+  const uint64_t rest = idx / kR;
+  const uint32_t d = (uint32_t)(rest % n_dense), b = (uint32_t)(rest / n_dense);
+  compose_column(phases[dense[d]], gates, mats + (uint64_t)b * mat_stride, c);
+}
+
+// The same over the dense phases of many programs at once (a batch of
+// requests, each with its own matrices): one thread per unit and column.
+__global__ void k_compose_units(const ComposeUnit* __restrict__ units, uint32_t n_units) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n_units * kR) return;
+  const ComposeUnit u = units[idx / kR];
+  compose_column(u.phases[u.phase], u.gates, u.mats, (uint32_t)(idx % kR));
+}
+
+hipError_t launch_compose_units(const ComposeUnit* units, uint32_t n_units, hipStream_t st) {
+  const uint64_t total = (uint64_t)n_units * kR;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_compose_units, dim3((uint32_t)((total + 127) / 128)), dim3(128), 0, st, units, n_units);
+  return hipGetLastError();
 }
 
 hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint32_t n_dense, const DGate* gates,
@@ -1597,7 +1616,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             __syncthreads();
           }
           if (a.phase_count) {
-            run_phases<false, true>(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
+            run_phases<true, true>(tile, (uint32_t)dim, tid, (uint32_t)dim >> kRegBits, flags, R.phases, a.phase_begin,
                        a.phase_count, R.gates, R.mats);
           } else {
             // fewer than 4 qubits: one LDS sweep per gate (slots are unswizzled for T < 16)
@@ -1629,7 +1648,7 @@ __global__ __launch_bounds__(kTileThreads) void k_persistent(
             __syncthreads();
             if (w + 1 < a.tiles && tid < nthr)
               fetch16(nx, slot, tile_base(w + 1, free_mask) | tb, h0, h1, h2, h3, a.init != 0, F);
-            run_phases<false, true>(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
+            run_phases<true, true>(tile, T, tid, nthr, flags, R.phases, a.phase_begin, a.phase_count, R.gates, R.mats);
             if (tid < nthr) store_tile16(tile, slot, a, tile_base(w, free_mask), tid, F);
             __syncthreads();
           }
