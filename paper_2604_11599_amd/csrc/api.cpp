@@ -1069,6 +1069,8 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     std::vector<ReqDev> rd(pers.size());
     std::vector<uint32_t> item_req(items);
     std::vector<ComposeUnit> units;  // the dense phases of every request, composed in one launch
+    std::vector<BindUnit> binds;     // the matrix slots of every request, bound in one launch
+    uint64_t bind_total = 0;
     size_t mo = 0, to = 0, fo = 0;
     uint32_t ib = 0;
     for (size_t i = 0; i < pers.size(); ++i) {
@@ -1081,7 +1083,9 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       const double* rows = nullptr;
       uint32_t stride = 0;
       HIP_TRY(bind_theta(p, d_theta + to, 1, ext, st, &rows, &stride));
-      HIP_TRY(launch_bind_matrices(p->d_src, slots, rows, stride, 1, d_mats + mo, nullptr, st));
+      (void)stride;  // one theta row per request
+      binds.push_back({p->d_src, rows, d_mats + mo, bind_total});
+      bind_total += slots;
       for (uint32_t ph : p->plan.dense_phases) units.push_back({p->d_phases, p->d_gates, d_mats + mo, ph, 0u});
       ReqDev& R = rd[i];
       std::memset(&R, 0, sizeof(R));
@@ -1112,7 +1116,14 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       mo += std::max<size_t>(1, slots) * kMatStride;
       to += std::max<uint32_t>(1, P);
     }
-    // the composed 16x16 matrices of every request's dense phases, in one launch
+    // every request's gate matrices, then the composed 16x16 matrices of
+    // their dense phases, one launch each
+    if (!binds.empty()) {
+      BindUnit* d_binds = nullptr;
+      HIP_TRY(scr.get(binds.size(), &d_binds));
+      HIP_TRY(hipMemcpyAsync(d_binds, binds.data(), binds.size() * sizeof(BindUnit), hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_bind_units(d_binds, (uint32_t)binds.size(), bind_total, st));
+    }
     if (!units.empty()) {
       ComposeUnit* d_units = nullptr;
       HIP_TRY(scr.get(units.size(), &d_units));

@@ -58,6 +58,16 @@ struct ComposeUnit {
   uint32_t pad;
 };
 hipError_t launch_compose_units(const ComposeUnit* units, uint32_t n_units, hipStream_t st);
+// The matrix slots of one program to bind: slots [slot_begin, next unit's
+// slot_begin) of the flat range are slots 0.. of `src`, bound from the theta
+// row `theta` into `mats`.
+struct BindUnit {
+  const GateSrc* src;
+  const double* theta;
+  double* mats;
+  uint64_t slot_begin;
+};
+hipError_t launch_bind_units(const BindUnit* units, uint32_t n_units, uint64_t n_total, hipStream_t st);
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);

@@ -100,20 +100,14 @@ hipError_t launch_derive_params(const double* theta, uint32_t P, uint32_t D, con
   return hipGetLastError();
 }
 
-__global__ void k_bind_matrices(const GateSrc* __restrict__ src, uint32_t n_slots,
-                                const double* __restrict__ theta, uint32_t n_params, uint32_t batch,
-                                double* __restrict__ mats, double* __restrict__ dmats) {
-  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)n_slots * batch) return;
-  uint32_t b = (uint32_t)(idx / n_slots), slot = (uint32_t)(idx % n_slots);
-  const GateSrc& g = src[slot];
+// One matrix slot from its source and a theta row: the 2x2 matrix at m and,
+// when dm is set, its derivatives by each angle.
+__device__ __forceinline__ void bind_slot(const GateSrc& g, const double* __restrict__ th, double* m, double* dm) {
   double a[3];
   for (int k = 0; k < 3; ++k) {
     a[k] = g.offset[k];
-    if (g.param[k] != QSV_NONE) a[k] += g.scale[k] * theta[(uint64_t)b * n_params + g.param[k]];
+    if (g.param[k] != QSV_NONE) a[k] += g.scale[k] * th[g.param[k]];
   }
-  double* m = mats + idx * kMatStride;
-  double* dm = dmats ? dmats + idx * 3 * kMatStride : nullptr;
   const double2 Z0 = make_double2(0, 0), O1 = make_double2(1, 0), I1 = make_double2(0, 1);
   const double r2 = 0.70710678118654752440;
   if (dm)
@@ -178,6 +172,41 @@ __global__ void k_bind_matrices(const GateSrc* __restrict__ src, uint32_t n_slot
     }
     default: set2(m, O1, Z0, Z0, O1); break;  // ID, SWAP (unused)
   }
+}
+
+
+__global__ void k_bind_matrices(const GateSrc* __restrict__ src, uint32_t n_slots,
+                                const double* __restrict__ theta, uint32_t n_params, uint32_t batch,
+                                double* __restrict__ mats, double* __restrict__ dmats) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)n_slots * batch) return;
+  uint32_t b = (uint32_t)(idx / n_slots), slot = (uint32_t)(idx % n_slots);
+  bind_slot(src[slot], theta + (uint64_t)b * n_params, mats + idx * kMatStride,
+            dmats ? dmats + idx * 3 * kMatStride : nullptr);
+}
+
+// The matrix slots of many programs at once (a batch of requests, each with its
+// own theta row and matrices): one thread per slot; unit k covers slots
+// [units[k].slot_begin, units[k + 1].slot_begin) of the flat range.
+__global__ void k_bind_units(const BindUnit* __restrict__ units, uint32_t n_units, uint64_t n_total) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_total) return;
+  uint32_t lo = 0, hi = n_units;  // the last unit whose slot_begin <= idx
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (units[mid].slot_begin <= idx) lo = mid;
+    else hi = mid;
+  }
+  const BindUnit u = units[lo];
+  const uint64_t slot = idx - u.slot_begin;
+  bind_slot(u.src[slot], u.theta, u.mats + slot * kMatStride, nullptr);
+}
+
+hipError_t launch_bind_units(const BindUnit* units, uint32_t n_units, uint64_t n_total, hipStream_t st) {
+  if (!n_total || !n_units) return hipSuccess;
+  hipLaunchKernelGGL(k_bind_units, dim3((uint32_t)((n_total + 255) / 256)), dim3(256), 0, st, units, n_units,
+                     n_total);
+  return hipGetLastError();
 }
 
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
