@@ -11,6 +11,7 @@
 #include "planner.h"
 
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <set>
 
@@ -130,13 +131,64 @@ void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
       const uint64_t w = ((1ull << kRegBits) - 1ull) << a;
       if (std::find(seeds.begin(), seeds.end(), w) == seeds.end()) seeds.push_back(w);
     }
+    // the lookahead below estimates the rest with these seeds; the choice
+    // itself also tries every set of kRegBits local bits
+    const std::vector<uint64_t> base_seeds = seeds;
+    if (pa->t >= (uint32_t)kRegBits && pa->t <= 12u)
+      for (uint64_t w = (1ull << kRegBits) - 1ull; w < (1ull << pa->t);) {
+        if (std::find(seeds.begin(), seeds.end(), w) == seeds.end()) seeds.push_back(w);
+        const uint64_t u = w & (0ull - w), v = w + u;
+        w = v + (((v ^ w) / u) >> 2);
+      }
+    // phases the plain greedy choice needs for a gate list
+    std::function<uint32_t(const std::vector<GateRef>&)> greedy_phases = [&](const std::vector<GateRef>& r0) {
+      std::vector<GateRef> r = r0, nx;
+      std::vector<uint8_t> tk;
+      uint32_t np = 0;
+      while (!r.empty()) {
+        uint32_t bc = 0;
+        std::vector<uint8_t> bt;
+        for (uint64_t s : base_seeds) {
+          uint32_t c = 0;
+          grow(r, s, kRegBits, &tk, &c);
+          if (c > bc) {
+            bc = c;
+            bt = tk;
+          }
+        }
+        nx.clear();
+        for (size_t i = 0; i < r.size(); ++i)
+          if (!bt[i]) nx.push_back(r[i]);
+        r.swap(nx);
+        ++np;
+      }
+      return np;
+    };
+    struct Cand {
+      uint32_t c;
+      uint64_t R;
+      std::vector<uint8_t> taken;
+    };
+    std::vector<Cand> cands;
     for (uint64_t s : seeds) {
       uint32_t c = 0;
       uint64_t R = grow(rem, s, kRegBits, &taken, &c);
-      if (c > best) {
-        best = c;
-        bestR = R;
-        best_taken = taken;
+      if (c) cands.push_back({c, R, taken});
+    }
+    std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.c > y.c; });
+    // one step of lookahead over the best candidates: the fewest phases in
+    // total (this one plus the greedy plan of the rest), then the most gates
+    uint32_t best_total = UINT32_MAX;
+    for (size_t k = 0; k < cands.size() && k < 16; ++k) {
+      std::vector<GateRef> rest;
+      for (size_t i = 0; i < rem.size(); ++i)
+        if (!cands[k].taken[i]) rest.push_back(rem[i]);
+      const uint32_t total = 1 + greedy_phases(rest);
+      if (total < best_total || (total == best_total && cands[k].c > best)) {
+        best_total = total;
+        best = cands[k].c;
+        bestR = cands[k].R;
+        best_taken = cands[k].taken;
       }
     }
     // pad with the highest unused local bits (keeps the low bits on lanes)
