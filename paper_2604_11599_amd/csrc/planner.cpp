@@ -108,6 +108,8 @@ uint64_t grow(const std::vector<GateRef>& rem, uint64_t start, uint32_t tmax,
 // Reorders the gates of pass *pa into phases whose gates touch at most
 // kRegBits tile-local bits, greedily (same growth rule as the tile chooser,
 // on local bit masks), and records the phases.
+constexpr int kLook = 2;  // further choices the phase planner looks ahead
+
 void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
   std::vector<GateRef> rem;
   std::vector<DGate> src(plan->gates.begin() + pa->gate_begin,
@@ -176,14 +178,36 @@ void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
       if (c) cands.push_back({c, R, taken});
     }
     std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.c > y.c; });
-    // one step of lookahead over the best candidates: the fewest phases in
-    // total (this one plus the greedy plan of the rest), then the most gates
+    // the fewest phases for a gate list when the next kLook choices each try
+    // their best few candidates and the rest is planned greedily
+    std::function<uint32_t(const std::vector<GateRef>&, int)> look = [&](const std::vector<GateRef>& r, int depth) {
+      if (r.empty()) return 0u;
+      if (depth == 0) return greedy_phases(r);
+      std::vector<Cand> cs;
+      std::vector<uint8_t> tk;
+      for (uint64_t s : base_seeds) {
+        uint32_t c = 0;
+        const uint64_t R = grow(r, s, kRegBits, &tk, &c);
+        if (c) cs.push_back({c, R, tk});
+      }
+      std::stable_sort(cs.begin(), cs.end(), [](const Cand& x, const Cand& y) { return x.c > y.c; });
+      uint32_t bt = UINT32_MAX;
+      for (size_t k = 0; k < cs.size() && k < 4; ++k) {
+        std::vector<GateRef> rest;
+        for (size_t i = 0; i < r.size(); ++i)
+          if (!cs[k].taken[i]) rest.push_back(r[i]);
+        bt = std::min(bt, 1 + look(rest, depth - 1));
+      }
+      return bt;
+    };
+    // lookahead over the best candidates: the fewest phases in total (this
+    // one plus the best plan of the rest), then the most gates
     uint32_t best_total = UINT32_MAX;
     for (size_t k = 0; k < cands.size() && k < 16; ++k) {
       std::vector<GateRef> rest;
       for (size_t i = 0; i < rem.size(); ++i)
         if (!cands[k].taken[i]) rest.push_back(rem[i]);
-      const uint32_t total = 1 + greedy_phases(rest);
+      const uint32_t total = 1 + look(rest, kLook);
       if (total < best_total || (total == best_total && cands[k].c > best)) {
         best_total = total;
         best = cands[k].c;
