@@ -412,11 +412,66 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
           if (std::find(seeds.begin(), seeds.end(), s) == seeds.end()) seeds.push_back(s);
         }
       }
+      // greedy register-phase count of the gates a candidate tile takes
+      auto est_phases = [&](uint64_t T, const std::vector<uint8_t>& tk) {
+        std::vector<GateRef> g, nx;
+        for (size_t i = 0; i < rem.size(); ++i)
+          if (tk[i]) g.push_back(rem[i]);
+        std::vector<uint64_t> subs;
+        std::vector<uint32_t> bits;
+        for (uint32_t q = 0; q < n; ++q)
+          if ((T >> q) & 1ull) bits.push_back(q);
+        const uint32_t nb = (uint32_t)bits.size();
+        if (nb < (uint32_t)kRegBits) return 1u;
+        for (uint32_t m = (1u << kRegBits) - 1u; m < (1u << nb);) {
+          uint64_t sm = 0;
+          for (uint32_t j = 0; j < nb; ++j)
+            if ((m >> j) & 1u) sm |= 1ull << bits[j];
+          subs.push_back(sm);
+          const uint32_t u = m & (0u - m), v = m + u;
+          m = v + (((v ^ m) / u) >> 2);
+        }
+        std::vector<uint8_t> t2, bt;
+        uint32_t np = 0;
+        while (!g.empty()) {
+          uint32_t bc = 0;
+          for (uint64_t sm : subs) {
+            uint32_t c2 = 0;
+            grow(g, sm, kRegBits, &t2, &c2);
+            if (c2 > bc) {
+              bc = c2;
+              bt = t2;
+            }
+          }
+          if (!bc) break;
+          nx.clear();
+          for (size_t i = 0; i < g.size(); ++i)
+            if (!bt[i]) nx.push_back(g[i]);
+          g.swap(nx);
+          ++np;
+        }
+        return np;
+      };
+      // among the tiles that take at least 90 % of the most gates any seed
+      // takes, the lowest estimated cost per gate: the tile's phases plus the
+      // pass's own HBM read and write, which costs about 0.6 of a phase
+      uint32_t cmax = 0;
+      std::vector<std::pair<uint64_t, uint32_t>> grown;
       for (uint64_t s : seeds) {
         if ((uint32_t)__builtin_popcountll(s) > tmax) continue;
         uint32_t c = 0;
-        uint64_t T = grow(rem, s, tmax, &taken, &c);
-        if (c > best) {
+        grow(rem, s, tmax, &taken, &c);
+        grown.push_back({s, c});
+        cmax = std::max(cmax, c);
+      }
+      double best_score = 1e300;
+      for (const auto& sc : grown) {
+        if (!sc.second || sc.second * 10u < cmax * 9u) continue;
+        uint32_t c = 0;
+        const uint64_t T = grow(rem, sc.first, tmax, &taken, &c);
+        const double score = opt.register_phases ? (0.6 + est_phases(T, taken)) / c : 1.0 / c;
+        if (score < best_score) {
+          best_score = score;
           best = c;
           bestT = T;
           best_taken = taken;
