@@ -13,7 +13,10 @@
 #include <algorithm>
 #include <functional>
 #include <cstring>
+#include <map>
 #include <set>
+#include <string>
+#include <unordered_map>
 
 namespace qsv {
 
@@ -180,9 +183,18 @@ void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
     std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.c > y.c; });
     // the fewest phases for a gate list when the next kLook choices each try
     // their best few candidates and the rest is planned greedily
+    // results by (depth, remaining gates): different orders of the same
+    // choices leave the same rest, which is planned once per decision
+    std::unordered_map<std::string, uint32_t> memo;
+    const size_t words = (src.size() + 63) / 64;
     std::function<uint32_t(const std::vector<GateRef>&, int)> look = [&](const std::vector<GateRef>& r, int depth) {
       if (r.empty()) return 0u;
-      if (depth == 0) return greedy_phases(r);
+      std::string key(1 + 8 * words, '\0');
+      key[0] = (char)depth;
+      for (const GateRef& g : r) key[1 + g.instr / 8] |= (char)(1u << (g.instr % 8));
+      const auto hit = memo.find(key);
+      if (hit != memo.end()) return hit->second;
+      if (depth == 0) return memo[key] = greedy_phases(r);
       std::vector<Cand> cs;
       std::vector<uint8_t> tk;
       for (uint64_t s : base_seeds) {
@@ -198,7 +210,7 @@ void split_phases(Plan* plan, PassArgs* pa, uint32_t candidates) {
           if (!cs[k].taken[i]) rest.push_back(r[i]);
         bt = std::min(bt, 1 + look(rest, depth - 1));
       }
-      return bt;
+      return memo[key] = bt;
     };
     // lookahead over the best candidates: the fewest phases in total (this
     // one plus the best plan of the rest), then the most gates
@@ -412,8 +424,10 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
           if (std::find(seeds.begin(), seeds.end(), s) == seeds.end()) seeds.push_back(s);
         }
       }
-      // greedy register-phase count of the gates a candidate tile takes
-      auto est_phases = [&](uint64_t T, const std::vector<uint8_t>& tk) {
+      // greedy register-phase count of the gates a candidate tile takes, by
+      // (tile, gates taken): several seeds often grow into the same tile
+      std::map<std::pair<uint64_t, std::vector<uint8_t>>, uint32_t> est_memo;
+      auto est_phases_raw = [&](uint64_t T, const std::vector<uint8_t>& tk) {
         std::vector<GateRef> g, nx;
         for (size_t i = 0; i < rem.size(); ++i)
           if (tk[i]) g.push_back(rem[i]);
@@ -451,6 +465,12 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
           ++np;
         }
         return np;
+      };
+      auto est_phases = [&](uint64_t T, const std::vector<uint8_t>& tk) {
+        const auto key = std::make_pair(T, tk);
+        const auto hit = est_memo.find(key);
+        if (hit != est_memo.end()) return hit->second;
+        return est_memo[key] = est_phases_raw(T, tk);
       };
       // among the tiles that take at least 90 % of the most gates any seed
       // takes, the lowest estimated cost per gate: the tile's phases plus the
