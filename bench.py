@@ -428,8 +428,9 @@ def bench_batching(args):
     """c3: 4096 shots of the 16-qubit RUS circuit plus 256 distinct 12..18-qubit
     circuits of the same structure (16 shots each) in one qsv_run_batch call per
     step. The 256-circuit mix runs as work items of one persistent launch; the
-    4096-shot request (13..20 qubits, at least 64 shots) runs after it on the
-    tile passes with shared trajectories, as qsv_run_batch routes it."""
+    4096-shot request (13..20 qubits, at least 64 shots) runs on the tile
+    passes with shared trajectories, on the context's batch fork from a second
+    host thread while the persistent launches run, as qsv_run_batch routes it."""
     import workloads as W
     from paper_2604_11599_amd import Context
     ctx = Context(0, profile=True)

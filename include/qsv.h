@@ -370,7 +370,12 @@ qsv_status qsv_run_shots_noalloc(qsv_context* ctx, const qsv_program* prog, cons
    branches) share the GPU. States of up to 12 qubits stay in LDS for the whole
    program; states of 13..20 qubits live in a per-workgroup HBM slot; requests
    with more qubits, and requests of 13..20 qubits with at least 64 shots, run
-   through qsv_run_shots with shared trajectories after the launch. The path
+   through qsv_run_shots with shared trajectories. When a batch has both kinds,
+   those calls run on a context forked from ctx (created on the first such
+   batch, with scratch of its own, and destroyed with ctx), driven from a second
+   host thread while the persistent launches run, so the two overlap on the
+   GPU; ctx itself must not be a fork, use an arena, or be capturing, else they
+   run after the launch on ctx. The call returns when both are done. The path
    is chosen from the request alone. Every item is
    computed the same way whatever else is in the batch, so a request's results
    do not depend on the batch it is part of. The paper runs whole suites of

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -61,6 +62,11 @@ struct qsv_context {
   bool capturing = false;  // launches are being recorded into a HIP graph
   std::string arch;        // the device's architecture name (autotuning cache key)
   qsv_context* parent = nullptr;  // a forked context runs its parent's programs
+  // qsv_run_batch's second lane: a fork that runs the tile-pass requests from
+  // a host thread of their own while this context runs the persistent
+  // launches (created on first use, destroyed with this context)
+  qsv_context* batch_fork = nullptr;
+  hipEvent_t batch_ev = nullptr;  // orders the fork's work after this context's queued work
   bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0 && !noalloc && !capturing; }
   // the arena scratch is carved from in the current call, if any
   uint8_t* call_arena() const { return noalloc ? static_cast<uint8_t*>(noalloc_scratch(device)) : arena; }
@@ -203,6 +209,29 @@ hipError_t upload(const std::vector<T>& v, T** out) {
 enum Kind { K_PASS = 0, K_SITE = 1, K_OTHER = 2, K_HAM = 3, K_SWEEP = 4, K_PERSISTENT = 5 };
 
 // Brackets one launch with profiling events when the context profiles.
+// a += b, field by field (the batch fork's launches counted in its parent)
+void add_profile(qsv_profile* a, const qsv_profile& b) {
+  a->pass_launches += b.pass_launches;
+  a->pass_ms += b.pass_ms;
+  a->pass_uncond_launches += b.pass_uncond_launches;
+  a->pass_uncond_ms += b.pass_uncond_ms;
+  a->pass_uncond_bytes += b.pass_uncond_bytes;
+  a->pass_uncond_flops += b.pass_uncond_flops;
+  a->site_launches += b.site_launches;
+  a->site_ms += b.site_ms;
+  a->other_launches += b.other_launches;
+  a->other_ms += b.other_ms;
+  a->ham_launches += b.ham_launches;
+  a->ham_ms += b.ham_ms;
+  a->ham_bytes += b.ham_bytes;
+  a->sweep_launches += b.sweep_launches;
+  a->sweep_ms += b.sweep_ms;
+  a->sweep_bytes += b.sweep_bytes;
+  a->persistent_launches += b.persistent_launches;
+  a->persistent_ms += b.persistent_ms;
+  a->persistent_bytes += b.persistent_bytes;
+}
+
 struct Prof {
   qsv_context* ctx;
   hipStream_t st;
@@ -560,7 +589,9 @@ qsv_status qsv_context_fork(qsv_context* parent, qsv_context** out) {
 
 void qsv_destroy(qsv_context* ctx) {
   if (!ctx) return;
+  if (ctx->batch_fork) qsv_destroy(ctx->batch_fork);
   ignore(enter_device(ctx->device));
+  if (ctx->batch_ev) ignore(hipEventDestroy(ctx->batch_ev));
   ignore(hipStreamSynchronize(ctx->stream));
   for (hipEvent_t e : ctx->ev_pool) ignore(hipEventDestroy(e));
   for (auto& b : ctx->cache)
@@ -1027,6 +1058,48 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
   }
   if (items > 0xFFFFFFFFull) return set_err(ctx, QSV_ERR_LIMIT, "too many work items in one batch");
   hipStream_t st = ctx->stream;
+  // The tile-pass requests, with shared trajectories (bit-identical to running
+  // every shot from |0...0>), each as one qsv_run_shots call.
+  auto run_big = [&](qsv_context* c) -> qsv_status {
+    for (uint32_t r : big) {
+      qsv_run_opts o = reqs[r].opts;
+      o.state_out = nullptr;
+      o.flags = QSV_RUN_SHARE_TRAJ;
+      qsv_shot_results out = reqs[r].out;
+      const qsv_status rc = qsv_run_shots(c, reqs[r].prog, reqs[r].theta, reqs[r].n_shots, &o, &out);
+      if (rc != QSV_OK) return rc;
+    }
+    return QSV_OK;
+  };
+  // With persistent work too, they run on the batch fork from a second host
+  // thread, so their launches overlap the persistent launches (the first of
+  // which, the shared prefixes, occupies few CUs). Not for a fork (forks are
+  // not forked), a caller's arena (the fork would allocate), or capture.
+  qsv_status big_rc = QSV_OK;
+  std::thread big_th;
+  struct Join {
+    std::thread& t;
+    ~Join() {
+      if (t.joinable()) t.join();
+    }
+  } join{big_th};
+  if (!big.empty() && !pers.empty() && !ctx->parent && !ctx->arena && !ctx->noalloc && !ctx->capturing) {
+    if (!ctx->batch_fork) {
+      if (qsv_context_fork(ctx, &ctx->batch_fork) != QSV_OK) ctx->batch_fork = nullptr;
+      if (ctx->batch_fork && hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming) != hipSuccess) {
+        clear_error();
+        ctx->batch_ev = nullptr;
+        qsv_destroy(ctx->batch_fork);
+        ctx->batch_fork = nullptr;
+      }
+    }
+    if (ctx->batch_fork) {
+      HIP_TRY(hipEventRecord(ctx->batch_ev, st));
+      HIP_TRY(hipStreamWaitEvent(ctx->batch_fork->stream, ctx->batch_ev, 0));
+      qsv_context* f = ctx->batch_fork;
+      big_th = std::thread([&big_rc, &run_big, f] { big_rc = run_big(f); });
+    }
+  }
   if (!pers.empty()) {
     // widest circuits first: long items start early and short ones fill in
     std::stable_sort(pers.begin(), pers.end(), [&](uint32_t a, uint32_t b) {
@@ -1225,15 +1298,17 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       }
     }
   }
-  for (uint32_t r : big) {
-    qsv_run_opts o = reqs[r].opts;
-    o.state_out = nullptr;
-    o.flags = QSV_RUN_SHARE_TRAJ;  // bit-identical to running every shot from |0...0>
-    qsv_shot_results out = reqs[r].out;
-    qsv_status rc = qsv_run_shots(ctx, reqs[r].prog, reqs[r].theta, reqs[r].n_shots, &o, &out);
-    if (rc != QSV_OK) return rc;
+  if (big_th.joinable()) {
+    big_th.join();
+    qsv_context* f = ctx->batch_fork;
+    if (ctx->profiling()) {
+      add_profile(&ctx->prof, f->prof);
+      std::memset(&f->prof, 0, sizeof(f->prof));
+    }
+    if (big_rc != QSV_OK) return set_err(ctx, big_rc, f->err);
+    return QSV_OK;
   }
-  return QSV_OK;
+  return run_big(ctx);
 }
 
 }  // extern "C"
