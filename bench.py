@@ -384,8 +384,8 @@ def bench_shots(args):
                                "ms_per_step": 1e3 * dt_n / args.steps, "rate": 1e-3,
                                "passes_per_shot": noisy.info.n_passes,
                                "note": "same program loaded with depolarizing slots: after every gate each of "
-                                       "its qubits takes X, Y or Z with probability 1e-3/3; each shot binds and "
-                                       "composes its own matrices"}
+                                       "its qubits takes X, Y or Z with probability 1e-3/3; each shot binds its own "
+                                       "matrices and composes the dense phases in which it draws a Pauli"}
         log("depolarizing steps done")
     if args.workload == "c2":
         # the same steps with trajectory sharing (shots with equal measurement histories share one state)

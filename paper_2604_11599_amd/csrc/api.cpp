@@ -101,6 +101,7 @@ struct qsv_program {
   qsv_noise* d_noise = nullptr;
   uint32_t* d_noise_slot = nullptr;
   uint32_t* d_noise_ctr = nullptr;
+  uint32_t* d_noise_dense = nullptr;  // per noise slot: the dense phase holding it, or kNoDense
   uint32_t* d_csr_off = nullptr;
   uint32_t* d_csr_sj = nullptr;
   double* d_csr_scale = nullptr;
@@ -375,7 +376,7 @@ void free_plan_buffers(qsv_program* p) {
   void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense,
                   p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off,
                   p->d_code, p->d_lin_off, p->d_lin_in, p->d_lin_coef, p->d_noise, p->d_noise_slot,
-                  p->d_noise_ctr};
+                  p->d_noise_ctr, p->d_noise_dense};
   for (void* q : ptrs)
     if (q) ignore(hipFree(q));
   p->d_gates = nullptr;
@@ -399,6 +400,7 @@ void free_plan_buffers(qsv_program* p) {
   p->d_noise = nullptr;
   p->d_noise_slot = nullptr;
   p->d_noise_ctr = nullptr;
+  p->d_noise_dense = nullptr;
 }
 
 // Plans the program's stream with options o and uploads the plan (replacing a
@@ -494,6 +496,18 @@ qsv_status install_plan(qsv_context* ctx, qsv_program* p, const PlanOptions& o) 
   if (e == hipSuccess) e = upload(p->noise, &p->d_noise);
   if (e == hipSuccess) e = upload(pl.noise_slot, &p->d_noise_slot);
   if (e == hipSuccess) e = upload(pl.noise_ctr, &p->d_noise_ctr);
+  if (e == hipSuccess && !pl.noise_slot.empty()) {
+    // the dense phase (index into dense_phases) whose composed matrix holds each noise slot
+    std::vector<uint32_t> slot_dense(pl.gate_src.size(), kNoDense), nd(pl.noise_slot.size(), kNoDense);
+    for (size_t d = 0; d < pl.dense_phases.size(); ++d) {
+      const Phase& ph = pl.phases[pl.dense_phases[d]];
+      for (uint32_t g = ph.gate_begin; g < ph.gate_begin + ph.gate_count; ++g)
+        if (pl.gates[g].mat < slot_dense.size()) slot_dense[pl.gates[g].mat] = (uint32_t)d;
+    }
+    for (size_t k = 0; k < pl.noise_slot.size(); ++k)
+      if (pl.noise_slot[k] < slot_dense.size()) nd[k] = slot_dense[pl.noise_slot[k]];
+    e = upload(nd, &p->d_noise_dense);
+  }
   if (desc->n_derived) {
     std::vector<uint32_t> loff(desc->n_derived + 1, 0), lin_in;
     std::vector<double> lin_coef;
@@ -683,7 +697,7 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   // shots per batch: what fits in the arena / free memory after the per-shot scratch
   size_t per_shot = state_bytes + sizeof(ShotCtl) + cw * 8 + maxrec + opts->forced_len +
                     (size_t)prog->pblocks * kSiteBins * 8 + 4 * 256 +
-                    (noisy ? pl.gate_src.size() * kMatStride * 8 : 0);
+                    (noisy ? pl.gate_src.size() * kMatStride * 8 + pl.dense_phases.size() : 0);
   const bool in_arena = ctx->call_arena() != nullptr;
   size_t budget = in_arena ? ctx->call_arena_bytes() : (free_device_bytes() / 10) * 8;
   size_t fixed = pl.gate_src.size() * kMatStride * 8 + prog->desc.n_params * 8 + (1u << 20) +
@@ -707,7 +721,12 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   HIP_TRY(scr.get(std::max<uint32_t>(1, prog->desc.n_params), &d_theta));
   // matrices: one set for the call, or one per shot of a batch when noisy
   const uint64_t ms = noisy ? (uint64_t)std::max<uint32_t>(1, n_slots) * kMatStride : 0;
-  HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride * (noisy ? batch : 1), &d_mats));
+  // (noisy: one more set after the shots' sets, bound without Paulis: the
+  // composed matrices of every phase in which a shot draws none)
+  HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride * (noisy ? batch + 1 : 1), &d_mats));
+  const uint32_t n_dense = (uint32_t)pl.dense_phases.size();
+  uint8_t* d_dirty = nullptr;
+  if (noisy && n_dense) HIP_TRY(scr.get((size_t)((batch * n_dense + 3) & ~3ull), &d_dirty));
   double* d_ext = nullptr;
   if (prog->desc.n_derived) HIP_TRY(scr.get(prog->desc.n_params + prog->desc.n_derived, &d_ext));
   if (prog->desc.n_params)
@@ -726,12 +745,21 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     uint32_t stride = 0;
     const uint32_t sets = noisy ? bs : 1u;
     HIP_TRY(bind_theta(prog, d_theta, 1, d_ext, st, &rows, &stride));
-    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, noisy ? 0u : stride, sets, d_mats, nullptr, st));
-    if (noisy)
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, noisy ? 0u : stride, noisy ? bs + 1u : 1u, d_mats,
+                                 nullptr, st));
+    if (noisy) {
+      // the shots' Paulis, marking the phases they fall in; the clean set (after
+      // the shots') composed once, and copied into every phase no Pauli touched
+      double* clean = d_mats + (uint64_t)bs * ms;
       HIP_TRY(launch_noise_matrices(prog->d_noise_slot, prog->d_noise_ctr, (uint32_t)pl.noise_slot.size(),
-                                    prog->d_noise, rb.key, opts->depolarizing, bs, ms, d_mats, st));
-    HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, (uint32_t)pl.dense_phases.size(), prog->d_gates,
-                                 sets, ms, d_mats, st));
+                                    prog->d_noise, rb.key, opts->depolarizing, bs, ms, d_mats, prog->d_noise_dense,
+                                    n_dense, d_dirty, st));
+      HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, n_dense, prog->d_gates, 1u, ms, clean, st));
+      HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, n_dense, prog->d_gates, bs, ms, d_mats, st,
+                                   d_dirty, clean));
+      return QSV_OK;
+    }
+    HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, n_dense, prog->d_gates, sets, ms, d_mats, st));
     return QSV_OK;
   };
   if (!use_graph && !noisy) {

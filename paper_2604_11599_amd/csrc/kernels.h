@@ -45,9 +45,11 @@ hipError_t launch_derive_params(const double* theta, uint32_t P, uint32_t D, con
                                 const double* coef, uint32_t batch, double* out, hipStream_t st);
 // Per-shot Paulis of the depolarizing slots (rate p; key = (seed, first shot)
 // in device memory, shot s uses key word 1 + s) into the shots' matrices.
+// nd, n_dense, dirty: see k_noise_matrices (dirty may be null; else it is
+// cleared here first, shots * n_dense bytes, rounded up to whole words).
 hipError_t launch_noise_matrices(const uint32_t* slot, const uint32_t* ctr, uint32_t n, const qsv_noise* noise,
                                  const uint64_t* key, double p, uint32_t shots, uint64_t mat_stride, double* mats,
-                                 hipStream_t st);
+                                 const uint32_t* nd, uint32_t n_dense, uint8_t* dirty, hipStream_t st);
 // One dense phase of one program to compose: phase `phase` of `phases`, its
 // gates in `gates`, its matrix slots (gate matrices bound) at `mats`.
 struct ComposeUnit {
@@ -71,8 +73,10 @@ hipError_t launch_bind_units(const BindUnit* units, uint32_t n_units, uint64_t n
 hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const double* theta,
                                 uint32_t n_params, uint32_t batch, double* mats, double* dmats,
                                 hipStream_t st);
+// dirty, clean: see k_compose_dense (both null: compose every phase of every batch element).
 hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint32_t n_dense, const DGate* gates,
-                                uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st);
+                                uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st,
+                                const uint8_t* dirty = nullptr, const double* clean = nullptr);
 hipError_t launch_init_ctl(ShotCtl* ctl, uint64_t* creg, uint32_t cw, uint8_t* record, uint32_t max_record,
                            uint32_t shots, hipStream_t st);
 hipError_t launch_init_state(double2* state, uint64_t stride, uint32_t n, uint32_t shots, hipStream_t st,

@@ -225,9 +225,13 @@ hipError_t launch_bind_matrices(const GateSrc* src, uint32_t n_slots, const doub
 // as u = (w >> 11) 2^-53, puts X (u < p/3), Y (u < 2p/3), Z (u < p) or the
 // identity into matrix slot slot[e] of shot s. The fourth counter word is 0 in
 // every measure/reset event's counter, so the two kinds of draws never meet.
+// With dirty: a slot that draws a Pauli marks dirty[s * n_dense + nd[e]]
+// (nd[e]: the dense phase holding slot e, or kNoDense), so that only those
+// phases of the shot are composed again.
 __global__ void k_noise_matrices(const uint32_t* __restrict__ slot, const uint32_t* __restrict__ ctr, uint32_t n,
                                  const qsv_noise* __restrict__ noise, const uint64_t* __restrict__ key, double p,
-                                 uint32_t shots, uint64_t mat_stride, double* __restrict__ mats) {
+                                 uint32_t shots, uint64_t mat_stride, double* __restrict__ mats,
+                                 const uint32_t* __restrict__ nd, uint32_t n_dense, uint8_t* __restrict__ dirty) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)n * shots) return;
   const uint32_t s = (uint32_t)(idx / n), e = (uint32_t)(idx % n);
@@ -237,19 +241,28 @@ __global__ void k_noise_matrices(const uint32_t* __restrict__ slot, const uint32
   const double u = (double)(c0 >> 11) * 0x1p-53;
   const double2 Z0 = make_double2(0, 0), O1 = make_double2(1, 0);
   double* m = mats + (uint64_t)s * mat_stride + (uint64_t)slot[e] * kMatStride;
+  if (u < p && dirty && nd[e] != kNoDense) dirty[(uint64_t)s * n_dense + nd[e]] = 1;
   if (u >= p) set2(m, O1, Z0, Z0, O1);
   else if (u < p / 3.0) set2(m, Z0, O1, O1, Z0);
   else if (u < 2.0 * p / 3.0) set2(m, Z0, make_double2(0, -1), make_double2(0, 1), Z0);
   else set2(m, O1, Z0, Z0, make_double2(-1, 0));
 }
 
+// one workgroup clears n words (a fill kernel: safe to capture in a graph)
+__global__ void k_zero_u32(uint32_t* p, uint32_t n);
+
 hipError_t launch_noise_matrices(const uint32_t* slot, const uint32_t* ctr, uint32_t n, const qsv_noise* noise,
                                  const uint64_t* key, double p, uint32_t shots, uint64_t mat_stride, double* mats,
-                                 hipStream_t st) {
+                                 const uint32_t* nd, uint32_t n_dense, uint8_t* dirty, hipStream_t st) {
+  if (dirty && n_dense && shots) {
+    const uint64_t words = ((uint64_t)shots * n_dense + 3) / 4;
+    if (words > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(dirty), (uint32_t)words);
+  }
   const uint64_t total = (uint64_t)n * shots;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_noise_matrices, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, slot, ctr, n, noise,
-                     key, p, shots, mat_stride, mats);
+                     key, p, shots, mat_stride, mats, nd, n_dense, dirty);
   return hipGetLastError();
 }
 
@@ -583,15 +596,30 @@ __device__ __forceinline__ void compose_column(const Phase& ph, const DGate* __r
   for (uint32_t r = 0; r < (uint32_t)kR; ++r) A[dense_pos(r, c)] = a[r];
 }
 
+// With dirty: a phase whose slots all hold what they hold in the matrix set
+// `clean` (dirty[b * n_dense + d] == 0) takes its column from clean's composed
+// matrix, the same gate list applied to the same matrices.
 __global__ void k_compose_dense(const Phase* __restrict__ phases, const uint32_t* __restrict__ dense,
                                 uint32_t n_dense, const DGate* __restrict__ gates, uint32_t batch,
-                                uint64_t mat_stride, double* __restrict__ mats) {
+                                uint64_t mat_stride, double* __restrict__ mats, const uint8_t* __restrict__ dirty,
+                                const double* __restrict__ clean) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)n_dense * kR * batch) return;
+  // column fastest, then batch element, then phase: the lanes of a wave
+  // compose one phase (one gate list, no divergence) for four batch elements
   const uint32_t c = (uint32_t)(idx % kR);
   const uint64_t rest = idx / kR;
-  const uint32_t d = (uint32_t)(rest % n_dense), b = (uint32_t)(rest / n_dense);
-  compose_column(phases[dense[d]], gates, mats + (uint64_t)b * mat_stride, c);
+  const uint32_t b = (uint32_t)(rest % batch), d = (uint32_t)(rest / batch);
+  const Phase ph = phases[dense[d]];
+  double* mb = mats + (uint64_t)b * mat_stride;
+  if (dirty && !dirty[(uint64_t)b * n_dense + d]) {
+    const double2* src = reinterpret_cast<const double2*>(clean + (uint64_t)ph.dense * kMatStride);
+    double2* dst = reinterpret_cast<double2*>(mb + (uint64_t)ph.dense * kMatStride);
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)kR; ++r) dst[dense_pos(r, c)] = src[dense_pos(r, c)];
+    return;
+  }
+  compose_column(ph, gates, mb, c);
 }
 
 // The same over the dense phases of many programs at once (a batch of
@@ -611,11 +639,12 @@ hipError_t launch_compose_units(const ComposeUnit* units, uint32_t n_units, hipS
 }
 
 hipError_t launch_compose_dense(const Phase* phases, const uint32_t* dense, uint32_t n_dense, const DGate* gates,
-                                uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st) {
+                                uint32_t batch, uint64_t mat_stride, double* mats, hipStream_t st,
+                                const uint8_t* dirty, const double* clean) {
   const uint64_t total = (uint64_t)n_dense * kR * batch;
   if (!total) return hipSuccess;
   hipLaunchKernelGGL(k_compose_dense, dim3((uint32_t)((total + 127) / 128)), dim3(128), 0, st, phases, dense,
-                     n_dense, gates, batch, mat_stride, mats);
+                     n_dense, gates, batch, mat_stride, mats, dirty, clean);
   return hipGetLastError();
 }
 

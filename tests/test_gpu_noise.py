@@ -73,6 +73,15 @@ def test_noisy_c1_and_dense_matrix_core_passes_match_oracle(ctx):
     _check(ctx, src, 0.01, 6, seed=5)
 
 
+def test_low_rate_takes_clean_phases_and_matches_oracle(ctx):
+    """At a low rate most (shot, dense phase) pairs draw no Pauli: those take
+    the phase's matrix composed once from the set without Paulis, the others
+    are composed for their shot. Shots with and without draws match the
+    oracle (bits, record probabilities, shot 0's amplitudes)."""
+    _check(ctx, W.c1_program(seed=9), 0.002, 40, seed=13)
+    _check(ctx, W.c2_program(seed=2, n=14, layers=8), 0.002, 8, seed=14)
+
+
 def test_noisy_complex64_matches_oracle_outside_the_tie_band(ctx):
     _check(ctx, W.c1_program(seed=6), 0.03, 16, seed=7, band=1e-4, amp_tol=2e-5, complex64=True)
 
