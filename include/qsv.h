@@ -238,7 +238,9 @@ typedef struct {
    and are bound per call from theta). The stream itself is what the paper's
    AST visitor emits, with gates, measurements, resets and the feed-forward of
    `if` statements on bits and registers (Methodology, kernel generation via
-   AST visitor; transpiling dynamic control flow).
+   AST visitor; transpiling dynamic control flow). A program without
+   parameters also has its gate matrices bound and its dense phases composed
+   here, on ctx's stream (the call waits for them), once for every later call.
    Errors: QSV_ERR_ARG (malformed stream: qubit/bit/flag/predicate out of range),
    QSV_ERR_LIMIT (more than 34 qubits). *out is freed with qsv_program_free. */
 qsv_status qsv_load_program(qsv_context* ctx, const qsv_program_desc* desc, qsv_program** out);

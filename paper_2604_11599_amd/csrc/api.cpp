@@ -102,6 +102,9 @@ struct qsv_program {
   uint32_t* d_noise_slot = nullptr;
   uint32_t* d_noise_ctr = nullptr;
   uint32_t* d_noise_dense = nullptr;  // per noise slot: the dense phase holding it, or kNoDense
+  // a program without parameters: its matrix slots bound and its dense phases
+  // composed once, when the plan is installed (every call reads them)
+  double* d_const_mats = nullptr;
   uint32_t* d_csr_off = nullptr;
   uint32_t* d_csr_sj = nullptr;
   double* d_csr_scale = nullptr;
@@ -376,7 +379,7 @@ void free_plan_buffers(qsv_program* p) {
   void* ptrs[] = {p->d_gates, p->d_phases, p->d_steps, p->d_passes, p->d_sites, p->d_src, p->d_dense,
                   p->d_events, p->d_preds, p->d_csr_off, p->d_csr_sj, p->d_csr_scale, p->d_ang_ent, p->d_ang_off,
                   p->d_code, p->d_lin_off, p->d_lin_in, p->d_lin_coef, p->d_noise, p->d_noise_slot,
-                  p->d_noise_ctr, p->d_noise_dense};
+                  p->d_noise_ctr, p->d_noise_dense, p->d_const_mats};
   for (void* q : ptrs)
     if (q) ignore(hipFree(q));
   p->d_gates = nullptr;
@@ -401,6 +404,7 @@ void free_plan_buffers(qsv_program* p) {
   p->d_noise_slot = nullptr;
   p->d_noise_ctr = nullptr;
   p->d_noise_dense = nullptr;
+  p->d_const_mats = nullptr;
 }
 
 // Plans the program's stream with options o and uploads the plan (replacing a
@@ -525,6 +529,19 @@ qsv_status install_plan(qsv_context* ctx, qsv_program* p, const PlanOptions& o) 
   if (e == hipSuccess) e = upload(off, &p->d_csr_off);
   if (e == hipSuccess) e = upload(sj, &p->d_csr_sj);
   if (e == hipSuccess) e = upload(sc, &p->d_csr_scale);
+  if (e == hipSuccess && desc->n_params == 0 && !pl.gate_src.empty()) {
+    // no parameter: the same matrices at every call, bound and composed here
+    // (noise slots as the identity: also the noise-free set of noisy calls)
+    const uint32_t n_slots = (uint32_t)pl.gate_src.size();
+    e = hipMalloc(reinterpret_cast<void**>(&p->d_const_mats), (size_t)n_slots * kMatStride * sizeof(double));
+    // (no slot reads theta; the pointer passed for it is only a valid address)
+    if (e == hipSuccess)
+      e = launch_bind_matrices(p->d_src, n_slots, p->d_const_mats, 0u, 1u, p->d_const_mats, nullptr, ctx->stream);
+    if (e == hipSuccess)
+      e = launch_compose_dense(p->d_phases, p->d_dense, (uint32_t)pl.dense_phases.size(), p->d_gates, 1u, 0u,
+                               p->d_const_mats, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  }
   if (e != hipSuccess) {
     free_plan_buffers(p);
     return set_err(ctx, e == hipErrorOutOfMemory ? QSV_ERR_NOMEM : QSV_ERR_DEVICE,
@@ -723,7 +740,14 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
   const uint64_t ms = noisy ? (uint64_t)std::max<uint32_t>(1, n_slots) * kMatStride : 0;
   // (noisy: one more set after the shots' sets, bound without Paulis: the
   // composed matrices of every phase in which a shot draws none)
-  HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride * (noisy ? batch + 1 : 1), &d_mats));
+  // (a program without parameters reads the matrices composed at load; its
+  // noisy calls take them as the set without Paulis)
+  double* const cmats = prog->d_const_mats;
+  if (noisy || !cmats)
+    HIP_TRY(scr.get((size_t)std::max<uint32_t>(1, n_slots) * kMatStride * (noisy ? batch + (cmats ? 0 : 1) : 1),
+                    &d_mats));
+  else
+    d_mats = cmats;
   const uint32_t n_dense = (uint32_t)pl.dense_phases.size();
   uint8_t* d_dirty = nullptr;
   if (noisy && n_dense) HIP_TRY(scr.get((size_t)((batch * n_dense + 3) & ~3ull), &d_dirty));
@@ -744,17 +768,20 @@ qsv_status qsv_run_shots(qsv_context* ctx, const qsv_program* prog, const double
     const double* rows = nullptr;
     uint32_t stride = 0;
     const uint32_t sets = noisy ? bs : 1u;
+    if (!noisy && cmats) return QSV_OK;  // bound and composed at load
     HIP_TRY(bind_theta(prog, d_theta, 1, d_ext, st, &rows, &stride));
-    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, noisy ? 0u : stride, noisy ? bs + 1u : 1u, d_mats,
-                                 nullptr, st));
+    HIP_TRY(launch_bind_matrices(prog->d_src, n_slots, rows, noisy ? 0u : stride,
+                                 noisy ? bs + (cmats ? 0u : 1u) : 1u, d_mats, nullptr, st));
     if (noisy) {
-      // the shots' Paulis, marking the phases they fall in; the clean set (after
-      // the shots') composed once, and copied into every phase no Pauli touched
-      double* clean = d_mats + (uint64_t)bs * ms;
+      // the shots' Paulis, marking the phases they fall in; the set without
+      // Paulis (composed at load, else after the shots' sets and composed
+      // here) is copied into every phase no Pauli touched
+      double* clean = cmats ? cmats : d_mats + (uint64_t)bs * ms;
       HIP_TRY(launch_noise_matrices(prog->d_noise_slot, prog->d_noise_ctr, (uint32_t)pl.noise_slot.size(),
                                     prog->d_noise, rb.key, opts->depolarizing, bs, ms, d_mats, prog->d_noise_dense,
                                     n_dense, d_dirty, st));
-      HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, n_dense, prog->d_gates, 1u, ms, clean, st));
+      if (!cmats)
+        HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, n_dense, prog->d_gates, 1u, ms, clean, st));
       HIP_TRY(launch_compose_dense(prog->d_phases, prog->d_dense, n_dense, prog->d_gates, bs, ms, d_mats, st,
                                    d_dirty, clean));
       return QSV_OK;
@@ -1185,9 +1212,13 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       uint32_t stride = 0;
       HIP_TRY(bind_theta(p, d_theta + to, 1, ext, st, &rows, &stride));
       (void)stride;  // one theta row per request
-      binds.push_back({p->d_src, rows, d_mats + mo, bind_total});
-      bind_total += slots;
-      for (uint32_t ph : p->plan.dense_phases) units.push_back({p->d_phases, p->d_gates, d_mats + mo, ph, 0u});
+      // a program without parameters reads the matrices composed at load
+      double* const rmats = p->d_const_mats ? p->d_const_mats : d_mats + mo;
+      if (!p->d_const_mats) {
+        binds.push_back({p->d_src, rows, rmats, bind_total});
+        bind_total += slots;
+        for (uint32_t ph : p->plan.dense_phases) units.push_back({p->d_phases, p->d_gates, rmats, ph, 0u});
+      }
       ReqDev& R = rd[i];
       std::memset(&R, 0, sizeof(R));
       R.steps = p->d_steps;
@@ -1198,7 +1229,7 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       R.events = p->d_events;
       R.preds = p->d_preds;
       R.code = p->d_code;
-      R.mats = d_mats + mo;
+      R.mats = rmats;
       if (q.opts.forced_len) {
         HIP_TRY(hipMemcpyAsync(d_forced + fo, q.opts.forced, q.n_shots * q.opts.forced_len, hipMemcpyHostToDevice, st));
         R.forced = d_forced + fo;
