@@ -1182,15 +1182,14 @@ __global__ __launch_bounds__(2 * kTileThreads, D8Waves<CT>::kMin) void k_tile_pa
 // (unrestricted) index space; every thread keeps its own 16 bins in LDS and
 // the bins are summed in a fixed order, so the result does not depend on how
 // many shots share the launch.
+// The histogram of one block of one shot's state over the site's qubits (see
+// k_site_reduce), summed in a fixed order; threads tid < kSiteBins return bin
+// tid, the others 0. Every thread of the workgroup calls it (two barriers).
 template <typename CT>
-__global__ __launch_bounds__(kRedThreads) void k_site_reduce(
-    const CT* __restrict__ state, uint64_t stride, const ShotCtl* __restrict__ ctl, SiteArgs a,
-    double* __restrict__ partials, uint32_t pblocks, const uint32_t* __restrict__ buf_of) {
-  __shared__ double bins[kSiteBins][kRedThreads];
-  __shared__ double red[kRedThreads / kSiteBins][kSiteBins];
-  const uint32_t shot = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
-  const ShotCtl* c = ctl + shot;
-  double* out = partials + ((uint64_t)shot * pblocks + blk) * kSiteBins;
+__device__ __forceinline__ double site_bins(const CT* __restrict__ state, uint64_t stride,
+                                            const ShotCtl* __restrict__ c, const SiteArgs& a, uint32_t blk,
+                                            uint64_t buf, uint32_t tid, double (*bins)[kRedThreads],
+                                            double (*red)[kSiteBins]) {
   for (int b = 0; b < kSiteBins; ++b) bins[b][tid] = 0.0;
   if (c->status == 0) {
     const uint64_t M = c->pend_mask, F = c->frame, Vm = c->pend_val ^ (F & M);
@@ -1199,7 +1198,7 @@ __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
     const uint64_t nfree = 1ull << (a.n - r);
     const uint64_t per = (nfree + a.blocks - 1) / a.blocks;
     const uint64_t j0 = per * blk, j1 = (j0 + per < nfree) ? j0 + per : nfree;
-    const CT* st = state + (uint64_t)(buf_of ? buf_of[shot] : shot) * stride;
+    const CT* st = state + buf * stride;
     uint32_t qbit[kSiteQubits];
     uint32_t fq = 0;
     for (uint32_t k = 0; k < a.nq; ++k) {
@@ -1234,11 +1233,21 @@ __global__ __launch_bounds__(kRedThreads) void k_site_reduce(
     red[part][b] = acc;
   }
   __syncthreads();
-  if (tid < kSiteBins) {
-    double acc = 0.0;
+  double acc = 0.0;
+  if (tid < kSiteBins)
     for (uint32_t part = 0; part < kRedThreads / kSiteBins; ++part) acc += red[part][tid];
-    out[tid] = acc;
-  }
+  return acc;
+}
+
+template <typename CT>
+__global__ __launch_bounds__(kRedThreads) void k_site_reduce(
+    const CT* __restrict__ state, uint64_t stride, const ShotCtl* __restrict__ ctl, SiteArgs a,
+    double* __restrict__ partials, uint32_t pblocks, const uint32_t* __restrict__ buf_of) {
+  __shared__ double bins[kSiteBins][kRedThreads];
+  __shared__ double red[kRedThreads / kSiteBins][kSiteBins];
+  const uint32_t shot = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  const double v = site_bins(state, stride, ctl + shot, a, blk, buf_of ? buf_of[shot] : shot, tid, bins, red);
+  if (tid < kSiteBins) partials[((uint64_t)shot * pblocks + blk) * kSiteBins + tid] = v;
 }
 
 // A classical expression (postfix code from code[pc] to its QSV_C_END) on one
@@ -1417,6 +1426,26 @@ __device__ __forceinline__ void site_events(ShotCtl& cc, const double* bins, con
   cc.frame ^= xf;
 }
 
+// The site's events for one shot from its 16 bins, by one thread.
+__device__ __forceinline__ void finalize_shot(ShotCtl* __restrict__ c, const double (&bins)[kSiteBins],
+                                              const SiteArgs& a, const SiteEvent* __restrict__ ev,
+                                              const DPred* __restrict__ preds, const qsv_cop* __restrict__ code,
+                                              uint64_t* __restrict__ creg, uint32_t cw, uint8_t* __restrict__ record,
+                                              uint32_t max_record, const uint8_t* __restrict__ forced,
+                                              uint32_t forced_len, uint64_t seed, uint64_t shot_base, uint32_t shot,
+                                              double readout_err, double reset_err,
+                                              const uint64_t* __restrict__ key) {
+  ShotCtl cc = *c;
+  if (key) {
+    seed = key[0];
+    shot_base = key[1];
+  }
+  site_events(cc, bins, a, ev, preds, code, creg + (uint64_t)shot * cw, record + (uint64_t)shot * max_record,
+              max_record, forced ? forced + (uint64_t)shot * forced_len : nullptr, forced_len, seed,
+              shot_base + shot, readout_err, reset_err);
+  *c = cc;
+}
+
 __global__ __launch_bounds__(64) void k_site_finalize(
     ShotCtl* __restrict__ ctl, SiteArgs a, const SiteEvent* __restrict__ ev,
     const DPred* __restrict__ preds, const qsv_cop* __restrict__ code, const double* __restrict__ partials,
@@ -1439,19 +1468,51 @@ __global__ __launch_bounds__(64) void k_site_finalize(
   if (tid != 0 || c->status != 0) return;
   double bins[kSiteBins];
   for (int b = 0; b < kSiteBins; ++b) bins[b] = a.nq ? ((part[0][b] + part[1][b]) + part[2][b]) + part[3][b] : 0.0;
-  ShotCtl cc = *c;
-  if (key) {
-    seed = key[0];
-    shot_base = key[1];
-  }
-  site_events(cc, bins, a, ev, preds, code, creg + (uint64_t)shot * cw, record + (uint64_t)shot * max_record,
-              max_record, forced ? forced + (uint64_t)shot * forced_len : nullptr, forced_len, seed,
-              shot_base + shot, readout_err, reset_err);
-  *c = cc;
+  finalize_shot(c, bins, a, ev, preds, code, creg, cw, record, max_record, forced, forced_len, seed, shot_base, shot,
+                readout_err, reset_err, key);
+}
+
+// Both steps of a site whose histogram takes one block (states of up to 14
+// qubits) and whose shots own their states: one workgroup per shot builds the
+// bins as k_site_reduce does and its first thread runs the events. The bins
+// equal those of the two launches (there each is the one block's sum plus
+// three zeros).
+template <typename CT>
+__global__ __launch_bounds__(kRedThreads) void k_site_fused(
+    const CT* __restrict__ state, uint64_t stride, ShotCtl* __restrict__ ctl, SiteArgs a,
+    const SiteEvent* __restrict__ ev, const DPred* __restrict__ preds, const qsv_cop* __restrict__ code,
+    uint64_t* __restrict__ creg, uint32_t cw, uint8_t* __restrict__ record, uint32_t max_record,
+    const uint8_t* __restrict__ forced, uint32_t forced_len, uint64_t seed, uint64_t shot_base,
+    const uint32_t* __restrict__ buf_of, double readout_err, double reset_err, const uint64_t* __restrict__ key) {
+  __shared__ double bins[kSiteBins][kRedThreads];
+  __shared__ double red[kRedThreads / kSiteBins][kSiteBins];
+  __shared__ double fin[kSiteBins];
+  const uint32_t shot = blockIdx.x, tid = threadIdx.x;
+  ShotCtl* c = ctl + shot;
+  const double v = site_bins(state, stride, c, a, 0u, buf_of ? buf_of[shot] : shot, tid, bins, red);
+  if (tid < kSiteBins) fin[tid] = v;
+  __syncthreads();
+  if (tid != 0 || c->status != 0) return;
+  double b16[kSiteBins];
+  for (int b = 0; b < kSiteBins; ++b) b16[b] = fin[b];
+  finalize_shot(c, b16, a, ev, preds, code, creg, cw, record, max_record, forced, forced_len, seed, shot_base, shot,
+                readout_err, reset_err, key);
 }
 
 hipError_t launch_site(const RunBuffers& rb, const SiteArgs& a, const SiteEvent* ev, const DPred* preds,
                        const qsv_cop* code, hipStream_t st) {
+  if (a.nq && a.blocks == 1 && !rb.slot_of) {
+    if (rb.c64)
+      hipLaunchKernelGGL(k_site_fused<float2>, dim3(rb.shots), dim3(kRedThreads), 0, st,
+                         reinterpret_cast<const float2*>(rb.state), rb.stride, rb.ctl, a, ev, preds, code, rb.creg,
+                         rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len, rb.seed, rb.shot_base, rb.buf_of,
+                         rb.readout_err, rb.reset_err, rb.key);
+    else
+      hipLaunchKernelGGL(k_site_fused<double2>, dim3(rb.shots), dim3(kRedThreads), 0, st, rb.state, rb.stride, rb.ctl,
+                         a, ev, preds, code, rb.creg, rb.cw, rb.record, rb.max_record, rb.forced, rb.forced_len,
+                         rb.seed, rb.shot_base, rb.buf_of, rb.readout_err, rb.reset_err, rb.key);
+    return hipGetLastError();
+  }
   if (a.nq) {
     // with trajectory sharing the histograms are taken per slot (slot control
     // blocks in site_ctl), the outcomes per shot
