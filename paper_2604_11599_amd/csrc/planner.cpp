@@ -619,10 +619,27 @@ Plan build_plan(const qsv_program_desc& d, const PlanOptions& opt) {
     close();
   };
 
+  // Flag updates move back over the gates before them whose guards do not
+  // read the flag they write: a gate changes no classical bit or flag, and a
+  // flag update reads none of the amplitudes, so the two commute. The flags of
+  // an if/else that follows another if then join the site before the first
+  // if's gates, and the guarded gates of both share a pass.
+  std::vector<uint32_t> order(d.n_instr);
+  for (uint32_t i = 0; i < d.n_instr; ++i) order[i] = i;
+  for (size_t k = 0; k < order.size(); ++k) {
+    const qsv_instr& in = d.instr[order[k]];
+    if (in.op != QSV_OP_SETF && in.op != QSV_OP_CLRF) continue;
+    const uint64_t fb = 1ull << in.flag;
+    for (size_t j = k; j > 0; --j) {
+      const qsv_instr& g = d.instr[order[j - 1]];
+      if ((g.op != QSV_OP_GATE && g.op != QSV_OP_NOISE) || (g.guard & fb)) break;
+      std::swap(order[j - 1], order[j]);
+    }
+  }
   // Cut the stream into gate runs and event runs.
   std::vector<uint32_t> run;
   bool in_site = false;
-  for (uint32_t i = 0; i < d.n_instr; ++i) {
+  for (uint32_t i : order) {
     const qsv_instr& in = d.instr[i];
     bool event = in.op != QSV_OP_GATE && in.op != QSV_OP_NOISE;
     bool foldable_x = in.op == QSV_OP_GATE && in.kind == QSV_G_X && in_site;

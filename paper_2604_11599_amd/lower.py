@@ -35,6 +35,7 @@ Control flow becomes flags (64 per shot) and guard masks:
                         condition is not a register compared with a constant
 Custom ``gate`` definitions are inlined.
 """
+import collections
 import math
 
 import numpy as np
@@ -321,13 +322,16 @@ class _Lowerer:
         self.csigned = {}           # classical register or variable -> read as two's complement
         self.consts, self.gatedefs = {}, {}
         self.nq = self.nc = self.npar = 0
-        self.free = list(range(63, -1, -1))
+        # free flags, least recently released first: consecutive ifs take
+        # different flags, so the planner can move an if's flag updates over
+        # the gates of the if before it (gates whose guards read other flags)
+        self.free = collections.deque(range(64))
 
     # -- flags --
     def _alloc(self):
         if not self.free:
             raise F.QasmError("control flow nested too deeply (more than 64 live flags)")
-        return self.free.pop()
+        return self.free.popleft()
 
     def _release(self, f):
         self.free.append(f)
