@@ -371,14 +371,15 @@ qsv_status qsv_run_shots_noalloc(qsv_context* ctx, const qsv_program* prog, cons
    different widths and trajectories of different lengths (loop exits, taken
    branches) share the GPU. States of up to 12 qubits stay in LDS for the whole
    program; states of 13..20 qubits live in a per-workgroup HBM slot; requests
-   with more qubits, and requests of 13..20 qubits with at least 64 shots, run
-   through qsv_run_shots with shared trajectories. When a batch has both kinds,
-   those calls run on a context forked from ctx (created on the first such
-   batch, with scratch of its own, and destroyed with ctx), driven from a second
-   host thread while the persistent launches run, so the two overlap on the
-   GPU; ctx itself must not be a fork, use an arena, or be capturing, else they
-   run after the launch on ctx. The call returns when both are done. The path
-   is chosen from the request alone. Every item is
+   with more qubits, requests of 18..20 qubits, and requests of 13..17 qubits
+   with at least 64 shots run through qsv_run_shots with shared trajectories.
+   When a batch has both kinds, those calls run on up to 12 contexts forked from
+   ctx (created on first use, with scratch of their own, and destroyed with
+   ctx), each driven from a host thread of its own while the persistent
+   launches run, so all of them overlap on the GPU; ctx itself must not be a
+   fork, use an arena, or be capturing, else they run after the launch on ctx.
+   The call returns when all are done. The path is chosen from the request
+   alone. Every item is
    computed the same way whatever else is in the batch, so a request's results
    do not depend on the batch it is part of. The paper runs whole suites of
    circuits of 2..20 qubits and the dynamic circuits over many shots

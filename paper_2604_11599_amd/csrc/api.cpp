@@ -62,11 +62,11 @@ struct qsv_context {
   bool capturing = false;  // launches are being recorded into a HIP graph
   std::string arch;        // the device's architecture name (autotuning cache key)
   qsv_context* parent = nullptr;  // a forked context runs its parent's programs
-  // qsv_run_batch's second lane: a fork that runs the tile-pass requests from
-  // a host thread of their own while this context runs the persistent
+  // qsv_run_batch's extra lanes: forks that run the tile-pass requests, each
+  // from a host thread of its own, while this context runs the persistent
   // launches (created on first use, destroyed with this context)
-  qsv_context* batch_fork = nullptr;
-  hipEvent_t batch_ev = nullptr;  // orders the fork's work after this context's queued work
+  std::vector<qsv_context*> batch_forks;
+  hipEvent_t batch_ev = nullptr;  // orders the forks' work after this context's queued work
   bool profiling() const { return (flags & QSV_FLAG_PROFILE) != 0 && !noalloc && !capturing; }
   // the arena scratch is carved from in the current call, if any
   uint8_t* call_arena() const { return noalloc ? static_cast<uint8_t*>(noalloc_scratch(device)) : arena; }
@@ -620,7 +620,7 @@ qsv_status qsv_context_fork(qsv_context* parent, qsv_context** out) {
 
 void qsv_destroy(qsv_context* ctx) {
   if (!ctx) return;
-  if (ctx->batch_fork) qsv_destroy(ctx->batch_fork);
+  for (qsv_context* f : ctx->batch_forks) qsv_destroy(f);
   ignore(enter_device(ctx->device));
   if (ctx->batch_ev) ignore(hipEventDestroy(ctx->batch_ev));
   ignore(hipStreamSynchronize(ctx->stream));
@@ -1078,6 +1078,13 @@ qsv_status qsv_run_shots_noalloc(qsv_context* ctx, const qsv_program* prog, cons
   return st;
 }
 
+// Streamed-state requests at least this wide take the tile passes whatever
+// their shot count: one workgroup per state would make their long
+// trajectories the tail of the persistent launch.
+constexpr uint32_t kTilePathMinWidth = 18;
+// Forks (each with a host thread) that run a batch's tile-pass requests.
+constexpr size_t kBatchLanes = 12;
+
 qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_reqs) {
   if (!ctx || (n_reqs && !reqs)) return set_err(ctx, QSV_ERR_ARG, "null argument");
   HIP_TRY(enter_device(ctx->device));
@@ -1101,7 +1108,8 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     // wide states, and streamed states with many shots, run on the tile-pass
     // path (decided from the request alone, so its results do not depend on
     // the rest of the batch)
-    if (n > (uint32_t)kStreamMaxBits || (n > (uint32_t)kResidentMaxBits && q.n_shots >= kTilePathMinShots)) {
+    if (n > (uint32_t)kStreamMaxBits ||
+        (n > (uint32_t)kResidentMaxBits && (q.n_shots >= kTilePathMinShots || n >= kTilePathMinWidth))) {
       big.push_back(r);
       continue;
     }
@@ -1115,8 +1123,9 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
   hipStream_t st = ctx->stream;
   // The tile-pass requests, with shared trajectories (bit-identical to running
   // every shot from |0...0>), each as one qsv_run_shots call.
-  auto run_big = [&](qsv_context* c) -> qsv_status {
-    for (uint32_t r : big) {
+  auto run_big = [&](qsv_context* c, uint32_t lane, uint32_t stride) -> qsv_status {
+    for (size_t k = lane; k < big.size(); k += stride) {
+      const uint32_t r = big[k];
       qsv_run_opts o = reqs[r].opts;
       o.state_out = nullptr;
       o.flags = QSV_RUN_SHARE_TRAJ;
@@ -1126,33 +1135,37 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
     }
     return QSV_OK;
   };
-  // With persistent work too, they run on the batch fork from a second host
-  // thread, so their launches overlap the persistent launches (the first of
-  // which, the shared prefixes, occupies few CUs). Not for a fork (forks are
-  // not forked), a caller's arena (the fork would allocate), or capture.
-  qsv_status big_rc = QSV_OK;
-  std::thread big_th;
+  // With persistent work too, they run on the batch forks, each from a host
+  // thread of its own (request k on lane k mod lanes), so their launches
+  // overlap each other and the persistent launches. Not for a fork (forks are
+  // not forked), a caller's arena (a fork would allocate), or capture.
+  const uint32_t lanes = (uint32_t)std::min<size_t>(kBatchLanes, big.size());
+  std::vector<qsv_status> big_rc(lanes, QSV_OK);
+  std::vector<std::thread> big_th;
   struct Join {
-    std::thread& t;
+    std::vector<std::thread>& t;
     ~Join() {
-      if (t.joinable()) t.join();
+      for (std::thread& x : t)
+        if (x.joinable()) x.join();
     }
   } join{big_th};
-  if (!big.empty() && !pers.empty() && !ctx->parent && !ctx->arena && !ctx->noalloc && !ctx->capturing) {
-    if (!ctx->batch_fork) {
-      if (qsv_context_fork(ctx, &ctx->batch_fork) != QSV_OK) ctx->batch_fork = nullptr;
-      if (ctx->batch_fork && hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming) != hipSuccess) {
-        clear_error();
-        ctx->batch_ev = nullptr;
-        qsv_destroy(ctx->batch_fork);
-        ctx->batch_fork = nullptr;
-      }
+  if (lanes && !pers.empty() && !ctx->parent && !ctx->arena && !ctx->noalloc && !ctx->capturing) {
+    while (ctx->batch_forks.size() < lanes) {
+      qsv_context* f = nullptr;
+      if (qsv_context_fork(ctx, &f) != QSV_OK) break;
+      ctx->batch_forks.push_back(f);
     }
-    if (ctx->batch_fork) {
+    if (!ctx->batch_ev && hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming) != hipSuccess) {
+      clear_error();
+      ctx->batch_ev = nullptr;
+    }
+    if (ctx->batch_forks.size() >= lanes && ctx->batch_ev) {
       HIP_TRY(hipEventRecord(ctx->batch_ev, st));
-      HIP_TRY(hipStreamWaitEvent(ctx->batch_fork->stream, ctx->batch_ev, 0));
-      qsv_context* f = ctx->batch_fork;
-      big_th = std::thread([&big_rc, &run_big, f] { big_rc = run_big(f); });
+      for (uint32_t l = 0; l < lanes; ++l) HIP_TRY(hipStreamWaitEvent(ctx->batch_forks[l]->stream, ctx->batch_ev, 0));
+      for (uint32_t l = 0; l < lanes; ++l)
+        big_th.emplace_back([&big_rc, &run_big, &ctx, l, lanes] {
+          big_rc[l] = run_big(ctx->batch_forks[l], l, lanes);
+        });
     }
   }
   if (!pers.empty()) {
@@ -1357,17 +1370,20 @@ qsv_status qsv_run_batch(qsv_context* ctx, const qsv_request* reqs, uint32_t n_r
       }
     }
   }
-  if (big_th.joinable()) {
-    big_th.join();
-    qsv_context* f = ctx->batch_fork;
-    if (ctx->profiling()) {
-      add_profile(&ctx->prof, f->prof);
-      std::memset(&f->prof, 0, sizeof(f->prof));
+  if (!big_th.empty()) {
+    for (std::thread& t : big_th) t.join();
+    for (uint32_t l = 0; l < lanes; ++l) {
+      qsv_context* f = ctx->batch_forks[l];
+      if (ctx->profiling()) {
+        add_profile(&ctx->prof, f->prof);
+        std::memset(&f->prof, 0, sizeof(f->prof));
+      }
     }
-    if (big_rc != QSV_OK) return set_err(ctx, big_rc, f->err);
+    for (uint32_t l = 0; l < lanes; ++l)
+      if (big_rc[l] != QSV_OK) return set_err(ctx, big_rc[l], ctx->batch_forks[l]->err);
     return QSV_OK;
   }
-  return run_big(ctx);
+  return run_big(ctx, 0, 1);
 }
 
 }  // extern "C"

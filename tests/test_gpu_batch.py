@@ -158,30 +158,35 @@ def _same(a, b):
 
 
 def test_batch_overlapped_route_equals_separate_runs():
-    """With persistent and tile-pass requests in one batch, the tile-pass ones
-    run on the context's batch fork from a second host thread, overlapping the
-    persistent launches: repeated batches (the fork reused) give the results of
-    the same requests run separately, the fork's launches are counted in the
-    context's profile, and a forked context (which runs them after the launch
-    on itself) gives the same results."""
+    """With persistent and tile-pass requests in one batch (an 18-qubit request
+    takes the tile passes at any shot count), the tile-pass ones run on the
+    context's batch forks, one host thread each, overlapping the persistent
+    launch: repeated batches (the forks reused) give the results of the same
+    requests run separately, the forks' launches are counted in the context's
+    profile, and a forked context (which runs them after the launch on itself)
+    gives the same results; the 18-qubit request agrees with the oracle."""
     from paper_2604_11599_amd import Context
     c = Context(0, profile=True)
     try:
         big1 = c.load(W.c3_program(3, n=16))
         big2 = c.load(W.random_dynamic_program(322, 15, n_ops=40, final_measure=True))
+        wide_src = W.c3_program(77, n=18, layers=3)     # 18 qubits: the tile passes at any shot count
+        wide = c.load(wide_src)
         smalls = [c.load(W.c3_program(20 + k, n=n, layers=3)) for k, n in enumerate((8, 12, 14, 17))]
-        reqs = [{"prog": big1, "shots": 80, "seed": 3}, {"prog": big2, "shots": 64, "seed": 4, "shot_offset": 7}]
+        reqs = [{"prog": big1, "shots": 80, "seed": 3}, {"prog": big2, "shots": 64, "seed": 4, "shot_offset": 7},
+                {"prog": wide, "shots": 6, "seed": 8}]
         reqs += [{"prog": p, "shots": 10, "seed": 30 + k} for k, p in enumerate(smalls)]
-        sep_big = [big1.run_shots(80, seed=3, share=True), big2.run_shots(64, seed=4, shot_offset=7, share=True)]
-        sep_small = c.run_batch(reqs[2:])
+        sep_big = [big1.run_shots(80, seed=3, share=True), big2.run_shots(64, seed=4, shot_offset=7, share=True),
+                   wide.run_shots(6, seed=8, share=True)]
+        sep_small = c.run_batch(reqs[3:])
         for rep in range(3):
             say(f"overlapped batch, repetition {rep}")
             c.profile_reset()
             res = c.run_batch(reqs)
             prof = c.profile()
-            _same(res[0], sep_big[0])
-            _same(res[1], sep_big[1])
-            for a, b in zip(res[2:], sep_small):
+            for a, b in zip(res[:3], sep_big):
+                _same(a, b)
+            for a, b in zip(res[3:], sep_small):
                 _same(a, b)
             assert prof["persistent_launches"] >= 1 and prof["pass_launches"] >= 1
         f = c.fork()
@@ -190,6 +195,7 @@ def test_batch_overlapped_route_equals_separate_runs():
         for a, b in zip(res_f, res):
             _same(a, b)
         _check(W.random_dynamic_program(322, 15, n_ops=40, final_measure=True), res[1], 64, 4, 7)
+        _check(wide_src, res[2], 6, 8)
     finally:
         c.close()
 
