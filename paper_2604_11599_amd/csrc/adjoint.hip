@@ -892,8 +892,20 @@ __global__ void k_grad_reduce(const double* __restrict__ gpart, uint32_t parts, 
   if (idx >= (uint64_t)batch * gate_count * 3) return;
   uint32_t j = idx % 3, gi = (idx / 3) % gate_count, b = (uint32_t)(idx / 3 / gate_count);
   if (j >= gates[gi].nang) return;
+  // the partials of tile w at src[w * step], added in tile order; each group
+  // of 16 is loaded before it is added, so the loads are in flight together
+  const double* src = gpart + ((uint64_t)b * parts * gate_count + gi) * 3 + j;
+  const uint64_t step = (uint64_t)gate_count * 3;
   double acc = 0.0;
-  for (uint32_t w = 0; w < parts; ++w) acc += gpart[(((uint64_t)b * parts + w) * gate_count + gi) * 3 + j];
+  uint32_t w = 0;
+  for (; w + 16 <= parts; w += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = src[(uint64_t)(w + u) * step];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += v[u];
+  }
+  for (; w < parts; ++w) acc += src[(uint64_t)w * step];
   dEda[((uint64_t)b * n_slots + gates[gi].mat) * 3 + j] = acc;
 }
 
